@@ -1,0 +1,140 @@
+#!/usr/bin/env python3
+"""Throughput of the gas-kinetic flux + update step on one MI355X.
+
+Default workload: 2D shock/boundary-layer interaction, 1024 x 512 wall-stretched grid,
+Mach-2 inflow, 8-degree oblique shock from the top boundary, adiabatic no-slip wall,
+frozen seeded k/omega.  A step is one explicit time step of the whole path (CFL time
+step, strain rate, every face flux, conservative update, residual).  The FP64 form is
+the headline `value`; the FP32-flux form (flux arithmetic in FP32, everything else FP64)
+is reported beside it with its error against the FP64 run.
+
+Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6    # scalar FP32 VALU at the same rate (packed FP32 is not used)
+HBM_PEAK_GBS = 8000.0
+
+
+def _leg(case, steps, warmup):
+    import torch
+
+    from paper_1302_2132_amd import Solver, gks_kernel_times, gks_set_timing
+    s = Solver(case)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    gks_set_timing(s.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = gks_kernel_times(s.h)
+    r = s.residual()
+    W = s.fields("cons")
+    s.close()
+    return {"seconds": t1 - t0, "kernels": kt, "res": r, "W": W}
+
+
+def _roofline(case, leg, steps, flops_face, peak):
+    n = case.n
+    faces = (n[0] + 1) * n[1] + n[0] * (n[1] + 1) if case.dim == 2 else \
+        3 * (n[0] + 1) * n[1] * n[2]
+    face_s = leg["kernels"]["face_ms"] / 1e3 / steps
+    achieved = flops_face * faces / face_s / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "k_face", "flops_per_face": flops_face, "faces_per_launch": faces,
+            "avg_launch_us": round(face_s * 1e6, 2)}
+
+
+def _cpu_baseline(case, target_s=15.0):
+    import oracle
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
+    t0 = time.perf_counter()
+    r = oracle.run(case, 1, nthreads=threads)
+    t1 = time.perf_counter()
+    one = t1 - t0
+    more = max(0, min(20, int(target_s / max(one, 1e-3)) - 1))
+    if more:
+        t2 = time.perf_counter()
+        oracle.run(case, more, nthreads=threads, W=r["W"])
+        t3 = time.perf_counter()
+        total, steps = one + (t3 - t2), 1 + more
+    else:
+        total, steps = one, 1
+    return {"value": case.ncells * steps / total, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the full {case.n[0]}x{case.n[1]} workload "
+                      f"({total:.1f} s, OpenMP over faces/cells)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(multi-GPU sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from inputs import cases as C
+    from paper_1302_2132_amd import gks_face_flops
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+
+    case = C.sbli(1024, 512)
+    K, Wm = args.steps, args.warmup
+    leg64 = _leg(case, K, Wm)
+    value = case.ncells * K / leg64["seconds"]
+    flops2d = gks_face_flops(2, "fp64")
+    out = {
+        "metric": "cell-updates/s FP64 vs FP32-flux at stated err; p50/p99 served solve latency",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": leg64["seconds"] * 1e3 / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "sbli_1024x512: 2D Mach-2 shock/boundary-layer interaction, "
+                               "8-deg oblique shock, adiabatic no-slip wall, tanh wall-stretched y, "
+                               "frozen seeded k/omega, CFL 0.5",
+                   "cells": case.ncells, "precision": "fp64"},
+        "roofline": _roofline(case, leg64, K, flops2d, FP64_PEAK_TFLOPS),
+        "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg64["kernels"].items() if k != "steps"},
+    }
+    if not args.no_fp32:
+        c32 = C.sbli(1024, 512, precision="fp32_flux")
+        leg32 = _leg(c32, K, Wm)
+        err = []
+        for m in range(case.nvar):
+            ref = leg64["W"][m]
+            err.append(float(np.max(np.abs(leg32["W"][m] - ref)) / np.max(np.abs(ref))))
+        out["fp32_flux"] = {
+            "value": c32.ncells * K / leg32["seconds"], "unit": "cell-updates/s",
+            "ms_per_step": leg32["seconds"] * 1e3 / K,
+            "max_rel_err_vs_fp64_per_field": err, "after_steps": K + Wm,
+            "roofline": _roofline(c32, leg32, K, flops2d, FP32_PEAK_TFLOPS),
+            "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg32["kernels"].items() if k != "steps"},
+        }
+    if not args.no_cpu:
+        out["cpu_baseline"] = _cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * gks.h -- C ABI of the MI355X gas-kinetic flux/update library (libgks.so).
+ *
+ * The library advances the compressible Navier-Stokes equations with the turbulent
+ * gas-kinetic scheme of M. Righi, "A gas-kinetic scheme for the simulation of
+ * compressible turbulent flows" (arXiv:1302.2132): at every cell face a BGK (Xu-type)
+ * flux built from the Kogan integral solution (Eqs. integralbgk, resultingf, fluxesf),
+ * with a relaxation time made of a laminar part, the k-omega turbulent part and an
+ * artificial part (Eqs. relaxation time, taua, tautchenadjusted), followed by the
+ * conservative finite-volume update on a stretched Cartesian grid (section
+ * "Implementation of the turbulent gas-kinetic scheme in a finite-volume solver").
+ * k and omega are frozen inputs.
+ *
+ * Conventions used by every entry point
+ *  - Cells are stored structure-of-arrays, x fastest: field m of cell (i, j, k) is at
+ *    m * ncells + (k * ny + j) * nx + i.  Conservative variables are
+ *    (rho, rho U, rho V, [rho W], rho E), nvar = dim + 2.
+ *  - Pointers named dev_* are device (HBM) pointers; all other pointers are host memory.
+ *    The library copies every host input it needs during the call that receives it.
+ *  - The caller owns device memory: it passes a workspace of the size the library asks
+ *    for (a torch uint8 CUDA tensor works), and the library never allocates device
+ *    memory itself.  The workspace must stay allocated until gks_destroy.
+ *  - Every call returns a gks_status.  Asynchronous device errors (a non-positive
+ *    density or pressure, a non-finite value) are raised by the kernels into a
+ *    device-side flag and reported by the next synchronising call (gks_residual,
+ *    gks_fields, gks_destroy) as GKS_ERR_NONPHYSICAL; after that only gks_fields and
+ *    gks_destroy are accepted on the handle.
+ *  - One handle belongs to one HIP stream; handles are independent of each other.
+ */
+#ifndef GKS_H
+#define GKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GKS_OK = 0,
+    GKS_ERR_ARG = 1,          /* invalid argument or configuration */
+    GKS_ERR_NONPHYSICAL = 2,  /* rho <= 0, p <= 0 or non-finite state met */
+    GKS_ERR_NOMEM = 3,        /* workspace too small */
+    GKS_ERR_DEVICE = 4,       /* a HIP call failed */
+    GKS_ERR_STATE = 5         /* call not allowed in the handle's current state */
+} gks_status;
+
+/* Boundary conditions per axis side.  Two ghost layers are synthesised on the fly:
+ *  PERIODIC  wrap-around (both sides of the axis must be periodic);
+ *  WALL      no-slip adiabatic wall: mirror image with every momentum component negated;
+ *  DIRICHLET fixed state, bc_data = nvar conservative values;
+ *  PROFILE   fixed state per boundary cell, bc_data = nvar x ntan values (field-major),
+ *            ntan = product of the other axes' cell counts, tangential index with the
+ *            lower axis fastest; ghost cells beyond the tangential range use the nearest;
+ *  OUTFLOW   zeroth-order extrapolation (copy of the boundary cell).
+ * k, omega and the strain rate of a ghost cell are those of its interior image
+ * (wrapped for PERIODIC, mirrored for WALL, nearest boundary cell otherwise). */
+enum { GKS_BC_PERIODIC = 0, GKS_BC_WALL = 1, GKS_BC_DIRICHLET = 2, GKS_BC_PROFILE = 3, GKS_BC_OUTFLOW = 4 };
+
+/* Arithmetic of the flux evaluation.  FP32_FLUX evaluates moments, coefficients and the
+ * time-integrated flux in FP32; reconstruction, primitive recovery, the conservative
+ * update and the time-step/residual reductions stay FP64. */
+enum { GKS_FP64 = 0, GKS_FP32_FLUX = 1 };
+
+/* Fields for gks_fields. CONS: conservative state (nvar x ncells). PRIM: rho, U, V, [W],
+ * p (nvar x ncells). STRAIN: strain-rate magnitude sqrt(2 S_ab S_ab) (ncells). */
+enum { GKS_FIELD_CONS = 0, GKS_FIELD_PRIM = 1, GKS_FIELD_STRAIN = 2 };
+
+typedef struct {
+    int32_t dim;                  /* 2 or 3 */
+    int64_t n[3];                 /* cells per axis (>= 2 each); n[2] ignored in 2D */
+    const double* xf[3];          /* host: n[d]+1 increasing face coordinates per axis */
+    int32_t bc[3][2];             /* GKS_BC_* for [axis][low, high] */
+    const double* bc_data[3][2];  /* host: DIRICHLET / PROFILE data, else NULL */
+    double gamma;                 /* ratio of specific heats, 1 < gamma <= 1 + 2/dim */
+    double prandtl;               /* Prandtl number of the heat-flux correction */
+    double mu;                    /* constant laminar viscosity (tau_lam = mu / p) */
+    double c_a;                   /* artificial relaxation coefficient of Eq. taua (>= 0) */
+    double c_mu;                  /* C_mu of the k-omega relaxation time (0.09) */
+    double cfl;                   /* CFL number of the global time step */
+    double t_end;                 /* > 0: clip the last step to land on t_end, then stop */
+    int32_t precision;            /* GKS_FP64 or GKS_FP32_FLUX */
+} gks_config;
+
+typedef struct gks_ctx* gks_handle;
+
+/* Device workspace needed by one solve (state double buffer, frozen fields, face fluxes,
+ * metrics, reduction partials).  This is the HBM footprint used for admission. */
+gks_status gks_workspace_bytes(const gks_config* cfg, size_t* bytes);
+
+/* Validate cfg and the initial state, copy W (nvar x ncells), k and omega (ncells) from
+ * the host into dev_workspace (256-byte aligned, >= gks_workspace_bytes), and compute the
+ * first CFL step on `hip_stream` (a hipStream_t; NULL = default stream).  Returns
+ * GKS_ERR_ARG for a bad config, k < 0, omega <= 0; GKS_ERR_NONPHYSICAL for rho <= 0 or
+ * p <= 0; GKS_ERR_NOMEM if bytes is too small. */
+gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+                    const double* W, const double* k, const double* omega, gks_handle* out);
+
+/* Enqueue nsteps explicit steps (asynchronous; no host synchronisation).  Each step: CFL
+ * time step from the current state, strain rate, every face flux, conservative update,
+ * residual and next time step, all on the device. */
+gks_status gks_step(gks_handle h, int32_t nsteps);
+
+/* Synchronise and report the last step: res[nvar] = sqrt(mean(((W^{n+1}-W^n)/dt)^2)) per
+ * field, the step dt_last, the time t and the number of steps done.  Any pointer may be
+ * NULL. */
+gks_status gks_residual(gks_handle h, double* res, double* dt_last, double* t, int64_t* steps_done);
+
+/* Synchronise and copy a field (GKS_FIELD_*) to host memory. */
+gks_status gks_fields(gks_handle h, int32_t which, double* host_out);
+
+/* Device pointer of the current conservative state (nvar x ncells, FP64). Valid until the
+ * next gks_step. */
+gks_status gks_state_device_ptr(gks_handle h, const double** dev_W);
+
+/* Synchronise and release the handle (the caller frees the workspace). */
+gks_status gks_destroy(gks_handle h);
+
+/* Per-kernel timing for benchmarks.  While enabled, gks_step records HIP events on the
+ * handle's stream around each of its three launches (strain, face, update).
+ * gks_kernel_times synchronises and returns the summed milliseconds of each launch kind
+ * since timing was enabled, and the number of steps timed; enabling again resets. */
+gks_status gks_set_timing(gks_handle h, int32_t enable);
+gks_status gks_kernel_times(gks_handle h, double* ms /*[3]*/, int64_t* steps_timed);
+
+/* Text of the last error on the handle (or of the last failed handle-less call if NULL). */
+const char* gks_last_error(gks_handle h);
+
+/* Algorithmic FP operation count of one face flux of the given dimension and precision:
+ * +, -, *, / and sqrt count 1, a fused multiply-add 2, each exp/erfc/expm1 call 1.
+ * Counted by running the flux code on the host with a counting number type. */
+gks_status gks_face_flops(int32_t dim, int32_t precision, double* flops);
+
+/* ---------------------------------------------------------------------------------- */
+/* Batched form: many independent solves (any mix of sizes, dims, precisions) advanced  */
+/* by persistent kernels that walk one device tile table per step.                       */
+/* ---------------------------------------------------------------------------------- */
+typedef struct gks_batch_ctx* gks_batch;
+
+/* Device workspace of a batch table able to hold up to `capacity` solves. */
+gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
+
+/* Create a batch over `count` initialised handles (all on the same device; their own
+ * streams are not used: batch work runs on `hip_stream`).  The table lives in
+ * dev_workspace.  Handles stay owned by the caller and must outlive the batch. */
+gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity,
+                            void* dev_workspace, size_t bytes, void* hip_stream, gks_batch* out);
+
+/* Replace the member list (admission/retirement).  The device table is rewritten in
+ * place, so a captured step graph stays valid. */
+gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t count);
+
+/* Enqueue nsteps steps of every member (members that reached t_end or raised an error
+ * are skipped on the device).  When a graph is captured (gks_batch_capture) the steps
+ * replay it. */
+gks_status gks_batch_step(gks_batch b, int32_t nsteps);
+
+/* Capture one step of the batch as a HIP graph; later gks_batch_step calls replay it. */
+gks_status gks_batch_capture(gks_batch b);
+
+/* Launch shape of the batch kernels: kind 0 = strain, 1 = face (2D FP64), 2 = face
+ * (2D FP32), 3 = face (3D FP64), 4 = face (3D FP32), 5 = update.  grid = number of
+ * persistent workgroups (0 = one per tile).  Invalidates a captured graph. */
+gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid);
+
+/* Synchronise; copy per-member steps done, residual (nvar each, 5 slots per member),
+ * time and status (0 running, 1 done by t_end, 2 error) into host arrays (any NULL). */
+gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* t, int32_t* state);
+
+gks_status gks_batch_destroy(gks_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GKS_H */

@@ -1,0 +1,98 @@
+// gks_device.hpp -- device-side data layout shared by the kernels and the host code of
+// libgks: per-solve descriptor, per-solve step state, and the tile table that lets one
+// set of persistent kernels advance any mix of solves.
+#pragma once
+#include <stdint.h>
+
+namespace gks {
+
+constexpr int CELL_TILE = 256;   // cells per tile of the strain/update kernels (= block size)
+constexpr int FACE_TILE = 64;    // faces per tile of the face kernel (= block size, one wave)
+constexpr int NCLS = 4;          // face-kernel classes: (dim 2|3) x (FP64|FP32 flux)
+
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_DIRICHLET = 2, BC_PROFILE = 3, BC_OUTFLOW = 4 };
+
+// Step state of one solve, written only by the last workgroup of the update kernel (and
+// by atomics from every workgroup).
+struct alignas(64) State {
+    double dt;          // step size of the step about to run
+    double t;           // time reached
+    double t_after;     // time at the end of the step about to run (t_end when clipped)
+    double dt_last;     // size of the last completed step
+    double res[5];      // residual of the last completed step
+    double res_first[5];
+    unsigned long long rate_bits;  // max CFL rate of the state being produced (bit pattern)
+    unsigned int tiles_done;       // update tiles finished in the current step
+    int parity;         // W[parity] is the current state
+    int err;            // bit 0: non-physical state met
+    int active;         // 1 while stepping
+    long long steps;
+};
+
+// Device descriptor of one solve.  Extended metric arrays are offset so that index i of
+// axis d (i from -2) reads xf[d][i], xc[d][i], dx[d][i].
+struct Inst {
+    int dim, nv, precision, cls;
+    int n[3];
+    int ntan[3];               // cells in a boundary plane of axis d
+    long long ncells;
+    long long nface[3];        // faces normal to axis d
+    int bc[3][2];
+    double gamma, prandtl, mu, c_a, c_mu, cfl, t_end, b;
+    double* W[2];
+    const double* k;
+    const double* om;
+    double* S;
+    void* F[3];                // face fluxes per axis: [nv][nface[d]], double or float
+    const double* xf[3];
+    const double* xc[3];
+    const double* dx[3];
+    const double* bcd[3][2];
+    double* part;              // residual partial sums [ntile_cell][nv]
+    State* st;
+    int ntile_cell;
+    int ntile_face[3];
+    int ntile_face_all;
+};
+
+// Tile table header; arrays follow at offsets computed by TabView.
+struct TabHdr {
+    int count;
+    int total_cell;
+    int ncls[NCLS];
+    int total_face[NCLS];
+};
+
+__host__ __device__ inline size_t tab_align(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct TabView {
+    TabHdr* hdr;
+    Inst* inst;          // [cap]
+    int* cell_prefix;    // [cap + 1]
+    int* cls_member;     // [NCLS][cap]
+    int* cls_prefix;     // [NCLS][cap + 1]
+    __host__ __device__ TabView(void* base, int cap)
+    {
+        char* p = (char*)base;
+        hdr = (TabHdr*)p;
+        size_t off = tab_align(sizeof(TabHdr));
+        inst = (Inst*)(p + off);
+        off = tab_align(off + sizeof(Inst) * (size_t)cap);
+        cell_prefix = (int*)(p + off);
+        off += sizeof(int) * (size_t)(cap + 1);
+        cls_member = (int*)(p + off);
+        off += sizeof(int) * (size_t)NCLS * cap;
+        cls_prefix = (int*)(p + off);
+    }
+    __host__ __device__ static size_t bytes(int cap)
+    {
+        size_t off = tab_align(sizeof(TabHdr));
+        off = tab_align(off + sizeof(Inst) * (size_t)cap);
+        off += sizeof(int) * (size_t)(cap + 1);
+        off += sizeof(int) * (size_t)NCLS * cap;
+        off += sizeof(int) * (size_t)NCLS * (cap + 1);
+        return tab_align(off);
+    }
+};
+
+}  // namespace gks

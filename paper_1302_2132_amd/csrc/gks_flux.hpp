@@ -1,0 +1,421 @@
+// gks_flux.hpp -- closed-form per-interface flux of the turbulent gas-kinetic scheme.
+//
+// One face, face-local frame (index 1 of a state vector is the normal momentum).  The
+// scheme is Xu's BGK-NS flux as used by Righi (arXiv:1302.2132): the Kogan integral
+// solution of the BGK model (Eq. integralbgk) with a Chapman-Enskog initial distribution
+// on each side (Eq. initialf0), an equilibrium state built from the two half-space
+// Maxwellians (Eq. intermediatestate) with its own linear expansion in space and time
+// (Eq. eqlgform), integrated exactly over the time step (Eqs. resultingf, fluxesf), with
+// tau = mu/p + tau_a + k-omega part (Eqs. relaxation time, taua, tautchenadjusted) and the
+// Prandtl-number correction of the heat flux.
+//
+// How this differs from a literal evaluation:
+//  * moments factorise into a u-moment sequence (full line or half line) times
+//    tangential/internal moments; every <u^k psi (a.psi)> used here is a closed form in
+//    five u-moments (tmom), so no moment table over (u, v, w, xi) is ever built;
+//  * every moment-matrix system M(g) a = r is solved in closed form (solve);
+//  * the time-integrated compatibility condition makes int int psi f = dt W0 +
+//    dt^2/2 rho0 <psi Abar.psi>, so the u-less moments needed by the heat-flux
+//    correction come for free from the right-hand side of the Abar system.
+//
+// Scalar type R is double (FP64 form) or float (FP32-flux form); reconstruction and
+// primitive recovery arrive in double.  The code is plain templated arithmetic so that
+// the library can also run it on the host with an operation-counting number type.
+#pragma once
+
+#ifndef GKS_HD
+#define GKS_HD __host__ __device__
+#endif
+
+namespace gks {
+
+GKS_HD inline double g_sqrt(double x) { return sqrt(x); }
+GKS_HD inline float g_sqrt(float x) { return sqrtf(x); }
+GKS_HD inline double g_exp(double x) { return exp(x); }
+GKS_HD inline float g_exp(float x) { return expf(x); }
+GKS_HD inline double g_erfc(double x) { return erfc(x); }
+GKS_HD inline float g_erfc(float x) { return erfcf(x); }
+GKS_HD inline double g_abs(double x) { return fabs(x); }
+GKS_HD inline float g_abs(float x) { return fabsf(x); }
+
+template <typename R> GKS_HD inline R rconst(double v) { return R(v); }
+
+// Maxwellian in the face-local frame together with the derived quantities every moment
+// needs.  h = 1/(2 lambda) is the variance of each velocity component; bt = b - 1 is the
+// number of quadratic degrees of freedom besides the normal velocity.
+template <typename R, int D>
+struct Mx {
+    R rho, U[D], lam, h;
+    R vt2;   // |tangential velocity|^2
+    R q;     // <v^2 + w^2 + xi^2> = vt2 + bt h
+};
+
+template <typename R, int D>
+GKS_HD inline void mx_set(Mx<R, D>& g, R rho, const R* U, R lam, R h, R bt)
+{
+    g.rho = rho;
+    g.lam = lam;
+    g.h = h;
+    R v2 = R(0);
+    for (int d = 0; d < D; ++d) g.U[d] = U[d];
+    for (int d = 1; d < D; ++d) v2 = v2 + U[d] * U[d];
+    g.vt2 = v2;
+    g.q = v2 + bt * h;
+}
+
+// u-moment recurrence  m_{n+1} = U m_n + n h m_{n-1}  (Gaussian, integration by parts),
+// filled from the first two entries up to index `last`.
+template <typename R>
+GKS_HD inline void urec(R* m, R U, R h, int last)
+{
+    for (int n = 1; n < last; ++n) m[n + 1] = U * m[n] + R(n) * h * m[n - 1];
+}
+
+// T = <u^k psi (a.psi)> from u-moments mk[0..4] = <u^k> .. <u^{k+4}> (full or half line),
+// tangential velocities and xi over all values.  With c0 = a_0 + a_t.V_t + a_E q/2 and
+// P_j = c0 <u^{k+j}> + a_u <u^{k+j+1}> + a_E/2 <u^{k+j+2}>:
+//   T_rho = P_0, T_u = P_1, T_t = V_t P_0 + <u^k> (a_t + a_E V_t) h,
+//   T_E = (P_2 + q P_0 + <u^k> X)/2,  X = 2h (a_t.V_t + a_E vt2) + a_E bt h^2
+// (the X and h terms are the covariances of v_t and of v^2+w^2+xi^2 with a.psi).
+template <typename R, int D>
+GKS_HD inline void tmom(const Mx<R, D>& g, const R* mk, const R* a, R bt, R* T)
+{
+    const R aE = a[D + 1];
+    R aV = R(0);
+    for (int t = 1; t < D; ++t) aV = aV + a[1 + t] * g.U[t];
+    const R half = R(0.5);
+    const R c0 = a[0] + aV + half * aE * g.q;
+    const R P0 = c0 * mk[0] + a[1] * mk[1] + half * aE * mk[2];
+    const R P1 = c0 * mk[1] + a[1] * mk[2] + half * aE * mk[3];
+    const R P2 = c0 * mk[2] + a[1] * mk[3] + half * aE * mk[4];
+    const R X = R(2) * g.h * (aV + aE * g.vt2) + aE * bt * g.h * g.h;
+    T[0] = P0;
+    T[1] = P1;
+    for (int t = 1; t < D; ++t) T[1 + t] = g.U[t] * P0 + mk[0] * (a[1 + t] + aE * g.U[t]) * g.h;
+    T[D + 1] = half * (P2 + g.q * P0 + mk[0] * X);
+}
+
+// <u^k psi> (a = unit vector on the density slot)
+template <typename R, int D>
+GKS_HD inline void tmom1(const Mx<R, D>& g, const R* mk, R* T)
+{
+    T[0] = mk[0];
+    T[1] = mk[1];
+    for (int t = 1; t < D; ++t) T[1 + t] = g.U[t] * mk[0];
+    T[D + 1] = R(0.5) * (mk[2] + g.q * mk[0]);
+}
+
+// Closed-form solution of <psi (a.psi)>_g = r (b = total degrees of freedom):
+//   a_E = (4 lam^2 / b) [2 r_E - 2 U.r_m + r_rho (|U|^2 - b/(2 lam))]
+//   a_d = 2 lam (r_d - U_d r_rho) - U_d a_E
+//   a_rho = r_rho - U.a_m - a_E (|U|^2 + b/(2 lam)) / 2
+template <typename R, int D>
+GKS_HD inline void solve(const Mx<R, D>& g, const R* r, R b, R inv_b, R* a)
+{
+    R U2 = R(0), Ur = R(0);
+    for (int d = 0; d < D; ++d) { U2 = U2 + g.U[d] * g.U[d]; Ur = Ur + g.U[d] * r[1 + d]; }
+    const R bh = b * g.h;
+    const R aE = R(4) * g.lam * g.lam * inv_b * (R(2) * r[D + 1] - R(2) * Ur + r[0] * (U2 - bh));
+    R Ua = R(0);
+    for (int d = 0; d < D; ++d) {
+        a[1 + d] = R(2) * g.lam * (r[1 + d] - g.U[d] * r[0]) - g.U[d] * aE;
+        Ua = Ua + g.U[d] * a[1 + d];
+    }
+    a[0] = r[0] - Ua - R(0.5) * aE * (U2 + bh);
+    a[D + 1] = aE;
+}
+
+// Time weights of the Kogan solution over [0, dt] (x = dt/tau, E = e^{-x}):
+//   gam0 = dt - tau(1-E), gam1 = 2tau^2(1-E) - tau dt(1+E), gam2 = dt^2/2 - tau dt + tau^2(1-E),
+//   gam3 = tau(1-E), gam4 = -(2tau^2(1-E) - tau dt E), gam5 = -tau^2(1-E),
+// and the ratios c1, c4, c5 = gam1, gam4, gam5 over tau*gam0 of the integrated compatibility
+// condition.  Below x = 1/2 the cancelling combinations come from their Taylor series.
+template <typename R>
+struct Kw {
+    R g[6];
+    R c1, c4, c5;
+};
+
+template <typename R>
+GKS_HD inline Kw<R> kogan(R tau, R dt)
+{
+    Kw<R> k;
+    if (!(tau > R(0))) {
+        k.g[0] = dt; k.g[1] = R(0); k.g[2] = R(0.5) * dt * dt;
+        k.g[3] = R(0); k.g[4] = R(0); k.g[5] = R(0);
+        k.c1 = R(-1); k.c4 = R(0); k.c5 = R(0);
+        return k;
+    }
+    const R x = dt / tau;
+    R s, g0, g1, g2, g4;
+    if (x < R(0.5)) {
+        // s = x - x^2/2! + x^3/3! ..., g0 = x - s, g1 = sum_{n>=3} (-1)^n (n-2) x^n/n!,
+        // g2 = sum_{n>=3} (-1)^{n+1} x^n/n!, g4 = x + g1.  Horner form, truncated where
+        // x^n/n! < 2^-60 for x < 1/2.
+        const int NT = sizeof(R) > 4 ? 17 : 10;
+        R ps = R(0), p0 = R(0), p1 = R(0), p2 = R(0);
+        for (int n = NT; n >= 1; --n) {
+            const R inv = R(1) / R(n);
+            const R sg = (n & 1) ? R(1) : R(-1);          // (-1)^{n+1}
+            ps = (ps + sg) * x * inv;
+            p0 = (p0 + (n >= 2 ? -sg : R(0))) * x * inv;
+            p1 = (p1 + (n >= 3 ? -sg * R(n - 2) : R(0))) * x * inv;
+            p2 = (p2 + (n >= 3 ? sg : R(0))) * x * inv;
+        }
+        s = ps; g0 = p0; g1 = p1; g2 = p2;
+        g4 = x + g1;
+    } else {
+        const R E = g_exp(-x);
+        s = R(1) - E;
+        g0 = x - s;
+        g1 = R(2) * s - x * (R(1) + E);
+        g2 = R(0.5) * x * x - x + s;
+        g4 = R(2) * s - x * E;
+    }
+    const R t2 = tau * tau;
+    k.g[0] = tau * g0;
+    k.g[1] = t2 * g1;
+    k.g[2] = t2 * g2;
+    k.g[3] = tau * s;
+    k.g[4] = -t2 * g4;
+    k.g[5] = -t2 * s;
+    const R ig0 = R(1) / g0;
+    k.c1 = g1 * ig0;
+    k.c4 = -g4 * ig0;
+    k.c5 = -s * ig0;
+    return k;
+}
+
+// Inputs of one face in the wide type H (FP64 on the device): reconstructed states,
+// minmod slopes, cell averages of the two neighbours, centre-to-face distances, face means
+// of k, omega and strain rate, and the step.
+template <int D, typename H = double>
+struct FaceIn {
+    H Wl[D + 2], Wr[D + 2], sl[D + 2], sr[D + 2], Wi[D + 2], Wi1[D + 2];
+    H dxl, dxr, kf, wf, Sf, dt;
+};
+
+struct GasC {
+    double gamma, prandtl, mu, c_a, c_mu, b;
+};
+
+template <typename H>
+GKS_HD inline H minmod(H p, H q)
+{
+    if (!(p * q > H(0))) return H(0);
+    return (p > H(0)) ? (p < q ? p : q) : (p > q ? p : q);
+}
+
+// MUSCL reconstruction along the face normal from four cell averages Wc[0..3] (cells
+// i-1, i, i+1, i+2 around face i+1/2) and their centres: minmod of the one-sided
+// differences on centre-to-centre distances, conservative variables.
+template <int D, typename H>
+GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const H* xc, H xface, FaceIn<D, H>& in)
+{
+    for (int m = 0; m < D + 2; ++m) {
+        const H d0 = (Wc[1][m] - Wc[0][m]) / (xc[1] - xc[0]);
+        const H d1 = (Wc[2][m] - Wc[1][m]) / (xc[2] - xc[1]);
+        const H d2 = (Wc[3][m] - Wc[2][m]) / (xc[3] - xc[2]);
+        const H sl = minmod(d0, d1), sr = minmod(d1, d2);
+        in.sl[m] = sl;
+        in.sr[m] = sr;
+        in.Wl[m] = Wc[1][m] + sl * (xface - xc[1]);
+        in.Wr[m] = Wc[2][m] - sr * (xc[2] - xface);
+        in.Wi[m] = Wc[1][m];
+        in.Wi1[m] = Wc[2][m];
+    }
+    in.dxl = xface - xc[1];
+    in.dxr = xc[2] - xface;
+}
+
+// Primitive recovery in the wide type: rho, U, p.  Returns false for rho <= 0 or p <= 0
+// (or non-finite).
+template <int D, typename H>
+GKS_HD inline bool prim_wide(const H* W, H b, H& rho, H* U, H& p)
+{
+    rho = W[0];
+    H ke = H(0);
+    for (int d = 0; d < D; ++d) { U[d] = W[1 + d] / rho; ke = ke + U[d] * W[1 + d]; }
+    p = (H(2) / b) * (W[D + 1] - H(0.5) * ke);
+    return (rho > H(0)) && (p > H(0)) && (p < H(1e300)) && (rho < H(1e300));
+}
+
+// The flux.  Returns 0, or 1 when a state met is non-physical (then F is meaningless).
+// F receives the time-integrated flux (it already contains dt) in the face-local frame.
+//
+// Evaluation order keeps few values live: after the interface state and tau are known,
+// the equilibrium-slope terms, then the left side, then the right side are each folded
+// into F and into the right-hand side Rv of the Abar system as soon as their
+// coefficients exist; Abar and the remaining equilibrium terms come last.
+template <typename R, int D, typename H = double>
+GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
+{
+    constexpr int NV = D + 2;
+    const R b = R(gas.b), inv_b = R(1.0 / gas.b), bt = R(gas.b - 1.0);
+    const R half = R(0.5);
+    const R rsqpi_half = R(0.28209479177387814);   // 1/(2 sqrt(pi))
+    const H bw = H(gas.b);
+
+    // --- left / right Maxwellians (wide primitive recovery) -------------------------
+    H rl, Ul[D], pl, rr, Ur[D], pr;
+    if (!prim_wide<D>(in.Wl, bw, rl, Ul, pl) || !prim_wide<D>(in.Wr, bw, rr, Ur, pr)) return 1;
+    Mx<R, D> gl, gr;
+    {
+        R u[D];
+        for (int d = 0; d < D; ++d) u[d] = R(Ul[d]);
+        mx_set(gl, R(rl), u, R(H(0.5) * rl / pl), R(pl / rl), bt);
+        for (int d = 0; d < D; ++d) u[d] = R(Ur[d]);
+        mx_set(gr, R(rr), u, R(H(0.5) * rr / pr), R(pr / rr), bt);
+    }
+
+    // --- half-line u-moments: left over u>0, right over u<0 -------------------------
+    R ml[8], mr[8];
+    {
+        const R sq = g_sqrt(gl.lam);
+        const R U = gl.U[0];
+        ml[0] = half * g_erfc(-sq * U);
+        ml[1] = U * ml[0] + g_exp(-gl.lam * U * U) * rsqpi_half / sq;
+        urec(ml, U, gl.h, 6);
+    }
+    {
+        const R sq = g_sqrt(gr.lam);
+        const R U = gr.U[0];
+        mr[0] = half * g_erfc(sq * U);
+        mr[1] = U * mr[0] - g_exp(-gr.lam * U * U) * rsqpi_half / sq;
+        urec(mr, U, gr.h, 6);
+    }
+
+    // --- interface equilibrium state W0 (Eq. intermediatestate) ---------------------
+    R W0[NV];
+    {
+        R tl[NV], tr[NV];
+        tmom1(gl, ml, tl);
+        tmom1(gr, mr, tr);
+        for (int m = 0; m < NV; ++m) W0[m] = gl.rho * tl[m] + gr.rho * tr[m];
+    }
+    H r0, U0d[D], p0;
+    {
+        H w0[NV];
+        for (int m = 0; m < NV; ++m) w0[m] = H(W0[m]);
+        if (!prim_wide<D>(w0, bw, r0, U0d, p0)) return 1;
+    }
+    Mx<R, D> g0;
+    {
+        R u[D];
+        for (int d = 0; d < D; ++d) u[d] = R(U0d[d]);
+        mx_set(g0, R(r0), u, R(H(0.5) * r0 / p0), R(p0 / r0), bt);
+    }
+
+    // --- relaxation time (laminar + artificial + k-omega) and time weights ----------
+    H tau;
+    {
+        const H eta = in.Sf / (H(gas.c_mu) * in.wf);
+        tau = H(gas.mu) / p0 + H(gas.c_a) * g_abs(pr - pl) / (pr + pl) * in.dt +
+              (in.kf / in.wf) / ((p0 / r0) * g_sqrt(H(1) + eta * eta));
+    }
+    const R dt = R(in.dt);
+    const Kw<R> kw = kogan(R(tau), dt);
+
+    // Rv accumulates rho0 <psi Abar.psi>_g0 from the time-integrated compatibility condition:
+    //   c1 rho0 (<u psi abar_l.psi>_{g0,>0} + <u psi abar_r.psi>_{g0,<0})
+    // + c4 (rho_l <u psi a_l.psi>_{l,>0} + rho_r <u psi a_r.psi>_{r,<0})
+    // + c5 (rho_l <psi A_l.psi>_{l,>0} + rho_r <psi A_r.psi>_{r,<0})
+    R Rv[NV];
+
+    // --- equilibrium slopes through W0 (Eq. eqlgform): gam1 and c1 terms -------------
+    {
+        R m0p[8], m0n[8];
+        const R U = g0.U[0];
+        const R sq = g_sqrt(g0.lam);
+        const R small = half * g_erfc(g_abs(sq * U));   // one erfc serves both halves
+        const R tail = g_exp(-g0.lam * U * U) * rsqpi_half / sq;
+        const bool upos = U >= R(0);
+        m0p[0] = upos ? R(1) - small : small;
+        m0n[0] = upos ? small : R(1) - small;
+        m0p[1] = U * m0p[0] + tail;
+        m0n[1] = U * m0n[0] - tail;
+        urec(m0p, U, g0.h, 6);
+        urec(m0n, U, g0.h, 6);
+        R r[NV], ab[NV], T1[NV], T2[NV];
+        const H il = H(1) / (r0 * in.dxl), ir = H(1) / (r0 * in.dxr);
+        for (int m = 0; m < NV; ++m) r[m] = R((H(W0[m]) - in.Wi[m]) * il);
+        solve(g0, r, b, inv_b, ab);
+        tmom(g0, m0p + 1, ab, bt, T1);                 // <u psi abar_l.psi>_{g0,>0}
+        tmom(g0, m0p + 2, ab, bt, T2);                 // <u^2 psi abar_l.psi>_{g0,>0}
+        for (int m = 0; m < NV; ++m) r[m] = R((in.Wi1[m] - H(W0[m])) * ir);
+        solve(g0, r, b, inv_b, ab);
+        R T3[NV];
+        tmom(g0, m0n + 1, ab, bt, T3);
+        for (int m = 0; m < NV; ++m) Rv[m] = kw.c1 * g0.rho * (T1[m] + T3[m]);
+        tmom(g0, m0n + 2, ab, bt, T3);
+        for (int m = 0; m < NV; ++m) F[m] = g0.rho * kw.g[1] * (T2[m] + T3[m]);
+    }
+
+    // --- one side of the initial distribution (Eq. initialf0): slopes a from dW/dx,
+    //     time coefficients A from the compatibility condition at t = 0, then the
+    //     gam3..gam5 flux terms and the c4, c5 terms of Rv -------------------------
+    auto side = [&](const Mx<R, D>& g, const R* mh, const H* slope, H rho) {
+        R r[NV], a[NV], A[NV], T[NV], mf[8];
+        const R ir = R(H(1) / rho);
+        for (int m = 0; m < NV; ++m) r[m] = R(slope[m]) * ir;
+        solve(g, r, b, inv_b, a);
+        mf[0] = R(1);
+        mf[1] = g.U[0];
+        urec(mf, g.U[0], g.h, 5);
+        tmom(g, mf + 1, a, bt, T);                     // <u psi (a.psi)> over all u
+        for (int m = 0; m < NV; ++m) T[m] = -T[m];
+        solve(g, T, b, inv_b, A);
+        const R rg = g.rho;
+        R acc[NV];
+        tmom1(g, mh + 1, T);
+        for (int m = 0; m < NV; ++m) acc[m] = kw.g[3] * T[m];
+        tmom(g, mh + 2, a, bt, T);
+        for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[4] * T[m];
+        tmom(g, mh + 1, A, bt, T);
+        for (int m = 0; m < NV; ++m) F[m] = F[m] + rg * (acc[m] + kw.g[5] * T[m]);
+        tmom(g, mh + 1, a, bt, T);
+        for (int m = 0; m < NV; ++m) acc[m] = kw.c4 * T[m];
+        tmom(g, mh, A, bt, T);
+        for (int m = 0; m < NV; ++m) Rv[m] = Rv[m] + rg * (acc[m] + kw.c5 * T[m]);
+    };
+    side(gl, ml, in.sl, rl);
+    side(gr, mr, in.sr, rr);
+
+    // --- Abar, then the gam0 and gam2 equilibrium terms ------------------------------
+    {
+        R m0[8], r[NV], Ab[NV], T[NV];
+        const R i0 = R(H(1) / r0);
+        for (int m = 0; m < NV; ++m) r[m] = Rv[m] * i0;
+        solve(g0, r, b, inv_b, Ab);
+        m0[0] = R(1);
+        m0[1] = g0.U[0];
+        urec(m0, g0.U[0], g0.h, 5);
+        R acc[NV];
+        tmom1(g0, m0 + 1, T);
+        for (int m = 0; m < NV; ++m) acc[m] = kw.g[0] * T[m];
+        tmom(g0, m0 + 1, Ab, bt, T);
+        for (int m = 0; m < NV; ++m) F[m] = F[m] + g0.rho * (acc[m] + kw.g[2] * T[m]);
+    }
+
+    // --- Prandtl-number correction of the energy flux -------------------------------
+    // q = int int (u - U0)(|u - U0|^2 + xi^2)/2 f
+    //   = (F_E - U0.F_m + |U0|^2 F_rho/2) - U0_n (G_E - U0.G_m + |U0|^2 G_rho/2),
+    // with G = int int psi f = dt W0 + dt^2/2 Rv (the integrated compatibility condition).
+    {
+        const R pfix = R(1.0 / gas.prandtl - 1.0);
+        R Gv[NV];
+        const R hdt2 = half * dt * dt;
+        for (int m = 0; m < NV; ++m) Gv[m] = dt * W0[m] + hdt2 * Rv[m];
+        R uF = R(0), uG = R(0), U2 = R(0);
+        for (int d = 0; d < D; ++d) {
+            uF = uF + g0.U[d] * F[1 + d];
+            uG = uG + g0.U[d] * Gv[1 + d];
+            U2 = U2 + g0.U[d] * g0.U[d];
+        }
+        const R q = (F[D + 1] - uF + half * U2 * F[0]) - g0.U[0] * (Gv[D + 1] - uG + half * U2 * Gv[0]);
+        F[D + 1] = F[D + 1] + pfix * q;
+    }
+    return 0;
+}
+
+}  // namespace gks

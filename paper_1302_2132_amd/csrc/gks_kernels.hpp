@@ -1,0 +1,511 @@
+// gks_kernels.hpp -- gfx950 kernels of the turbulent gas-kinetic step.
+//
+// One step of every active solve in a tile table is three launches:
+//   k_strain  cell tiles: strain-rate magnitude of each cell from central differences
+//             of the cell velocities (ghost neighbours synthesised from the BCs);
+//   k_face    face tiles of one (dim, precision) class: minmod reconstruction along the
+//             face normal (four cells, ghosts synthesised), then the gas-kinetic flux of
+//             gks_flux.hpp, written once per face (structure of arrays per axis);
+//   k_update  cell tiles: conservative FP64 update, positivity check, residual partial
+//             sums and the CFL rate of the new state; the last workgroup of a solve
+//             finishes its step (residual, next dt, time, buffer swap) with no host work.
+// All kernels walk the tile table with a grid-stride loop, so a fixed grid (and a
+// captured graph) serves any membership.  Workgroup ids are remapped so that consecutive
+// tiles, which share halo cells, land on the same XCD (L2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gks_device.hpp"
+#include "gks_flux.hpp"
+
+namespace gks {
+
+// --------------------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------------------
+__device__ inline int xcd_block()
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs; renumber so that XCD x owns
+    // a contiguous run of virtual ids.
+    const int g = gridDim.x, b = blockIdx.x;
+    if (g % 8) return b;
+    return (b % 8) * (g / 8) + b / 8;
+}
+
+// index of the member owning `tile` (prefix has count+1 entries, prefix[0] = 0)
+__device__ inline int find_member(const int* prefix, int count, int tile)
+{
+    int lo = 0, hi = count;   // invariant prefix[lo] <= tile < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= tile) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline int image_index(int bc, int i, int n)
+{
+    if (i < 0) {
+        if (bc == BC_PERIODIC) return i + n;
+        if (bc == BC_WALL) return -1 - i;
+        return 0;
+    }
+    if (i >= n) {
+        if (bc == BC_PERIODIC) return i - n;
+        if (bc == BC_WALL) return 2 * n - 1 - i;
+        return n - 1;
+    }
+    return i;
+}
+
+__device__ inline long long cell_index(const Inst& I, int i, int j, int k)
+{
+    return ((long long)k * I.n[1] + j) * I.n[0] + i;
+}
+
+// Conservative state of cell c (c[d] may be a ghost index in [-2, n+1]; the other
+// coordinates are interior).  Synthesises ghosts from the boundary condition of axis d.
+template <int D>
+__device__ inline __attribute__((always_inline)) void load_state(const Inst& I, const double* __restrict__ W, int d,
+                                                                 const int* c, double* w)
+{
+    constexpr int NV = D + 2;
+    const int n = I.n[d];
+    const int id = c[d];
+    if (id >= 0 && id < n) {
+        const long long idx = cell_index(I, c[0], c[1], D == 3 ? c[2] : 0);
+        for (int m = 0; m < NV; ++m) w[m] = W[m * I.ncells + idx];
+        return;
+    }
+    const int side = id < 0 ? 0 : 1;
+    const int bc = I.bc[d][side];
+    if (bc == BC_DIRICHLET) {
+        const double* s = I.bcd[d][side];
+        for (int m = 0; m < NV; ++m) w[m] = s[m];
+        return;
+    }
+    if (bc == BC_PROFILE) {
+        int t = 0, stride = 1;
+        for (int a = 0; a < D; ++a) {
+            if (a == d) continue;
+            t += c[a] * stride;
+            stride *= I.n[a];
+        }
+        const double* s = I.bcd[d][side];
+        for (int m = 0; m < NV; ++m) w[m] = s[(long long)m * I.ntan[d] + t];
+        return;
+    }
+    int cc[3] = {c[0], c[1], D == 3 ? c[2] : 0};
+    cc[d] = image_index(bc, id, n);
+    const long long idx = cell_index(I, cc[0], cc[1], cc[2]);
+    for (int m = 0; m < NV; ++m) w[m] = W[m * I.ncells + idx];
+    if (bc == BC_WALL)
+        for (int m = 1; m <= D; ++m) w[m] = -w[m];
+}
+
+// flat index of the interior image of cell c (only c[d] may be a ghost)
+template <int D>
+__device__ inline long long image_cell(const Inst& I, int d, const int* c)
+{
+    int cc[3] = {c[0], c[1], D == 3 ? c[2] : 0};
+    const int n = I.n[d];
+    if (cc[d] < 0) cc[d] = image_index(I.bc[d][0], cc[d], n);
+    else if (cc[d] >= n) cc[d] = image_index(I.bc[d][1], cc[d], n);
+    return cell_index(I, cc[0], cc[1], cc[2]);
+}
+
+// --------------------------------------------------------------------------------------
+// strain rate
+// --------------------------------------------------------------------------------------
+template <int D>
+__device__ inline void strain_cell(const Inst& I, long long cell)
+{
+    const double* __restrict__ W = I.W[I.st->parity];
+    int c[3];
+    c[0] = (int)(cell % I.n[0]);
+    c[1] = (int)((cell / I.n[0]) % I.n[1]);
+    c[2] = (D == 3) ? (int)(cell / ((long long)I.n[0] * I.n[1])) : 0;
+    double g[3][3];
+    for (int b = 0; b < D; ++b) {
+        double wp[D + 2], wm[D + 2];
+        int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+        cp[b] += 1;
+        cm[b] -= 1;
+        load_state<D>(I, W, b, cp, wp);
+        load_state<D>(I, W, b, cm, wm);
+        const double h = I.xc[b][c[b] + 1] - I.xc[b][c[b] - 1];
+        const double ip = 1.0 / wp[0], im = 1.0 / wm[0], ih = 1.0 / h;
+        for (int a = 0; a < D; ++a) g[a][b] = (wp[1 + a] * ip - wm[1 + a] * im) * ih;
+    }
+    double ss = 0.0;
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+            const double s = 0.5 * (g[a][b] + g[b][a]);
+            ss += s * s;
+        }
+    I.S[cell] = sqrt(2.0 * ss);
+}
+
+__global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ table, int cap, int force)
+{
+    TabView tv(const_cast<void*>(table), cap);
+    const int count = tv.hdr->count;
+    const int total = tv.hdr->total_cell;
+    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+        const int mi = find_member(tv.cell_prefix, count, tile);
+        const Inst& I = tv.inst[mi];
+        if (!force && !I.st->active) continue;
+        const long long cell = (long long)(tile - tv.cell_prefix[mi]) * CELL_TILE + threadIdx.x;
+        if (cell >= I.ncells) continue;
+        if (I.dim == 2) strain_cell<2>(I, cell);
+        else strain_cell<3>(I, cell);
+    }
+}
+
+// --------------------------------------------------------------------------------------
+// face fluxes
+// --------------------------------------------------------------------------------------
+// One face normal to axis DIR.  The axis is a template parameter so that every stencil
+// index and the rotation to the face-local frame are compile-time (no private arrays).
+template <typename R, int D, int DIR>
+__device__ inline void face_one(const Inst& I, long long f)
+{
+    constexpr int NV = D + 2;
+    // face coordinates: the face lies on the low side of cell fc along axis DIR
+    const int fn0 = I.n[0] + (DIR == 0), fn1 = I.n[1] + (DIR == 1);
+    int fc[3];
+    fc[0] = (int)(f % fn0);
+    fc[1] = (int)((f / fn0) % fn1);
+    fc[2] = (D == 3) ? (int)(f / ((long long)fn0 * fn1)) : 0;
+    const double* __restrict__ W = I.W[I.st->parity];
+    const double* __restrict__ xcd = I.xc[DIR];
+
+    double Wc[4][NV], xc[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        int c[3] = {fc[0], fc[1], fc[2]};
+        c[DIR] += o - 2;
+        load_state<D>(I, W, DIR, c, Wc[o]);
+        xc[o] = xcd[c[DIR]];
+    }
+    FaceIn<D, double> in;
+    reconstruct<D, double>(Wc, xc, I.xf[DIR][fc[DIR]], in);
+
+    // face-local frame: normal momentum first, then the remaining axes in order
+    constexpr int P1 = DIR == 0 ? 1 : 0;             // first tangential axis
+    constexpr int P2 = DIR == 2 ? 1 : 2;             // second tangential axis (3D)
+    if (DIR != 0) {
+        double* v[6] = {in.Wl, in.Wr, in.sl, in.sr, in.Wi, in.Wi1};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double mn = v[q][1 + DIR], t1 = v[q][1 + P1];
+            double t2 = 0.0;
+            if (D == 3) t2 = v[q][1 + P2];
+            v[q][1] = mn;
+            v[q][2] = t1;
+            if (D == 3) v[q][3] = t2;
+        }
+    }
+    {
+        int cl[3] = {fc[0], fc[1], fc[2]};
+        cl[DIR] -= 1;
+        const long long il = image_cell<D>(I, DIR, cl), ir = image_cell<D>(I, DIR, fc);
+        in.kf = 0.5 * (I.k[il] + I.k[ir]);
+        in.wf = 0.5 * (I.om[il] + I.om[ir]);
+        in.Sf = 0.5 * (I.S[il] + I.S[ir]);
+    }
+    in.dt = I.st->dt;
+    GasC gas{I.gamma, I.prandtl, I.mu, I.c_a, I.c_mu, I.b};
+    R F[NV];
+    if (face_flux<R, D, double>(in, gas, F)) atomicOr(&I.st->err, 1);
+    R* __restrict__ out = (R*)I.F[DIR];
+    const long long nf = I.nface[DIR];
+    out[f] = F[0];
+    out[(long long)(1 + DIR) * nf + f] = F[1];
+    out[(long long)(1 + P1) * nf + f] = F[2];
+    if (D == 3) out[(long long)(1 + P2) * nf + f] = F[3];
+    out[(long long)(D + 1) * nf + f] = F[D + 1];
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(2))) void k_face(const void* __restrict__ table, int cap, int cls)
+{
+    TabView tv(const_cast<void*>(table), cap);
+    const int count = tv.hdr->ncls[cls];
+    const int total = tv.hdr->total_face[cls];
+    const int* prefix = tv.cls_prefix + cls * (cap + 1);
+    const int* member = tv.cls_member + cls * cap;
+    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+        const int mj = find_member(prefix, count, tile);
+        const Inst& I = tv.inst[member[mj]];
+        if (!I.st->active) continue;
+        int lt = tile - prefix[mj];
+        if (lt < I.ntile_face[0]) {
+            const long long f = (long long)lt * FACE_TILE + threadIdx.x;
+            if (f < I.nface[0]) face_one<R, D, 0>(I, f);
+            continue;
+        }
+        lt -= I.ntile_face[0];
+        if (D == 2 || lt < I.ntile_face[1]) {
+            const long long f = (long long)lt * FACE_TILE + threadIdx.x;
+            if (f < I.nface[1]) face_one<R, D, 1>(I, f);
+            continue;
+        }
+        lt -= I.ntile_face[1];
+        const long long f = (long long)lt * FACE_TILE + threadIdx.x;
+        if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1)>(I, f);
+    }
+}
+
+// --------------------------------------------------------------------------------------
+// update, reductions and end of step
+// --------------------------------------------------------------------------------------
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <int D, typename RF>
+__device__ inline void update_cell(const Inst& I, long long cell, double dt, double* r2, double& rate, int& bad)
+{
+    constexpr int NV = D + 2;
+    const int cur = I.st->parity;
+    const double* __restrict__ Wo = I.W[cur];
+    double* __restrict__ Wn = I.W[cur ^ 1];
+    int c[3];
+    c[0] = (int)(cell % I.n[0]);
+    c[1] = (int)((cell / I.n[0]) % I.n[1]);
+    c[2] = (D == 3) ? (int)(cell / ((long long)I.n[0] * I.n[1])) : 0;
+    double w[NV];
+    double idx_[3];
+    for (int d = 0; d < D; ++d) idx_[d] = 1.0 / I.dx[d][c[d]];
+    for (int m = 0; m < NV; ++m) {
+        const double old = Wo[m * I.ncells + cell];
+        double acc = old;
+        for (int d = 0; d < D; ++d) {
+            int fn[3] = {I.n[0], I.n[1], D == 3 ? I.n[2] : 1};
+            fn[d] += 1;
+            const long long lo = ((long long)c[2] * fn[1] + c[1]) * fn[0] + c[0];
+            const long long hi = lo + (d == 0 ? 1 : (d == 1 ? fn[0] : (long long)fn[0] * fn[1]));
+            const RF* __restrict__ F = (const RF*)I.F[d] + (long long)m * I.nface[d];
+            acc -= (double(F[hi]) - double(F[lo])) * idx_[d];
+        }
+        w[m] = acc;
+        Wn[m * I.ncells + cell] = acc;
+        const double r = (acc - old) / dt;
+        r2[m] = r * r;
+    }
+    // positivity and the CFL rate of the new state
+    double ke = 0.0, U[3];
+    const double rho = w[0];
+    for (int d = 0; d < D; ++d) { U[d] = w[1 + d] / rho; ke += U[d] * w[1 + d]; }
+    const double p = (2.0 / I.b) * (w[D + 1] - 0.5 * ke);
+    if (!(rho > 0.0) || !(p > 0.0) || !(rho < 1e300) || !(p < 1e300)) { bad = 1; rate = 0.0; return; }
+    const double cs = sqrt(I.gamma * p / rho);
+    const double fac = fmax(4.0 / 3.0, I.gamma / I.prandtl);
+    const double nu = (I.mu + rho * I.k[cell] / I.om[cell]) / rho * fac;
+    double r = 0.0, r2s = 0.0;
+    for (int d = 0; d < D; ++d) {
+        const double h = I.dx[d][c[d]];
+        r += (fabs(U[d]) + cs) / h;
+        r2s += 1.0 / (h * h);
+    }
+    rate = r + 2.0 * nu * r2s;
+}
+
+// time step following a state whose max CFL rate is `rate`, and the time it ends at
+__device__ inline void next_step(const Inst& I, State* st, double rate, double t)
+{
+    double dt = I.cfl / rate, ta = t + dt;
+    if (I.t_end > 0.0) {
+        if (t >= I.t_end) st->active = 0;
+        else if (ta >= I.t_end) { dt = I.t_end - t; ta = I.t_end; }
+    }
+    if (!(rate > 0.0) || !(dt > 0.0)) st->active = 0;
+    st->dt = dt;
+    st->t_after = ta;
+    st->rate_bits = 0ull;
+    st->tiles_done = 0u;
+}
+
+// Workgroup-wide end of step for member I (all CELL_TILE threads call it).
+__device__ inline void finish_step(const Inst& I, double* sh)
+{
+    State* st = I.st;
+    const int nv = I.nv;
+    const int nt = I.ntile_cell;
+    // deterministic sum of the per-tile partials: fixed stride per thread, fixed tree
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < nt; t += CELL_TILE)
+        for (int m = 0; m < nv; ++m) acc[m] += I.part[(long long)t * nv + m];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int m = 0; m < nv; ++m) {
+        const double s = wave_sum(acc[m]);
+        if (lane == 0) sh[m * 4 + wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double N = (double)I.ncells;
+        for (int m = 0; m < nv; ++m) {
+            const double s = (sh[m * 4 + 0] + sh[m * 4 + 1]) + (sh[m * 4 + 2] + sh[m * 4 + 3]);
+            st->res[m] = sqrt(s / N);
+        }
+        st->dt_last = st->dt;
+        st->t = st->t_after;
+        st->steps += 1;
+        if (st->steps == 1)
+            for (int m = 0; m < nv; ++m) st->res_first[m] = st->res[m];
+        st->parity ^= 1;
+        const double rate = __longlong_as_double((long long)st->rate_bits);
+        next_step(I, st, rate, st->t);
+        if (st->err) st->active = 0;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ table, int cap)
+{
+    TabView tv(const_cast<void*>(table), cap);
+    const int count = tv.hdr->count;
+    const int total = tv.hdr->total_cell;
+    __shared__ double sh_sum[5 * 4];
+    __shared__ double sh_max[4];
+    __shared__ int sh_bad[4];
+    __shared__ int sh_last;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+        const int mi = find_member(tv.cell_prefix, count, tile);
+        const Inst& I = tv.inst[mi];
+        if (!I.st->active) continue;
+        const int lt = tile - tv.cell_prefix[mi];
+        const long long cell = (long long)lt * CELL_TILE + threadIdx.x;
+        double r2[5] = {0, 0, 0, 0, 0};
+        double rate = 0.0;
+        int bad = 0;
+        const double dt = I.st->dt;
+        if (cell < I.ncells) {
+            if (I.dim == 2) {
+                if (I.precision) update_cell<2, float>(I, cell, dt, r2, rate, bad);
+                else update_cell<2, double>(I, cell, dt, r2, rate, bad);
+            } else {
+                if (I.precision) update_cell<3, float>(I, cell, dt, r2, rate, bad);
+                else update_cell<3, double>(I, cell, dt, r2, rate, bad);
+            }
+        }
+        // workgroup reductions in a fixed order
+        for (int m = 0; m < I.nv; ++m) {
+            const double s = wave_sum(r2[m]);
+            if (lane == 0) sh_sum[m * 4 + wv] = s;
+        }
+        {
+            const double mx = wave_max(rate);
+            const int any = __any(bad);
+            if (lane == 0) { sh_max[wv] = mx; sh_bad[wv] = any; }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            State* st = I.st;
+            for (int m = 0; m < I.nv; ++m)
+                I.part[(long long)lt * I.nv + m] =
+                    (sh_sum[m * 4 + 0] + sh_sum[m * 4 + 1]) + (sh_sum[m * 4 + 2] + sh_sum[m * 4 + 3]);
+            const double mx = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
+            atomicMax(&st->rate_bits, (unsigned long long)__double_as_longlong(mx));
+            if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&st->err, 1);
+            __threadfence();
+            const unsigned int done = __hip_atomic_fetch_add(&st->tiles_done, 1u, __ATOMIC_ACQ_REL,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+            sh_last = (done + 1u == (unsigned int)I.ntile_cell);
+        }
+        __syncthreads();
+        if (sh_last) {
+            __threadfence();
+            finish_step(I, sh_sum);
+        }
+        __syncthreads();
+    }
+}
+
+// Max CFL rate of the current state of each member and its first step (used at init and
+// after a checkpoint restore).  Single workgroup per member is not needed: same table walk.
+__global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ table, int cap)
+{
+    TabView tv(const_cast<void*>(table), cap);
+    const int count = tv.hdr->count;
+    const int total = tv.hdr->total_cell;
+    __shared__ double sh_max[4];
+    __shared__ int sh_bad[4];
+    __shared__ int sh_last;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+        const int mi = find_member(tv.cell_prefix, count, tile);
+        const Inst& I = tv.inst[mi];
+        const int lt = tile - tv.cell_prefix[mi];
+        const long long cell = (long long)lt * CELL_TILE + threadIdx.x;
+        double rate = 0.0;
+        int bad = 0;
+        if (cell < I.ncells) {
+            const double* W = I.W[I.st->parity];
+            const int D = I.dim;
+            double w[5];
+            for (int m = 0; m < I.nv; ++m) w[m] = W[m * I.ncells + cell];
+            int c[3];
+            c[0] = (int)(cell % I.n[0]);
+            c[1] = (int)((cell / I.n[0]) % I.n[1]);
+            c[2] = (D == 3) ? (int)(cell / ((long long)I.n[0] * I.n[1])) : 0;
+            double ke = 0.0, U[3];
+            for (int d = 0; d < D; ++d) { U[d] = w[1 + d] / w[0]; ke += U[d] * w[1 + d]; }
+            const double rho = w[0], p = (2.0 / I.b) * (w[D + 1] - 0.5 * ke);
+            if (!(rho > 0.0) || !(p > 0.0)) bad = 1;
+            else {
+                const double cs = sqrt(I.gamma * p / rho);
+                const double nu = (I.mu + rho * I.k[cell] / I.om[cell]) / rho * fmax(4.0 / 3.0, I.gamma / I.prandtl);
+                double r = 0.0, r2s = 0.0;
+                for (int d = 0; d < D; ++d) {
+                    const double h = I.dx[d][c[d]];
+                    r += (fabs(U[d]) + cs) / h;
+                    r2s += 1.0 / (h * h);
+                }
+                rate = r + 2.0 * nu * r2s;
+            }
+        }
+        const double mx = wave_max(rate);
+        const int any = __any(bad);
+        if (lane == 0) { sh_max[wv] = mx; sh_bad[wv] = any; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            State* st = I.st;
+            const double m = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
+            atomicMax(&st->rate_bits, (unsigned long long)__double_as_longlong(m));
+            if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&st->err, 1);
+            __threadfence();
+            const unsigned int done = __hip_atomic_fetch_add(&st->tiles_done, 1u, __ATOMIC_ACQ_REL,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+            sh_last = (done + 1u == (unsigned int)I.ntile_cell);
+        }
+        __syncthreads();
+        if (sh_last && threadIdx.x == 0) {
+            __threadfence();
+            State* st = I.st;
+            st->active = 1;
+            const double rate = __longlong_as_double((long long)st->rate_bits);
+            next_step(I, st, rate, st->t);
+            if (st->err) st->active = 0;
+        }
+        __syncthreads();
+    }
+}
+
+template __global__ void k_face<double, 2>(const void*, int, int);
+template __global__ void k_face<float, 2>(const void*, int, int);
+template __global__ void k_face<double, 3>(const void*, int, int);
+template __global__ void k_face<float, 3>(const void*, int, int);
+
+}  // namespace gks

@@ -1,0 +1,761 @@
+// gks_lib.hip -- host side of libgks: the C ABI declared in include/gks.h.
+//
+// Device memory is the caller's: every solve lives in one workspace laid out by
+// `layout()`; a batch keeps only its tile table in its own workspace.  Nothing here
+// calls hipMalloc.  Host inputs are validated and copied during gks_init.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gks.h"
+#include "gks_kernels.hpp"
+
+using namespace gks;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Layout {
+    size_t W[2], k, om, S, F[3], xf[3], xc[3], dx[3], bcd[3][2], part, st, tab, total;
+    long long ncells, nface[3];
+    int ntan[3];
+    int ntile_cell, ntile_face[3];
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int nvar_of(const gks_config* c) { return c->dim + 2; }
+
+bool config_ok(const gks_config* c, std::string* why)
+{
+    auto fail = [&](const char* m) { if (why) *why = m; return false; };
+    if (!c) return fail("config is NULL");
+    if (c->dim != 2 && c->dim != 3) return fail("dim must be 2 or 3");
+    for (int d = 0; d < c->dim; ++d) {
+        if (c->n[d] < 2) return fail("every axis needs at least 2 cells");
+        if (c->n[d] > (1 << 24)) return fail("axis too long");
+        if (!c->xf[d]) return fail("face coordinates missing");
+        for (long long i = 0; i < c->n[d]; ++i)
+            if (!(c->xf[d][i + 1] > c->xf[d][i])) return fail("face coordinates must increase");
+        for (int s = 0; s < 2; ++s) {
+            const int bc = c->bc[d][s];
+            if (bc < GKS_BC_PERIODIC || bc > GKS_BC_OUTFLOW) return fail("unknown boundary condition");
+            if ((bc == GKS_BC_DIRICHLET || bc == GKS_BC_PROFILE) && !c->bc_data[d][s])
+                return fail("boundary data missing");
+        }
+        if ((c->bc[d][0] == GKS_BC_PERIODIC) != (c->bc[d][1] == GKS_BC_PERIODIC))
+            return fail("periodic boundaries come in pairs");
+    }
+    long long nc = 1;
+    for (int d = 0; d < c->dim; ++d) nc *= c->n[d];
+    if (nc > (1ll << 30)) return fail("too many cells");
+    if (!(c->gamma > 1.0)) return fail("gamma must exceed 1");
+    if (2.0 / (c->gamma - 1.0) < c->dim) return fail("gamma leaves no room for the internal degrees of freedom");
+    if (!(c->prandtl > 0.0) || !(c->mu >= 0.0) || !(c->c_a >= 0.0) || !(c->c_mu > 0.0) || !(c->cfl > 0.0) ||
+        !(c->t_end >= 0.0))
+        return fail("gas or time-step parameter out of range");
+    if (c->precision != GKS_FP64 && c->precision != GKS_FP32_FLUX) return fail("unknown precision");
+    return true;
+}
+
+void layout(const gks_config* c, Layout* L)
+{
+    const int nv = nvar_of(c), D = c->dim;
+    long long n[3] = {c->n[0], c->n[1], D == 3 ? c->n[2] : 1};
+    L->ncells = n[0] * n[1] * n[2];
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
+    const size_t cellb = sizeof(double) * (size_t)L->ncells;
+    L->W[0] = take(cellb * nv);
+    L->W[1] = take(cellb * nv);
+    L->k = take(cellb);
+    L->om = take(cellb);
+    L->S = take(cellb);
+    const size_t fb = c->precision == GKS_FP32_FLUX ? sizeof(float) : sizeof(double);
+    for (int d = 0; d < 3; ++d) {
+        L->nface[d] = 0;
+        L->ntile_face[d] = 0;
+        L->ntan[d] = 1;
+        L->F[d] = L->xf[d] = L->xc[d] = L->dx[d] = 0;
+        L->bcd[d][0] = L->bcd[d][1] = 0;
+        if (d >= D) continue;
+        L->nface[d] = L->ncells / n[d] * (n[d] + 1);
+        L->ntan[d] = (int)(L->ncells / n[d]);
+        L->ntile_face[d] = (int)((L->nface[d] + FACE_TILE - 1) / FACE_TILE);
+        L->F[d] = take(fb * nv * (size_t)L->nface[d]);
+        L->xf[d] = take(sizeof(double) * (n[d] + 5));
+        L->xc[d] = take(sizeof(double) * (n[d] + 4));
+        L->dx[d] = take(sizeof(double) * (n[d] + 4));
+        for (int s = 0; s < 2; ++s) {
+            if (c->bc[d][s] == GKS_BC_DIRICHLET) L->bcd[d][s] = take(sizeof(double) * nv);
+            else if (c->bc[d][s] == GKS_BC_PROFILE) L->bcd[d][s] = take(sizeof(double) * nv * (size_t)L->ntan[d]);
+        }
+    }
+    L->ntile_cell = (int)((L->ncells + CELL_TILE - 1) / CELL_TILE);
+    L->part = take(sizeof(double) * nv * (size_t)L->ntile_cell);
+    L->st = take(sizeof(State));
+    L->tab = take(TabView::bytes(1));
+    L->total = off;
+}
+
+// extended face coordinates, centres and widths (two ghost layers per side)
+void metrics(const gks_config* c, int d, std::vector<double>& xf, std::vector<double>& xc, std::vector<double>& dx)
+{
+    const long long n = c->n[d];
+    const double* f = c->xf[d];
+    xf.assign(n + 5, 0.0);
+    for (long long i = 0; i <= n; ++i) xf[i + 2] = f[i];
+    const bool per = c->bc[d][0] == GKS_BC_PERIODIC;
+    for (int m = 1; m <= 2; ++m) {
+        xf[2 - m] = per ? f[0] - (f[n] - f[n - m]) : 2.0 * f[0] - f[m];
+        xf[n + 2 + m] = per ? f[n] + (f[m] - f[0]) : 2.0 * f[n] - f[n - m];
+    }
+    xc.assign(n + 4, 0.0);
+    dx.assign(n + 4, 0.0);
+    for (long long i = 0; i < n + 4; ++i) {
+        xc[i] = 0.5 * (xf[i] + xf[i + 1]);
+        dx[i] = xf[i + 1] - xf[i];
+    }
+}
+
+bool state_ok(int D, const double* w, double gamma)
+{
+    const double rho = w[0];
+    double ke = 0.0;
+    for (int d = 0; d < D; ++d) ke += w[1 + d] * w[1 + d] / rho;
+    const double p = (gamma - 1.0) * (w[D + 1] - 0.5 * ke);
+    return rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p);
+}
+
+}  // namespace
+
+struct gks_ctx {
+    gks_config cfg;
+    int nv, cls;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    Layout L;
+    Inst inst;      // host copy of the device descriptor
+    void* tab;      // single-member tile table (device)
+    State* st;      // device step state
+    std::string err;
+    bool broken;
+    int grid_cell, grid_face;
+    bool timing;
+    std::vector<hipEvent_t> events;   // pool, 4 per timed step
+    size_t events_used;
+    long long steps_timed;
+};
+
+struct gks_batch_ctx {
+    std::vector<gks_handle> members;
+    int cap;
+    hipStream_t stream;
+    void* tab;
+    int grid[6];
+    bool captured;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int cls_present;
+    std::vector<char> host_tab;
+    std::string err;
+};
+
+static gks_status fail_h(gks_ctx* h, gks_status s, const std::string& msg)
+{
+    if (h) h->err = msg;
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(h, call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail_h((h), GKS_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static int cls_of(int dim, int precision) { return (dim == 3 ? 2 : 0) + (precision ? 1 : 0); }
+
+static int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+// Fill a host image of a tile table for `members` (capacity cap).
+static void build_table(std::vector<char>& img, int cap, const std::vector<const Inst*>& members)
+{
+    img.assign(TabView::bytes(cap), 0);
+    TabView tv(img.data(), cap);
+    tv.hdr->count = (int)members.size();
+    int cells = 0, faces[NCLS] = {0, 0, 0, 0};
+    tv.cell_prefix[0] = 0;
+    for (int c = 0; c < NCLS; ++c) tv.cls_prefix[c * (cap + 1)] = 0;
+    for (size_t i = 0; i < members.size(); ++i) {
+        const Inst& I = *members[i];
+        tv.inst[i] = I;
+        cells += I.ntile_cell;
+        tv.cell_prefix[i + 1] = cells;
+        const int c = I.cls;
+        const int j = tv.hdr->ncls[c]++;
+        tv.cls_member[c * cap + j] = (int)i;
+        faces[c] += I.ntile_face_all;
+        tv.cls_prefix[c * (cap + 1) + j + 1] = faces[c];
+    }
+    tv.hdr->total_cell = cells;
+    for (int c = 0; c < NCLS; ++c) tv.hdr->total_face[c] = faces[c];
+}
+
+typedef void (*face_kernel_t)(const void*, int, int);
+static face_kernel_t face_kernel(int cls)
+{
+    switch (cls) {
+    case 0: return k_face<double, 2>;
+    case 1: return k_face<float, 2>;
+    case 2: return k_face<double, 3>;
+    default: return k_face<float, 3>;
+    }
+}
+
+extern "C" {
+
+gks_status gks_workspace_bytes(const gks_config* cfg, size_t* bytes)
+{
+    std::string why;
+    if (!bytes) return fail_h(nullptr, GKS_ERR_ARG, "bytes is NULL");
+    if (!config_ok(cfg, &why)) return fail_h(nullptr, GKS_ERR_ARG, why);
+    Layout L;
+    layout(cfg, &L);
+    *bytes = L.total;
+    return GKS_OK;
+}
+
+gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+                    const double* W, const double* k, const double* omega, gks_handle* out)
+{
+    std::string why;
+    if (!out) return fail_h(nullptr, GKS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!config_ok(cfg, &why)) return fail_h(nullptr, GKS_ERR_ARG, why);
+    if (!W || !k || !omega || !dev_workspace) return fail_h(nullptr, GKS_ERR_ARG, "NULL input array");
+    if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
+    Layout L;
+    layout(cfg, &L);
+    if (bytes < L.total) return fail_h(nullptr, GKS_ERR_NOMEM, "workspace too small");
+    const int nv = nvar_of(cfg), D = cfg->dim;
+    const long long N = L.ncells;
+    // validate the initial state and the frozen turbulence fields
+    for (long long i = 0; i < N; ++i) {
+        double w[5];
+        for (int m = 0; m < nv; ++m) w[m] = W[m * N + i];
+        if (!state_ok(D, w, cfg->gamma)) return fail_h(nullptr, GKS_ERR_NONPHYSICAL, "initial state has rho <= 0 or p <= 0");
+        if (!(k[i] >= 0.0) || !isfinite(k[i])) return fail_h(nullptr, GKS_ERR_ARG, "k must be finite and >= 0");
+        if (!(omega[i] > 0.0) || !isfinite(omega[i])) return fail_h(nullptr, GKS_ERR_ARG, "omega must be finite and > 0");
+    }
+    for (int d = 0; d < D; ++d)
+        for (int s = 0; s < 2; ++s) {
+            const int bc = cfg->bc[d][s];
+            if (bc == GKS_BC_DIRICHLET && !state_ok(D, cfg->bc_data[d][s], cfg->gamma))
+                return fail_h(nullptr, GKS_ERR_NONPHYSICAL, "Dirichlet state is not physical");
+            if (bc == GKS_BC_PROFILE)
+                for (int t = 0; t < L.ntan[d]; ++t) {
+                    double w[5];
+                    for (int m = 0; m < nv; ++m) w[m] = cfg->bc_data[d][s][(long long)m * L.ntan[d] + t];
+                    if (!state_ok(D, w, cfg->gamma)) return fail_h(nullptr, GKS_ERR_NONPHYSICAL, "profile state is not physical");
+                }
+        }
+
+    gks_ctx* h = new gks_ctx();
+    h->cfg = *cfg;
+    for (int d = 0; d < 3; ++d) {
+        h->cfg.xf[d] = nullptr;
+        h->cfg.bc_data[d][0] = h->cfg.bc_data[d][1] = nullptr;
+    }
+    h->nv = nv;
+    h->cls = cls_of(D, cfg->precision);
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = (char*)dev_workspace;
+    h->ws_bytes = bytes;
+    h->L = L;
+    h->broken = false;
+    h->timing = false;
+    h->events_used = 0;
+    h->steps_timed = 0;
+    char* ws = h->ws;
+    hipStream_t s = h->stream;
+    const size_t cellb = sizeof(double) * (size_t)N;
+
+    Inst& I = h->inst;
+    memset(&I, 0, sizeof(I));
+    I.dim = D;
+    I.nv = nv;
+    I.precision = cfg->precision;
+    I.cls = h->cls;
+    for (int d = 0; d < 3; ++d) {
+        I.n[d] = d < D ? (int)cfg->n[d] : 1;
+        I.ntan[d] = L.ntan[d];
+        I.nface[d] = L.nface[d];
+        I.ntile_face[d] = L.ntile_face[d];
+        for (int sd = 0; sd < 2; ++sd) I.bc[d][sd] = d < D ? cfg->bc[d][sd] : GKS_BC_PERIODIC;
+    }
+    I.ncells = N;
+    I.gamma = cfg->gamma;
+    I.prandtl = cfg->prandtl;
+    I.mu = cfg->mu;
+    I.c_a = cfg->c_a;
+    I.c_mu = cfg->c_mu;
+    I.cfl = cfg->cfl;
+    I.t_end = cfg->t_end;
+    I.b = 2.0 / (cfg->gamma - 1.0);
+    I.W[0] = (double*)(ws + L.W[0]);
+    I.W[1] = (double*)(ws + L.W[1]);
+    I.k = (const double*)(ws + L.k);
+    I.om = (const double*)(ws + L.om);
+    I.S = (double*)(ws + L.S);
+    I.part = (double*)(ws + L.part);
+    I.st = (State*)(ws + L.st);
+    I.ntile_cell = L.ntile_cell;
+    I.ntile_face_all = L.ntile_face[0] + L.ntile_face[1] + L.ntile_face[2];
+
+    HIP_TRY(h, hipMemcpyAsync(I.W[0], W, cellb * nv, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync((void*)I.k, k, cellb, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync((void*)I.om, omega, cellb, hipMemcpyHostToDevice, s));
+    for (int d = 0; d < D; ++d) {
+        std::vector<double> xf, xc, dx;
+        metrics(cfg, d, xf, xc, dx);
+        I.F[d] = (void*)(ws + L.F[d]);
+        I.xf[d] = (const double*)(ws + L.xf[d]) + 2;
+        I.xc[d] = (const double*)(ws + L.xc[d]) + 2;
+        I.dx[d] = (const double*)(ws + L.dx[d]) + 2;
+        HIP_TRY(h, hipMemcpyAsync(ws + L.xf[d], xf.data(), sizeof(double) * xf.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(ws + L.xc[d], xc.data(), sizeof(double) * xc.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(ws + L.dx[d], dx.data(), sizeof(double) * dx.size(), hipMemcpyHostToDevice, s));
+        for (int sd = 0; sd < 2; ++sd) {
+            const int bc = cfg->bc[d][sd];
+            if (bc == GKS_BC_DIRICHLET || bc == GKS_BC_PROFILE) {
+                const size_t nb = sizeof(double) * nv * (bc == GKS_BC_PROFILE ? (size_t)L.ntan[d] : 1);
+                I.bcd[d][sd] = (const double*)(ws + L.bcd[d][sd]);
+                HIP_TRY(h, hipMemcpyAsync(ws + L.bcd[d][sd], cfg->bc_data[d][sd], nb, hipMemcpyHostToDevice, s));
+            }
+        }
+    }
+    State st0;
+    memset(&st0, 0, sizeof(st0));
+    st0.active = 1;
+    HIP_TRY(h, hipMemcpyAsync(I.st, &st0, sizeof(State), hipMemcpyHostToDevice, s));
+    h->st = I.st;
+    h->tab = ws + L.tab;
+    std::vector<char> img;
+    std::vector<const Inst*> mem{&I};
+    build_table(img, 1, mem);
+    HIP_TRY(h, hipMemcpyAsync(h->tab, img.data(), img.size(), hipMemcpyHostToDevice, s));
+    h->grid_cell = L.ntile_cell;
+    h->grid_face = I.ntile_face_all;
+    hipLaunchKernelGGL(k_rate, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, (const void*)h->tab, 1);
+    HIP_TRY(h, hipGetLastError());
+    State st;
+    HIP_TRY(h, hipMemcpyAsync(&st, I.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    if (st.err) {
+        delete h;
+        return fail_h(nullptr, GKS_ERR_NONPHYSICAL, "initial state is not physical");
+    }
+    *out = h;
+    return GKS_OK;
+}
+
+static gks_status next_event(gks_ctx* h, hipEvent_t* ev)
+{
+    if (h->events_used == h->events.size()) {
+        hipEvent_t e;
+        HIP_TRY(h, hipEventCreate(&e));
+        h->events.push_back(e);
+    }
+    *ev = h->events[h->events_used++];
+    return GKS_OK;
+}
+
+static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
+{
+    hipStream_t s = h->stream;
+    const void* tab = h->tab;
+    face_kernel_t fk = face_kernel(h->cls);
+    for (int i = 0; i < nsteps; ++i) {
+        hipEvent_t ev[4];
+        if (h->timing) {
+            for (int q = 0; q < 4; ++q) {
+                gks_status r = next_event(h, &ev[q]);
+                if (r != GKS_OK) return r;
+            }
+            HIP_TRY(h, hipEventRecord(ev[0], s));
+        }
+        hipLaunchKernelGGL(k_strain, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1, 0);
+        if (h->timing) HIP_TRY(h, hipEventRecord(ev[1], s));
+        hipLaunchKernelGGL(fk, dim3(h->grid_face), dim3(FACE_TILE), 0, s, tab, 1, h->cls);
+        if (h->timing) HIP_TRY(h, hipEventRecord(ev[2], s));
+        hipLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
+        if (h->timing) {
+            HIP_TRY(h, hipEventRecord(ev[3], s));
+            h->steps_timed += 1;
+        }
+    }
+    HIP_TRY(h, hipGetLastError());
+    return GKS_OK;
+}
+
+gks_status gks_step(gks_handle h, int32_t nsteps)
+{
+    if (!h) return fail_h(nullptr, GKS_ERR_ARG, "NULL handle");
+    if (nsteps < 0) return fail_h(h, GKS_ERR_ARG, "nsteps < 0");
+    if (h->broken) return fail_h(h, GKS_ERR_STATE, "handle is in the error state");
+    return enqueue_steps(h, nsteps);
+}
+
+static gks_status read_state(gks_ctx* h, State* st)
+{
+    HIP_TRY(h, hipMemcpyAsync(st, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (st->err) {
+        h->broken = true;
+        return fail_h(h, GKS_ERR_NONPHYSICAL, "non-physical state (rho <= 0 or p <= 0 or non-finite)");
+    }
+    return GKS_OK;
+}
+
+gks_status gks_residual(gks_handle h, double* res, double* dt_last, double* t, int64_t* steps_done)
+{
+    if (!h) return fail_h(nullptr, GKS_ERR_ARG, "NULL handle");
+    State st;
+    gks_status r = read_state(h, &st);
+    if (res) for (int m = 0; m < h->nv; ++m) res[m] = st.res[m];
+    if (dt_last) *dt_last = st.dt_last;
+    if (t) *t = st.t;
+    if (steps_done) *steps_done = st.steps;
+    return r;
+}
+
+gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
+{
+    if (!h || !host_out) return fail_h(h, GKS_ERR_ARG, "NULL argument");
+    if (which < GKS_FIELD_CONS || which > GKS_FIELD_STRAIN) return fail_h(h, GKS_ERR_ARG, "unknown field");
+    State st;
+    HIP_TRY(h, hipMemcpyAsync(&st, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const long long N = h->L.ncells;
+    const int nv = h->nv, D = h->cfg.dim;
+    if (which == GKS_FIELD_STRAIN) {
+        hipLaunchKernelGGL(k_strain, dim3(h->grid_cell), dim3(CELL_TILE), 0, h->stream, (const void*)h->tab, 1, 1);
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(host_out, h->inst.S, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return GKS_OK;
+    }
+    HIP_TRY(h, hipMemcpyAsync(host_out, h->inst.W[st.parity], sizeof(double) * N * nv, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (which == GKS_FIELD_PRIM) {
+        for (long long i = 0; i < N; ++i) {
+            const double rho = host_out[i];
+            double ke = 0.0;
+            for (int d = 0; d < D; ++d) {
+                const double u = host_out[(1 + d) * N + i] / rho;
+                ke += u * host_out[(1 + d) * N + i];
+                host_out[(1 + d) * N + i] = u;
+            }
+            host_out[(D + 1) * N + i] = (h->cfg.gamma - 1.0) * (host_out[(D + 1) * N + i] - 0.5 * ke);
+        }
+    }
+    return GKS_OK;
+}
+
+gks_status gks_state_device_ptr(gks_handle h, const double** dev_W)
+{
+    if (!h || !dev_W) return fail_h(h, GKS_ERR_ARG, "NULL argument");
+    State st;
+    HIP_TRY(h, hipMemcpyAsync(&st, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    *dev_W = h->inst.W[st.parity];
+    return GKS_OK;
+}
+
+gks_status gks_set_timing(gks_handle h, int32_t enable)
+{
+    if (!h) return fail_h(nullptr, GKS_ERR_ARG, "NULL handle");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->timing = enable != 0;
+    h->events_used = 0;
+    h->steps_timed = 0;
+    return GKS_OK;
+}
+
+gks_status gks_kernel_times(gks_handle h, double* ms, int64_t* steps_timed)
+{
+    if (!h || !ms) return fail_h(h, GKS_ERR_ARG, "NULL argument");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    ms[0] = ms[1] = ms[2] = 0.0;
+    for (size_t i = 0; i + 4 <= h->events_used; i += 4) {
+        for (int q = 0; q < 3; ++q) {
+            float t = 0.f;
+            HIP_TRY(h, hipEventElapsedTime(&t, h->events[i + q], h->events[i + q + 1]));
+            ms[q] += t;
+        }
+    }
+    if (steps_timed) *steps_timed = h->steps_timed;
+    return GKS_OK;
+}
+
+gks_status gks_destroy(gks_handle h)
+{
+    if (!h) return GKS_OK;
+    State st;
+    gks_status r = GKS_OK;
+    if (hipMemcpyAsync(&st, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        r = GKS_ERR_DEVICE;
+    else if (st.err && !h->broken)
+        r = GKS_ERR_NONPHYSICAL;
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    delete h;
+    return r;
+}
+
+const char* gks_last_error(gks_handle h)
+{
+    if (h) return h->err.c_str();
+    return g_last_error.c_str();
+}
+
+// ------------------------------------------------------------------------------------
+// batch
+// ------------------------------------------------------------------------------------
+gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes)
+{
+    if (capacity < 1 || !bytes) return fail_h(nullptr, GKS_ERR_ARG, "bad capacity");
+    *bytes = TabView::bytes(capacity);
+    return GKS_OK;
+}
+
+static gks_status batch_upload(gks_batch b)
+{
+    std::vector<const Inst*> mem;
+    int present = 0;
+    for (gks_handle h : b->members) {
+        mem.push_back(&h->inst);
+        present |= 1 << h->cls;
+    }
+    build_table(b->host_tab, b->cap, mem);
+    if (hipMemcpyAsync(b->tab, b->host_tab.data(), b->host_tab.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        b->err = "table upload failed";
+        g_last_error = b->err;
+        return GKS_ERR_DEVICE;
+    }
+    if (b->captured && (present & ~b->cls_present)) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->captured = false;
+    }
+    if (!b->captured) b->cls_present = present;
+    return GKS_OK;
+}
+
+gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity, void* dev_workspace, size_t bytes,
+                            void* hip_stream, gks_batch* out)
+{
+    if (!out || (!hs && count) || count < 0 || capacity < 1 || count > capacity || !dev_workspace)
+        return fail_h(nullptr, GKS_ERR_ARG, "bad batch arguments");
+    if (bytes < TabView::bytes(capacity)) return fail_h(nullptr, GKS_ERR_NOMEM, "batch workspace too small");
+    if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
+    for (int i = 0; i < count; ++i)
+        if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
+    gks_batch b = new gks_batch_ctx();
+    b->members.assign(hs, hs + count);
+    b->cap = capacity;
+    b->stream = (hipStream_t)hip_stream;
+    b->tab = dev_workspace;
+    b->captured = false;
+    b->cls_present = 0;
+    const int cus = device_cus();
+    b->grid[0] = cus * 8;        // strain: 256-thread workgroups
+    b->grid[5] = cus * 8;        // update
+    for (int c = 1; c <= 4; ++c) b->grid[c] = cus * 16;   // face: one-wave workgroups
+    gks_status r = batch_upload(b);
+    if (r != GKS_OK) { delete b; return r; }
+    *out = b;
+    return GKS_OK;
+}
+
+gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t count)
+{
+    if (!b || count < 0 || count > b->cap || (!hs && count)) return fail_h(nullptr, GKS_ERR_ARG, "bad member list");
+    for (int i = 0; i < count; ++i)
+        if (!hs[i]) return fail_h(nullptr, GKS_ERR_ARG, "NULL member");
+    b->members.assign(hs, hs + count);
+    return batch_upload(b);
+}
+
+static void batch_launch(gks_batch b, int present)
+{
+    const void* tab = b->tab;
+    hipLaunchKernelGGL(k_strain, dim3(b->grid[0]), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0);
+    for (int c = 0; c < NCLS; ++c)
+        if (present & (1 << c))
+            hipLaunchKernelGGL(face_kernel(c), dim3(b->grid[1 + c]), dim3(FACE_TILE), 0, b->stream, tab, b->cap, c);
+    hipLaunchKernelGGL(k_update, dim3(b->grid[5]), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
+}
+
+gks_status gks_batch_step(gks_batch b, int32_t nsteps)
+{
+    if (!b || nsteps < 0) return fail_h(nullptr, GKS_ERR_ARG, "bad batch step");
+    for (int i = 0; i < nsteps; ++i) {
+        if (b->captured) {
+            if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "graph launch failed");
+        } else {
+            batch_launch(b, b->cls_present);
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "batch launch failed");
+    return GKS_OK;
+}
+
+gks_status gks_batch_capture(gks_batch b)
+{
+    if (!b) return fail_h(nullptr, GKS_ERR_ARG, "NULL batch");
+    if (b->captured) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->captured = false;
+    }
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail_h(nullptr, GKS_ERR_DEVICE, "begin capture failed");
+    batch_launch(b, b->cls_present);
+    if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess)
+        return fail_h(nullptr, GKS_ERR_DEVICE, "end capture failed");
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(b->graph);
+        return fail_h(nullptr, GKS_ERR_DEVICE, "graph instantiate failed");
+    }
+    b->captured = true;
+    return GKS_OK;
+}
+
+gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid)
+{
+    if (!b || kind < 0 || kind > 5 || grid < 0) return fail_h(nullptr, GKS_ERR_ARG, "bad launch shape");
+    if (grid == 0) grid = 1 << 20;   // effectively one workgroup per tile for any batch we admit
+    b->grid[kind] = grid;
+    if (b->captured) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->captured = false;
+    }
+    return GKS_OK;
+}
+
+gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* t, int32_t* state)
+{
+    if (!b) return fail_h(nullptr, GKS_ERR_ARG, "NULL batch");
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "sync failed");
+    std::vector<State> sts(b->members.size());
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (hipMemcpy(&sts[i], b->members[i]->st, sizeof(State), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail_h(nullptr, GKS_ERR_DEVICE, "state read failed");
+    for (size_t i = 0; i < sts.size(); ++i) {
+        if (steps) steps[i] = sts[i].steps;
+        if (res) for (int m = 0; m < 5; ++m) res[5 * i + m] = sts[i].res[m];
+        if (t) t[i] = sts[i].t;
+        if (state) state[i] = sts[i].err ? 2 : (sts[i].active ? 0 : 1);
+        if (sts[i].err) b->members[i]->broken = true;
+    }
+    return GKS_OK;
+}
+
+gks_status gks_batch_destroy(gks_batch b)
+{
+    if (!b) return GKS_OK;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->captured) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+    }
+    delete b;
+    return GKS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------
+// operation count of one face on the host
+// ------------------------------------------------------------------------------------
+namespace gks {
+struct CR {
+    double v;
+    static thread_local double n;
+    CR() : v(0) {}
+    CR(double x) : v(x) {}
+    CR(int x) : v(x) {}
+    explicit operator double() const { return v; }
+};
+thread_local double CR::n = 0;
+inline CR operator+(CR a, CR b) { CR::n += 1; return CR(a.v + b.v); }
+inline CR operator-(CR a, CR b) { CR::n += 1; return CR(a.v - b.v); }
+inline CR operator*(CR a, CR b) { CR::n += 1; return CR(a.v * b.v); }
+inline CR operator/(CR a, CR b) { CR::n += 1; return CR(a.v / b.v); }
+inline CR operator-(CR a) { return CR(-a.v); }
+inline bool operator<(CR a, CR b) { return a.v < b.v; }
+inline bool operator>(CR a, CR b) { return a.v > b.v; }
+inline bool operator>=(CR a, CR b) { return a.v >= b.v; }
+inline bool operator<=(CR a, CR b) { return a.v <= b.v; }
+inline CR g_sqrt(CR a) { CR::n += 1; return CR(sqrt(a.v)); }
+inline CR g_exp(CR a) { CR::n += 1; return CR(exp(a.v)); }
+inline CR g_erfc(CR a) { CR::n += 1; return CR(erfc(a.v)); }
+inline CR g_abs(CR a) { return CR(fabs(a.v)); }
+
+template <int D>
+static double count_face()
+{
+    constexpr int NV = D + 2;
+    // a representative interior face: distinct left/right states, nonzero slopes, tau ~ dt/3
+    const double prim[4][5] = {{1.00, 0.30, -0.10, 0.05, 0.90}, {1.10, 0.25, -0.05, 0.02, 1.00},
+                               {0.95, 0.35, -0.12, 0.04, 0.85}, {1.05, 0.28, -0.08, 0.03, 0.95}};
+    const double gamma = 1.4;
+    CR Wc[4][NV], xc[4];
+    for (int o = 0; o < 4; ++o) {
+        const double rho = prim[o][0], p = prim[o][4];
+        double ke = 0.0;
+        Wc[o][0] = CR(rho);
+        for (int d = 0; d < D; ++d) { Wc[o][1 + d] = CR(rho * prim[o][1 + d]); ke += rho * prim[o][1 + d] * prim[o][1 + d]; }
+        Wc[o][D + 1] = CR(p / (gamma - 1.0) + 0.5 * ke);
+        xc[o] = CR(0.01 * (o - 1.5));
+    }
+    CR::n = 0;
+    FaceIn<D, CR> in;
+    reconstruct<D, CR>(Wc, xc, CR(0.0), in);
+    in.kf = CR(1e-3);
+    in.wf = CR(10.0);
+    in.Sf = CR(5.0);
+    in.dt = CR(3e-3);
+    GasC gas{gamma, 0.72, 1e-3, 0.1, 0.09, 2.0 / (gamma - 1.0)};
+    CR F[NV];
+    face_flux<CR, D, CR>(in, gas, F);
+    return CR::n;
+}
+}  // namespace gks
+
+extern "C" gks_status gks_face_flops(int32_t dim, int32_t precision, double* flops)
+{
+    if (!flops || (dim != 2 && dim != 3) || (precision != GKS_FP64 && precision != GKS_FP32_FLUX))
+        return fail_h(nullptr, GKS_ERR_ARG, "bad arguments");
+    *flops = dim == 2 ? gks::count_face<2>() : gks::count_face<3>();
+    return GKS_OK;
+}

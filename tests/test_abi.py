@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every entry point include/gks.h declares; host-only
+paths (workspace sizing, configuration validation, the flop count) work without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from inputs import cases as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    txt = open(os.path.join(ROOT, "include", "gks.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gks_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    import paper_1302_2132_amd as P
+    assert sorted(P.EXPORTED) == declared()
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1302_2132_amd as P
+    L = ctypes.CDLL(P.lib_path)
+    for name in declared():
+        assert hasattr(L, name), name
+
+
+def test_workspace_bytes_and_validation():
+    import paper_1302_2132_amd as P
+    c = C.mixing_layer(64)
+    nb = P.gks_workspace_bytes(P.config_from_case(c))
+    # two FP64 state buffers + k, omega, strain + x/y face fluxes at least
+    assert nb >= 8 * 64 * 64 * (4 * 2 + 3) + 8 * 4 * 2 * 65 * 64
+    bad = c.copy()
+    bad.bc = [["periodic", "outflow"], ["periodic", "periodic"]]
+    with pytest.raises(P.GksError) as e:
+        P.gks_workspace_bytes(P.config_from_case(bad))
+    assert e.value.status == P.GKS_ERR_ARG
+    bad = c.copy()
+    bad.xf = [c.xf[0][::-1].copy(), c.xf[1]]
+    with pytest.raises(P.GksError):
+        P.gks_workspace_bytes(P.config_from_case(bad))
+    bad = c.copy()
+    bad.gamma = 2.5          # fewer than D total degrees of freedom
+    with pytest.raises(P.GksError):
+        P.gks_workspace_bytes(P.config_from_case(bad))
+    fp32 = c.copy()
+    fp32.precision = "fp32_flux"
+    assert P.gks_workspace_bytes(P.config_from_case(fp32)) < nb
+
+
+def test_init_validation_before_any_device_call():
+    import paper_1302_2132_amd as P
+    c = C.mixing_layer(16)
+    cfg = P.config_from_case(c)
+    with pytest.raises(P.GksError) as e:     # workspace too small
+        P.gks_init(cfg, 256, 16, 0, c.W, c.k, c.omega)
+    assert e.value.status == P.GKS_ERR_NOMEM
+    with pytest.raises(P.GksError) as e:     # misaligned workspace
+        P.gks_init(cfg, 257, 1 << 30, 0, c.W, c.k, c.omega)
+    assert e.value.status == P.GKS_ERR_ARG
+
+
+def test_face_flop_count():
+    import paper_1302_2132_amd as P
+    f2, f3 = P.gks_face_flops(2), P.gks_face_flops(3)
+    assert 500 < f2 < f3 < 5000

@@ -1,0 +1,79 @@
+"""Batched form: every solve gives the same result alone and inside a persistent batch
+(mixed sizes, dimensions and precisions; with and without a captured graph)."""
+import numpy as np
+import pytest
+
+from gpu_util import banner
+from inputs import cases as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    out = [
+        C.mixing_layer(40, seed=11),
+        C.sbli(48, 24, precision="fp32_flux"),
+        C.isotropic_box(10, precision="fp64"),
+        C.uniform_flow(dim=3, n=(9, 7, 5), bc=[["dirichlet", "outflow"], ["wall", "wall"], ["periodic", "periodic"]]),
+        C.sod_tube(60, ny=2, t_end=0.02),
+        C.mixing_layer(33, seed=12, precision="fp32_flux"),
+    ]
+    out[3].precision = "fp32_flux"
+    rng = np.random.default_rng(4)
+    out[3].W = out[3].W * (1 + 0.03 * rng.uniform(-1, 1, size=out[3].W.shape))
+    return out
+
+
+def _alone(case, n):
+    from paper_1302_2132_amd import Solver
+    s = Solver(case)
+    s.step(n)
+    r = s.residual()
+    W = s.fields("cons")
+    s.close()
+    return W, r
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_alone_bitwise(graph):
+    from paper_1302_2132_amd import Batch, Solver
+    n = 25
+    cases = _cases()
+    ref = [_alone(c, n) for c in cases]
+    banner(f"batch of {len(cases)} graph={graph}")
+    solvers = [Solver(c) for c in cases]
+    b = Batch(solvers, capacity=8)
+    if graph:
+        b.capture()
+    b.step(n)
+    st = b.status()
+    for i, (c, s) in enumerate(zip(cases, solvers)):
+        W = s.fields("cons")
+        r = s.residual()
+        assert st["steps"][i] == ref[i][1]["steps"]
+        assert np.array_equal(W, ref[i][0]), (i, c.name)
+        assert np.array_equal(r["res"], ref[i][1]["res"]), (i, c.name)
+        assert r["t"] == ref[i][1]["t"]
+    assert st["state"][4] == 1          # the shock tube reached its end time
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_membership_change_keeps_graph():
+    """Admit and retire members between replays of one captured graph."""
+    from paper_1302_2132_amd import Batch, Solver
+    a, bcase, ccase = C.mixing_layer(24, seed=1), C.mixing_layer(30, seed=2), C.sbli(40, 20)
+    ref_b = _alone(bcase, 10)
+    ref_c = _alone(ccase, 6)
+    sa, sb, sc = Solver(a), Solver(bcase), Solver(ccase)
+    b = Batch([sa, sb], capacity=4)
+    b.capture()
+    b.step(4)
+    b.set_members([sb, sc])          # retire a, admit c (same classes: graph kept)
+    b.step(6)
+    assert np.array_equal(sb.fields("cons"), ref_b[0])
+    assert np.array_equal(sc.fields("cons"), ref_c[0])
+    b.close()
+    for s in (sa, sb, sc):
+        s.close()

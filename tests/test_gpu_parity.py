@@ -1,0 +1,201 @@
+"""GPU path (libgks through its C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances: FP64 flux <= 1e-12 and FP32 flux <= 1e-5, per field, normwise
+(max |gpu - oracle| / max |oracle|), after the stated number of steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import banner, field_errors, run_gpu
+from inputs import cases as C
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _compare(case, nsteps, tol, check_res=True):
+    banner(f"{case.name} {case.precision} steps={nsteps}")
+    Wg, rg = run_gpu(case, nsteps)
+    ro = oracle.run(case, nsteps, nthreads=0)
+    err = field_errors(Wg, ro["W"])
+    print(f"  field errors {err}", flush=True)
+    assert rg["steps"] == ro["steps"]
+    assert np.all(err <= tol), err
+    rel_t = abs(rg["t"] - ro["t"]) / max(ro["t"], 1e-300)
+    assert rel_t <= (1e-13 if tol <= TOL64 else 1e-5), (rg["t"], ro["t"])
+    if check_res:
+        rr = np.max(np.abs(rg["res"] - ro["res"])) / max(np.max(np.abs(ro["res"])), 1e-300)
+        assert rr <= (1e-9 if tol <= TOL64 else 1e-2), (rg["res"], ro["res"])
+    return Wg, rg, ro
+
+
+def test_mixing_layer_64_fp64_100_steps():
+    _compare(C.mixing_layer(64, steps=100), 100, TOL64)
+
+
+def test_sbli_small_fp64_all_boundaries():
+    # wall (bottom), fixed inflow (left), outflow (right), post-shock profile (top), stretched y
+    _compare(C.sbli(96, 48), 60, TOL64)
+
+
+def test_isotropic_small_fp64():
+    c = C.isotropic_box(16, precision="fp64")
+    _compare(c, 20, TOL64)
+
+
+def test_isotropic_small_fp32_flux():
+    c = C.isotropic_box(16, precision="fp32_flux")
+    _compare(c, 20, TOL32)
+
+
+def test_mixing_layer_fp32_flux():
+    c = C.mixing_layer(64, steps=100, precision="fp32_flux")
+    _compare(c, 100, TOL32)
+
+
+def test_sbli_small_fp32_flux():
+    c = C.sbli(96, 48, precision="fp32_flux")
+    _compare(c, 60, TOL32)
+
+
+@pytest.mark.parametrize("n", [(2, 2, 1), (67, 3, 1), (5, 130, 1), (3, 2, 2), (9, 7, 5)])
+def test_ragged_and_minimal_sizes(n):
+    dim = 3 if n[2] > 1 else 2
+    c = C.uniform_flow(dim=dim, n=n, bc=[["periodic", "periodic"]] * dim)
+    rng = np.random.default_rng(sum(n))
+    c.W = c.W * (1.0 + 0.05 * rng.uniform(-1, 1, size=c.W.shape))
+    _compare(c, 4, TOL64)
+
+
+def test_3d_mixed_boundaries():
+    bc = [["dirichlet", "outflow"], ["wall", "profile"], ["outflow", "wall"]]
+    c = C.uniform_flow(dim=3, n=(9, 7, 6), bc=bc, vel=(0.4, 0.1, -0.2))
+    rng = np.random.default_rng(3)
+    c.W = c.W * (1.0 + 0.05 * rng.uniform(-1, 1, size=c.W.shape))
+    _compare(c, 6, TOL64)
+
+
+def test_free_stream_gpu():
+    bc = [["dirichlet", "outflow"], ["outflow", "profile"]]
+    c = C.uniform_flow(dim=2, n=(40, 33, 1), bc=bc)
+    Wg, r = run_gpu(c, 5)
+    assert np.max(np.abs(Wg - c.W)) <= 1e-14 * np.max(np.abs(c.W))
+
+
+def test_conservation_gpu():
+    c = C.mixing_layer(48, seed=7)
+    vol = np.outer(np.diff(c.xf[1]), np.diff(c.xf[0]))
+    Wg, _ = run_gpu(c, 30)
+    for m in range(4):
+        before, after = np.sum(c.W[m, 0] * vol), np.sum(Wg[m, 0] * vol)
+        assert abs(after - before) <= 1e-13 * np.sum(np.abs(c.W[m, 0]) * vol)
+
+
+def test_sod_gpu_end_time():
+    c = C.sod_tube(200, ny=2, t_end=0.2)
+    banner("sod 200 to t=0.2")
+    Wg, rg = run_gpu(c, 2000)
+    ro = oracle.run(c, 2000)
+    assert rg["t"] == 0.2 and ro["t"] == 0.2
+    assert rg["steps"] == ro["steps"]
+    assert np.all(field_errors(Wg, ro["W"]) <= TOL64)
+
+
+def test_fields_prim_and_strain():
+    from paper_1302_2132_amd import Solver
+    c = C.mixing_layer(32, seed=2)
+    s = Solver(c)
+    try:
+        s.step(3)
+        cons = s.fields("cons")
+        prim = s.fields("prim")
+        S = s.fields("strain")
+    finally:
+        s.close()
+    rho = cons[0]
+    assert np.allclose(prim[1], cons[1] / rho, rtol=1e-15, atol=0)
+    p = (c.gamma - 1) * (cons[3] - 0.5 * (cons[1] ** 2 + cons[2] ** 2) / rho)
+    assert np.allclose(prim[3], p, rtol=1e-13, atol=0)
+    So = oracle.strain(c, cons)
+    assert np.max(np.abs(S - So)) <= 1e-12 * np.max(np.abs(So))
+
+
+def test_nonphysical_blowup_reported():
+    from paper_1302_2132_amd import GKS_ERR_NONPHYSICAL, GKS_ERR_STATE, GksError, Solver
+    c = C.sod_tube(64, ny=2)
+    c.cfl = 50.0
+    s = Solver(c)
+    try:
+        s.step(40)
+        with pytest.raises(GksError) as e:
+            s.residual()
+        assert e.value.status == GKS_ERR_NONPHYSICAL
+        with pytest.raises(GksError) as e:
+            s.step(1)
+        assert e.value.status == GKS_ERR_STATE
+        s.fields("cons")           # still allowed
+    finally:
+        s.close()
+
+
+def test_init_rejects_bad_inputs():
+    from paper_1302_2132_amd import GKS_ERR_ARG, GKS_ERR_NONPHYSICAL, GksError, Solver
+    c = C.mixing_layer(16)
+    c.W[3, 0, 2, 2] = 0.0           # p < 0
+    with pytest.raises(GksError) as e:
+        Solver(c)
+    assert e.value.status == GKS_ERR_NONPHYSICAL
+    c = C.mixing_layer(16)
+    c.omega[0, 1, 1] = 0.0
+    with pytest.raises(GksError) as e:
+        Solver(c)
+    assert e.value.status == GKS_ERR_ARG
+
+
+# ---------------------------------------------------------------------------------
+# full sizes: one step checked cell by cell at sampled cells
+# ---------------------------------------------------------------------------------
+def _sampled_step(case, warm, ncells, tol, seed=0):
+    from paper_1302_2132_amd import Solver
+    banner(f"{case.name} {case.precision} sampled step after {warm}")
+    s = Solver(case)
+    try:
+        s.step(warm)
+        Wa = s.fields("cons")
+        ra = s.residual()
+        s.step(1)
+        Wb = s.fields("cons")
+        rb = s.residual()
+    finally:
+        s.close()
+    assert rb["steps"] == warm + 1
+    dt = oracle.cfl_dt(case, Wa)
+    if case.t_end == 0.0:
+        assert abs(rb["dt"] - dt) <= 1e-13 * dt, (rb["dt"], dt)
+    rng = np.random.default_rng(seed)
+    N = case.ncells
+    cells = np.unique(np.concatenate([rng.integers(0, N, size=ncells),
+                                      np.arange(min(N, 64)), np.arange(max(N - 64, 0), N)]))
+    new = oracle.step_cells(case, Wa, rb["dt"], cells)
+    got = Wb.reshape(case.nvar, -1)[:, cells].T
+    scale = np.max(np.abs(Wa.reshape(case.nvar, -1)), axis=1)
+    err = np.max(np.abs(got - new), axis=0) / scale
+    print(f"  sampled errors {err}", flush=True)
+    assert np.all(err <= tol), err
+
+
+def test_sbli_full_size_fp64_sampled():
+    _sampled_step(C.sbli(), 20, 4000, TOL64)
+
+
+def test_sbli_full_size_fp32_flux_sampled():
+    _sampled_step(C.sbli(precision="fp32_flux"), 20, 4000, TOL32)
+
+
+def test_isotropic_full_size_fp32_flux_sampled():
+    _sampled_step(C.isotropic_box(256), 2, 2000, TOL32)
