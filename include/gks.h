@@ -141,9 +141,12 @@ typedef struct gks_batch_ctx* gks_batch;
 /* Device workspace of a batch table able to hold up to `capacity` solves. */
 gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
 
-/* Create a batch over `count` initialised handles (all on the same device; their own
- * streams are not used: batch work runs on `hip_stream`).  The table lives in
- * dev_workspace.  Handles stay owned by the caller and must outlive the batch. */
+/* Create a batch over `count` initialised handles (all on the same device).  Batch work
+ * runs on `hip_stream`, which must not be the legacy null stream if the batch is to be
+ * captured as a graph.  Creation (and gks_batch_set_members) waits for the members' own
+ * streams; afterwards every per-handle call on a member first waits for the batch stream.
+ * The table lives in dev_workspace.  Handles stay owned by the caller and must outlive
+ * the batch. */
 gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity,
                             void* dev_workspace, size_t bytes, void* hip_stream, gks_batch* out);
 

@@ -237,9 +237,10 @@ def isotropic_box(N: int = 256, seed: int = 2, Ma_t: float = 0.5, k0: float = 4.
     ux_h = ux_h - KX * dot
     uy_h = uy_h - KY * dot
     uz_h = uz_h - KZ * dot
-    ux = np.fft.irfftn(ux_h, s=(N, N, N))
-    uy = np.fft.irfftn(uy_h, s=(N, N, N))
-    uz = np.fft.irfftn(uz_h, s=(N, N, N))
+    ax = (0, 1, 2)
+    ux = np.fft.irfftn(ux_h, s=(N, N, N), axes=ax)
+    uy = np.fft.irfftn(uy_h, s=(N, N, N), axes=ax)
+    uz = np.fft.irfftn(uz_h, s=(N, N, N), axes=ax)
     rms = math.sqrt(float(np.mean(ux ** 2 + uy ** 2 + uz ** 2)))
     s = Ma_t / rms
     ux, uy, uz = ux * s, uy * s, uz * s
@@ -248,7 +249,7 @@ def isotropic_box(N: int = 256, seed: int = 2, Ma_t: float = 0.5, k0: float = 4.
     for comp in (ux, uy, uz):
         ch = np.fft.rfftn(comp)
         for Kd in (KX, KY, KZ):
-            g = np.fft.irfftn(1j * Kd * ch, s=(N, N, N))
+            g = np.fft.irfftn(1j * Kd * ch, s=(N, N, N), axes=ax)
             grad2 += float(np.mean(g * g))
     nu = mu / 1.0
     K_res = 0.5 * float(np.mean(ux ** 2 + uy ** 2 + uz ** 2))

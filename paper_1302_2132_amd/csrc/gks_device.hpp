@@ -12,8 +12,8 @@ constexpr int NCLS = 4;          // face-kernel classes: (dim 2|3) x (FP64|FP32 
 
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_DIRICHLET = 2, BC_PROFILE = 3, BC_OUTFLOW = 4 };
 
-// Step state of one solve, written only by the last workgroup of the update kernel (and
-// by atomics from every workgroup).
+// Step state of one solve, written by the end-of-step kernel (and by atomics from the
+// update kernel's workgroups).
 struct alignas(64) State {
     double dt;          // step size of the step about to run
     double t;           // time reached
@@ -22,7 +22,6 @@ struct alignas(64) State {
     double res[5];      // residual of the last completed step
     double res_first[5];
     unsigned long long rate_bits;  // max CFL rate of the state being produced (bit pattern)
-    unsigned int tiles_done;       // update tiles finished in the current step
     int parity;         // W[parity] is the current state
     int err;            // bit 0: non-physical state met
     int active;         // 1 while stepping
@@ -35,8 +34,8 @@ struct Inst {
     int dim, nv, precision, cls;
     int n[3];
     int ntan[3];               // cells in a boundary plane of axis d
-    long long ncells;
-    long long nface[3];        // faces normal to axis d
+    int ncells;                // < 2^29 (validated), so cell and face indices fit in int
+    int nface[3];              // faces normal to axis d
     int bc[3][2];
     double gamma, prandtl, mu, c_a, c_mu, cfl, t_end, b;
     double* W[2];

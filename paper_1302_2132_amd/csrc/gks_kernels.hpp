@@ -59,9 +59,9 @@ __device__ inline int image_index(int bc, int i, int n)
     return i;
 }
 
-__device__ inline long long cell_index(const Inst& I, int i, int j, int k)
+__device__ inline int cell_index(const Inst& I, int i, int j, int k)
 {
-    return ((long long)k * I.n[1] + j) * I.n[0] + i;
+    return (k * I.n[1] + j) * I.n[0] + i;
 }
 
 // Conservative state of cell c (c[d] may be a ghost index in [-2, n+1]; the other
@@ -74,8 +74,8 @@ __device__ inline __attribute__((always_inline)) void load_state(const Inst& I, 
     const int n = I.n[d];
     const int id = c[d];
     if (id >= 0 && id < n) {
-        const long long idx = cell_index(I, c[0], c[1], D == 3 ? c[2] : 0);
-        for (int m = 0; m < NV; ++m) w[m] = W[m * I.ncells + idx];
+        const int idx = cell_index(I, c[0], c[1], D == 3 ? c[2] : 0);
+        for (int m = 0; m < NV; ++m) w[m] = W[(long long)m * I.ncells + idx];
         return;
     }
     const int side = id < 0 ? 0 : 1;
@@ -98,15 +98,15 @@ __device__ inline __attribute__((always_inline)) void load_state(const Inst& I, 
     }
     int cc[3] = {c[0], c[1], D == 3 ? c[2] : 0};
     cc[d] = image_index(bc, id, n);
-    const long long idx = cell_index(I, cc[0], cc[1], cc[2]);
-    for (int m = 0; m < NV; ++m) w[m] = W[m * I.ncells + idx];
+    const int idx = cell_index(I, cc[0], cc[1], cc[2]);
+    for (int m = 0; m < NV; ++m) w[m] = W[(long long)m * I.ncells + idx];
     if (bc == BC_WALL)
         for (int m = 1; m <= D; ++m) w[m] = -w[m];
 }
 
 // flat index of the interior image of cell c (only c[d] may be a ghost)
 template <int D>
-__device__ inline long long image_cell(const Inst& I, int d, const int* c)
+__device__ inline int image_cell(const Inst& I, int d, const int* c)
 {
     int cc[3] = {c[0], c[1], D == 3 ? c[2] : 0};
     const int n = I.n[d];
@@ -119,13 +119,13 @@ __device__ inline long long image_cell(const Inst& I, int d, const int* c)
 // strain rate
 // --------------------------------------------------------------------------------------
 template <int D>
-__device__ inline void strain_cell(const Inst& I, long long cell)
+__device__ inline void strain_cell(const Inst& I, int cell)
 {
     const double* __restrict__ W = I.W[I.st->parity];
     int c[3];
-    c[0] = (int)(cell % I.n[0]);
-    c[1] = (int)((cell / I.n[0]) % I.n[1]);
-    c[2] = (D == 3) ? (int)(cell / ((long long)I.n[0] * I.n[1])) : 0;
+    c[0] = cell % I.n[0];
+    c[1] = (cell / I.n[0]) % I.n[1];
+    c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
     double g[3][3];
     for (int b = 0; b < D; ++b) {
         double wp[D + 2], wm[D + 2];
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
         const int mi = find_member(tv.cell_prefix, count, tile);
         const Inst& I = tv.inst[mi];
         if (!force && !I.st->active) continue;
-        const long long cell = (long long)(tile - tv.cell_prefix[mi]) * CELL_TILE + threadIdx.x;
+        const int cell = (tile - tv.cell_prefix[mi]) * CELL_TILE + (int)threadIdx.x;
         if (cell >= I.ncells) continue;
         if (I.dim == 2) strain_cell<2>(I, cell);
         else strain_cell<3>(I, cell);
@@ -169,15 +169,15 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
 // One face normal to axis DIR.  The axis is a template parameter so that every stencil
 // index and the rotation to the face-local frame are compile-time (no private arrays).
 template <typename R, int D, int DIR>
-__device__ inline void face_one(const Inst& I, long long f)
+__device__ inline void face_one(const Inst& I, int f)
 {
     constexpr int NV = D + 2;
     // face coordinates: the face lies on the low side of cell fc along axis DIR
     const int fn0 = I.n[0] + (DIR == 0), fn1 = I.n[1] + (DIR == 1);
     int fc[3];
-    fc[0] = (int)(f % fn0);
-    fc[1] = (int)((f / fn0) % fn1);
-    fc[2] = (D == 3) ? (int)(f / ((long long)fn0 * fn1)) : 0;
+    fc[0] = f % fn0;
+    fc[1] = (f / fn0) % fn1;
+    fc[2] = (D == 3) ? f / (fn0 * fn1) : 0;
     const double* __restrict__ W = I.W[I.st->parity];
     const double* __restrict__ xcd = I.xc[DIR];
 
@@ -210,7 +210,7 @@ __device__ inline void face_one(const Inst& I, long long f)
     {
         int cl[3] = {fc[0], fc[1], fc[2]};
         cl[DIR] -= 1;
-        const long long il = image_cell<D>(I, DIR, cl), ir = image_cell<D>(I, DIR, fc);
+        const int il = image_cell<D>(I, DIR, cl), ir = image_cell<D>(I, DIR, fc);
         in.kf = 0.5 * (I.k[il] + I.k[ir]);
         in.wf = 0.5 * (I.om[il] + I.om[ir]);
         in.Sf = 0.5 * (I.S[il] + I.S[ir]);
@@ -220,7 +220,7 @@ __device__ inline void face_one(const Inst& I, long long f)
     R F[NV];
     if (face_flux<R, D, double>(in, gas, F)) atomicOr(&I.st->err, 1);
     R* __restrict__ out = (R*)I.F[DIR];
-    const long long nf = I.nface[DIR];
+    const long long nf = I.nface[DIR];   // 64-bit: component offsets m * nf may pass 2^31
     out[f] = F[0];
     out[(long long)(1 + DIR) * nf + f] = F[1];
     out[(long long)(1 + P1) * nf + f] = F[2];
@@ -228,8 +228,14 @@ __device__ inline void face_one(const Inst& I, long long f)
     out[(long long)(D + 1) * nf + f] = F[D + 1];
 }
 
+#ifndef GKS_FACE_WAVES_PER_EU
+#define GKS_FACE_WAVES_PER_EU 2
+#endif
+// Register budget of the face kernel: at least this many waves per SIMD (2 leaves 256
+// VGPRs per lane; the FP64 flux then spills a little).
 template <typename R, int D>
-__global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(2))) void k_face(const void* __restrict__ table, int cap, int cls)
+__global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(GKS_FACE_WAVES_PER_EU)))
+void k_face(const void* __restrict__ table, int cap, int cls)
 {
     TabView tv(const_cast<void*>(table), cap);
     const int count = tv.hdr->ncls[cls];
@@ -242,18 +248,18 @@ __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(2))) 
         if (!I.st->active) continue;
         int lt = tile - prefix[mj];
         if (lt < I.ntile_face[0]) {
-            const long long f = (long long)lt * FACE_TILE + threadIdx.x;
+            const int f = lt * FACE_TILE + (int)threadIdx.x;
             if (f < I.nface[0]) face_one<R, D, 0>(I, f);
             continue;
         }
         lt -= I.ntile_face[0];
         if (D == 2 || lt < I.ntile_face[1]) {
-            const long long f = (long long)lt * FACE_TILE + threadIdx.x;
+            const int f = lt * FACE_TILE + (int)threadIdx.x;
             if (f < I.nface[1]) face_one<R, D, 1>(I, f);
             continue;
         }
         lt -= I.ntile_face[1];
-        const long long f = (long long)lt * FACE_TILE + threadIdx.x;
+        const int f = lt * FACE_TILE + (int)threadIdx.x;
         if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1)>(I, f);
     }
 }
@@ -274,32 +280,32 @@ __device__ inline double wave_max(double v)
 }
 
 template <int D, typename RF>
-__device__ inline void update_cell(const Inst& I, long long cell, double dt, double* r2, double& rate, int& bad)
+__device__ inline void update_cell(const Inst& I, int cell, double dt, double* r2, double& rate, int& bad)
 {
     constexpr int NV = D + 2;
     const int cur = I.st->parity;
     const double* __restrict__ Wo = I.W[cur];
     double* __restrict__ Wn = I.W[cur ^ 1];
     int c[3];
-    c[0] = (int)(cell % I.n[0]);
-    c[1] = (int)((cell / I.n[0]) % I.n[1]);
-    c[2] = (D == 3) ? (int)(cell / ((long long)I.n[0] * I.n[1])) : 0;
+    c[0] = cell % I.n[0];
+    c[1] = (cell / I.n[0]) % I.n[1];
+    c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
     double w[NV];
     double idx_[3];
     for (int d = 0; d < D; ++d) idx_[d] = 1.0 / I.dx[d][c[d]];
     for (int m = 0; m < NV; ++m) {
-        const double old = Wo[m * I.ncells + cell];
+        const double old = Wo[(long long)m * I.ncells + cell];
         double acc = old;
+#pragma unroll
         for (int d = 0; d < D; ++d) {
-            int fn[3] = {I.n[0], I.n[1], D == 3 ? I.n[2] : 1};
-            fn[d] += 1;
-            const long long lo = ((long long)c[2] * fn[1] + c[1]) * fn[0] + c[0];
-            const long long hi = lo + (d == 0 ? 1 : (d == 1 ? fn[0] : (long long)fn[0] * fn[1]));
+            const int fn0 = I.n[0] + (d == 0), fn1 = I.n[1] + (d == 1);
+            const int lo = (c[2] * fn1 + c[1]) * fn0 + c[0];
+            const int hi = lo + (d == 0 ? 1 : (d == 1 ? fn0 : fn0 * fn1));
             const RF* __restrict__ F = (const RF*)I.F[d] + (long long)m * I.nface[d];
             acc -= (double(F[hi]) - double(F[lo])) * idx_[d];
         }
         w[m] = acc;
-        Wn[m * I.ncells + cell] = acc;
+        Wn[(long long)m * I.ncells + cell] = acc;
         const double r = (acc - old) / dt;
         r2[m] = r * r;
     }
@@ -333,42 +339,6 @@ __device__ inline void next_step(const Inst& I, State* st, double rate, double t
     st->dt = dt;
     st->t_after = ta;
     st->rate_bits = 0ull;
-    st->tiles_done = 0u;
-}
-
-// Workgroup-wide end of step for member I (all CELL_TILE threads call it).
-__device__ inline void finish_step(const Inst& I, double* sh)
-{
-    State* st = I.st;
-    const int nv = I.nv;
-    const int nt = I.ntile_cell;
-    // deterministic sum of the per-tile partials: fixed stride per thread, fixed tree
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < nt; t += CELL_TILE)
-        for (int m = 0; m < nv; ++m) acc[m] += I.part[(long long)t * nv + m];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int m = 0; m < nv; ++m) {
-        const double s = wave_sum(acc[m]);
-        if (lane == 0) sh[m * 4 + wv] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double N = (double)I.ncells;
-        for (int m = 0; m < nv; ++m) {
-            const double s = (sh[m * 4 + 0] + sh[m * 4 + 1]) + (sh[m * 4 + 2] + sh[m * 4 + 3]);
-            st->res[m] = sqrt(s / N);
-        }
-        st->dt_last = st->dt;
-        st->t = st->t_after;
-        st->steps += 1;
-        if (st->steps == 1)
-            for (int m = 0; m < nv; ++m) st->res_first[m] = st->res[m];
-        st->parity ^= 1;
-        const double rate = __longlong_as_double((long long)st->rate_bits);
-        next_step(I, st, rate, st->t);
-        if (st->err) st->active = 0;
-    }
-    __syncthreads();
 }
 
 __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ table, int cap)
@@ -379,14 +349,13 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
     __shared__ double sh_sum[5 * 4];
     __shared__ double sh_max[4];
     __shared__ int sh_bad[4];
-    __shared__ int sh_last;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mi = find_member(tv.cell_prefix, count, tile);
         const Inst& I = tv.inst[mi];
         if (!I.st->active) continue;
         const int lt = tile - tv.cell_prefix[mi];
-        const long long cell = (long long)lt * CELL_TILE + threadIdx.x;
+        const int cell = lt * CELL_TILE + (int)threadIdx.x;
         double r2[5] = {0, 0, 0, 0, 0};
         double rate = 0.0;
         int bad = 0;
@@ -419,22 +388,12 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
             const double mx = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
             atomicMax(&st->rate_bits, (unsigned long long)__double_as_longlong(mx));
             if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&st->err, 1);
-            __threadfence();
-            const unsigned int done = __hip_atomic_fetch_add(&st->tiles_done, 1u, __ATOMIC_ACQ_REL,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-            sh_last = (done + 1u == (unsigned int)I.ntile_cell);
-        }
-        __syncthreads();
-        if (sh_last) {
-            __threadfence();
-            finish_step(I, sh_sum);
         }
         __syncthreads();
     }
 }
 
-// Max CFL rate of the current state of each member and its first step (used at init and
-// after a checkpoint restore).  Single workgroup per member is not needed: same table walk.
+// Max CFL rate of the current state of each member (first step at init).
 __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ table, int cap)
 {
     TabView tv(const_cast<void*>(table), cap);
@@ -442,24 +401,23 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
     const int total = tv.hdr->total_cell;
     __shared__ double sh_max[4];
     __shared__ int sh_bad[4];
-    __shared__ int sh_last;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mi = find_member(tv.cell_prefix, count, tile);
         const Inst& I = tv.inst[mi];
         const int lt = tile - tv.cell_prefix[mi];
-        const long long cell = (long long)lt * CELL_TILE + threadIdx.x;
+        const int cell = lt * CELL_TILE + (int)threadIdx.x;
         double rate = 0.0;
         int bad = 0;
         if (cell < I.ncells) {
             const double* W = I.W[I.st->parity];
             const int D = I.dim;
             double w[5];
-            for (int m = 0; m < I.nv; ++m) w[m] = W[m * I.ncells + cell];
+            for (int m = 0; m < I.nv; ++m) w[m] = W[(long long)m * I.ncells + cell];
             int c[3];
-            c[0] = (int)(cell % I.n[0]);
-            c[1] = (int)((cell / I.n[0]) % I.n[1]);
-            c[2] = (D == 3) ? (int)(cell / ((long long)I.n[0] * I.n[1])) : 0;
+            c[0] = cell % I.n[0];
+            c[1] = (cell / I.n[0]) % I.n[1];
+            c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
             double ke = 0.0, U[3];
             for (int d = 0; d < D; ++d) { U[d] = w[1 + d] / w[0]; ke += U[d] * w[1 + d]; }
             const double rho = w[0], p = (2.0 / I.b) * (w[D + 1] - 0.5 * ke);
@@ -485,18 +443,55 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
             const double m = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
             atomicMax(&st->rate_bits, (unsigned long long)__double_as_longlong(m));
             if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&st->err, 1);
-            __threadfence();
-            const unsigned int done = __hip_atomic_fetch_add(&st->tiles_done, 1u, __ATOMIC_ACQ_REL,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-            sh_last = (done + 1u == (unsigned int)I.ntile_cell);
         }
         __syncthreads();
-        if (sh_last && threadIdx.x == 0) {
-            __threadfence();
-            State* st = I.st;
-            st->active = 1;
-            const double rate = __longlong_as_double((long long)st->rate_bits);
-            next_step(I, st, rate, st->t);
+    }
+}
+
+// End of a step (mode 0) or of the initial rate pass (mode 1), one workgroup per member:
+// deterministic residual from the per-tile partials (fixed stride per thread, fixed
+// tree), time, buffer swap and the next CFL step.  Runs after k_update / k_rate, so the
+// kernel boundary orders every partial sum and atomic before it.
+__global__ __launch_bounds__(CELL_TILE) void k_finish(const void* __restrict__ table, int cap, int mode)
+{
+    TabView tv(const_cast<void*>(table), cap);
+    const int count = tv.hdr->count;
+    __shared__ double sh[5 * 4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
+        const Inst& I = tv.inst[mi];
+        State* st = I.st;
+        if (mode == 0 && !st->active) continue;
+        if (mode == 1) {
+            if (threadIdx.x == 0) {
+                st->active = 1;
+                next_step(I, st, __longlong_as_double((long long)st->rate_bits), st->t);
+                if (st->err) st->active = 0;
+            }
+            continue;
+        }
+        const int nv = I.nv, nt = I.ntile_cell;
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int t = threadIdx.x; t < nt; t += CELL_TILE)
+            for (int m = 0; m < nv; ++m) acc[m] += I.part[(long long)t * nv + m];
+        for (int m = 0; m < nv; ++m) {
+            const double s = wave_sum(acc[m]);
+            if (lane == 0) sh[m * 4 + wv] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double N = (double)I.ncells;
+            for (int m = 0; m < nv; ++m) {
+                const double s = (sh[m * 4 + 0] + sh[m * 4 + 1]) + (sh[m * 4 + 2] + sh[m * 4 + 3]);
+                st->res[m] = sqrt(s / N);
+            }
+            st->dt_last = st->dt;
+            st->t = st->t_after;
+            st->steps += 1;
+            if (st->steps == 1)
+                for (int m = 0; m < nv; ++m) st->res_first[m] = st->res[m];
+            st->parity ^= 1;
+            next_step(I, st, __longlong_as_double((long long)st->rate_bits), st->t);
             if (st->err) st->active = 0;
         }
         __syncthreads();

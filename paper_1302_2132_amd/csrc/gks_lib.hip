@@ -55,7 +55,7 @@ bool config_ok(const gks_config* c, std::string* why)
     }
     long long nc = 1;
     for (int d = 0; d < c->dim; ++d) nc *= c->n[d];
-    if (nc > (1ll << 30)) return fail("too many cells");
+    if (nc > (1ll << 29)) return fail("too many cells");
     if (!(c->gamma > 1.0)) return fail("gamma must exceed 1");
     if (2.0 / (c->gamma - 1.0) < c->dim) return fail("gamma leaves no room for the internal degrees of freedom");
     if (!(c->prandtl > 0.0) || !(c->mu >= 0.0) || !(c->c_a >= 0.0) || !(c->c_mu > 0.0) || !(c->cfl > 0.0) ||
@@ -150,6 +150,7 @@ struct gks_ctx {
     bool broken;
     int grid_cell, grid_face;
     bool timing;
+    hipStream_t batch_stream;         // stream of the batch that last advanced this solve
     std::vector<hipEvent_t> events;   // pool, 4 per timed step
     size_t events_used;
     long long steps_timed;
@@ -182,6 +183,14 @@ static gks_status fail_h(gks_ctx* h, gks_status s, const std::string& msg)
         if (e_ != hipSuccess)                                                              \
             return fail_h((h), GKS_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
+
+// Work on a solve may have been enqueued by a batch on the batch's stream: wait for it
+// before the handle's own stream reads the state.
+static gks_status sync_batch(gks_ctx* h)
+{
+    if (h->batch_stream && h->batch_stream != h->stream) HIP_TRY(h, hipStreamSynchronize(h->batch_stream));
+    return GKS_OK;
+}
 
 static int cls_of(int dim, int precision) { return (dim == 3 ? 2 : 0) + (precision ? 1 : 0); }
 
@@ -290,6 +299,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     h->L = L;
     h->broken = false;
     h->timing = false;
+    h->batch_stream = nullptr;
     h->events_used = 0;
     h->steps_timed = 0;
     char* ws = h->ws;
@@ -305,11 +315,11 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     for (int d = 0; d < 3; ++d) {
         I.n[d] = d < D ? (int)cfg->n[d] : 1;
         I.ntan[d] = L.ntan[d];
-        I.nface[d] = L.nface[d];
+        I.nface[d] = (int)L.nface[d];
         I.ntile_face[d] = L.ntile_face[d];
         for (int sd = 0; sd < 2; ++sd) I.bc[d][sd] = d < D ? cfg->bc[d][sd] : GKS_BC_PERIODIC;
     }
-    I.ncells = N;
+    I.ncells = (int)N;
     I.gamma = cfg->gamma;
     I.prandtl = cfg->prandtl;
     I.mu = cfg->mu;
@@ -363,6 +373,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     h->grid_cell = L.ntile_cell;
     h->grid_face = I.ntile_face_all;
     hipLaunchKernelGGL(k_rate, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, (const void*)h->tab, 1);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, (const void*)h->tab, 1, 1);
     HIP_TRY(h, hipGetLastError());
     State st;
     HIP_TRY(h, hipMemcpyAsync(&st, I.st, sizeof(State), hipMemcpyDeviceToHost, s));
@@ -405,6 +416,7 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
         hipLaunchKernelGGL(fk, dim3(h->grid_face), dim3(FACE_TILE), 0, s, tab, 1, h->cls);
         if (h->timing) HIP_TRY(h, hipEventRecord(ev[2], s));
         hipLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, tab, 1, 0);
         if (h->timing) {
             HIP_TRY(h, hipEventRecord(ev[3], s));
             h->steps_timed += 1;
@@ -419,11 +431,15 @@ gks_status gks_step(gks_handle h, int32_t nsteps)
     if (!h) return fail_h(nullptr, GKS_ERR_ARG, "NULL handle");
     if (nsteps < 0) return fail_h(h, GKS_ERR_ARG, "nsteps < 0");
     if (h->broken) return fail_h(h, GKS_ERR_STATE, "handle is in the error state");
+    gks_status r = sync_batch(h);
+    if (r != GKS_OK) return r;
     return enqueue_steps(h, nsteps);
 }
 
 static gks_status read_state(gks_ctx* h, State* st)
 {
+    gks_status r = sync_batch(h);
+    if (r != GKS_OK) return r;
     HIP_TRY(h, hipMemcpyAsync(st, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     if (st->err) {
@@ -449,6 +465,8 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
 {
     if (!h || !host_out) return fail_h(h, GKS_ERR_ARG, "NULL argument");
     if (which < GKS_FIELD_CONS || which > GKS_FIELD_STRAIN) return fail_h(h, GKS_ERR_ARG, "unknown field");
+    gks_status rs = sync_batch(h);
+    if (rs != GKS_OK) return rs;
     State st;
     HIP_TRY(h, hipMemcpyAsync(&st, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -481,6 +499,8 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
 gks_status gks_state_device_ptr(gks_handle h, const double** dev_W)
 {
     if (!h || !dev_W) return fail_h(h, GKS_ERR_ARG, "NULL argument");
+    gks_status rs = sync_batch(h);
+    if (rs != GKS_OK) return rs;
     State st;
     HIP_TRY(h, hipMemcpyAsync(&st, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -519,6 +539,7 @@ gks_status gks_destroy(gks_handle h)
     if (!h) return GKS_OK;
     State st;
     gks_status r = GKS_OK;
+    if (h->batch_stream && h->batch_stream != h->stream) (void)hipStreamSynchronize(h->batch_stream);
     if (hipMemcpyAsync(&st, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)
         r = GKS_ERR_DEVICE;
@@ -550,6 +571,13 @@ static gks_status batch_upload(gks_batch b)
     std::vector<const Inst*> mem;
     int present = 0;
     for (gks_handle h : b->members) {
+        // work the member enqueued on its own stream must finish before batch work starts
+        if (h->stream != b->stream && hipStreamSynchronize(h->stream) != hipSuccess) {
+            b->err = "member stream sync failed";
+            g_last_error = b->err;
+            return GKS_ERR_DEVICE;
+        }
+        h->batch_stream = b->stream;
         mem.push_back(&h->inst);
         present |= 1 << h->cls;
     }
@@ -612,6 +640,7 @@ static void batch_launch(gks_batch b, int present)
         if (present & (1 << c))
             hipLaunchKernelGGL(face_kernel(c), dim3(b->grid[1 + c]), dim3(FACE_TILE), 0, b->stream, tab, b->cap, c);
     hipLaunchKernelGGL(k_update, dim3(b->grid[5]), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
+    hipLaunchKernelGGL(k_finish, dim3(b->cap), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0);
 }
 
 gks_status gks_batch_step(gks_batch b, int32_t nsteps)

@@ -307,6 +307,9 @@ class Batch:
         self.capacity = capacity or max(len(self.solvers), 1)
         nbytes = gks_batch_workspace_bytes(self.capacity)
         with torch.cuda.device(device):
+            # a stream of its own: the null stream cannot be captured into a graph
+            if stream is None:
+                stream = torch.cuda.Stream(device=device)
             self.stream, sp = _torch_stream(stream)
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
             self.b = gks_batch_create([s.h for s in self.solvers], self.capacity, self.ws.data_ptr(), nbytes, sp)
