@@ -9,6 +9,7 @@ namespace gks {
 constexpr int CELL_TILE = 256;   // cells per tile of the strain/update kernels (= block size)
 constexpr int FACE_TILE = 64;    // faces per tile of the face kernel (= block size, one wave)
 constexpr int NCLS = 4;          // face-kernel classes: (dim 2|3) x (FP64|FP32 flux)
+constexpr int PSTRIDE = 6;       // per-tile partials: nv residual sums (slots 0..4), CFL rate max (slot 5)
 
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_DIRICHLET = 2, BC_PROFILE = 3, BC_OUTFLOW = 4 };
 
@@ -21,7 +22,6 @@ struct alignas(64) State {
     double dt_last;     // size of the last completed step
     double res[5];      // residual of the last completed step
     double res_first[5];
-    unsigned long long rate_bits;  // max CFL rate of the state being produced (bit pattern)
     int parity;         // W[parity] is the current state
     int err;            // bit 0: non-physical state met
     int active;         // 1 while stepping
@@ -47,7 +47,7 @@ struct Inst {
     const double* xc[3];
     const double* dx[3];
     const double* bcd[3][2];
-    double* part;              // residual partial sums [ntile_cell][nv]
+    double* part;              // per-tile partials [ntile_cell][PSTRIDE]
     State* st;
     int ntile_cell;
     int ntile_face[3];

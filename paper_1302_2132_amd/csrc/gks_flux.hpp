@@ -268,29 +268,32 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
         mx_set(gr, R(rr), u, R(H(0.5) * rr / pr), R(pr / rr), bt);
     }
 
-    // --- half-line u-moments: left over u>0, right over u<0 -------------------------
-    R ml[8], mr[8];
+    // --- half-line u-moments: left over u>0, right over u<0.  Only <u^0>, <u^1> are
+    //     kept; higher ones are regenerated by the recurrence where they are used. ----
+    R ml01[2], mr01[2];
     {
         const R sq = g_sqrt(gl.lam);
         const R U = gl.U[0];
-        ml[0] = half * g_erfc(-sq * U);
-        ml[1] = U * ml[0] + g_exp(-gl.lam * U * U) * rsqpi_half / sq;
-        urec(ml, U, gl.h, 6);
+        ml01[0] = half * g_erfc(-sq * U);
+        ml01[1] = U * ml01[0] + g_exp(-gl.lam * U * U) * rsqpi_half / sq;
     }
     {
         const R sq = g_sqrt(gr.lam);
         const R U = gr.U[0];
-        mr[0] = half * g_erfc(sq * U);
-        mr[1] = U * mr[0] - g_exp(-gr.lam * U * U) * rsqpi_half / sq;
-        urec(mr, U, gr.h, 6);
+        mr01[0] = half * g_erfc(sq * U);
+        mr01[1] = U * mr01[0] - g_exp(-gr.lam * U * U) * rsqpi_half / sq;
     }
 
     // --- interface equilibrium state W0 (Eq. intermediatestate) ---------------------
     R W0[NV];
     {
-        R tl[NV], tr[NV];
-        tmom1(gl, ml, tl);
-        tmom1(gr, mr, tr);
+        R tl[NV], tr[NV], m3[3];
+        m3[0] = ml01[0]; m3[1] = ml01[1];
+        urec(m3, gl.U[0], gl.h, 2);
+        tmom1(gl, m3, tl);
+        m3[0] = mr01[0]; m3[1] = mr01[1];
+        urec(m3, gr.U[0], gr.h, 2);
+        tmom1(gr, m3, tr);
         for (int m = 0; m < NV; ++m) W0[m] = gl.rho * tl[m] + gr.rho * tr[m];
     }
     H r0, U0d[D], p0;
@@ -354,8 +357,8 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
     // --- one side of the initial distribution (Eq. initialf0): slopes a from dW/dx,
     //     time coefficients A from the compatibility condition at t = 0, then the
     //     gam3..gam5 flux terms and the c4, c5 terms of Rv -------------------------
-    auto side = [&](const Mx<R, D>& g, const R* mh, const H* slope, H rho) {
-        R r[NV], a[NV], A[NV], T[NV], mf[8];
+    auto side = [&](const Mx<R, D>& g, const R* m01, const H* slope, H rho) {
+        R r[NV], a[NV], A[NV], T[NV], mf[8], mh[8];
         const R ir = R(H(1) / rho);
         for (int m = 0; m < NV; ++m) r[m] = R(slope[m]) * ir;
         solve(g, r, b, inv_b, a);
@@ -365,6 +368,9 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
         tmom(g, mf + 1, a, bt, T);                     // <u psi (a.psi)> over all u
         for (int m = 0; m < NV; ++m) T[m] = -T[m];
         solve(g, T, b, inv_b, A);
+        mh[0] = m01[0];
+        mh[1] = m01[1];
+        urec(mh, g.U[0], g.h, 6);
         const R rg = g.rho;
         R acc[NV];
         tmom1(g, mh + 1, T);
@@ -378,8 +384,8 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
         tmom(g, mh, A, bt, T);
         for (int m = 0; m < NV; ++m) Rv[m] = Rv[m] + rg * (acc[m] + kw.c5 * T[m]);
     };
-    side(gl, ml, in.sl, rl);
-    side(gr, mr, in.sr, rr);
+    side(gl, ml01, in.sl, rl);
+    side(gr, mr01, in.sr, rr);
 
     // --- Abar, then the gam0 and gam2 equilibrium terms ------------------------------
     {

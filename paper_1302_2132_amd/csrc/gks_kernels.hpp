@@ -338,7 +338,6 @@ __device__ inline void next_step(const Inst& I, State* st, double rate, double t
     if (!(rate > 0.0) || !(dt > 0.0)) st->active = 0;
     st->dt = dt;
     st->t_after = ta;
-    st->rate_bits = 0ull;
 }
 
 __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ table, int cap)
@@ -381,13 +380,11 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            State* st = I.st;
+            double* part = I.part + (long long)lt * PSTRIDE;
             for (int m = 0; m < I.nv; ++m)
-                I.part[(long long)lt * I.nv + m] =
-                    (sh_sum[m * 4 + 0] + sh_sum[m * 4 + 1]) + (sh_sum[m * 4 + 2] + sh_sum[m * 4 + 3]);
-            const double mx = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
-            atomicMax(&st->rate_bits, (unsigned long long)__double_as_longlong(mx));
-            if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&st->err, 1);
+                part[m] = (sh_sum[m * 4 + 0] + sh_sum[m * 4 + 1]) + (sh_sum[m * 4 + 2] + sh_sum[m * 4 + 3]);
+            part[5] = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
+            if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&I.st->err, 1);
         }
         __syncthreads();
     }
@@ -439,59 +436,74 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
         if (lane == 0) { sh_max[wv] = mx; sh_bad[wv] = any; }
         __syncthreads();
         if (threadIdx.x == 0) {
-            State* st = I.st;
-            const double m = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
-            atomicMax(&st->rate_bits, (unsigned long long)__double_as_longlong(m));
-            if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&st->err, 1);
+            I.part[(long long)lt * PSTRIDE + 5] = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
+            if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&I.st->err, 1);
         }
         __syncthreads();
     }
 }
 
 // End of a step (mode 0) or of the initial rate pass (mode 1), one workgroup per member:
-// deterministic residual from the per-tile partials (fixed stride per thread, fixed
-// tree), time, buffer swap and the next CFL step.  Runs after k_update / k_rate, so the
-// kernel boundary orders every partial sum and atomic before it.
+// residual from the per-tile partial sums and the CFL rate from the per-tile maxima (fixed
+// stride per thread, fixed reduction tree: deterministic), then time, buffer swap and the
+// next CFL step.  Runs after k_update / k_rate, so the kernel boundary orders every
+// partial before it.  Loads of four tiles are issued together to hide their latency.
 __global__ __launch_bounds__(CELL_TILE) void k_finish(const void* __restrict__ table, int cap, int mode)
 {
     TabView tv(const_cast<void*>(table), cap);
     const int count = tv.hdr->count;
-    __shared__ double sh[5 * 4];
+    __shared__ double sh[6 * 4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
         const Inst& I = tv.inst[mi];
         State* st = I.st;
         if (mode == 0 && !st->active) continue;
-        if (mode == 1) {
-            if (threadIdx.x == 0) {
-                st->active = 1;
-                next_step(I, st, __longlong_as_double((long long)st->rate_bits), st->t);
-                if (st->err) st->active = 0;
-            }
-            continue;
-        }
         const int nv = I.nv, nt = I.ntile_cell;
-        double acc[5] = {0, 0, 0, 0, 0};
-        for (int t = threadIdx.x; t < nt; t += CELL_TILE)
-            for (int m = 0; m < nv; ++m) acc[m] += I.part[(long long)t * nv + m];
+        const int first = mode == 0 ? 0 : 5;    // mode 1 needs the rate only
+        double acc[5] = {0, 0, 0, 0, 0}, rmax = 0.0;
+        const double* __restrict__ part = I.part;
+        for (int t0 = threadIdx.x; t0 < nt; t0 += 4 * CELL_TILE) {
+            double v[4][6];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = t0 + q * CELL_TILE;
+#pragma unroll
+                for (int m = 0; m < 6; ++m)
+                    v[q][m] = (t < nt && (m >= first) && (m < nv || m == 5)) ? part[(long long)t * PSTRIDE + m] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                for (int m = 0; m < 5; ++m) acc[m] += v[q][m];
+                rmax = fmax(rmax, v[q][5]);
+            }
+        }
         for (int m = 0; m < nv; ++m) {
             const double s = wave_sum(acc[m]);
             if (lane == 0) sh[m * 4 + wv] = s;
         }
+        {
+            const double s = wave_max(rmax);
+            if (lane == 0) sh[5 * 4 + wv] = s;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            const double N = (double)I.ncells;
-            for (int m = 0; m < nv; ++m) {
-                const double s = (sh[m * 4 + 0] + sh[m * 4 + 1]) + (sh[m * 4 + 2] + sh[m * 4 + 3]);
-                st->res[m] = sqrt(s / N);
+            const double rate = fmax(fmax(sh[20], sh[21]), fmax(sh[22], sh[23]));
+            if (mode == 1) {
+                st->active = 1;
+            } else {
+                const double N = (double)I.ncells;
+                for (int m = 0; m < nv; ++m) {
+                    const double s = (sh[m * 4 + 0] + sh[m * 4 + 1]) + (sh[m * 4 + 2] + sh[m * 4 + 3]);
+                    st->res[m] = sqrt(s / N);
+                }
+                st->dt_last = st->dt;
+                st->t = st->t_after;
+                st->steps += 1;
+                if (st->steps == 1)
+                    for (int m = 0; m < nv; ++m) st->res_first[m] = st->res[m];
+                st->parity ^= 1;
             }
-            st->dt_last = st->dt;
-            st->t = st->t_after;
-            st->steps += 1;
-            if (st->steps == 1)
-                for (int m = 0; m < nv; ++m) st->res_first[m] = st->res[m];
-            st->parity ^= 1;
-            next_step(I, st, __longlong_as_double((long long)st->rate_bits), st->t);
+            next_step(I, st, rate, st->t);
             if (st->err) st->active = 0;
         }
         __syncthreads();

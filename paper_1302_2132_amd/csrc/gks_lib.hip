@@ -99,7 +99,7 @@ void layout(const gks_config* c, Layout* L)
         }
     }
     L->ntile_cell = (int)((L->ncells + CELL_TILE - 1) / CELL_TILE);
-    L->part = take(sizeof(double) * nv * (size_t)L->ntile_cell);
+    L->part = take(sizeof(double) * PSTRIDE * (size_t)L->ntile_cell);
     L->st = take(sizeof(State));
     L->tab = take(TabView::bytes(1));
     L->total = off;
