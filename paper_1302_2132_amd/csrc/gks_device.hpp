@@ -38,6 +38,7 @@ struct Inst {
     int nface[3];              // faces normal to axis d
     int bc[3][2];
     double gamma, prandtl, mu, c_a, c_mu, cfl, t_end, b;
+    double two_over_b, inv_b, inv_cmu, pfix;   // 2/b, 1/b, 1/C_mu, 1/Pr - 1
     double* W[2];
     const double* k;
     const double* om;
@@ -46,6 +47,10 @@ struct Inst {
     const double* xf[3];
     const double* xc[3];
     const double* dx[3];
+    const double* idx[3];      // 1/dx[i], i from -2 to n+1
+    const double* ic2[3];      // 1/(xc[i+1] - xc[i-1]), i from 0 to n-1 (central differences)
+    const double* icd[3];      // 1/(xc[i+1] - xc[i]), i from -2 to n
+    const double* fgeo[3];     // per face f in [0, n]: xf-xc[f-1], xc[f]-xf, and their inverses
     const double* bcd[3][2];
     double* part;              // per-tile partials [ntile_cell][PSTRIDE]
     State* st;

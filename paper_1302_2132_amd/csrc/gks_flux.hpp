@@ -187,16 +187,18 @@ GKS_HD inline Kw<R> kogan(R tau, R dt)
 }
 
 // Inputs of one face in the wide type H (FP64 on the device): reconstructed states,
-// minmod slopes, cell averages of the two neighbours, centre-to-face distances, face means
-// of k, omega and strain rate, and the step.
+// minmod slopes, cell averages of the two neighbours, inverse centre-to-face distances,
+// face means of k, omega and strain rate, and the step.
 template <int D, typename H = double>
 struct FaceIn {
     H Wl[D + 2], Wr[D + 2], sl[D + 2], sr[D + 2], Wi[D + 2], Wi1[D + 2];
-    H dxl, dxr, kf, wf, Sf, dt;
+    H idl, idr, kf, wf, Sf, dt;
 };
 
+// Per-solve constants; the reciprocals are formed once on the host.
 struct GasC {
-    double gamma, prandtl, mu, c_a, c_mu, b;
+    double mu, c_a, b;
+    double two_over_b, inv_b, inv_cmu, pfix;   // 2/b, 1/b, 1/C_mu, 1/Pr - 1
 };
 
 template <typename H>
@@ -206,37 +208,45 @@ GKS_HD inline H minmod(H p, H q)
     return (p > H(0)) ? (p < q ? p : q) : (p > q ? p : q);
 }
 
+// Face geometry along the normal: inverse distances between the centres of cells
+// i-1, i, i+1, i+2 (icd[0..2]), centre-to-face distances dl, dr and their inverses.
+template <typename H>
+struct FaceGeo {
+    H icd[3], dl, dr, idl, idr;
+};
+
 // MUSCL reconstruction along the face normal from four cell averages Wc[0..3] (cells
-// i-1, i, i+1, i+2 around face i+1/2) and their centres: minmod of the one-sided
-// differences on centre-to-centre distances, conservative variables.
+// i-1, i, i+1, i+2 around face i+1/2): minmod of the one-sided differences on
+// centre-to-centre distances, conservative variables.
 template <int D, typename H>
-GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const H* xc, H xface, FaceIn<D, H>& in)
+GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const FaceGeo<H>& geo, FaceIn<D, H>& in)
 {
     for (int m = 0; m < D + 2; ++m) {
-        const H d0 = (Wc[1][m] - Wc[0][m]) / (xc[1] - xc[0]);
-        const H d1 = (Wc[2][m] - Wc[1][m]) / (xc[2] - xc[1]);
-        const H d2 = (Wc[3][m] - Wc[2][m]) / (xc[3] - xc[2]);
+        const H d0 = (Wc[1][m] - Wc[0][m]) * geo.icd[0];
+        const H d1 = (Wc[2][m] - Wc[1][m]) * geo.icd[1];
+        const H d2 = (Wc[3][m] - Wc[2][m]) * geo.icd[2];
         const H sl = minmod(d0, d1), sr = minmod(d1, d2);
         in.sl[m] = sl;
         in.sr[m] = sr;
-        in.Wl[m] = Wc[1][m] + sl * (xface - xc[1]);
-        in.Wr[m] = Wc[2][m] - sr * (xc[2] - xface);
+        in.Wl[m] = Wc[1][m] + sl * geo.dl;
+        in.Wr[m] = Wc[2][m] - sr * geo.dr;
         in.Wi[m] = Wc[1][m];
         in.Wi1[m] = Wc[2][m];
     }
-    in.dxl = xface - xc[1];
-    in.dxr = xc[2] - xface;
+    in.idl = geo.idl;
+    in.idr = geo.idr;
 }
 
-// Primitive recovery in the wide type: rho, U, p.  Returns false for rho <= 0 or p <= 0
-// (or non-finite).
+// Primitive recovery in the wide type: rho, 1/rho, U, p.  Returns false for rho <= 0 or
+// p <= 0 (or non-finite).
 template <int D, typename H>
-GKS_HD inline bool prim_wide(const H* W, H b, H& rho, H* U, H& p)
+GKS_HD inline bool prim_wide(const H* W, H two_over_b, H& rho, H& irho, H* U, H& p)
 {
     rho = W[0];
+    irho = H(1) / rho;
     H ke = H(0);
-    for (int d = 0; d < D; ++d) { U[d] = W[1 + d] / rho; ke = ke + U[d] * W[1 + d]; }
-    p = (H(2) / b) * (W[D + 1] - H(0.5) * ke);
+    for (int d = 0; d < D; ++d) { U[d] = W[1 + d] * irho; ke = ke + U[d] * W[1 + d]; }
+    p = two_over_b * (W[D + 1] - H(0.5) * ke);
     return (rho > H(0)) && (p > H(0)) && (p < H(1e300)) && (rho < H(1e300));
 }
 
@@ -251,37 +261,38 @@ template <typename R, int D, typename H = double>
 GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
 {
     constexpr int NV = D + 2;
-    const R b = R(gas.b), inv_b = R(1.0 / gas.b), bt = R(gas.b - 1.0);
+    const R b = R(gas.b), inv_b = R(gas.inv_b), bt = R(gas.b - 1.0);
     const R half = R(0.5);
     const R rsqpi_half = R(0.28209479177387814);   // 1/(2 sqrt(pi))
-    const H bw = H(gas.b);
+    const H bw = H(gas.two_over_b);
 
     // --- left / right Maxwellians (wide primitive recovery) -------------------------
-    H rl, Ul[D], pl, rr, Ur[D], pr;
-    if (!prim_wide<D>(in.Wl, bw, rl, Ul, pl) || !prim_wide<D>(in.Wr, bw, rr, Ur, pr)) return 1;
+    H rl, irl, Ul[D], pl, rr, irr, Ur[D], pr;
+    if (!prim_wide<D>(in.Wl, bw, rl, irl, Ul, pl) || !prim_wide<D>(in.Wr, bw, rr, irr, Ur, pr)) return 1;
     Mx<R, D> gl, gr;
     {
         R u[D];
+        const H hl = pl * irl, hr = pr * irr;        // 1/(2 lambda) = p/rho
         for (int d = 0; d < D; ++d) u[d] = R(Ul[d]);
-        mx_set(gl, R(rl), u, R(H(0.5) * rl / pl), R(pl / rl), bt);
+        mx_set(gl, R(rl), u, R(H(0.5) / hl), R(hl), bt);
         for (int d = 0; d < D; ++d) u[d] = R(Ur[d]);
-        mx_set(gr, R(rr), u, R(H(0.5) * rr / pr), R(pr / rr), bt);
+        mx_set(gr, R(rr), u, R(H(0.5) / hr), R(hr), bt);
     }
 
     // --- half-line u-moments: left over u>0, right over u<0.  Only <u^0>, <u^1> are
     //     kept; higher ones are regenerated by the recurrence where they are used. ----
     R ml01[2], mr01[2];
     {
-        const R sq = g_sqrt(gl.lam);
+        const R isq = g_sqrt(R(2) * gl.h);            // 1/sqrt(lambda)
         const R U = gl.U[0];
-        ml01[0] = half * g_erfc(-sq * U);
-        ml01[1] = U * ml01[0] + g_exp(-gl.lam * U * U) * rsqpi_half / sq;
+        ml01[0] = half * g_erfc(-gl.lam * isq * U);
+        ml01[1] = U * ml01[0] + g_exp(-gl.lam * U * U) * rsqpi_half * isq;
     }
     {
-        const R sq = g_sqrt(gr.lam);
+        const R isq = g_sqrt(R(2) * gr.h);
         const R U = gr.U[0];
-        mr01[0] = half * g_erfc(sq * U);
-        mr01[1] = U * mr01[0] - g_exp(-gr.lam * U * U) * rsqpi_half / sq;
+        mr01[0] = half * g_erfc(gr.lam * isq * U);
+        mr01[1] = U * mr01[0] - g_exp(-gr.lam * U * U) * rsqpi_half * isq;
     }
 
     // --- interface equilibrium state W0 (Eq. intermediatestate) ---------------------
@@ -296,25 +307,27 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
         tmom1(gr, m3, tr);
         for (int m = 0; m < NV; ++m) W0[m] = gl.rho * tl[m] + gr.rho * tr[m];
     }
-    H r0, U0d[D], p0;
+    H r0, ir0, U0d[D], p0;
     {
         H w0[NV];
         for (int m = 0; m < NV; ++m) w0[m] = H(W0[m]);
-        if (!prim_wide<D>(w0, bw, r0, U0d, p0)) return 1;
+        if (!prim_wide<D>(w0, bw, r0, ir0, U0d, p0)) return 1;
     }
+    const H h0 = p0 * ir0;
     Mx<R, D> g0;
     {
         R u[D];
         for (int d = 0; d < D; ++d) u[d] = R(U0d[d]);
-        mx_set(g0, R(r0), u, R(H(0.5) * r0 / p0), R(p0 / r0), bt);
+        mx_set(g0, R(r0), u, R(H(0.5) / h0), R(h0), bt);
     }
 
     // --- relaxation time (laminar + artificial + k-omega) and time weights ----------
     H tau;
     {
-        const H eta = in.Sf / (H(gas.c_mu) * in.wf);
-        tau = H(gas.mu) / p0 + H(gas.c_a) * g_abs(pr - pl) / (pr + pl) * in.dt +
-              (in.kf / in.wf) / ((p0 / r0) * g_sqrt(H(1) + eta * eta));
+        const H iw = H(1) / in.wf, ip0 = H(1) / p0;
+        const H eta = in.Sf * iw * H(gas.inv_cmu);
+        tau = H(gas.mu) * ip0 + (in.kf * iw) * (r0 * ip0) / g_sqrt(H(1) + eta * eta);
+        if (gas.c_a > 0.0) tau = tau + H(gas.c_a) * g_abs(pr - pl) / (pr + pl) * in.dt;
     }
     const R dt = R(in.dt);
     const Kw<R> kw = kogan(R(tau), dt);
@@ -329,9 +342,9 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
     {
         R m0p[8], m0n[8];
         const R U = g0.U[0];
-        const R sq = g_sqrt(g0.lam);
-        const R small = half * g_erfc(g_abs(sq * U));   // one erfc serves both halves
-        const R tail = g_exp(-g0.lam * U * U) * rsqpi_half / sq;
+        const R isq = g_sqrt(R(2) * g0.h);             // 1/sqrt(lambda0)
+        const R small = half * g_erfc(g_abs(g0.lam * isq * U));   // one erfc serves both halves
+        const R tail = g_exp(-g0.lam * U * U) * rsqpi_half * isq;
         const bool upos = U >= R(0);
         m0p[0] = upos ? R(1) - small : small;
         m0n[0] = upos ? small : R(1) - small;
@@ -340,7 +353,7 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
         urec(m0p, U, g0.h, 6);
         urec(m0n, U, g0.h, 6);
         R r[NV], ab[NV], T1[NV], T2[NV];
-        const H il = H(1) / (r0 * in.dxl), ir = H(1) / (r0 * in.dxr);
+        const H il = ir0 * in.idl, ir = ir0 * in.idr;
         for (int m = 0; m < NV; ++m) r[m] = R((H(W0[m]) - in.Wi[m]) * il);
         solve(g0, r, b, inv_b, ab);
         tmom(g0, m0p + 1, ab, bt, T1);                 // <u psi abar_l.psi>_{g0,>0}
@@ -357,9 +370,9 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
     // --- one side of the initial distribution (Eq. initialf0): slopes a from dW/dx,
     //     time coefficients A from the compatibility condition at t = 0, then the
     //     gam3..gam5 flux terms and the c4, c5 terms of Rv -------------------------
-    auto side = [&](const Mx<R, D>& g, const R* m01, const H* slope, H rho) {
+    auto side = [&](const Mx<R, D>& g, const R* m01, const H* slope, H irho) {
         R r[NV], a[NV], A[NV], T[NV], mf[8], mh[8];
-        const R ir = R(H(1) / rho);
+        const R ir = R(irho);
         for (int m = 0; m < NV; ++m) r[m] = R(slope[m]) * ir;
         solve(g, r, b, inv_b, a);
         mf[0] = R(1);
@@ -384,13 +397,13 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
         tmom(g, mh, A, bt, T);
         for (int m = 0; m < NV; ++m) Rv[m] = Rv[m] + rg * (acc[m] + kw.c5 * T[m]);
     };
-    side(gl, ml01, in.sl, rl);
-    side(gr, mr01, in.sr, rr);
+    side(gl, ml01, in.sl, irl);
+    side(gr, mr01, in.sr, irr);
 
     // --- Abar, then the gam0 and gam2 equilibrium terms ------------------------------
     {
         R m0[8], r[NV], Ab[NV], T[NV];
-        const R i0 = R(H(1) / r0);
+        const R i0 = R(ir0);
         for (int m = 0; m < NV; ++m) r[m] = Rv[m] * i0;
         solve(g0, r, b, inv_b, Ab);
         m0[0] = R(1);
@@ -408,7 +421,7 @@ GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
     //   = (F_E - U0.F_m + |U0|^2 F_rho/2) - U0_n (G_E - U0.G_m + |U0|^2 G_rho/2),
     // with G = int int psi f = dt W0 + dt^2/2 Rv (the integrated compatibility condition).
     {
-        const R pfix = R(1.0 / gas.prandtl - 1.0);
+        const R pfix = R(gas.pfix);
         R Gv[NV];
         const R hdt2 = half * dt * dt;
         for (int m = 0; m < NV; ++m) Gv[m] = dt * W0[m] + hdt2 * Rv[m];

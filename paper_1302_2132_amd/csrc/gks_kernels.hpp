@@ -134,8 +134,7 @@ __device__ inline void strain_cell(const Inst& I, int cell)
         cm[b] -= 1;
         load_state<D>(I, W, b, cp, wp);
         load_state<D>(I, W, b, cm, wm);
-        const double h = I.xc[b][c[b] + 1] - I.xc[b][c[b] - 1];
-        const double ip = 1.0 / wp[0], im = 1.0 / wm[0], ih = 1.0 / h;
+        const double ip = 1.0 / wp[0], im = 1.0 / wm[0], ih = I.ic2[b][c[b]];
         for (int a = 0; a < D; ++a) g[a][b] = (wp[1 + a] * ip - wm[1 + a] * im) * ih;
     }
     double ss = 0.0;
@@ -179,18 +178,29 @@ __device__ inline void face_one(const Inst& I, int f)
     fc[1] = (f / fn0) % fn1;
     fc[2] = (D == 3) ? f / (fn0 * fn1) : 0;
     const double* __restrict__ W = I.W[I.st->parity];
-    const double* __restrict__ xcd = I.xc[DIR];
 
-    double Wc[4][NV], xc[4];
+    double Wc[4][NV];
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         int c[3] = {fc[0], fc[1], fc[2]};
         c[DIR] += o - 2;
         load_state<D>(I, W, DIR, c, Wc[o]);
-        xc[o] = xcd[c[DIR]];
+    }
+    FaceGeo<double> geo;
+    {
+        const int i = fc[DIR];
+        const double* icd = I.icd[DIR];
+        geo.icd[0] = icd[i - 2];
+        geo.icd[1] = icd[i - 1];
+        geo.icd[2] = icd[i];
+        const double* fg = I.fgeo[DIR] + 4 * i;
+        geo.dl = fg[0];
+        geo.dr = fg[1];
+        geo.idl = fg[2];
+        geo.idr = fg[3];
     }
     FaceIn<D, double> in;
-    reconstruct<D, double>(Wc, xc, I.xf[DIR][fc[DIR]], in);
+    reconstruct<D, double>(Wc, geo, in);
 
     // face-local frame: normal momentum first, then the remaining axes in order
     constexpr int P1 = DIR == 0 ? 1 : 0;             // first tangential axis
@@ -216,7 +226,7 @@ __device__ inline void face_one(const Inst& I, int f)
         in.Sf = 0.5 * (I.S[il] + I.S[ir]);
     }
     in.dt = I.st->dt;
-    GasC gas{I.gamma, I.prandtl, I.mu, I.c_a, I.c_mu, I.b};
+    GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
     R F[NV];
     if (face_flux<R, D, double>(in, gas, F)) atomicOr(&I.st->err, 1);
     R* __restrict__ out = (R*)I.F[DIR];
@@ -292,7 +302,8 @@ __device__ inline void update_cell(const Inst& I, int cell, double dt, double* r
     c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
     double w[NV];
     double idx_[3];
-    for (int d = 0; d < D; ++d) idx_[d] = 1.0 / I.dx[d][c[d]];
+    for (int d = 0; d < D; ++d) idx_[d] = I.idx[d][c[d]];
+    const double idt = 1.0 / dt;
     for (int m = 0; m < NV; ++m) {
         const double old = Wo[(long long)m * I.ncells + cell];
         double acc = old;
@@ -306,23 +317,23 @@ __device__ inline void update_cell(const Inst& I, int cell, double dt, double* r
         }
         w[m] = acc;
         Wn[(long long)m * I.ncells + cell] = acc;
-        const double r = (acc - old) / dt;
+        const double r = (acc - old) * idt;
         r2[m] = r * r;
     }
     // positivity and the CFL rate of the new state
     double ke = 0.0, U[3];
-    const double rho = w[0];
-    for (int d = 0; d < D; ++d) { U[d] = w[1 + d] / rho; ke += U[d] * w[1 + d]; }
-    const double p = (2.0 / I.b) * (w[D + 1] - 0.5 * ke);
+    const double rho = w[0], irho = 1.0 / rho;
+    for (int d = 0; d < D; ++d) { U[d] = w[1 + d] * irho; ke += U[d] * w[1 + d]; }
+    const double p = I.two_over_b * (w[D + 1] - 0.5 * ke);
     if (!(rho > 0.0) || !(p > 0.0) || !(rho < 1e300) || !(p < 1e300)) { bad = 1; rate = 0.0; return; }
-    const double cs = sqrt(I.gamma * p / rho);
+    // CFL rate  sum_d (|U_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2
+    const double cs = sqrt(I.gamma * p * irho);
     const double fac = fmax(4.0 / 3.0, I.gamma / I.prandtl);
-    const double nu = (I.mu + rho * I.k[cell] / I.om[cell]) / rho * fac;
+    const double nu = (I.mu * irho + I.k[cell] / I.om[cell]) * fac;
     double r = 0.0, r2s = 0.0;
     for (int d = 0; d < D; ++d) {
-        const double h = I.dx[d][c[d]];
-        r += (fabs(U[d]) + cs) / h;
-        r2s += 1.0 / (h * h);
+        r += (fabs(U[d]) + cs) * idx_[d];
+        r2s += idx_[d] * idx_[d];
     }
     rate = r + 2.0 * nu * r2s;
 }

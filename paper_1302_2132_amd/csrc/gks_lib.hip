@@ -23,7 +23,7 @@ namespace {
 thread_local std::string g_last_error;
 
 struct Layout {
-    size_t W[2], k, om, S, F[3], xf[3], xc[3], dx[3], bcd[3][2], part, st, tab, total;
+    size_t W[2], k, om, S, F[3], xf[3], xc[3], dx[3], idx[3], ic2[3], icd[3], fgeo[3], bcd[3][2], part, st, tab, total;
     long long ncells, nface[3];
     int ntan[3];
     int ntile_cell, ntile_face[3];
@@ -83,7 +83,7 @@ void layout(const gks_config* c, Layout* L)
         L->nface[d] = 0;
         L->ntile_face[d] = 0;
         L->ntan[d] = 1;
-        L->F[d] = L->xf[d] = L->xc[d] = L->dx[d] = 0;
+        L->F[d] = L->xf[d] = L->xc[d] = L->dx[d] = L->idx[d] = L->ic2[d] = L->icd[d] = L->fgeo[d] = 0;
         L->bcd[d][0] = L->bcd[d][1] = 0;
         if (d >= D) continue;
         L->nface[d] = L->ncells / n[d] * (n[d] + 1);
@@ -93,6 +93,10 @@ void layout(const gks_config* c, Layout* L)
         L->xf[d] = take(sizeof(double) * (n[d] + 5));
         L->xc[d] = take(sizeof(double) * (n[d] + 4));
         L->dx[d] = take(sizeof(double) * (n[d] + 4));
+        L->idx[d] = take(sizeof(double) * (n[d] + 4));
+        L->ic2[d] = take(sizeof(double) * n[d]);
+        L->icd[d] = take(sizeof(double) * (n[d] + 3));
+        L->fgeo[d] = take(sizeof(double) * 4 * (n[d] + 1));
         for (int s = 0; s < 2; ++s) {
             if (c->bc[d][s] == GKS_BC_DIRICHLET) L->bcd[d][s] = take(sizeof(double) * nv);
             else if (c->bc[d][s] == GKS_BC_PROFILE) L->bcd[d][s] = take(sizeof(double) * nv * (size_t)L->ntan[d]);
@@ -105,8 +109,10 @@ void layout(const gks_config* c, Layout* L)
     L->total = off;
 }
 
-// extended face coordinates, centres and widths (two ghost layers per side)
-void metrics(const gks_config* c, int d, std::vector<double>& xf, std::vector<double>& xc, std::vector<double>& dx)
+// extended face coordinates, centres and widths (two ghost layers per side), inverse
+// centre-to-centre distances, and per-face centre-to-face distances with their inverses
+void metrics(const gks_config* c, int d, std::vector<double>& xf, std::vector<double>& xc, std::vector<double>& dx,
+             std::vector<double>& idx, std::vector<double>& ic2, std::vector<double>& icd, std::vector<double>& fgeo)
 {
     const long long n = c->n[d];
     const double* f = c->xf[d];
@@ -122,6 +128,20 @@ void metrics(const gks_config* c, int d, std::vector<double>& xf, std::vector<do
     for (long long i = 0; i < n + 4; ++i) {
         xc[i] = 0.5 * (xf[i] + xf[i + 1]);
         dx[i] = xf[i + 1] - xf[i];
+    }
+    idx.assign(n + 4, 0.0);
+    for (long long i = 0; i < n + 4; ++i) idx[i] = 1.0 / dx[i];
+    ic2.assign(n, 0.0);
+    for (long long i = 0; i < n; ++i) ic2[i] = 1.0 / (xc[i + 3] - xc[i + 1]);
+    icd.assign(n + 3, 0.0);
+    for (long long i = 0; i < n + 3; ++i) icd[i] = 1.0 / (xc[i + 1] - xc[i]);
+    fgeo.assign(4 * (n + 1), 0.0);
+    for (long long f = 0; f <= n; ++f) {
+        const double dl = xf[f + 2] - xc[f + 1], dr = xc[f + 2] - xf[f + 2];
+        fgeo[4 * f + 0] = dl;
+        fgeo[4 * f + 1] = dr;
+        fgeo[4 * f + 2] = 1.0 / dl;
+        fgeo[4 * f + 3] = 1.0 / dr;
     }
 }
 
@@ -328,6 +348,10 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.cfl = cfg->cfl;
     I.t_end = cfg->t_end;
     I.b = 2.0 / (cfg->gamma - 1.0);
+    I.two_over_b = cfg->gamma - 1.0;
+    I.inv_b = 1.0 / I.b;
+    I.inv_cmu = 1.0 / cfg->c_mu;
+    I.pfix = 1.0 / cfg->prandtl - 1.0;
     I.W[0] = (double*)(ws + L.W[0]);
     I.W[1] = (double*)(ws + L.W[1]);
     I.k = (const double*)(ws + L.k);
@@ -342,12 +366,20 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     HIP_TRY(h, hipMemcpyAsync((void*)I.k, k, cellb, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipMemcpyAsync((void*)I.om, omega, cellb, hipMemcpyHostToDevice, s));
     for (int d = 0; d < D; ++d) {
-        std::vector<double> xf, xc, dx;
-        metrics(cfg, d, xf, xc, dx);
+        std::vector<double> xf, xc, dx, idx, ic2, icd, fgeo;
+        metrics(cfg, d, xf, xc, dx, idx, ic2, icd, fgeo);
         I.F[d] = (void*)(ws + L.F[d]);
         I.xf[d] = (const double*)(ws + L.xf[d]) + 2;
         I.xc[d] = (const double*)(ws + L.xc[d]) + 2;
         I.dx[d] = (const double*)(ws + L.dx[d]) + 2;
+        I.idx[d] = (const double*)(ws + L.idx[d]) + 2;
+        I.ic2[d] = (const double*)(ws + L.ic2[d]);
+        HIP_TRY(h, hipMemcpyAsync(ws + L.idx[d], idx.data(), sizeof(double) * idx.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(ws + L.ic2[d], ic2.data(), sizeof(double) * ic2.size(), hipMemcpyHostToDevice, s));
+        I.icd[d] = (const double*)(ws + L.icd[d]) + 2;
+        I.fgeo[d] = (const double*)(ws + L.fgeo[d]);
+        HIP_TRY(h, hipMemcpyAsync(ws + L.icd[d], icd.data(), sizeof(double) * icd.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipMemcpyAsync(ws + L.fgeo[d], fgeo.data(), sizeof(double) * fgeo.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(h, hipMemcpyAsync(ws + L.xf[d], xf.data(), sizeof(double) * xf.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(h, hipMemcpyAsync(ws + L.xc[d], xc.data(), sizeof(double) * xc.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(h, hipMemcpyAsync(ws + L.dx[d], dx.data(), sizeof(double) * dx.size(), hipMemcpyHostToDevice, s));
@@ -757,24 +789,28 @@ static double count_face()
     // a representative interior face: distinct left/right states, nonzero slopes, tau ~ dt/3
     const double prim[4][5] = {{1.00, 0.30, -0.10, 0.05, 0.90}, {1.10, 0.25, -0.05, 0.02, 1.00},
                                {0.95, 0.35, -0.12, 0.04, 0.85}, {1.05, 0.28, -0.08, 0.03, 0.95}};
-    const double gamma = 1.4;
-    CR Wc[4][NV], xc[4];
+    const double gamma = 1.4, h = 0.01;
+    CR Wc[4][NV];
     for (int o = 0; o < 4; ++o) {
         const double rho = prim[o][0], p = prim[o][4];
         double ke = 0.0;
         Wc[o][0] = CR(rho);
         for (int d = 0; d < D; ++d) { Wc[o][1 + d] = CR(rho * prim[o][1 + d]); ke += rho * prim[o][1 + d] * prim[o][1 + d]; }
         Wc[o][D + 1] = CR(p / (gamma - 1.0) + 0.5 * ke);
-        xc[o] = CR(0.01 * (o - 1.5));
     }
+    FaceGeo<CR> geo;
+    for (int q = 0; q < 3; ++q) geo.icd[q] = CR(1.0 / h);
+    geo.dl = geo.dr = CR(0.5 * h);
+    geo.idl = geo.idr = CR(2.0 / h);
     CR::n = 0;
     FaceIn<D, CR> in;
-    reconstruct<D, CR>(Wc, xc, CR(0.0), in);
+    reconstruct<D, CR>(Wc, geo, in);
     in.kf = CR(1e-3);
     in.wf = CR(10.0);
     in.Sf = CR(5.0);
     in.dt = CR(3e-3);
-    GasC gas{gamma, 0.72, 1e-3, 0.1, 0.09, 2.0 / (gamma - 1.0)};
+    const double b = 2.0 / (gamma - 1.0);
+    GasC gas{1e-3, 0.1, b, 2.0 / b, 1.0 / b, 1.0 / 0.09, 1.0 / 0.72 - 1.0};
     CR F[NV];
     face_flux<CR, D, CR>(in, gas, F);
     return CR::n;
