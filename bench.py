@@ -56,6 +56,80 @@ def _roofline(case, leg, steps, flops_face, peak):
             "avg_launch_us": round(face_s * 1e6, 2)}
 
 
+def _batch_leg(steps=200, count=64, check=8):
+    """64 independent 2D meshes of uneven size (64^2..512^2; mixing layers and
+    Galilean-shifted shock tubes), FP32-flux, `steps` steps each: the plain per-case loop
+    (each solve stepped on its own, one after the other) against one batch whose
+    persistent kernels walk all meshes per launch (online-autotuned shapes, one captured
+    graph per step).  Both timings include every step; the autotuner's steps are real
+    steps of the batch."""
+    import numpy as np
+    import torch
+
+    from inputs import cases as C
+    from paper_1302_2132_amd import Batch, Solver
+    from paper_1302_2132_amd.autotune import autotune
+    cases = C.batch_cases(count, seed=3, steps=steps, precision="fp32_flux")
+    cell_updates = sum(c.ncells for c in cases) * steps
+    solvers = [Solver(c) for c in cases]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    ref = [solvers[i].fields("cons") for i in range(check)]
+    for s in solvers:
+        s.close()
+    del solvers
+    torch.cuda.empty_cache()
+
+    solvers = [Solver(c) for c in cases]
+    b = Batch(solvers, capacity=count)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    shape, tune_steps, tune_s = autotune(b, use_cache=False)
+    b.capture()
+    b.step(steps - tune_steps)
+    st = b.status()
+    t_batch = time.perf_counter() - t0
+    same = all(np.array_equal(solvers[i].fields("cons"), ref[i]) for i in range(check))
+    ok_steps = bool(np.all(st["steps"] == steps))
+    b.close()
+    for s in solvers:
+        s.close()
+    return {
+        "workload": f"{count} 2D meshes 64^2..512^2 (mixing layers, shifted shock tubes), FP32-flux, "
+                    f"{steps} steps each (seed 3)",
+        "cells": int(sum(c.ncells for c in cases)),
+        "batched_value": cell_updates / t_batch, "loop_value": cell_updates / t_loop,
+        "unit": "cell-updates/s", "speedup_vs_loop": t_loop / t_batch,
+        "batched_s": t_batch, "loop_s": t_loop,
+        "autotune": {"shape": shape, "steps": tune_steps, "seconds": tune_s},
+        "all_members_stepped": ok_steps, "bitwise_equal_to_loop_first_%d" % check: same,
+    }
+
+
+def _serve_leg(full=False):
+    """Poisson-arrival stream of solves (seeded, mean 20 req/s) mixing 2D mixing layers
+    (FP64), shock/boundary-layer interactions (N x N/2, FP32-flux) and 3D isotropic boxes
+    (FP32-flux); each runs to a residual fall of 1e-6 or its step cap.  Continuous
+    batching against the FIFO one-solve-at-a-time loop on the same trace.  The default
+    trace is a reduced one (fewer, smaller requests, lower step cap) so the benchmark stays
+    within minutes; --serve-full runs the stated one."""
+    from inputs import cases as C
+    from paper_1302_2132_amd.serve import run_batched, run_fifo
+    if full:
+        reqs = C.serve_trace(256, seed=4, rate=20.0)
+        desc = "256 requests, 20 req/s, 2D 128^2..1024^2 (SBLI N x N/2), 3D 64^3..128^3, tol 1e-6 or 5000 steps"
+    else:
+        reqs = C.serve_trace(24, seed=4, rate=20.0, n2d=(128, 384), n3d=(32, 64), max_steps=300)
+        desc = "24 requests, 20 req/s, 2D 128^2..384^2 (SBLI N x N/2), 3D 32^3..64^3, tol 1e-6 or 300 steps"
+    batched, _ = run_batched(reqs, C.request_case, quantum=20)
+    fifo, _ = run_fifo(reqs, C.request_case, quantum=20)
+    return {"trace": desc + " (seed 4)", "batched": batched, "fifo_loop": fifo}
+
+
 def _cpu_baseline(case, target_s=15.0):
     import oracle
     threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
@@ -84,6 +158,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--serve-full", action="store_true", help="served leg on the full 256-request trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), to calibrate "
                          "the HBM byte counters of a profiler against a known traffic")
@@ -143,6 +220,10 @@ def main():
             "roofline": _roofline(c32, leg32, K, flops2d, FP32_PEAK_TFLOPS),
             "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg32["kernels"].items() if k != "steps"},
         }
+    if not args.no_batch:
+        out["batched"] = _batch_leg()
+    if not args.no_serve:
+        out["served"] = _serve_leg(args.serve_full)
     if not args.no_cpu:
         out["cpu_baseline"] = _cpu_baseline(case)
     print(json.dumps(out), flush=True)

@@ -81,6 +81,7 @@ typedef struct {
     double cfl;                   /* CFL number of the global time step */
     double t_end;                 /* > 0: clip the last step to land on t_end, then stop */
     int32_t precision;            /* GKS_FP64 or GKS_FP32_FLUX */
+    int64_t max_steps;            /* > 0: the solve stops (on the device) after this many steps */
 } gks_config;
 
 typedef struct gks_ctx* gks_handle;
@@ -103,9 +104,11 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
 gks_status gks_step(gks_handle h, int32_t nsteps);
 
 /* Synchronise and report the last step: res[nvar] = sqrt(mean(((W^{n+1}-W^n)/dt)^2)) per
- * field, the step dt_last, the time t and the number of steps done.  Any pointer may be
+ * field, res_first[nvar] the same for the first step of the solve (for convergence
+ * ratios), the step dt_last, the time t and the number of steps done.  Any pointer may be
  * NULL. */
-gks_status gks_residual(gks_handle h, double* res, double* dt_last, double* t, int64_t* steps_done);
+gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt_last, double* t,
+                        int64_t* steps_done);
 
 /* Synchronise and copy a field (GKS_FIELD_*) to host memory. */
 gks_status gks_fields(gks_handle h, int32_t which, double* host_out);
@@ -164,12 +167,16 @@ gks_status gks_batch_capture(gks_batch b);
 
 /* Launch shape of the batch kernels: kind 0 = strain, 1 = face (2D FP64), 2 = face
  * (2D FP32), 3 = face (3D FP64), 4 = face (3D FP32), 5 = update.  grid = number of
- * persistent workgroups (0 = one per tile).  Invalidates a captured graph. */
-gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid);
+ * persistent workgroups walking the tile table (0 = one per tile).  tile = faces per
+ * face-kernel tile and workgroup (64, 128 or 256) for the face kinds, 0 otherwise.
+ * Results do not depend on the launch shape (bitwise).  Invalidates a captured graph. */
+gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile);
 
-/* Synchronise; copy per-member steps done, residual (nvar each, 5 slots per member),
- * time and status (0 running, 1 done by t_end, 2 error) into host arrays (any NULL). */
-gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* t, int32_t* state);
+/* Synchronise; copy per-member steps done, residual of the last step and of the first
+ * step (5 slots per member each), time and status (0 running, 1 done by t_end, 2 error)
+ * into host arrays (any NULL). */
+gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* res_first, double* t,
+                            int32_t* state);
 
 gks_status gks_batch_destroy(gks_batch b);
 

@@ -46,6 +46,7 @@ class Case:
     t_end: float = 0.0            # 0 => no end time
     steps: int = 100
     precision: str = "fp64"       # "fp64" | "fp32_flux"
+    max_steps: int = 0            # > 0: a solver stops after this many steps
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -443,6 +444,7 @@ def request_case(req) -> Case:
     else:
         c = isotropic_box(side, seed=seed, steps=req["max_steps"], precision="fp32_flux")
     c.name = f"req{req['id']}_{c.name}"
+    c.max_steps = int(req["max_steps"])
     return c
 
 

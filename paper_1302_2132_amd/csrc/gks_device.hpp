@@ -7,7 +7,7 @@
 namespace gks {
 
 constexpr int CELL_TILE = 256;   // cells per tile of the strain/update kernels (= block size)
-constexpr int FACE_TILE = 64;    // faces per tile of the face kernel (= block size, one wave)
+constexpr int FACE_TILE = 64;    // default faces per tile of the face kernel (= block size)
 constexpr int NCLS = 4;          // face-kernel classes: (dim 2|3) x (FP64|FP32 flux)
 constexpr int PSTRIDE = 6;       // per-tile partials: nv residual sums (slots 0..4), CFL rate max (slot 5)
 
@@ -57,6 +57,8 @@ struct Inst {
     int ntile_cell;
     int ntile_face[3];
     int ntile_face_all;
+    int face_tile;             // faces per face-kernel tile in the table holding this copy
+    long long max_steps;       // > 0: deactivate after this many steps
 };
 
 // Tile table header; arrays follow at offsets computed by TabView.

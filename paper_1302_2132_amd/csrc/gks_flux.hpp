@@ -258,7 +258,7 @@ GKS_HD inline bool prim_wide(const H* W, H two_over_b, H& rho, H& irho, H* U, H&
 // into F and into the right-hand side Rv of the Abar system as soon as their
 // coefficients exist; Abar and the remaining equilibrium terms come last.
 template <typename R, int D, typename H = double>
-GKS_HD inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
+GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
 {
     constexpr int NV = D + 2;
     const R b = R(gas.b), inv_b = R(gas.inv_b), bt = R(gas.b - 1.0);

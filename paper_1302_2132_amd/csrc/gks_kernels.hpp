@@ -168,7 +168,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
 // One face normal to axis DIR.  The axis is a template parameter so that every stencil
 // index and the rotation to the face-local frame are compile-time (no private arrays).
 template <typename R, int D, int DIR>
-__device__ inline void face_one(const Inst& I, int f)
+__device__ __attribute__((always_inline)) inline void face_one(const Inst& I, int f)
 {
     constexpr int NV = D + 2;
     // face coordinates: the face lies on the low side of cell fc along axis DIR
@@ -238,13 +238,18 @@ __device__ inline void face_one(const Inst& I, int f)
     out[(long long)(D + 1) * nf + f] = F[D + 1];
 }
 
-#ifndef GKS_FACE_WAVES_PER_EU
-#define GKS_FACE_WAVES_PER_EU 2
+#ifndef GKS_FACE_WAVES_FP64
+#define GKS_FACE_WAVES_FP64 2
+#endif
+#ifndef GKS_FACE_WAVES_FP32
+#define GKS_FACE_WAVES_FP32 4
 #endif
 // Register budget of the face kernel: at least this many waves per SIMD (2 leaves 256
-// VGPRs per lane; the FP64 flux then spills a little).
-template <typename R, int D>
-__global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(GKS_FACE_WAVES_PER_EU)))
+// VGPRs per lane for the FP64 flux, 4 leaves 128 for the FP32 flux).  TILE faces per
+// workgroup (64, 128 or 256: a batch's autotuned shape).
+template <typename R, int D, int TILE>
+__global__ __launch_bounds__(TILE)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_FACE_WAVES_FP64)))
 void k_face(const void* __restrict__ table, int cap, int cls)
 {
     TabView tv(const_cast<void*>(table), cap);
@@ -258,18 +263,18 @@ void k_face(const void* __restrict__ table, int cap, int cls)
         if (!I.st->active) continue;
         int lt = tile - prefix[mj];
         if (lt < I.ntile_face[0]) {
-            const int f = lt * FACE_TILE + (int)threadIdx.x;
+            const int f = lt * TILE + (int)threadIdx.x;
             if (f < I.nface[0]) face_one<R, D, 0>(I, f);
             continue;
         }
         lt -= I.ntile_face[0];
         if (D == 2 || lt < I.ntile_face[1]) {
-            const int f = lt * FACE_TILE + (int)threadIdx.x;
+            const int f = lt * TILE + (int)threadIdx.x;
             if (f < I.nface[1]) face_one<R, D, 1>(I, f);
             continue;
         }
         lt -= I.ntile_face[1];
-        const int f = lt * FACE_TILE + (int)threadIdx.x;
+        const int f = lt * TILE + (int)threadIdx.x;
         if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1)>(I, f);
     }
 }
@@ -516,14 +521,23 @@ __global__ __launch_bounds__(CELL_TILE) void k_finish(const void* __restrict__ t
             }
             next_step(I, st, rate, st->t);
             if (st->err) st->active = 0;
+            if (I.max_steps > 0 && st->steps >= I.max_steps) st->active = 0;
         }
         __syncthreads();
     }
 }
 
-template __global__ void k_face<double, 2>(const void*, int, int);
-template __global__ void k_face<float, 2>(const void*, int, int);
-template __global__ void k_face<double, 3>(const void*, int, int);
-template __global__ void k_face<float, 3>(const void*, int, int);
+template __global__ void k_face<double, 2, 64>(const void*, int, int);
+template __global__ void k_face<double, 2, 128>(const void*, int, int);
+template __global__ void k_face<double, 2, 256>(const void*, int, int);
+template __global__ void k_face<double, 3, 64>(const void*, int, int);
+template __global__ void k_face<double, 3, 128>(const void*, int, int);
+template __global__ void k_face<double, 3, 256>(const void*, int, int);
+template __global__ void k_face<float, 2, 64>(const void*, int, int);
+template __global__ void k_face<float, 2, 128>(const void*, int, int);
+template __global__ void k_face<float, 2, 256>(const void*, int, int);
+template __global__ void k_face<float, 3, 64>(const void*, int, int);
+template __global__ void k_face<float, 3, 128>(const void*, int, int);
+template __global__ void k_face<float, 3, 256>(const void*, int, int);
 
 }  // namespace gks

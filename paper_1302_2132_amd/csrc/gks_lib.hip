@@ -62,6 +62,7 @@ bool config_ok(const gks_config* c, std::string* why)
         !(c->t_end >= 0.0))
         return fail("gas or time-step parameter out of range");
     if (c->precision != GKS_FP64 && c->precision != GKS_FP32_FLUX) return fail("unknown precision");
+    if (c->max_steps < 0) return fail("max_steps must be >= 0");
     return true;
 }
 
@@ -182,6 +183,7 @@ struct gks_batch_ctx {
     hipStream_t stream;
     void* tab;
     int grid[6];
+    int face_tile[NCLS];
     bool captured;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -222,8 +224,10 @@ static int device_cus()
     return cus;
 }
 
-// Fill a host image of a tile table for `members` (capacity cap).
-static void build_table(std::vector<char>& img, int cap, const std::vector<const Inst*>& members)
+// Fill a host image of a tile table for `members` (capacity cap), with face tiles of
+// face_tile[cls] faces for each face-kernel class.
+static void build_table(std::vector<char>& img, int cap, const std::vector<const Inst*>& members,
+                        const int* face_tile)
 {
     img.assign(TabView::bytes(cap), 0);
     TabView tv(img.data(), cap);
@@ -232,8 +236,15 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
     tv.cell_prefix[0] = 0;
     for (int c = 0; c < NCLS; ++c) tv.cls_prefix[c * (cap + 1)] = 0;
     for (size_t i = 0; i < members.size(); ++i) {
-        const Inst& I = *members[i];
-        tv.inst[i] = I;
+        tv.inst[i] = *members[i];
+        Inst& I = tv.inst[i];
+        const int ft = face_tile[I.cls];
+        I.face_tile = ft;
+        I.ntile_face_all = 0;
+        for (int d = 0; d < 3; ++d) {
+            I.ntile_face[d] = d < I.dim ? (I.nface[d] + ft - 1) / ft : 0;
+            I.ntile_face_all += I.ntile_face[d];
+        }
         cells += I.ntile_cell;
         tv.cell_prefix[i + 1] = cells;
         const int c = I.cls;
@@ -247,15 +258,23 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
 }
 
 typedef void (*face_kernel_t)(const void*, int, int);
-static face_kernel_t face_kernel(int cls)
+template <int T>
+static face_kernel_t face_kernel_t_(int cls)
 {
     switch (cls) {
-    case 0: return k_face<double, 2>;
-    case 1: return k_face<float, 2>;
-    case 2: return k_face<double, 3>;
-    default: return k_face<float, 3>;
+    case 0: return k_face<double, 2, T>;
+    case 1: return k_face<float, 2, T>;
+    case 2: return k_face<double, 3, T>;
+    default: return k_face<float, 3, T>;
     }
 }
+static face_kernel_t face_kernel(int cls, int tile)
+{
+    if (tile == 128) return face_kernel_t_<128>(cls);
+    if (tile == 256) return face_kernel_t_<256>(cls);
+    return face_kernel_t_<64>(cls);
+}
+static const int kDefaultFaceTiles[NCLS] = {FACE_TILE, FACE_TILE, FACE_TILE, FACE_TILE};
 
 extern "C" {
 
@@ -352,6 +371,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.inv_b = 1.0 / I.b;
     I.inv_cmu = 1.0 / cfg->c_mu;
     I.pfix = 1.0 / cfg->prandtl - 1.0;
+    I.max_steps = cfg->max_steps;
     I.W[0] = (double*)(ws + L.W[0]);
     I.W[1] = (double*)(ws + L.W[1]);
     I.k = (const double*)(ws + L.k);
@@ -360,6 +380,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.part = (double*)(ws + L.part);
     I.st = (State*)(ws + L.st);
     I.ntile_cell = L.ntile_cell;
+    I.face_tile = FACE_TILE;
     I.ntile_face_all = L.ntile_face[0] + L.ntile_face[1] + L.ntile_face[2];
 
     HIP_TRY(h, hipMemcpyAsync(I.W[0], W, cellb * nv, hipMemcpyHostToDevice, s));
@@ -400,7 +421,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     h->tab = ws + L.tab;
     std::vector<char> img;
     std::vector<const Inst*> mem{&I};
-    build_table(img, 1, mem);
+    build_table(img, 1, mem, kDefaultFaceTiles);
     HIP_TRY(h, hipMemcpyAsync(h->tab, img.data(), img.size(), hipMemcpyHostToDevice, s));
     h->grid_cell = L.ntile_cell;
     h->grid_face = I.ntile_face_all;
@@ -433,7 +454,7 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
 {
     hipStream_t s = h->stream;
     const void* tab = h->tab;
-    face_kernel_t fk = face_kernel(h->cls);
+    face_kernel_t fk = face_kernel(h->cls, FACE_TILE);
     for (int i = 0; i < nsteps; ++i) {
         hipEvent_t ev[4];
         if (h->timing) {
@@ -481,12 +502,14 @@ static gks_status read_state(gks_ctx* h, State* st)
     return GKS_OK;
 }
 
-gks_status gks_residual(gks_handle h, double* res, double* dt_last, double* t, int64_t* steps_done)
+gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt_last, double* t,
+                        int64_t* steps_done)
 {
     if (!h) return fail_h(nullptr, GKS_ERR_ARG, "NULL handle");
     State st;
     gks_status r = read_state(h, &st);
     if (res) for (int m = 0; m < h->nv; ++m) res[m] = st.res[m];
+    if (res_first) for (int m = 0; m < h->nv; ++m) res_first[m] = st.res_first[m];
     if (dt_last) *dt_last = st.dt_last;
     if (t) *t = st.t;
     if (steps_done) *steps_done = st.steps;
@@ -613,7 +636,7 @@ static gks_status batch_upload(gks_batch b)
         mem.push_back(&h->inst);
         present |= 1 << h->cls;
     }
-    build_table(b->host_tab, b->cap, mem);
+    build_table(b->host_tab, b->cap, mem, b->face_tile);
     if (hipMemcpyAsync(b->tab, b->host_tab.data(), b->host_tab.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
         b->err = "table upload failed";
@@ -649,6 +672,7 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
     b->grid[0] = cus * 8;        // strain: 256-thread workgroups
     b->grid[5] = cus * 8;        // update
     for (int c = 1; c <= 4; ++c) b->grid[c] = cus * 16;   // face: one-wave workgroups
+    for (int c = 0; c < NCLS; ++c) b->face_tile[c] = FACE_TILE;
     gks_status r = batch_upload(b);
     if (r != GKS_OK) { delete b; return r; }
     *out = b;
@@ -664,14 +688,26 @@ gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t coun
     return batch_upload(b);
 }
 
+// Grid of a launch kind: the persistent size set by gks_batch_set_launch, or (0) one
+// workgroup per tile of the current table.  The kernels walk the table with a grid-stride
+// loop, so any grid covers any membership (a captured graph keeps its grid).
+static int batch_grid(gks_batch b, int kind)
+{
+    if (b->grid[kind] > 0) return b->grid[kind];
+    TabView tv(b->host_tab.data(), b->cap);
+    const int tiles = (kind == 0 || kind == 5) ? tv.hdr->total_cell : tv.hdr->total_face[kind - 1];
+    return tiles > 0 ? tiles : 1;
+}
+
 static void batch_launch(gks_batch b, int present)
 {
     const void* tab = b->tab;
-    hipLaunchKernelGGL(k_strain, dim3(b->grid[0]), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0);
+    hipLaunchKernelGGL(k_strain, dim3(batch_grid(b, 0)), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0);
     for (int c = 0; c < NCLS; ++c)
         if (present & (1 << c))
-            hipLaunchKernelGGL(face_kernel(c), dim3(b->grid[1 + c]), dim3(FACE_TILE), 0, b->stream, tab, b->cap, c);
-    hipLaunchKernelGGL(k_update, dim3(b->grid[5]), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
+            hipLaunchKernelGGL(face_kernel(c, b->face_tile[c]), dim3(batch_grid(b, 1 + c)), dim3(b->face_tile[c]), 0,
+                               b->stream, tab, b->cap, c);
+    hipLaunchKernelGGL(k_update, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
     hipLaunchKernelGGL(k_finish, dim3(b->cap), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0);
 }
 
@@ -710,20 +746,27 @@ gks_status gks_batch_capture(gks_batch b)
     return GKS_OK;
 }
 
-gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid)
+gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile)
 {
     if (!b || kind < 0 || kind > 5 || grid < 0) return fail_h(nullptr, GKS_ERR_ARG, "bad launch shape");
-    if (grid == 0) grid = 1 << 20;   // effectively one workgroup per tile for any batch we admit
+    const bool face = kind >= 1 && kind <= 4;
+    if (face ? (tile != 64 && tile != 128 && tile != 256) : (tile != 0 && tile != CELL_TILE))
+        return fail_h(nullptr, GKS_ERR_ARG, "unsupported tile size");
     b->grid[kind] = grid;
     if (b->captured) {
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);
         b->captured = false;
     }
+    if (face && b->face_tile[kind - 1] != tile) {
+        b->face_tile[kind - 1] = tile;
+        return batch_upload(b);   // tile counts of that class change
+    }
     return GKS_OK;
 }
 
-gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* t, int32_t* state)
+gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* res_first, double* t,
+                            int32_t* state)
 {
     if (!b) return fail_h(nullptr, GKS_ERR_ARG, "NULL batch");
     if (hipStreamSynchronize(b->stream) != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "sync failed");
@@ -734,6 +777,7 @@ gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* t,
     for (size_t i = 0; i < sts.size(); ++i) {
         if (steps) steps[i] = sts[i].steps;
         if (res) for (int m = 0; m < 5; ++m) res[5 * i + m] = sts[i].res[m];
+        if (res_first) for (int m = 0; m < 5; ++m) res_first[5 * i + m] = sts[i].res_first[m];
         if (t) t[i] = sts[i].t;
         if (state) state[i] = sts[i].err ? 2 : (sts[i].active ? 0 : 1);
         if (sts[i].err) b->members[i]->broken = true;

@@ -45,6 +45,7 @@ class gks_config(C.Structure):
         ("gamma", C.c_double), ("prandtl", C.c_double), ("mu", C.c_double), ("c_a", C.c_double),
         ("c_mu", C.c_double), ("cfl", C.c_double), ("t_end", C.c_double),
         ("precision", C.c_int32),
+        ("max_steps", C.c_int64),
     ]
 
 
@@ -64,7 +65,7 @@ def lib():
         L.gks_workspace_bytes.argtypes = [C.POINTER(gks_config), sz]
         L.gks_init.argtypes = [C.POINTER(gks_config), vp, C.c_size_t, vp, dp, dp, dp, C.POINTER(vp)]
         L.gks_step.argtypes = [vp, i32]
-        L.gks_residual.argtypes = [vp, dp, dp, dp, C.POINTER(i64)]
+        L.gks_residual.argtypes = [vp, dp, dp, dp, dp, C.POINTER(i64)]
         L.gks_fields.argtypes = [vp, i32, dp]
         L.gks_state_device_ptr.argtypes = [vp, C.POINTER(vp)]
         L.gks_destroy.argtypes = [vp]
@@ -78,8 +79,8 @@ def lib():
         L.gks_batch_set_members.argtypes = [vp, C.POINTER(vp), i32]
         L.gks_batch_step.argtypes = [vp, i32]
         L.gks_batch_capture.argtypes = [vp]
-        L.gks_batch_set_launch.argtypes = [vp, i32, i32]
-        L.gks_batch_status.argtypes = [vp, C.POINTER(i64), dp, dp, C.POINTER(i32)]
+        L.gks_batch_set_launch.argtypes = [vp, i32, i32, i32]
+        L.gks_batch_status.argtypes = [vp, C.POINTER(i64), dp, dp, dp, C.POINTER(i32)]
         L.gks_batch_destroy.argtypes = [vp]
         for nm in EXPORTED:
             if nm != "gks_last_error":
@@ -121,6 +122,7 @@ class _Cfg:
         c.gamma, c.prandtl, c.mu, c.c_a = case.gamma, case.prandtl, case.mu, case.c_a
         c.c_mu, c.cfl, c.t_end = case.c_mu, case.cfl, case.t_end
         c.precision = PRECISION[case.precision]
+        c.max_steps = int(getattr(case, "max_steps", 0) or 0)
         self.c = c
 
 
@@ -152,12 +154,12 @@ def gks_step(h, nsteps):
 
 
 def gks_residual(h, nv):
-    res = np.zeros(nv)
+    res, res1 = np.zeros(nv), np.zeros(nv)
     dt, t = C.c_double(0), C.c_double(0)
     steps = C.c_int64(0)
-    st = lib().gks_residual(h, _dp(res), C.byref(dt), C.byref(t), C.byref(steps))
+    st = lib().gks_residual(h, _dp(res), _dp(res1), C.byref(dt), C.byref(t), C.byref(steps))
     _check(st, h)
-    return {"res": res, "dt": dt.value, "t": t.value, "steps": int(steps.value)}
+    return {"res": res, "res_first": res1, "dt": dt.value, "t": t.value, "steps": int(steps.value)}
 
 
 def gks_fields(h, which, shape):
@@ -229,18 +231,20 @@ def gks_batch_capture(b):
     _check(lib().gks_batch_capture(b))
 
 
-def gks_batch_set_launch(b, kind, grid):
-    _check(lib().gks_batch_set_launch(b, int(kind), int(grid)))
+def gks_batch_set_launch(b, kind, grid, tile=0):
+    _check(lib().gks_batch_set_launch(b, int(kind), int(grid), int(tile)))
 
 
 def gks_batch_status(b, count):
-    steps = np.zeros(count, dtype=np.int64)
+    steps = np.zeros(max(count, 1), dtype=np.int64)
     res = np.zeros(5 * max(count, 1))
+    res1 = np.zeros(5 * max(count, 1))
     t = np.zeros(max(count, 1))
     state = np.zeros(max(count, 1), dtype=np.int32)
-    _check(lib().gks_batch_status(b, steps.ctypes.data_as(C.POINTER(C.c_int64)), _dp(res), _dp(t),
+    _check(lib().gks_batch_status(b, steps.ctypes.data_as(C.POINTER(C.c_int64)), _dp(res), _dp(res1), _dp(t),
                                   state.ctypes.data_as(C.POINTER(C.c_int32))))
-    return {"steps": steps, "res": res[:5 * count].reshape(count, 5), "t": t[:count], "state": state[:count]}
+    return {"steps": steps[:count], "res": res[:5 * count].reshape(count, 5),
+            "res_first": res1[:5 * count].reshape(count, 5), "t": t[:count], "state": state[:count]}
 
 
 def gks_batch_destroy(b):
@@ -321,8 +325,8 @@ class Batch:
     def capture(self):
         gks_batch_capture(self.b)
 
-    def set_launch(self, kind, grid):
-        gks_batch_set_launch(self.b, kind, grid)
+    def set_launch(self, kind, grid, tile=0):
+        gks_batch_set_launch(self.b, kind, grid, tile)
 
     def step(self, n=1):
         gks_batch_step(self.b, n)

@@ -1,0 +1,184 @@
+"""Continuous-batching request loop for gas-kinetic solves on one GPU.
+
+Each request is a solve (a Case) that runs until its residual has fallen by `tol`
+relative to its first step (max over fields of res_m / res_first_m) or until
+`max_steps`.  The server keeps every admitted solve's state on the device and advances
+all of them together with the persistent batch kernels (one captured graph per step;
+admissions and retirements rewrite the batch table in place).  Requests are admitted in
+arrival order whenever a batch slot and enough HBM (the solve's workspace footprint)
+are free; new solves are initialised on a separate stream so that their set-up overlaps
+the running batch.  For comparison `run_fifo` serves the same trace one solve at a time
+with the plain per-solve loop.
+
+Latency of a request = completion time - arrival time (wall clock, arrivals replayed in
+real time from the trace).
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+
+
+def _converged(res, res_first, steps, tol, max_steps, nv):
+    if steps >= max_steps:
+        return True
+    r0 = np.asarray(res_first[:nv])
+    r = np.asarray(res[:nv])
+    mask = r0 > 0
+    if steps < 2 or not np.any(mask):
+        return False
+    return float(np.max(r[mask] / r0[mask])) <= tol
+
+
+def _summary(lat, cell_updates, makespan, n):
+    lat = np.asarray(lat)
+    return {
+        "requests": n,
+        "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+        "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+        "mean_latency_s": float(np.mean(lat)) if len(lat) else None,
+        "makespan_s": makespan,
+        "throughput_req_s": n / makespan if makespan > 0 else None,
+        "cell_updates_per_s": cell_updates / makespan if makespan > 0 else None,
+    }
+
+
+def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=20, keep_fields=False,
+                device="cuda:0"):
+    """Serve `requests` (dicts with id, arrival [s], max_steps, tol) with continuous
+    batching.  Returns (summary, per-request records)."""
+    import torch
+
+    from . import gks as G
+    torch.cuda.set_device(device)
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    run_stream = torch.cuda.Stream(device=device)
+    init_stream = torch.cuda.Stream(device=device)
+    pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
+    queue = collections.deque()
+    active = []          # (req, solver, bytes)
+    records = {}
+    used = 0
+    batch = None
+    batch_dirty = False
+    classes = set()
+    cell_updates = 0
+    t0 = time.perf_counter()
+
+    def now():
+        return time.perf_counter() - t0
+
+    while pending or queue or active:
+        t = now()
+        while pending and pending[0]["arrival"] <= t:
+            queue.append(pending.popleft())
+        admitted = False
+        while queue and len(active) < capacity:
+            req = queue[0]
+            case = make_case(req)
+            nbytes = G.gks_workspace_bytes(G.config_from_case(case))
+            if used + nbytes > hbm_budget and active:
+                break                                    # wait for memory to free up
+            queue.popleft()
+            with torch.cuda.stream(init_stream):
+                solver = G.Solver(case, device=device, stream=init_stream)
+            used += nbytes
+            active.append((req, solver, nbytes))
+            records[req["id"]] = {"id": req["id"], "arrival": req["arrival"], "admitted": now(),
+                                  "cells": case.ncells, "family": req.get("family"), "bytes": nbytes}
+            admitted = True
+        if admitted or (batch is not None and batch_dirty):
+            members = [s for _, s, _ in active]
+            new_classes = {(s.case.dim, s.case.precision) for s in members}
+            if batch is None:
+                batch = G.Batch(members, capacity=capacity, device=device, stream=run_stream)
+                for kind in (1, 2, 3, 4):
+                    batch.set_launch(kind, 16 * cus, 64)
+                batch.set_launch(0, 8 * cus, 0)
+                batch.set_launch(5, 8 * cus, 0)
+                batch.capture()
+                classes = new_classes
+            else:
+                batch.set_members(members)
+                if not new_classes <= classes:           # a new kernel class joins: recapture
+                    classes = classes | new_classes
+                    batch.capture()
+            batch_dirty = False
+        if not active:
+            if pending:
+                time.sleep(max(0.0, min(0.05, pending[0]["arrival"] - now())))
+            continue
+        batch.step(quantum)
+        st = batch.status()                               # synchronises the run stream
+        retire = []
+        for i, (req, solver, nbytes) in enumerate(active):
+            steps = int(st["steps"][i])
+            state = int(st["state"][i])
+            done = state != 0 or _converged(st["res"][i], st["res_first"][i], steps, req["tol"],
+                                            req["max_steps"], solver.case.nvar)
+            if done:
+                retire.append(i)
+        if retire:
+            tnow = now()
+            keep = []
+            for i, item in enumerate(active):
+                req, solver, nbytes = item
+                if i in retire:
+                    rec = records[req["id"]]
+                    rec["done"] = tnow
+                    rec["latency"] = tnow - req["arrival"]
+                    rec["steps"] = int(st["steps"][i])
+                    rec["state"] = int(st["state"][i])
+                    cell_updates += rec["steps"] * rec["cells"]
+                    if keep_fields:
+                        rec["fields"] = solver.fields("cons")
+                    solver.close()
+                    used -= nbytes
+                else:
+                    keep.append(item)
+            active = keep
+            batch_dirty = True
+        else:
+            batch_dirty = False
+    makespan = now()
+    if batch is not None:
+        batch.close()
+    lat = [r["latency"] for r in records.values()]
+    return _summary(lat, cell_updates, makespan, len(records)), records
+
+
+def run_fifo(requests, make_case, quantum=20, keep_fields=False, device="cuda:0"):
+    """The same trace served one solve at a time with the plain per-solve loop."""
+    import torch
+
+    from . import gks as G
+    torch.cuda.set_device(device)
+    reqs = sorted(requests, key=lambda r: r["arrival"])
+    records = {}
+    cell_updates = 0
+    t0 = time.perf_counter()
+    for req in reqs:
+        wait = req["arrival"] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        case = make_case(req)
+        s = G.Solver(case, device=device)
+        while True:
+            s.step(quantum)
+            r = s.residual()
+            steps = r["steps"]
+            if _converged(r["res"], r["res_first"], steps, req["tol"], req["max_steps"], case.nvar):
+                break
+        tnow = time.perf_counter() - t0
+        rec = {"id": req["id"], "arrival": req["arrival"], "done": tnow, "latency": tnow - req["arrival"],
+               "steps": steps, "cells": case.ncells, "family": req.get("family")}
+        if keep_fields:
+            rec["fields"] = s.fields("cons")
+        cell_updates += steps * case.ncells
+        s.close()
+        records[req["id"]] = rec
+    makespan = time.perf_counter() - t0
+    lat = [r["latency"] for r in records.values()]
+    return _summary(lat, cell_updates, makespan, len(records)), records

@@ -77,3 +77,44 @@ def test_batch_membership_change_keeps_graph():
     b.close()
     for s in (sa, sb, sc):
         s.close()
+
+
+def test_launch_shapes_do_not_change_results():
+    """Every tile size and persistent grid gives the same fields, bitwise."""
+    from paper_1302_2132_amd import Batch, Solver
+    cases = _cases()[:4]
+    ref = [_alone(c, 12) for c in cases]
+    solvers = [Solver(c) for c in cases]
+    b = Batch(solvers, capacity=4)
+    shapes = [(64, 0), (128, 512), (256, 0), (64, 4096)]
+    for i, (tile, grid) in enumerate(shapes):
+        for kind in (1, 2, 3, 4):
+            b.set_launch(kind, grid, tile)
+        b.set_launch(0, grid, 0)
+        b.set_launch(5, grid, 0)
+        b.step(3)
+    for s, r in zip(solvers, ref):
+        assert np.array_equal(s.fields("cons"), r[0])
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_autotuner_steps_are_real_steps():
+    from paper_1302_2132_amd import Batch, Solver
+    from paper_1302_2132_amd.autotune import autotune
+    cases = [C.mixing_layer(48, seed=5, precision="fp32_flux"), C.sbli(40, 20, precision="fp32_flux")]
+    solvers = [Solver(c) for c in cases]
+    b = Batch(solvers, capacity=2)
+    shape, steps, _ = autotune(b, steps_per_trial=1, use_cache=False)
+    assert steps > 0
+    b.capture()
+    b.step(5)
+    st = b.status()
+    assert np.all(st["steps"] == steps + 5)
+    for c, s in zip(cases, solvers):
+        W, r = _alone(c, steps + 5)
+        assert np.array_equal(s.fields("cons"), W)
+    b.close()
+    for s in solvers:
+        s.close()
