@@ -44,14 +44,38 @@ def _leg(case, steps, warmup):
     return {"seconds": t1 - t0, "kernels": kt, "res": r, "W": W}
 
 
+KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_lib.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_face_sbli_1024x512_hbm_traffic.md")
+
+
+def _profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when the kernel sources have changed since those counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1302_2132_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    try:
+        text = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text if ": " in line and not line.startswith(("|", "#")))
+    if vals.get("kernel_sources_sha", "").strip() != h.hexdigest()[:16]:
+        return None
+    v = vals.get(f"traffic_bytes_per_launch {kernel}")
+    return float(v) if v else None
+
+
 def _roofline(case, leg, steps, flops_face, peak):
     n = case.n
     faces = (n[0] + 1) * n[1] + n[0] * (n[1] + 1) if case.dim == 2 else \
         3 * (n[0] + 1) * n[1] * n[2]
     face_s = leg["kernels"]["face_ms"] / 1e3 / steps
     achieved = flops_face * faces / face_s / 1e12
+    kernel = "k_face<float,2,64>" if case.precision == "fp32_flux" else "k_face<double,2,64>"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4), "traffic": _profiled_traffic(kernel),
             "kernel": "k_face", "flops_per_face": flops_face, "faces_per_launch": faces,
             "avg_launch_us": round(face_s * 1e6, 2)}
 
@@ -123,8 +147,8 @@ def _serve_leg(full=False):
         reqs = C.serve_trace(256, seed=4, rate=20.0)
         desc = "256 requests, 20 req/s, 2D 128^2..1024^2 (SBLI N x N/2), 3D 64^3..128^3, tol 1e-6 or 5000 steps"
     else:
-        reqs = C.serve_trace(24, seed=4, rate=20.0, n2d=(128, 384), n3d=(32, 64), max_steps=300)
-        desc = "24 requests, 20 req/s, 2D 128^2..384^2 (SBLI N x N/2), 3D 32^3..64^3, tol 1e-6 or 300 steps"
+        reqs = C.serve_trace(32, seed=4, rate=20.0, n2d=(128, 384), n3d=(32, 64), max_steps=1500)
+        desc = "32 requests, 20 req/s, 2D 128^2..384^2 (SBLI N x N/2), 3D 32^3..64^3, tol 1e-6 or 1500 steps"
     batched, _ = run_batched(reqs, C.request_case, quantum=20)
     fifo, _ = run_fifo(reqs, C.request_case, quantum=20)
     return {"trace": desc + " (seed 4)", "batched": batched, "fifo_loop": fifo}
