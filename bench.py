@@ -70,7 +70,7 @@ def _profiled_traffic(kernel):
 def _roofline(case, leg, steps, flops_face, peak):
     n = case.n
     faces = (n[0] + 1) * n[1] + n[0] * (n[1] + 1) if case.dim == 2 else \
-        3 * (n[0] + 1) * n[1] * n[2]
+        (n[0] + 1) * n[1] * n[2] + n[0] * (n[1] + 1) * n[2] + n[0] * n[1] * (n[2] + 1)
     face_s = leg["kernels"]["face_ms"] / 1e3 / steps
     achieved = flops_face * faces / face_s / 1e12
     kernel = "k_face<float,2,64>" if case.precision == "fp32_flux" else "k_face<double,2,64>"
@@ -78,6 +78,37 @@ def _roofline(case, leg, steps, flops_face, peak):
             "frac": round(achieved / peak, 4), "traffic": _profiled_traffic(kernel),
             "kernel": "k_face", "flops_per_face": flops_face, "faces_per_launch": faces,
             "avg_launch_us": round(face_s * 1e6, 2)}
+
+
+def _iso_leg(steps=20, warmup=3):
+    """3D periodic isotropic box 256^3 (Ma_t 0.5), FP32-flux (the configuration's form) and
+    FP64, with the FP32-flux error against FP64 after the same steps."""
+    import numpy as np
+
+    from inputs import cases as C
+    from paper_1302_2132_amd import gks_face_flops
+    out = {"workload": "isotropic_256^3: 3D periodic decaying box, k0=4 spectrum, Ma_t 0.5, CFL 0.5",
+           "cells": 256 ** 3}
+    legs = {}
+    for prec in ("fp32_flux", "fp64"):
+        c = C.isotropic_box(256, precision=prec)
+        leg = _leg(c, steps, warmup)
+        legs[prec] = leg
+        out[prec] = {"value": c.ncells * steps / leg["seconds"], "unit": "cell-updates/s",
+                     "ms_per_step": leg["seconds"] * 1e3 / steps,
+                     "roofline": _roofline(c, leg, steps, gks_face_flops(3, prec), FP64_PEAK_TFLOPS),
+                     "kernel_ms_per_step": {k: round(v / steps, 4) for k, v in leg["kernels"].items()
+                                            if k != "steps"}}
+        out[prec]["roofline"]["traffic"] = None
+    W32, W64 = legs["fp32_flux"]["W"], legs["fp64"]["W"]
+    mom = np.sqrt(sum(W64[1 + d] ** 2 for d in range(3)))
+    err = []
+    for m in range(5):
+        scale = np.max(mom) if 1 <= m <= 3 else np.max(np.abs(W64[m]))
+        err.append(float(np.max(np.abs(W32[m] - W64[m])) / scale))
+    out["fp32_flux"]["max_rel_err_vs_fp64_per_field"] = err
+    out["fp32_flux"]["after_steps"] = steps + warmup
+    return out
 
 
 def _batch_leg(steps=200, count=64, check=8):
@@ -184,6 +215,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D isotropic-box leg")
     ap.add_argument("--serve-full", action="store_true", help="served leg on the full 256-request trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), to calibrate "
@@ -244,6 +276,8 @@ def main():
             "roofline": _roofline(c32, leg32, K, flops2d, FP32_PEAK_TFLOPS),
             "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg32["kernels"].items() if k != "steps"},
         }
+    if not args.no_3d:
+        out["isotropic_3d"] = _iso_leg()
     if not args.no_batch:
         out["batched"] = _batch_leg()
     if not args.no_serve:

@@ -59,6 +59,11 @@ def lib():
         if not os.path.exists(lib_path):
             raise RuntimeError(f"libgks.so not found at {lib_path}: build it with "
                                "`python -m paper_1302_2132_amd.build` (hipcc, gfx950)")
+        # Load torch's HIP runtime first: libgks.so then binds to the same runtime (its
+        # libamdhip64.so.7 dependency matches the already loaded soname).  Loaded the other
+        # way round, torch would bring a second runtime into the process and device
+        # pointers and streams would not be shared between the two.
+        import torch  # noqa: F401
         L = C.CDLL(lib_path)
         vp, dp, i32, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64
         sz = C.POINTER(C.c_size_t)

@@ -48,7 +48,12 @@ def _summary(lat, cell_updates, makespan, n):
 def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=20, keep_fields=False,
                 device="cuda:0"):
     """Serve `requests` (dicts with id, arrival [s], max_steps, tol) with continuous
-    batching.  Returns (summary, per-request records)."""
+    batching.  Returns (summary, per-request records).
+
+    Each iteration enqueues the next `quantum` steps of the running batch first, then does
+    the host work (building and initialising newly arrived solves on their own stream)
+    while those steps run, then synchronises, retires finished solves and admits the new
+    ones by rewriting the batch table in place."""
     import torch
 
     from . import gks as G
@@ -58,11 +63,10 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
     init_stream = torch.cuda.Stream(device=device)
     pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
     queue = collections.deque()
-    active = []          # (req, solver, bytes)
+    active = []          # (req, solver, bytes) being stepped by the batch
     records = {}
     used = 0
     batch = None
-    batch_dirty = False
     classes = set()
     cell_updates = 0
     t0 = time.perf_counter()
@@ -74,22 +78,45 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
         t = now()
         while pending and pending[0]["arrival"] <= t:
             queue.append(pending.popleft())
-        admitted = False
-        while queue and len(active) < capacity:
+        if active:
+            batch.step(quantum)                          # GPU works while the host admits
+        staged = []
+        while queue and len(active) + len(staged) < capacity:
             req = queue[0]
             case = make_case(req)
             nbytes = G.gks_workspace_bytes(G.config_from_case(case))
-            if used + nbytes > hbm_budget and active:
+            if used + nbytes > hbm_budget and (active or staged):
                 break                                    # wait for memory to free up
             queue.popleft()
             with torch.cuda.stream(init_stream):
                 solver = G.Solver(case, device=device, stream=init_stream)
             used += nbytes
-            active.append((req, solver, nbytes))
+            staged.append((req, solver, nbytes))
             records[req["id"]] = {"id": req["id"], "arrival": req["arrival"], "admitted": now(),
                                   "cells": case.ncells, "family": req.get("family"), "bytes": nbytes}
-            admitted = True
-        if admitted or (batch is not None and batch_dirty):
+        retired = False
+        if active:
+            st = batch.status()                          # synchronises the run stream
+            keep = []
+            tnow = now()
+            for i, item in enumerate(active):
+                req, solver, nbytes = item
+                steps, state = int(st["steps"][i]), int(st["state"][i])
+                if state != 0 or _converged(st["res"][i], st["res_first"][i], steps, req["tol"],
+                                            req["max_steps"], solver.case.nvar):
+                    rec = records[req["id"]]
+                    rec.update(done=tnow, latency=tnow - req["arrival"], steps=steps, state=state)
+                    cell_updates += steps * rec["cells"]
+                    if keep_fields:
+                        rec["fields"] = solver.fields("cons")
+                    solver.close()
+                    used -= nbytes
+                    retired = True
+                else:
+                    keep.append(item)
+            active = keep
+        if staged or retired:
+            active = active + staged
             members = [s for _, s, _ in active]
             new_classes = {(s.case.dim, s.case.precision) for s in members}
             if batch is None:
@@ -105,43 +132,8 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
                 if not new_classes <= classes:           # a new kernel class joins: recapture
                     classes = classes | new_classes
                     batch.capture()
-            batch_dirty = False
-        if not active:
-            if pending:
-                time.sleep(max(0.0, min(0.05, pending[0]["arrival"] - now())))
-            continue
-        batch.step(quantum)
-        st = batch.status()                               # synchronises the run stream
-        retire = []
-        for i, (req, solver, nbytes) in enumerate(active):
-            steps = int(st["steps"][i])
-            state = int(st["state"][i])
-            done = state != 0 or _converged(st["res"][i], st["res_first"][i], steps, req["tol"],
-                                            req["max_steps"], solver.case.nvar)
-            if done:
-                retire.append(i)
-        if retire:
-            tnow = now()
-            keep = []
-            for i, item in enumerate(active):
-                req, solver, nbytes = item
-                if i in retire:
-                    rec = records[req["id"]]
-                    rec["done"] = tnow
-                    rec["latency"] = tnow - req["arrival"]
-                    rec["steps"] = int(st["steps"][i])
-                    rec["state"] = int(st["state"][i])
-                    cell_updates += rec["steps"] * rec["cells"]
-                    if keep_fields:
-                        rec["fields"] = solver.fields("cons")
-                    solver.close()
-                    used -= nbytes
-                else:
-                    keep.append(item)
-            active = keep
-            batch_dirty = True
-        else:
-            batch_dirty = False
+        if not active and pending and not queue:
+            time.sleep(max(0.0, min(0.05, pending[0]["arrival"] - now())))
     makespan = now()
     if batch is not None:
         batch.close()

@@ -70,3 +70,16 @@ def test_face_flop_count():
     import paper_1302_2132_amd as P
     f2, f3 = P.gks_face_flops(2), P.gks_face_flops(3)
     assert 500 < f2 < f3 < 5000
+
+
+def test_binding_loads_torch_runtime_first():
+    """After lib() and a later `import torch` the process maps one HIP runtime (loading
+    libgks.so before torch used to map two, and the device was then invisible to one)."""
+    import subprocess
+    import sys
+    code = ("import paper_1302_2132_amd as P; P.lib(); import torch; "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-1000:]
+    paths = eval(r.stdout.strip().splitlines()[-1])
+    assert len(paths) == 1, paths
