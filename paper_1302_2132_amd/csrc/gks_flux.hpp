@@ -27,6 +27,8 @@
 #define GKS_HD __host__ __device__
 #endif
 
+#include "erfc_cheb.hpp"
+
 namespace gks {
 
 GKS_HD inline double g_sqrt(double x) { return sqrt(x); }
@@ -39,6 +41,40 @@ GKS_HD inline double g_abs(double x) { return fabs(x); }
 GKS_HD inline float g_abs(float x) { return fabsf(x); }
 
 template <typename R> GKS_HD inline R rconst(double v) { return R(v); }
+
+// erfc(ax) for ax >= 0, given e = exp(-ax^2) (which the half-line moments need anyway):
+// erfc(ax) = e g(ax) / (1 + 2 ax), with g(x) = (1 + 2x) exp(x^2) erfc(x) summed from its
+// Chebyshev series in y = (ax - K)/(ax + K) by Clenshaw's recurrence (coefficients of
+// erfc_cheb.hpp).  One division serves both the map and 1/(1 + 2 ax).
+template <typename R> struct ErfcSeries;
+template <> struct ErfcSeries<double> {
+    static constexpr int N = ERFC_N64;
+    GKS_HD static constexpr double c(int k) { return ERFC_C64[k]; }
+};
+template <> struct ErfcSeries<float> {
+    static constexpr int N = ERFC_N32;
+    GKS_HD static constexpr float c(int k) { return ERFC_C32[k]; }
+};
+
+template <typename R>
+GKS_HD inline R erfc_e(R ax, R e)
+{
+    const R K = R(ERFC_K);
+    const R p = ax + K, q = R(1) + R(2) * ax;
+    const R r = R(1) / (p * q);
+    const R y = (ax - K) * q * r;          // (ax - K)/(ax + K)
+    const R iq = p * r;                    // 1/(1 + 2 ax)
+    const R y2 = y + y;
+    R b1 = R(0), b2 = R(0);
+#pragma unroll
+    for (int k = ErfcSeries<R>::N - 1; k >= 1; --k) {
+        const R b0 = y2 * b1 - b2 + R(ErfcSeries<R>::c(k));
+        b2 = b1;
+        b1 = b0;
+    }
+    const R g = y * b1 - b2 + R(ErfcSeries<R>::c(0));
+    return e * g * iq;
+}
 
 // Maxwellian in the face-local frame together with the derived quantities every moment
 // needs.  h = 1/(2 lambda) is the variance of each velocity component; bt = b - 1 is the
@@ -281,18 +317,26 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
 
     // --- half-line u-moments: left over u>0, right over u<0.  Only <u^0>, <u^1> are
     //     kept; higher ones are regenerated by the recurrence where they are used. ----
+    //     <u^0>_{>0} = erfc(-sqrt(lambda) U)/2, <u^0>_{<0} = erfc(sqrt(lambda) U)/2; the
+    //     exp(-lambda U^2) of the first moment also scales the erfc evaluation.
     R ml01[2], mr01[2];
     {
         const R isq = g_sqrt(R(2) * gl.h);            // 1/sqrt(lambda)
         const R U = gl.U[0];
-        ml01[0] = half * g_erfc(-gl.lam * isq * U);
-        ml01[1] = U * ml01[0] + g_exp(-gl.lam * U * U) * rsqpi_half * isq;
+        const R x = -gl.lam * isq * U;
+        const R e = g_exp(-gl.lam * U * U);
+        const R hs = half * erfc_e(g_abs(x), e);
+        ml01[0] = x >= R(0) ? hs : R(1) - hs;
+        ml01[1] = U * ml01[0] + e * rsqpi_half * isq;
     }
     {
         const R isq = g_sqrt(R(2) * gr.h);
         const R U = gr.U[0];
-        mr01[0] = half * g_erfc(gr.lam * isq * U);
-        mr01[1] = U * mr01[0] - g_exp(-gr.lam * U * U) * rsqpi_half * isq;
+        const R x = gr.lam * isq * U;
+        const R e = g_exp(-gr.lam * U * U);
+        const R hs = half * erfc_e(g_abs(x), e);
+        mr01[0] = x >= R(0) ? hs : R(1) - hs;
+        mr01[1] = U * mr01[0] - e * rsqpi_half * isq;
     }
 
     // --- interface equilibrium state W0 (Eq. intermediatestate) ---------------------
@@ -343,8 +387,9 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         R m0p[8], m0n[8];
         const R U = g0.U[0];
         const R isq = g_sqrt(R(2) * g0.h);             // 1/sqrt(lambda0)
-        const R small = half * g_erfc(g_abs(g0.lam * isq * U));   // one erfc serves both halves
-        const R tail = g_exp(-g0.lam * U * U) * rsqpi_half * isq;
+        const R e = g_exp(-g0.lam * U * U);
+        const R small = half * erfc_e(g_abs(g0.lam * isq * U), e);   // one erfc serves both halves
+        const R tail = e * rsqpi_half * isq;
         const bool upos = U >= R(0);
         m0p[0] = upos ? R(1) - small : small;
         m0n[0] = upos ? small : R(1) - small;
