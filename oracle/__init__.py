@@ -48,27 +48,41 @@ class _Case(C.Structure):
 _lib = None
 
 
+def use_library(path):
+    """Point the wrapper at another build of the oracle (tests that plant mistakes in a
+    copy of the source use this); None restores the default library."""
+    global _lib
+    _lib = None
+    if path is not None:
+        _bind(C.CDLL(path))
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build()
-        _lib = C.CDLL(LIB)
-        dp = C.POINTER(C.c_double)
-        _lib.og_run.argtypes = [C.c_void_p, dp, dp, dp, C.c_int, C.c_int, dp, dp, dp, C.POINTER(C.c_long)]
-        _lib.og_dt.argtypes = [C.c_void_p, dp, dp, dp, dp]
-        _lib.og_strain_field.argtypes = [C.c_void_p, dp, dp]
-        _lib.og_ghost_fill.argtypes = [C.c_void_p, dp, dp]
-        _lib.og_step_cells.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, C.POINTER(C.c_long),
-                                       C.c_long, C.c_int, dp]
-        _lib.og_face_flux.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_double,
-                                      C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp]
-        _lib.og_moments_u.argtypes = [C.c_double, C.c_double, dp]
-        _lib.og_kogan.argtypes = [C.c_double, C.c_double, dp]
-        _lib.og_moment_solve.argtypes = [C.c_int, C.c_double, dp, dp, dp]
-        _lib.og_tau_value.argtypes = [C.c_double] * 11
-        _lib.og_tau_value.restype = C.c_double
+        _bind(C.CDLL(LIB))
     return _lib
+
+
+def _bind(L):
+    global _lib
+    _lib = L
+    dp = C.POINTER(C.c_double)
+    _lib.og_run.argtypes = [C.c_void_p, dp, dp, dp, C.c_int, C.c_int, dp, dp, dp, C.POINTER(C.c_long)]
+    _lib.og_dt.argtypes = [C.c_void_p, dp, dp, dp, dp]
+    _lib.og_strain_field.argtypes = [C.c_void_p, dp, dp]
+    _lib.og_ghost_fill.argtypes = [C.c_void_p, dp, dp]
+    _lib.og_step_cells.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, C.POINTER(C.c_long),
+                                   C.c_long, C.c_int, dp]
+    _lib.og_face_flux.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_double,
+                                  C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp]
+    _lib.og_moments_u.argtypes = [C.c_double, C.c_double, dp]
+    _lib.og_kogan.argtypes = [C.c_double, C.c_double, dp]
+    _lib.og_moment_solve.argtypes = [C.c_int, C.c_double, dp, dp, dp]
+    _lib.og_tau_value.argtypes = [C.c_double] * 11
+    _lib.og_tau_value.restype = C.c_double
 
 
 def _dp(a):

@@ -1,0 +1,110 @@
+"""The pins catch plausible mistakes in the oracle.
+
+Each mutant below plants one mistake (a flipped sign, a wrong index or range, a dropped
+factor, a swapped operand) into a copy of the oracle source, on the CPU.  The copy is
+compiled and the fast pins are run against it; every mutant must fail at least one pin.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_pins as P
+
+SRC = oracle.SRC
+
+MUTANTS = {
+    "half-line tail sign": ("M->u[R_POS][1] = U * M->u[R_POS][0] + tail;",
+                            "M->u[R_POS][1] = U * M->u[R_POS][0] - tail;"),
+    "moment recurrence factor": ("M->u[r][n + 1] = U * M->u[r][n] + n * h * M->u[r][n - 1];",
+                                 "M->u[r][n + 1] = U * M->u[r][n] + (n + 1) * h * M->u[r][n - 1];"),
+    "internal xi^4 moment": ("M->xi[2] = gas->K * (gas->K + 2.0) * h * h;", "M->xi[2] = gas->K * gas->K * h * h;"),
+    "interface state half lines swapped": (
+        "W0[m] = gl.rho * p_expect(&pm, &Ml, R_POS) + gr.rho * p_expect(&pm, &Mr, R_NEG);",
+        "W0[m] = gl.rho * p_expect(&pm, &Ml, R_NEG) + gr.rho * p_expect(&pm, &Mr, R_POS);"),
+    "compatibility sign": ("        r[m] = -p_expect(&prod, &Ml, R_ALL);\n    }\n    if ((st = og_solve_moment_system(gas, &Ml, r, A_l))) return st;",
+                           "        r[m] = p_expect(&prod, &Ml, R_ALL);\n    }\n    if ((st = og_solve_moment_system(gas, &Ml, r, A_l))) return st;"),
+    "time weight gam1": ("g1 = 2.0 * s - x * (1.0 + E);", "g1 = 2.0 * s - x * (1.0 - E);"),
+    "time weight c5 sign": ("k->c5 = -s / g0;", "k->c5 = s / g0;"),
+    "turbulent tau without strain": ("tau += (kf / wf) / ((p0 / rho0) * sqrt(1.0 + eta * eta));",
+                                     "tau += (kf / wf) / ((p0 / rho0) * sqrt(1.0 + eta));"),
+    "Prandtl factor": ("F[nv - 1] += (1.0 / gas->prandtl - 1.0) * q;", "F[nv - 1] += (gas->prandtl - 1.0) * q;"),
+    "heat flux frame": ("p_term(&lin1, -g0.U[0], 0, 0, 0, 0);", "p_term(&lin1, g0.U[0], 0, 0, 0, 0);"),
+    "minmod picks the larger": ("return (p > 0.0 ? 1.0 : -1.0) * fmin(fabs(p), fabs(q));",
+                                "return (p > 0.0 ? 1.0 : -1.0) * fmax(fabs(p), fabs(q));"),
+    "equilibrium slope distance": ("r[m] = (W0[m] - Wi[m]) / (g0.rho * dxl);", "r[m] = (W0[m] - Wi[m]) / (g0.rho * dxr);"),
+    "Abar time weight": ("ADD_TERM(g0.rho * kw.g[2], 0, R_ALL, p_lin(dim, Ab, &terms[nt].poly));",
+                         "ADD_TERM(g0.rho * kw.g[1], 0, R_ALL, p_lin(dim, Ab, &terms[nt].poly));"),
+    "wall mirrors normal momentum only": ("if (bc == OG_WALL && m >= 1 && m <= dim) v = -v;",
+                                          "if (bc == OG_WALL && m == 1) v = -v;"),
+    "update sign": ("acc -= (F[d][m * nf + hi] - F[d][m * nf + lo]) / gr->dx[d][idx[d] + 2];",
+                    "acc += (F[d][m * nf + hi] - F[d][m * nf + lo]) / gr->dx[d][idx[d] + 2];"),
+    "strain not symmetrised": ("double sab = 0.5 * (grad[a][b] + grad[b][a]);", "double sab = grad[a][b];"),
+    "viscous CFL term": ("r += 2.0 * nu * r2;", "r += nu * r2;"),
+    "periodic ghost face coordinates": ("gr->xfe[d][2 - m] = xf[0] - (xf[n] - xf[n - m]);",
+                                        "gr->xfe[d][2 - m] = xf[0] - (xf[m] - xf[0]);"),
+}
+
+
+def _sod_quick():
+    import exact_riemann as ER
+    from inputs import cases as C
+    case = C.sod_tube(100, ny=2, t_end=0.2)
+    r = oracle.run(case, 100000, nthreads=4)
+    x = 0.5 * (case.xf[0][1:] + case.xf[0][:-1])
+    ex = ER.sample((1, 0, 1), (0.125, 0, 0.1), x, 0.2)
+    assert float(np.mean(np.abs(r["W"][0, 0, 0] - ex[0]))) < 0.02
+
+
+PINS = [
+    lambda: P.test_p1_moments_vs_mpmath(0.7, 0.35),
+    lambda: P.test_kogan_weights_vs_time_quadrature(1.7),
+    lambda: P.test_kogan_weights_vs_time_quadrature(0.1),
+    lambda: P.test_p2_moment_solve(2),
+    lambda: P.test_p5_continuous_data_navier_stokes(2),
+    lambda: P.test_p5_prandtl_correction_heat_flux(2),
+    lambda: P.test_p6_euler_limit(2),
+    lambda: P.test_p7_collisionless_limit_kfvs(2),
+    lambda: P.test_p8_symmetries(2),
+    lambda: P.test_p11_turbulent_tau(),
+    lambda: P.test_ghost_fill_rules(),
+    lambda: P.test_cfl_dt_uniform(),
+    lambda: P.test_strain_rate_linear_field(),
+    lambda: P.test_p4_free_stream(2, None),
+    lambda: P.test_p10_conservation_periodic(),
+    lambda: P.test_p9_periodic_seam_invariance(),
+    lambda: P.test_coefficient_definitions_by_quadrature(2),
+    lambda: P.test_p16_flux_bruteforce(2, 1.0),
+    _sod_quick,
+]
+
+
+@pytest.fixture(scope="module")
+def source():
+    with open(SRC) as f:
+        return f.read()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, source, tmp_path):
+    old, new = MUTANTS[name]
+    assert source.count(old) == 1, f"mutation site not unique or missing: {name}"
+    src = tmp_path / "mutant.c"
+    src.write_text(source.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                           "-o", str(so), str(src), "-lm"])
+    oracle.use_library(str(so))
+    caught = None
+    try:
+        for i, pin in enumerate(PINS):
+            try:
+                pin()
+            except (AssertionError, oracle.OracleError, FloatingPointError, ValueError):
+                caught = i
+                break
+    finally:
+        oracle.use_library(None)
+    assert caught is not None, f"no pin caught the planted mistake: {name}"

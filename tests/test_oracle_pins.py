@@ -488,6 +488,29 @@ def test_p9_rotation_transpose():
     assert rel(bt, a) < 1e-13
 
 
+def test_p9_periodic_seam_invariance():
+    """A periodic axis has no special point: relabelling the cells of a stretched periodic
+    grid cyclically (moving the seam) gives the cyclically relabelled result."""
+    rng = np.random.default_rng(17)
+    n, k = 24, 7
+    w = rng.uniform(0.5, 2.0, size=n)
+    w /= w.sum()
+
+    def make(widths, roll):
+        c = C.mixing_layer(n, seed=4)
+        xf = np.concatenate([[0.0], np.cumsum(widths)])
+        c.xf = [xf, xf.copy()]
+        c.W = np.roll(np.roll(c.W, -roll, axis=3), -roll, axis=2).copy()
+        c.k = np.roll(np.roll(c.k, -roll, axis=2), -roll, axis=1).copy()
+        c.omega = np.roll(np.roll(c.omega, -roll, axis=2), -roll, axis=1).copy()
+        return c
+
+    a = oracle.run(make(w, 0), 4)["W"]
+    b = oracle.run(make(np.roll(w, -k), k), 4)["W"]
+    b = np.roll(np.roll(b, k, axis=3), k, axis=2)
+    assert rel(b, a) < 1e-12
+
+
 def test_p9_y_invariant_rows_identical():
     case = C.sod_tube(40, ny=4, t_end=0.0, steps=10)
     r = oracle.run(case, 10)
