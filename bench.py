@@ -44,7 +44,7 @@ def _leg(case, steps, warmup):
     return {"seconds": t1 - t0, "kernels": kt, "res": r, "W": W}
 
 
-KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_lib.hip")
+KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_lib.hip", "erfc_cheb.hpp")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_face_sbli_1024x512_hbm_traffic.md")
 
 
