@@ -165,12 +165,37 @@ GKS_HD inline void solve(const Mx<R, D>& g, const R* r, R b, R inv_b, R* a)
 //   gam0 = dt - tau(1-E), gam1 = 2tau^2(1-E) - tau dt(1+E), gam2 = dt^2/2 - tau dt + tau^2(1-E),
 //   gam3 = tau(1-E), gam4 = -(2tau^2(1-E) - tau dt E), gam5 = -tau^2(1-E),
 // and the ratios c1, c4, c5 = gam1, gam4, gam5 over tau*gam0 of the integrated compatibility
-// condition.  Below x = 1/2 the cancelling combinations come from their Taylor series.
+// condition.  Below x = 1/2 the cancelling combinations come from their power series.
 template <typename R>
 struct Kw {
     R g[6];
     R c1, c4, c5;
 };
+
+// Power series of the small-x weights with the leading powers factored out:
+//   x - (1 - E)        = x^2 P0(x),  P0 = sum_k (-1)^k x^k / (k+2)!
+//   2(1-E) - x(1+E)    = -x^3 P1(x), P1 = sum_k (-1)^k (k+1) x^k / (k+3)!
+//   x^2/2 - x + (1-E)  = x^3 P2(x),  P2 = sum_k (-1)^k x^k / (k+3)!
+// Only P2 is summed: P0 = 1/2 - x P2 (shift of the index), and P1 = P0 - 2 P2 because
+// (k+1)/(k+3)! = 1/(k+2)! - 2/(k+3)!.  For x < 1/2 neither step loses more than a factor
+// 3 to cancellation.  The coefficients (-1)^k/(k+3)! are formed at compile time (17! is
+// exact in double); the first dropped term is below 2^-60 (FP64, 15 terms) or 2^-27
+// (FP32, 8 terms) of P2.
+template <int N>
+struct KoganSeries {
+    double c[N];
+    constexpr KoganSeries() : c()
+    {
+        double f = 6.0;                                      // (k+3)!
+        for (int k = 0; k < N; ++k) {
+            c[k] = ((k & 1) ? -1.0 : 1.0) / f;
+            f *= double(k + 4);
+        }
+    }
+};
+template <typename R> struct KoganTerms { static constexpr int N = 15; };
+template <> struct KoganTerms<float> { static constexpr int N = 8; };
+constexpr KoganSeries<15> KOGAN_SERIES{};
 
 template <typename R>
 GKS_HD inline Kw<R> kogan(R tau, R dt)
@@ -185,20 +210,17 @@ GKS_HD inline Kw<R> kogan(R tau, R dt)
     const R x = dt / tau;
     R s, g0, g1, g2, g4;
     if (x < R(0.5)) {
-        // s = x - x^2/2! + x^3/3! ..., g0 = x - s, g1 = sum_{n>=3} (-1)^n (n-2) x^n/n!,
-        // g2 = sum_{n>=3} (-1)^{n+1} x^n/n!, g4 = x + g1.  Horner form, truncated where
-        // x^n/n! < 2^-60 for x < 1/2.
-        const int NT = sizeof(R) > 4 ? 17 : 10;
-        R ps = R(0), p0 = R(0), p1 = R(0), p2 = R(0);
-        for (int n = NT; n >= 1; --n) {
-            const R inv = R(1) / R(n);
-            const R sg = (n & 1) ? R(1) : R(-1);          // (-1)^{n+1}
-            ps = (ps + sg) * x * inv;
-            p0 = (p0 + (n >= 2 ? -sg : R(0))) * x * inv;
-            p1 = (p1 + (n >= 3 ? -sg * R(n - 2) : R(0))) * x * inv;
-            p2 = (p2 + (n >= 3 ? sg : R(0))) * x * inv;
-        }
-        s = ps; g0 = p0; g1 = p1; g2 = p2;
+        constexpr int N = KoganTerms<R>::N;
+        R p2 = R(KOGAN_SERIES.c[N - 1]);
+#pragma unroll
+        for (int j = N - 2; j >= 0; --j) p2 = p2 * x + R(KOGAN_SERIES.c[j]);
+        const R p0 = R(0.5) - x * p2;
+        const R p1 = p0 - R(2) * p2;
+        const R x2 = x * x, x3 = x2 * x;
+        g0 = x2 * p0;
+        g1 = -(x3 * p1);
+        g2 = x3 * p2;
+        s = x - g0;
         g4 = x + g1;
     } else {
         const R E = g_exp(-x);

@@ -1,17 +1,23 @@
 // gks_kernels.hpp -- gfx950 kernels of the turbulent gas-kinetic step.
 //
-// One step of every active solve in a tile table is three launches:
+// One step of every active solve in a tile table is four launches:
 //   k_strain  cell tiles: strain-rate magnitude of each cell from central differences
 //             of the cell velocities (ghost neighbours synthesised from the BCs);
 //   k_face    face tiles of one (dim, precision) class: minmod reconstruction along the
 //             face normal (four cells, ghosts synthesised), then the gas-kinetic flux of
 //             gks_flux.hpp, written once per face (structure of arrays per axis);
 //   k_update  cell tiles: conservative FP64 update, positivity check, residual partial
-//             sums and the CFL rate of the new state; the last workgroup of a solve
-//             finishes its step (residual, next dt, time, buffer swap) with no host work.
+//             sums and the CFL rate of the new state, per tile;
+//   k_finish  one workgroup per solve: residual, next dt, time and buffer swap.
 // All kernels walk the tile table with a grid-stride loop, so a fixed grid (and a
 // captured graph) serves any membership.  Workgroup ids are remapped so that consecutive
 // tiles, which share halo cells, land on the same XCD (L2).
+//
+// The table, the solve descriptors and (outside k_finish) the step state are read
+// through the constant address space: nothing writes them while these kernels run, so
+// their wave-uniform reads compile to scalar loads rather than chains of dependent
+// per-lane vector loads.  Ghost cells are chosen with selects, not branches, so that the
+// loads of a whole stencil are in flight together.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -20,6 +26,28 @@
 #include "gks_flux.hpp"
 
 namespace gks {
+
+template <typename T> using cptr = const __attribute__((address_space(4))) T*;
+template <typename T> using cref = const __attribute__((address_space(4))) T&;
+
+// The tile table as the stepping kernels see it (read-only, constant address space).
+struct TabC {
+    cptr<TabHdr> hdr;
+    cptr<Inst> inst;
+    cptr<int> cell_prefix, cls_member, cls_prefix;
+    __device__ TabC(const void* base, int cap)
+    {
+        const TabView tv(const_cast<void*>(base), cap);
+        hdr = (cptr<TabHdr>)tv.hdr;
+        inst = (cptr<Inst>)tv.inst;
+        cell_prefix = (cptr<int>)tv.cell_prefix;
+        cls_member = (cptr<int>)tv.cls_member;
+        cls_prefix = (cptr<int>)tv.cls_prefix;
+    }
+};
+
+// Step state of a solve, for kernels that do not write the fields they read.
+__device__ inline cref<State> state_of(cref<Inst> I) { return *(cptr<State>)I.st; }
 
 // --------------------------------------------------------------------------------------
 // helpers
@@ -34,7 +62,7 @@ __device__ inline int xcd_block()
 }
 
 // index of the member owning `tile` (prefix has count+1 entries, prefix[0] = 0)
-__device__ inline int find_member(const int* prefix, int count, int tile)
+__device__ inline int find_member(cptr<int> prefix, int count, int tile)
 {
     int lo = 0, hi = count;   // invariant prefix[lo] <= tile < prefix[hi]
     while (hi - lo > 1) {
@@ -44,74 +72,68 @@ __device__ inline int find_member(const int* prefix, int count, int tile)
     return lo;
 }
 
+// Interior cell whose value a (possibly ghost) index i along an axis of n cells takes:
+// periodic wrap, mirror behind a wall, nearest cell otherwise.
 __device__ inline int image_index(int bc, int i, int n)
 {
-    if (i < 0) {
-        if (bc == BC_PERIODIC) return i + n;
-        if (bc == BC_WALL) return -1 - i;
-        return 0;
-    }
-    if (i >= n) {
-        if (bc == BC_PERIODIC) return i - n;
-        if (bc == BC_WALL) return 2 * n - 1 - i;
-        return n - 1;
-    }
-    return i;
+    const bool lo = i < 0;
+    const int per = lo ? i + n : i - n;
+    const int wal = lo ? -1 - i : 2 * n - 1 - i;
+    const int cpy = lo ? 0 : n - 1;
+    const int g = bc == BC_PERIODIC ? per : (bc == BC_WALL ? wal : cpy);
+    return (i >= 0 && i < n) ? i : g;
 }
 
-__device__ inline int cell_index(const Inst& I, int i, int j, int k)
+__device__ inline int cell_index(cref<Inst> I, int i, int j, int k)
 {
     return (k * I.n[1] + j) * I.n[0] + i;
 }
 
 // Conservative state of cell c (c[d] may be a ghost index in [-2, n+1]; the other
-// coordinates are interior).  Synthesises ghosts from the boundary condition of axis d.
+// coordinates are interior).  Ghosts take the boundary condition of axis d: an interior
+// image (periodic, wall with the momentum negated, outflow), the fixed state, or the
+// fixed profile at the cell's position in the boundary plane.  Source, stride and element
+// are selected per lane, then every component is loaded unconditionally.
 template <int D>
-__device__ inline __attribute__((always_inline)) void load_state(const Inst& I, const double* __restrict__ W, int d,
+__device__ inline __attribute__((always_inline)) void load_state(cref<Inst> I, const double* __restrict__ W, int d,
                                                                  const int* c, double* w)
 {
     constexpr int NV = D + 2;
     const int n = I.n[d];
     const int id = c[d];
-    if (id >= 0 && id < n) {
-        const int idx = cell_index(I, c[0], c[1], D == 3 ? c[2] : 0);
-        for (int m = 0; m < NV; ++m) w[m] = W[(long long)m * I.ncells + idx];
-        return;
-    }
-    const int side = id < 0 ? 0 : 1;
-    const int bc = I.bc[d][side];
-    if (bc == BC_DIRICHLET) {
-        const double* s = I.bcd[d][side];
-        for (int m = 0; m < NV; ++m) w[m] = s[m];
-        return;
-    }
-    if (bc == BC_PROFILE) {
-        int t = 0, stride = 1;
-        for (int a = 0; a < D; ++a) {
-            if (a == d) continue;
-            t += c[a] * stride;
-            stride *= I.n[a];
-        }
-        const double* s = I.bcd[d][side];
-        for (int m = 0; m < NV; ++m) w[m] = s[(long long)m * I.ntan[d] + t];
-        return;
-    }
+    const bool hi = id >= n;
+    const bool ghost = id < 0 || hi;
+    const int bc0 = I.bc[d][0], bc1 = I.bc[d][1];
+    const int bc = ghost ? (hi ? bc1 : bc0) : -1;
     int cc[3] = {c[0], c[1], D == 3 ? c[2] : 0};
     cc[d] = image_index(bc, id, n);
-    const int idx = cell_index(I, cc[0], cc[1], cc[2]);
-    for (int m = 0; m < NV; ++m) w[m] = W[(long long)m * I.ncells + idx];
-    if (bc == BC_WALL)
-        for (int m = 1; m <= D; ++m) w[m] = -w[m];
+    int t = 0, stride = 1;                     // index in the boundary plane
+    for (int a = 0; a < D; ++a) {
+        if (a == d) continue;
+        t += c[a] * stride;
+        stride *= I.n[a];
+    }
+    const double* bd0 = I.bcd[d][0];
+    const double* bd1 = I.bcd[d][1];
+    const bool fixed = bc == BC_DIRICHLET, prof = bc == BC_PROFILE;
+    const double* src = (fixed || prof) ? (hi ? bd1 : bd0) : W;
+    const long long step = fixed ? 1 : (prof ? (long long)I.ntan[d] : (long long)I.ncells);
+    const long long e = fixed ? 0 : (prof ? (long long)t : (long long)cell_index(I, cc[0], cc[1], cc[2]));
+    const bool neg = bc == BC_WALL;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const double v = src[m * step + e];
+        w[m] = (m >= 1 && m <= D && neg) ? -v : v;
+    }
 }
 
 // flat index of the interior image of cell c (only c[d] may be a ghost)
 template <int D>
-__device__ inline int image_cell(const Inst& I, int d, const int* c)
+__device__ inline int image_cell(cref<Inst> I, int d, const int* c)
 {
     int cc[3] = {c[0], c[1], D == 3 ? c[2] : 0};
-    const int n = I.n[d];
-    if (cc[d] < 0) cc[d] = image_index(I.bc[d][0], cc[d], n);
-    else if (cc[d] >= n) cc[d] = image_index(I.bc[d][1], cc[d], n);
+    const int bc0 = I.bc[d][0], bc1 = I.bc[d][1];
+    cc[d] = image_index(cc[d] < 0 ? bc0 : bc1, cc[d], I.n[d]);
     return cell_index(I, cc[0], cc[1], cc[2]);
 }
 
@@ -119,9 +141,9 @@ __device__ inline int image_cell(const Inst& I, int d, const int* c)
 // strain rate
 // --------------------------------------------------------------------------------------
 template <int D>
-__device__ inline void strain_cell(const Inst& I, int cell)
+__device__ inline void strain_cell(cref<Inst> I, int cell)
 {
-    const double* __restrict__ W = I.W[I.st->parity];
+    const double* __restrict__ W = I.W[state_of(I).parity];
     int c[3];
     c[0] = cell % I.n[0];
     c[1] = (cell / I.n[0]) % I.n[1];
@@ -148,13 +170,13 @@ __device__ inline void strain_cell(const Inst& I, int cell)
 
 __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ table, int cap, int force)
 {
-    TabView tv(const_cast<void*>(table), cap);
+    const TabC tv(table, cap);
     const int count = tv.hdr->count;
     const int total = tv.hdr->total_cell;
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mi = find_member(tv.cell_prefix, count, tile);
-        const Inst& I = tv.inst[mi];
-        if (!force && !I.st->active) continue;
+        cref<Inst> I = tv.inst[mi];
+        if (!force && !state_of(I).active) continue;
         const int cell = (tile - tv.cell_prefix[mi]) * CELL_TILE + (int)threadIdx.x;
         if (cell >= I.ncells) continue;
         if (I.dim == 2) strain_cell<2>(I, cell);
@@ -168,7 +190,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
 // One face normal to axis DIR.  The axis is a template parameter so that every stencil
 // index and the rotation to the face-local frame are compile-time (no private arrays).
 template <typename R, int D, int DIR>
-__device__ __attribute__((always_inline)) inline void face_one(const Inst& I, int f)
+__device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int f)
 {
     constexpr int NV = D + 2;
     // face coordinates: the face lies on the low side of cell fc along axis DIR
@@ -177,7 +199,7 @@ __device__ __attribute__((always_inline)) inline void face_one(const Inst& I, in
     fc[0] = f % fn0;
     fc[1] = (f / fn0) % fn1;
     fc[2] = (D == 3) ? f / (fn0 * fn1) : 0;
-    const double* __restrict__ W = I.W[I.st->parity];
+    const double* __restrict__ W = I.W[state_of(I).parity];
 
     double Wc[4][NV];
 #pragma unroll
@@ -189,11 +211,11 @@ __device__ __attribute__((always_inline)) inline void face_one(const Inst& I, in
     FaceGeo<double> geo;
     {
         const int i = fc[DIR];
-        const double* icd = I.icd[DIR];
+        const double* __restrict__ icd = I.icd[DIR];
         geo.icd[0] = icd[i - 2];
         geo.icd[1] = icd[i - 1];
         geo.icd[2] = icd[i];
-        const double* fg = I.fgeo[DIR] + 4 * i;
+        const double* __restrict__ fg = I.fgeo[DIR] + 4 * i;
         geo.dl = fg[0];
         geo.dr = fg[1];
         geo.idl = fg[2];
@@ -225,7 +247,7 @@ __device__ __attribute__((always_inline)) inline void face_one(const Inst& I, in
         in.wf = 0.5 * (I.om[il] + I.om[ir]);
         in.Sf = 0.5 * (I.S[il] + I.S[ir]);
     }
-    in.dt = I.st->dt;
+    in.dt = state_of(I).dt;
     GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
     R F[NV];
     if (face_flux<R, D, double>(in, gas, F)) atomicOr(&I.st->err, 1);
@@ -238,29 +260,34 @@ __device__ __attribute__((always_inline)) inline void face_one(const Inst& I, in
     out[(long long)(D + 1) * nf + f] = F[D + 1];
 }
 
-#ifndef GKS_FACE_WAVES_FP64
-#define GKS_FACE_WAVES_FP64 2
+#ifndef GKS_FACE_WAVES_FP64_2D
+#define GKS_FACE_WAVES_FP64_2D 3
+#endif
+#ifndef GKS_FACE_WAVES_FP64_3D
+#define GKS_FACE_WAVES_FP64_3D 2
 #endif
 #ifndef GKS_FACE_WAVES_FP32
 #define GKS_FACE_WAVES_FP32 4
 #endif
-// Register budget of the face kernel: at least this many waves per SIMD (2 leaves 256
-// VGPRs per lane for the FP64 flux, 4 leaves 128 for the FP32 flux).  TILE faces per
-// workgroup (64, 128 or 256: a batch's autotuned shape).
+// Register budget of the face kernel: at least this many waves per SIMD (3 leaves 168
+// VGPRs per lane, enough for the 2D FP64 flux; 2 leaves 256 for the 3D FP64 flux; 4
+// leaves 128 for the FP32 flux).  TILE faces per workgroup (64, 128 or 256: a batch's
+// autotuned shape).
 template <typename R, int D, int TILE>
 __global__ __launch_bounds__(TILE)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_FACE_WAVES_FP64)))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32
+                                                  : (D == 2 ? GKS_FACE_WAVES_FP64_2D : GKS_FACE_WAVES_FP64_3D))))
 void k_face(const void* __restrict__ table, int cap, int cls)
 {
-    TabView tv(const_cast<void*>(table), cap);
+    const TabC tv(table, cap);
     const int count = tv.hdr->ncls[cls];
     const int total = tv.hdr->total_face[cls];
-    const int* prefix = tv.cls_prefix + cls * (cap + 1);
-    const int* member = tv.cls_member + cls * cap;
+    cptr<int> prefix = tv.cls_prefix + cls * (cap + 1);
+    cptr<int> member = tv.cls_member + cls * cap;
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mj = find_member(prefix, count, tile);
-        const Inst& I = tv.inst[member[mj]];
-        if (!I.st->active) continue;
+        cref<Inst> I = tv.inst[member[mj]];
+        if (!state_of(I).active) continue;
         int lt = tile - prefix[mj];
         if (lt < I.ntile_face[0]) {
             const int f = lt * TILE + (int)threadIdx.x;
@@ -295,10 +322,10 @@ __device__ inline double wave_max(double v)
 }
 
 template <int D, typename RF>
-__device__ inline void update_cell(const Inst& I, int cell, double dt, double* r2, double& rate, int& bad)
+__device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2, double& rate, int& bad)
 {
     constexpr int NV = D + 2;
-    const int cur = I.st->parity;
+    const int cur = state_of(I).parity;
     const double* __restrict__ Wo = I.W[cur];
     double* __restrict__ Wn = I.W[cur ^ 1];
     int c[3];
@@ -344,7 +371,7 @@ __device__ inline void update_cell(const Inst& I, int cell, double dt, double* r
 }
 
 // time step following a state whose max CFL rate is `rate`, and the time it ends at
-__device__ inline void next_step(const Inst& I, State* st, double rate, double t)
+__device__ inline void next_step(cref<Inst> I, State* st, double rate, double t)
 {
     double dt = I.cfl / rate, ta = t + dt;
     if (I.t_end > 0.0) {
@@ -358,7 +385,7 @@ __device__ inline void next_step(const Inst& I, State* st, double rate, double t
 
 __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ table, int cap)
 {
-    TabView tv(const_cast<void*>(table), cap);
+    const TabC tv(table, cap);
     const int count = tv.hdr->count;
     const int total = tv.hdr->total_cell;
     __shared__ double sh_sum[5 * 4];
@@ -367,14 +394,14 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mi = find_member(tv.cell_prefix, count, tile);
-        const Inst& I = tv.inst[mi];
-        if (!I.st->active) continue;
+        cref<Inst> I = tv.inst[mi];
+        if (!state_of(I).active) continue;
         const int lt = tile - tv.cell_prefix[mi];
         const int cell = lt * CELL_TILE + (int)threadIdx.x;
         double r2[5] = {0, 0, 0, 0, 0};
         double rate = 0.0;
         int bad = 0;
-        const double dt = I.st->dt;
+        const double dt = state_of(I).dt;
         if (cell < I.ncells) {
             if (I.dim == 2) {
                 if (I.precision) update_cell<2, float>(I, cell, dt, r2, rate, bad);
@@ -409,7 +436,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
 // Max CFL rate of the current state of each member (first step at init).
 __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ table, int cap)
 {
-    TabView tv(const_cast<void*>(table), cap);
+    const TabC tv(table, cap);
     const int count = tv.hdr->count;
     const int total = tv.hdr->total_cell;
     __shared__ double sh_max[4];
@@ -417,13 +444,13 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mi = find_member(tv.cell_prefix, count, tile);
-        const Inst& I = tv.inst[mi];
+        cref<Inst> I = tv.inst[mi];
         const int lt = tile - tv.cell_prefix[mi];
         const int cell = lt * CELL_TILE + (int)threadIdx.x;
         double rate = 0.0;
         int bad = 0;
         if (cell < I.ncells) {
-            const double* W = I.W[I.st->parity];
+            const double* W = I.W[state_of(I).parity];
             const int D = I.dim;
             double w[5];
             for (int m = 0; m < I.nv; ++m) w[m] = W[(long long)m * I.ncells + cell];
@@ -466,12 +493,12 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
 // partial before it.  Loads of four tiles are issued together to hide their latency.
 __global__ __launch_bounds__(CELL_TILE) void k_finish(const void* __restrict__ table, int cap, int mode)
 {
-    TabView tv(const_cast<void*>(table), cap);
+    const TabC tv(table, cap);
     const int count = tv.hdr->count;
     __shared__ double sh[6 * 4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
-        const Inst& I = tv.inst[mi];
+        cref<Inst> I = tv.inst[mi];
         State* st = I.st;
         if (mode == 0 && !st->active) continue;
         const int nv = I.nv, nt = I.ntile_cell;
