@@ -120,12 +120,15 @@ gks_status gks_state_device_ptr(gks_handle h, const double** dev_W);
 /* Synchronise and release the handle (the caller frees the workspace). */
 gks_status gks_destroy(gks_handle h);
 
-/* Per-kernel timing for benchmarks.  While enabled, gks_step records HIP events on the
- * handle's stream around each of its three launches (strain, face, update).
- * gks_kernel_times synchronises and returns the summed milliseconds of each launch kind
- * since timing was enabled, and the number of steps timed; enabling again resets. */
+/* Per-kernel timing for benchmarks.  While enabled, gks_step launches each kernel with a
+ * pair of HIP events on the handle's stream that the runtime stamps with that launch's
+ * own start and end (no extra packets between launches).  A step is three launches:
+ * strain (which also ends the previous step), face and update; a call adds one trailing
+ * end-of-step launch (finish).  gks_kernel_times synchronises and writes the summed
+ * milliseconds of each launch kind since timing was enabled (ms[0..3] = strain, face,
+ * update, finish) and the number of steps timed; enabling again resets. */
 gks_status gks_set_timing(gks_handle h, int32_t enable);
-gks_status gks_kernel_times(gks_handle h, double* ms /*[3]*/, int64_t* steps_timed);
+gks_status gks_kernel_times(gks_handle h, double* ms /*[4]*/, int64_t* steps_timed);
 
 /* Text of the last error on the handle (or of the last failed handle-less call if NULL). */
 const char* gks_last_error(gks_handle h);

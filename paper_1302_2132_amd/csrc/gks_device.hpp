@@ -13,8 +13,11 @@ constexpr int PSTRIDE = 6;       // per-tile partials: nv residual sums (slots 0
 
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_DIRICHLET = 2, BC_PROFILE = 3, BC_OUTFLOW = 4 };
 
-// Step state of one solve, written by the end-of-step kernel (and by atomics from the
-// update kernel's workgroups).
+// Step state of one solve.  The update kernel writes the new state into W[parity ^ 1] and
+// records it in `fresh` with `pending` set; the end of the step (residual, time, next dt,
+// parity flip, clearing `pending`) then runs either folded into the next step's strain
+// launch or as a trailing launch.  The strain pass reads W[fresh], which the end of the
+// step does not touch, so the two can share one launch without a race.
 struct alignas(64) State {
     double dt;          // step size of the step about to run
     double t;           // time reached
@@ -25,6 +28,8 @@ struct alignas(64) State {
     int parity;         // W[parity] is the current state
     int err;            // bit 0: non-physical state met
     int active;         // 1 while stepping
+    int fresh;          // W[fresh] is the newest state (== parity unless a step end is pending)
+    int pending;        // 1 between an update and the end of its step
     long long steps;
 };
 

@@ -1,14 +1,18 @@
 // gks_kernels.hpp -- gfx950 kernels of the turbulent gas-kinetic step.
 //
-// One step of every active solve in a tile table is four launches:
+// One step of every active solve in a tile table is three launches:
 //   k_strain  cell tiles: strain-rate magnitude of each cell from central differences
-//             of the cell velocities (ghost neighbours synthesised from the BCs);
+//             of the cell velocities (ghost neighbours synthesised from the BCs), and, in
+//             the same launch, the end of the previous step of each solve (below);
 //   k_face    face tiles of one (dim, precision) class: minmod reconstruction along the
 //             face normal (four cells, ghosts synthesised), then the gas-kinetic flux of
 //             gks_flux.hpp, written once per face (structure of arrays per axis);
 //   k_update  cell tiles: conservative FP64 update, positivity check, residual partial
-//             sums and the CFL rate of the new state, per tile;
-//   k_finish  one workgroup per solve: residual, next dt, time and buffer swap.
+//             sums and the CFL rate of the new state, per tile.
+// The end of a step (one workgroup per solve: residual, next dt, time, buffer swap) needs
+// every update tile, and the next face pass needs its dt; the strain pass needs neither,
+// so it shares a launch with it.  k_finish runs the end of the step on its own after the
+// last step of a call, so the state the host reads is complete.
 // All kernels walk the tile table with a grid-stride loop, so a fixed grid (and a
 // captured graph) serves any membership.  Workgroup ids are remapped so that consecutive
 // tiles, which share halo cells, land on the same XCD (L2).
@@ -143,7 +147,7 @@ __device__ inline int image_cell(cref<Inst> I, int d, const int* c)
 template <int D>
 __device__ inline void strain_cell(cref<Inst> I, int cell)
 {
-    const double* __restrict__ W = I.W[state_of(I).parity];
+    const double* __restrict__ W = I.W[state_of(I).fresh];
     int c[3];
     c[0] = cell % I.n[0];
     c[1] = (cell / I.n[0]) % I.n[1];
@@ -166,22 +170,6 @@ __device__ inline void strain_cell(cref<Inst> I, int cell)
             ss += s * s;
         }
     I.S[cell] = sqrt(2.0 * ss);
-}
-
-__global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ table, int cap, int force)
-{
-    const TabC tv(table, cap);
-    const int count = tv.hdr->count;
-    const int total = tv.hdr->total_cell;
-    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
-        const int mi = find_member(tv.cell_prefix, count, tile);
-        cref<Inst> I = tv.inst[mi];
-        if (!force && !state_of(I).active) continue;
-        const int cell = (tile - tv.cell_prefix[mi]) * CELL_TILE + (int)threadIdx.x;
-        if (cell >= I.ncells) continue;
-        if (I.dim == 2) strain_cell<2>(I, cell);
-        else strain_cell<3>(I, cell);
-    }
 }
 
 // --------------------------------------------------------------------------------------
@@ -332,24 +320,37 @@ __device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2
     c[0] = cell % I.n[0];
     c[1] = (cell / I.n[0]) % I.n[1];
     c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
-    double w[NV];
-    double idx_[3];
-    for (int d = 0; d < D; ++d) idx_[d] = I.idx[d][c[d]];
-    const double idt = 1.0 / dt;
-    for (int m = 0; m < NV; ++m) {
-        const double old = Wo[(long long)m * I.ncells + cell];
-        double acc = old;
+    // Every read of the cell first: the compiler cannot move a load above a store through
+    // another pointer, so reads interleaved with the stores below would be serialised.
+    double old[NV], fl[D][NV], fh[D][NV], idx_[3];
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int fn0 = I.n[0] + (d == 0), fn1 = I.n[1] + (d == 1);
-            const int lo = (c[2] * fn1 + c[1]) * fn0 + c[0];
-            const int hi = lo + (d == 0 ? 1 : (d == 1 ? fn0 : fn0 * fn1));
-            const RF* __restrict__ F = (const RF*)I.F[d] + (long long)m * I.nface[d];
-            acc -= (double(F[hi]) - double(F[lo])) * idx_[d];
+    for (int d = 0; d < D; ++d) idx_[d] = I.idx[d][c[d]];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) old[m] = Wo[(long long)m * I.ncells + cell];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int fn0 = I.n[0] + (d == 0), fn1 = I.n[1] + (d == 1);
+        const int lo = (c[2] * fn1 + c[1]) * fn0 + c[0];
+        const int hi = lo + (d == 0 ? 1 : (d == 1 ? fn0 : fn0 * fn1));
+        const long long nf = I.nface[d];
+        const RF* __restrict__ F = (const RF*)I.F[d];
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            fl[d][m] = double(F[m * nf + lo]);
+            fh[d][m] = double(F[m * nf + hi]);
         }
+    }
+    const double kc = I.k[cell], wc = I.om[cell];
+    double w[NV];
+    const double idt = 1.0 / dt;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        double acc = old[m];
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc -= (fh[d][m] - fl[d][m]) * idx_[d];
         w[m] = acc;
         Wn[(long long)m * I.ncells + cell] = acc;
-        const double r = (acc - old) * idt;
+        const double r = (acc - old[m]) * idt;
         r2[m] = r * r;
     }
     // positivity and the CFL rate of the new state
@@ -361,7 +362,7 @@ __device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2
     // CFL rate  sum_d (|U_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2
     const double cs = sqrt(I.gamma * p * irho);
     const double fac = fmax(4.0 / 3.0, I.gamma / I.prandtl);
-    const double nu = (I.mu * irho + I.k[cell] / I.om[cell]) * fac;
+    const double nu = (I.mu * irho + kc / wc) * fac;
     double r = 0.0, r2s = 0.0;
     for (int d = 0; d < D; ++d) {
         r += (fabs(U[d]) + cs) * idx_[d];
@@ -423,6 +424,9 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
         }
         __syncthreads();
         if (threadIdx.x == 0) {
+            State* st = I.st;                    // every workgroup of the solve writes the same values
+            st->fresh = state_of(I).parity ^ 1;
+            st->pending = 1;
             double* part = I.part + (long long)lt * PSTRIDE;
             for (int m = 0; m < I.nv; ++m)
                 part[m] = (sh_sum[m * 4 + 0] + sh_sum[m * 4 + 1]) + (sh_sum[m * 4 + 2] + sh_sum[m * 4 + 3]);
@@ -486,71 +490,101 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
     }
 }
 
-// End of a step (mode 0) or of the initial rate pass (mode 1), one workgroup per member:
-// residual from the per-tile partial sums and the CFL rate from the per-tile maxima (fixed
-// stride per thread, fixed reduction tree: deterministic), then time, buffer swap and the
-// next CFL step.  Runs after k_update / k_rate, so the kernel boundary orders every
-// partial before it.  Loads of four tiles are issued together to hide their latency.
+// End of a step (mode 0) or of the initial rate pass (mode 1) of one member, by one
+// workgroup: residual from the per-tile partial sums and the CFL rate from the per-tile
+// maxima (fixed stride per thread, fixed reduction tree: deterministic), then time,
+// buffer swap and the next CFL step.  Runs in a launch after k_update / k_rate, so the
+// kernel boundary orders every partial before it.  Loads of four tiles are issued
+// together to hide their latency.  `sh` holds 6 x 4 doubles of workgroup scratch.
+__device__ inline void finish_member(cref<Inst> I, int mode, double* sh)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    State* st = I.st;
+    if (mode == 0 && !st->pending) return;
+    const int nv = I.nv, nt = I.ntile_cell;
+    const int first = mode == 0 ? 0 : 5;    // mode 1 needs the rate only
+    double acc[5] = {0, 0, 0, 0, 0}, rmax = 0.0;
+    const double* __restrict__ part = I.part;
+    for (int t0 = threadIdx.x; t0 < nt; t0 += 4 * CELL_TILE) {
+        double v[4][6];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = t0 + q * CELL_TILE;
+#pragma unroll
+            for (int m = 0; m < 6; ++m)
+                v[q][m] = (t < nt && (m >= first) && (m < nv || m == 5)) ? part[(long long)t * PSTRIDE + m] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            for (int m = 0; m < 5; ++m) acc[m] += v[q][m];
+            rmax = fmax(rmax, v[q][5]);
+        }
+    }
+    for (int m = 0; m < nv; ++m) {
+        const double s = wave_sum(acc[m]);
+        if (lane == 0) sh[m * 4 + wv] = s;
+    }
+    {
+        const double s = wave_max(rmax);
+        if (lane == 0) sh[5 * 4 + wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double rate = fmax(fmax(sh[20], sh[21]), fmax(sh[22], sh[23]));
+        if (mode == 1) {
+            st->active = 1;
+        } else {
+            const double N = (double)I.ncells;
+            for (int m = 0; m < nv; ++m) {
+                const double s = (sh[m * 4 + 0] + sh[m * 4 + 1]) + (sh[m * 4 + 2] + sh[m * 4 + 3]);
+                st->res[m] = sqrt(s / N);
+            }
+            st->dt_last = st->dt;
+            st->t = st->t_after;
+            st->steps += 1;
+            if (st->steps == 1)
+                for (int m = 0; m < nv; ++m) st->res_first[m] = st->res[m];
+            st->parity ^= 1;
+            st->pending = 0;
+        }
+        next_step(I, st, rate, st->t);
+        if (st->err) st->active = 0;
+        if (I.max_steps > 0 && st->steps >= I.max_steps) st->active = 0;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(CELL_TILE) void k_finish(const void* __restrict__ table, int cap, int mode)
 {
     const TabC tv(table, cap);
     const int count = tv.hdr->count;
     __shared__ double sh[6 * 4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
+    for (int mi = blockIdx.x; mi < count; mi += gridDim.x) finish_member(tv.inst[mi], mode, sh);
+}
+
+// Strain pass over every cell tile of the table (of active members unless `force`).
+// With `finish` set, the first `count` work items instead end the pending step of each
+// member (the strain items read W[fresh], which ending a step leaves alone).
+__global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ table, int cap, int force, int finish)
+{
+    const TabC tv(table, cap);
+    const int count = tv.hdr->count;
+    const int head = finish ? count : 0;
+    const int total = head + tv.hdr->total_cell;
+    __shared__ double sh[6 * 4];
+    for (int item = xcd_block(); item < total; item += gridDim.x) {
+        if (item < head) {
+            finish_member(tv.inst[item], 0, sh);
+            continue;
+        }
+        const int tile = item - head;
+        const int mi = find_member(tv.cell_prefix, count, tile);
         cref<Inst> I = tv.inst[mi];
-        State* st = I.st;
-        if (mode == 0 && !st->active) continue;
-        const int nv = I.nv, nt = I.ntile_cell;
-        const int first = mode == 0 ? 0 : 5;    // mode 1 needs the rate only
-        double acc[5] = {0, 0, 0, 0, 0}, rmax = 0.0;
-        const double* __restrict__ part = I.part;
-        for (int t0 = threadIdx.x; t0 < nt; t0 += 4 * CELL_TILE) {
-            double v[4][6];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int t = t0 + q * CELL_TILE;
-#pragma unroll
-                for (int m = 0; m < 6; ++m)
-                    v[q][m] = (t < nt && (m >= first) && (m < nv || m == 5)) ? part[(long long)t * PSTRIDE + m] : 0.0;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                for (int m = 0; m < 5; ++m) acc[m] += v[q][m];
-                rmax = fmax(rmax, v[q][5]);
-            }
-        }
-        for (int m = 0; m < nv; ++m) {
-            const double s = wave_sum(acc[m]);
-            if (lane == 0) sh[m * 4 + wv] = s;
-        }
-        {
-            const double s = wave_max(rmax);
-            if (lane == 0) sh[5 * 4 + wv] = s;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const double rate = fmax(fmax(sh[20], sh[21]), fmax(sh[22], sh[23]));
-            if (mode == 1) {
-                st->active = 1;
-            } else {
-                const double N = (double)I.ncells;
-                for (int m = 0; m < nv; ++m) {
-                    const double s = (sh[m * 4 + 0] + sh[m * 4 + 1]) + (sh[m * 4 + 2] + sh[m * 4 + 3]);
-                    st->res[m] = sqrt(s / N);
-                }
-                st->dt_last = st->dt;
-                st->t = st->t_after;
-                st->steps += 1;
-                if (st->steps == 1)
-                    for (int m = 0; m < nv; ++m) st->res_first[m] = st->res[m];
-                st->parity ^= 1;
-            }
-            next_step(I, st, rate, st->t);
-            if (st->err) st->active = 0;
-            if (I.max_steps > 0 && st->steps >= I.max_steps) st->active = 0;
-        }
-        __syncthreads();
+        if (!force && !state_of(I).active) continue;
+        const int cell = (tile - tv.cell_prefix[mi]) * CELL_TILE + (int)threadIdx.x;
+        if (cell >= I.ncells) continue;
+        if (I.dim == 2) strain_cell<2>(I, cell);
+        else strain_cell<3>(I, cell);
     }
 }
 

@@ -3,6 +3,7 @@
 // Device memory is the caller's: every solve lives in one workspace laid out by
 // `layout()`; a batch keeps only its tile table in its own workspace.  Nothing here
 // calls hipMalloc.  Host inputs are validated and copied during gks_init.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -172,7 +173,8 @@ struct gks_ctx {
     int grid_cell, grid_face;
     bool timing;
     hipStream_t batch_stream;         // stream of the batch that last advanced this solve
-    std::vector<hipEvent_t> events;   // pool, 4 per timed step
+    std::vector<hipEvent_t> events;   // pool, a start/stop pair per timed launch
+    std::vector<int> timed_kind;      // launch kind of each pair: 0 strain, 1 face, 2 update, 3 finish
     size_t events_used;
     long long steps_timed;
 };
@@ -450,30 +452,43 @@ static gks_status next_event(gks_ctx* h, hipEvent_t* ev)
     return GKS_OK;
 }
 
+// Each step is three launches (strain with the previous step's end folded in, face,
+// update); one trailing k_finish ends the last step so the state is complete when the
+// call's work has run.
 static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
 {
     hipStream_t s = h->stream;
     const void* tab = h->tab;
     face_kernel_t fk = face_kernel(h->cls, FACE_TILE);
-    for (int i = 0; i < nsteps; ++i) {
-        hipEvent_t ev[4];
-        if (h->timing) {
-            for (int q = 0; q < 4; ++q) {
+    const int grid_head = h->grid_cell + 1;
+    if (nsteps == 0) return GKS_OK;
+    if (!h->timing) {
+        for (int i = 0; i < nsteps; ++i) {
+            hipLaunchKernelGGL(k_strain, dim3(grid_head), dim3(CELL_TILE), 0, s, tab, 1, 0, 1);
+            hipLaunchKernelGGL(fk, dim3(h->grid_face), dim3(FACE_TILE), 0, s, tab, 1, h->cls);
+            hipLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
+        }
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, tab, 1, 0);
+    } else {
+        // timed: the runtime stamps each launch's own start and end into its event pair
+        hipEvent_t ev[8];
+        for (int i = 0; i < nsteps; ++i) {
+            for (int q = 0; q < 6; ++q) {
                 gks_status r = next_event(h, &ev[q]);
                 if (r != GKS_OK) return r;
             }
-            HIP_TRY(h, hipEventRecord(ev[0], s));
-        }
-        hipLaunchKernelGGL(k_strain, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1, 0);
-        if (h->timing) HIP_TRY(h, hipEventRecord(ev[1], s));
-        hipLaunchKernelGGL(fk, dim3(h->grid_face), dim3(FACE_TILE), 0, s, tab, 1, h->cls);
-        if (h->timing) HIP_TRY(h, hipEventRecord(ev[2], s));
-        hipLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, tab, 1, 0);
-        if (h->timing) {
-            HIP_TRY(h, hipEventRecord(ev[3], s));
+            hipExtLaunchKernelGGL(k_strain, dim3(grid_head), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, 0, 1);
+            hipExtLaunchKernelGGL(fk, dim3(h->grid_face), dim3(FACE_TILE), 0, s, ev[2], ev[3], 0, tab, 1, h->cls);
+            hipExtLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, ev[4], ev[5], 0, tab, 1);
+            h->timed_kind.insert(h->timed_kind.end(), {0, 1, 2});
             h->steps_timed += 1;
         }
+        for (int q = 6; q < 8; ++q) {
+            gks_status r = next_event(h, &ev[q]);
+            if (r != GKS_OK) return r;
+        }
+        hipExtLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, ev[6], ev[7], 0, tab, 1, 0);
+        h->timed_kind.push_back(3);
     }
     HIP_TRY(h, hipGetLastError());
     return GKS_OK;
@@ -528,7 +543,7 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
     const long long N = h->L.ncells;
     const int nv = h->nv, D = h->cfg.dim;
     if (which == GKS_FIELD_STRAIN) {
-        hipLaunchKernelGGL(k_strain, dim3(h->grid_cell), dim3(CELL_TILE), 0, h->stream, (const void*)h->tab, 1, 1);
+        hipLaunchKernelGGL(k_strain, dim3(h->grid_cell), dim3(CELL_TILE), 0, h->stream, (const void*)h->tab, 1, 1, 0);
         HIP_TRY(h, hipGetLastError());
         HIP_TRY(h, hipMemcpyAsync(host_out, h->inst.S, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -569,6 +584,7 @@ gks_status gks_set_timing(gks_handle h, int32_t enable)
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->timing = enable != 0;
     h->events_used = 0;
+    h->timed_kind.clear();
     h->steps_timed = 0;
     return GKS_OK;
 }
@@ -577,13 +593,11 @@ gks_status gks_kernel_times(gks_handle h, double* ms, int64_t* steps_timed)
 {
     if (!h || !ms) return fail_h(h, GKS_ERR_ARG, "NULL argument");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    ms[0] = ms[1] = ms[2] = 0.0;
-    for (size_t i = 0; i + 4 <= h->events_used; i += 4) {
-        for (int q = 0; q < 3; ++q) {
-            float t = 0.f;
-            HIP_TRY(h, hipEventElapsedTime(&t, h->events[i + q], h->events[i + q + 1]));
-            ms[q] += t;
-        }
+    for (int q = 0; q < 4; ++q) ms[q] = 0.0;
+    for (size_t i = 0; i < h->timed_kind.size() && 2 * i + 1 < h->events_used; ++i) {
+        float t = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&t, h->events[2 * i], h->events[2 * i + 1]));
+        ms[h->timed_kind[i]] += t;
     }
     if (steps_timed) *steps_timed = h->steps_timed;
     return GKS_OK;
@@ -695,20 +709,21 @@ static int batch_grid(gks_batch b, int kind)
 {
     if (b->grid[kind] > 0) return b->grid[kind];
     TabView tv(b->host_tab.data(), b->cap);
-    const int tiles = (kind == 0 || kind == 5) ? tv.hdr->total_cell : tv.hdr->total_face[kind - 1];
+    // the strain launch also carries one end-of-step work item per member
+    const int tiles = kind == 0 ? tv.hdr->total_cell + tv.hdr->count
+                                : (kind == 5 ? tv.hdr->total_cell : tv.hdr->total_face[kind - 1]);
     return tiles > 0 ? tiles : 1;
 }
 
 static void batch_launch(gks_batch b, int present)
 {
     const void* tab = b->tab;
-    hipLaunchKernelGGL(k_strain, dim3(batch_grid(b, 0)), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0);
+    hipLaunchKernelGGL(k_strain, dim3(batch_grid(b, 0)), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0, 1);
     for (int c = 0; c < NCLS; ++c)
         if (present & (1 << c))
             hipLaunchKernelGGL(face_kernel(c, b->face_tile[c]), dim3(batch_grid(b, 1 + c)), dim3(b->face_tile[c]), 0,
                                b->stream, tab, b->cap, c);
     hipLaunchKernelGGL(k_update, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
-    hipLaunchKernelGGL(k_finish, dim3(b->cap), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0);
 }
 
 gks_status gks_batch_step(gks_batch b, int32_t nsteps)
@@ -721,6 +736,9 @@ gks_status gks_batch_step(gks_batch b, int32_t nsteps)
             batch_launch(b, b->cls_present);
         }
     }
+    // end of the last step (outside the captured step graph)
+    if (nsteps > 0)
+        hipLaunchKernelGGL(k_finish, dim3(b->cap), dim3(CELL_TILE), 0, b->stream, (const void*)b->tab, b->cap, 0);
     if (hipGetLastError() != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "batch launch failed");
     return GKS_OK;
 }

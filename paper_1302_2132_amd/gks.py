@@ -198,10 +198,10 @@ def gks_set_timing(h, enable):
 
 
 def gks_kernel_times(h):
-    ms = np.zeros(3)
+    ms = np.zeros(4)
     n = C.c_int64(0)
     _check(lib().gks_kernel_times(h, _dp(ms), C.byref(n)), h)
-    return {"strain_ms": ms[0], "face_ms": ms[1], "update_ms": ms[2], "steps": int(n.value)}
+    return {"strain_ms": ms[0], "face_ms": ms[1], "update_ms": ms[2], "finish_ms": ms[3], "steps": int(n.value)}
 
 
 def gks_batch_workspace_bytes(capacity):

@@ -1,0 +1,32 @@
+"""Per-kernel timing (gks_set_timing / gks_kernel_times): every launch kind gets a positive
+duration for every timed step, and stamping launches with events changes no result."""
+import numpy as np
+import pytest
+
+from gpu_util import banner
+from inputs import cases as C
+
+pytestmark = pytest.mark.gpu
+
+
+def test_timed_steps_match_untimed_bitwise():
+    import paper_1302_2132_amd as P
+    case = C.mixing_layer(64, seed=5)
+    banner("timing: mixing layer 64x64, 2 x 15 steps")
+    a = P.Solver(case)
+    a.step(30)
+    Wa = a.fields("cons")
+    a.close()
+    b = P.Solver(case)
+    b.step(15)
+    P.gks_set_timing(b.h, True)
+    b.step(15)
+    kt = P.gks_kernel_times(b.h)
+    P.gks_set_timing(b.h, False)
+    Wb = b.fields("cons")
+    b.close()
+    print(f"  kernel ms over 15 steps: {kt}", flush=True)
+    assert kt["steps"] == 15
+    for k in ("strain_ms", "face_ms", "update_ms", "finish_ms"):
+        assert kt[k] > 0.0, kt
+    assert np.array_equal(Wa, Wb)
