@@ -31,21 +31,66 @@
 
 namespace gks {
 
-GKS_HD inline double g_sqrt(double x) { return sqrt(x); }
-GKS_HD inline float g_sqrt(float x) { return sqrtf(x); }
 GKS_HD inline double g_exp(double x) { return exp(x); }
 GKS_HD inline float g_exp(float x) { return expf(x); }
-GKS_HD inline double g_erfc(double x) { return erfc(x); }
-GKS_HD inline float g_erfc(float x) { return erfcf(x); }
 GKS_HD inline double g_abs(double x) { return fabs(x); }
 GKS_HD inline float g_abs(float x) { return fabsf(x); }
+GKS_HD inline double g_min(double x, double y) { return fmin(x, y); }
+GKS_HD inline float g_min(float x, float y) { return fminf(x, y); }
+GKS_HD inline double g_copysign(double x, double s) { return copysign(x, s); }
+GKS_HD inline float g_copysign(float x, float s) { return copysignf(x, s); }
+
+// Reciprocal and reciprocal square root from the hardware estimates (v_rcp, v_rsq) refined
+// by Newton-Raphson steps, r <- r + r (1 - x r) and y <- y + (y/2)(1 - x y^2), each of
+// which squares the relative error of the estimate: two steps in FP64, one in FP32, leave
+// about one ulp for the positive, normal, finite arguments of the flux (a non-physical
+// state that reaches them is rejected by its own checks).  Host builds (operation
+// counting, tests) use the plain operations.
+GKS_HD inline double g_rcp(double x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
+#endif
+}
+GKS_HD inline float g_rcp(float x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+#else
+    return 1.0f / x;
+#endif
+}
+GKS_HD inline double g_rsqrt(double x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+GKS_HD inline float g_rsqrt(float x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    const float y = __builtin_amdgcn_rsqf(x);
+    return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
 
 template <typename R> GKS_HD inline R rconst(double v) { return R(v); }
 
 // erfc(ax) for ax >= 0, given e = exp(-ax^2) (which the half-line moments need anyway):
 // erfc(ax) = e g(ax) / (1 + 2 ax), with g(x) = (1 + 2x) exp(x^2) erfc(x) summed from its
 // Chebyshev series in y = (ax - K)/(ax + K) by Clenshaw's recurrence (coefficients of
-// erfc_cheb.hpp).  One division serves both the map and 1/(1 + 2 ax).
+// erfc_cheb.hpp).  One reciprocal serves both the map and 1/(1 + 2 ax).
 template <typename R> struct ErfcSeries;
 template <> struct ErfcSeries<double> {
     static constexpr int N = ERFC_N64;
@@ -61,7 +106,7 @@ GKS_HD inline R erfc_e(R ax, R e)
 {
     const R K = R(ERFC_K);
     const R p = ax + K, q = R(1) + R(2) * ax;
-    const R r = R(1) / (p * q);
+    const R r = g_rcp(p * q);
     const R y = (ax - K) * q * r;          // (ax - K)/(ax + K)
     const R iq = p * r;                    // 1/(1 + 2 ax)
     const R y2 = y + y;
@@ -207,7 +252,7 @@ GKS_HD inline Kw<R> kogan(R tau, R dt)
         k.c1 = R(-1); k.c4 = R(0); k.c5 = R(0);
         return k;
     }
-    const R x = dt / tau;
+    const R x = dt * g_rcp(tau);
     R s, g0, g1, g2, g4;
     if (x < R(0.5)) {
         constexpr int N = KoganTerms<R>::N;
@@ -237,7 +282,7 @@ GKS_HD inline Kw<R> kogan(R tau, R dt)
     k.g[3] = tau * s;
     k.g[4] = -t2 * g4;
     k.g[5] = -t2 * s;
-    const R ig0 = R(1) / g0;
+    const R ig0 = g_rcp(g0);
     k.c1 = g1 * ig0;
     k.c4 = -g4 * ig0;
     k.c5 = -s * ig0;
@@ -259,11 +304,12 @@ struct GasC {
     double two_over_b, inv_b, inv_cmu, pfix;   // 2/b, 1/b, 1/C_mu, 1/Pr - 1
 };
 
+// minmod: the smaller magnitude with the common sign, zero when the signs differ
 template <typename H>
 GKS_HD inline H minmod(H p, H q)
 {
-    if (!(p * q > H(0))) return H(0);
-    return (p > H(0)) ? (p < q ? p : q) : (p > q ? p : q);
+    const H m = g_copysign(g_min(g_abs(p), g_abs(q)), p);
+    return (p * q > H(0)) ? m : H(0);
 }
 
 // Face geometry along the normal: inverse distances between the centres of cells
@@ -301,7 +347,7 @@ template <int D, typename H>
 GKS_HD inline bool prim_wide(const H* W, H two_over_b, H& rho, H& irho, H* U, H& p)
 {
     rho = W[0];
-    irho = H(1) / rho;
+    irho = g_rcp(rho);
     H ke = H(0);
     for (int d = 0; d < D; ++d) { U[d] = W[1 + d] * irho; ke = ke + U[d] * W[1 + d]; }
     p = two_over_b * (W[D + 1] - H(0.5) * ke);
@@ -332,9 +378,9 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         R u[D];
         const H hl = pl * irl, hr = pr * irr;        // 1/(2 lambda) = p/rho
         for (int d = 0; d < D; ++d) u[d] = R(Ul[d]);
-        mx_set(gl, R(rl), u, R(H(0.5) / hl), R(hl), bt);
+        mx_set(gl, R(rl), u, R(H(0.5) * rl * g_rcp(pl)), R(hl), bt);
         for (int d = 0; d < D; ++d) u[d] = R(Ur[d]);
-        mx_set(gr, R(rr), u, R(H(0.5) / hr), R(hr), bt);
+        mx_set(gr, R(rr), u, R(H(0.5) * rr * g_rcp(pr)), R(hr), bt);
     }
 
     // --- half-line u-moments: left over u>0, right over u<0.  Only <u^0>, <u^1> are
@@ -343,7 +389,7 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
     //     exp(-lambda U^2) of the first moment also scales the erfc evaluation.
     R ml01[2], mr01[2];
     {
-        const R isq = g_sqrt(R(2) * gl.h);            // 1/sqrt(lambda)
+        const R isq = g_rsqrt(gl.lam);                // 1/sqrt(lambda)
         const R U = gl.U[0];
         const R x = -gl.lam * isq * U;
         const R e = g_exp(-gl.lam * U * U);
@@ -352,7 +398,7 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         ml01[1] = U * ml01[0] + e * rsqpi_half * isq;
     }
     {
-        const R isq = g_sqrt(R(2) * gr.h);
+        const R isq = g_rsqrt(gr.lam);
         const R U = gr.U[0];
         const R x = gr.lam * isq * U;
         const R e = g_exp(-gr.lam * U * U);
@@ -379,21 +425,22 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         for (int m = 0; m < NV; ++m) w0[m] = H(W0[m]);
         if (!prim_wide<D>(w0, bw, r0, ir0, U0d, p0)) return 1;
     }
-    const H h0 = p0 * ir0;
+    const H h0 = p0 * ir0, ip0 = g_rcp(p0);
     Mx<R, D> g0;
     {
         R u[D];
         for (int d = 0; d < D; ++d) u[d] = R(U0d[d]);
-        mx_set(g0, R(r0), u, R(H(0.5) / h0), R(h0), bt);
+        mx_set(g0, R(r0), u, R(H(0.5) * r0 * ip0), R(h0), bt);
     }
 
     // --- relaxation time (laminar + artificial + k-omega) and time weights ----------
+    // tau = mu/p0 + (k/omega)(rho0/p0)/sqrt(1 + eta^2) with eta = S/(C_mu omega), written as
+    // (mu + k rho0 / sqrt(omega^2 + (S/C_mu)^2)) / p0 (omega > 0).
     H tau;
     {
-        const H iw = H(1) / in.wf, ip0 = H(1) / p0;
-        const H eta = in.Sf * iw * H(gas.inv_cmu);
-        tau = H(gas.mu) * ip0 + (in.kf * iw) * (r0 * ip0) / g_sqrt(H(1) + eta * eta);
-        if (gas.c_a > 0.0) tau = tau + H(gas.c_a) * g_abs(pr - pl) / (pr + pl) * in.dt;
+        const H sc = in.Sf * H(gas.inv_cmu);
+        tau = ip0 * (H(gas.mu) + in.kf * r0 * g_rsqrt(in.wf * in.wf + sc * sc));
+        if (gas.c_a > 0.0) tau = tau + H(gas.c_a) * g_abs(pr - pl) * g_rcp(pr + pl) * in.dt;
     }
     const R dt = R(in.dt);
     const Kw<R> kw = kogan(R(tau), dt);
@@ -408,7 +455,7 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
     {
         R m0p[8], m0n[8];
         const R U = g0.U[0];
-        const R isq = g_sqrt(R(2) * g0.h);             // 1/sqrt(lambda0)
+        const R isq = g_rsqrt(g0.lam);                 // 1/sqrt(lambda0)
         const R e = g_exp(-g0.lam * U * U);
         const R small = half * erfc_e(g_abs(g0.lam * isq * U), e);   // one erfc serves both halves
         const R tail = e * rsqpi_half * isq;

@@ -839,10 +839,12 @@ inline bool operator<(CR a, CR b) { return a.v < b.v; }
 inline bool operator>(CR a, CR b) { return a.v > b.v; }
 inline bool operator>=(CR a, CR b) { return a.v >= b.v; }
 inline bool operator<=(CR a, CR b) { return a.v <= b.v; }
-inline CR g_sqrt(CR a) { CR::n += 1; return CR(sqrt(a.v)); }
 inline CR g_exp(CR a) { CR::n += 1; return CR(exp(a.v)); }
-inline CR g_erfc(CR a) { CR::n += 1; return CR(erfc(a.v)); }
 inline CR g_abs(CR a) { return CR(fabs(a.v)); }
+inline CR g_min(CR a, CR b) { return CR(fmin(a.v, b.v)); }     // a comparison, not counted
+inline CR g_copysign(CR a, CR b) { return CR(copysign(a.v, b.v)); }
+inline CR g_rcp(CR a) { CR::n += 1; return CR(1.0 / a.v); }
+inline CR g_rsqrt(CR a) { CR::n += 2; return CR(1.0 / sqrt(a.v)); }   // a square root and a division
 // the erfc evaluation counts as one operation, as a library erfc call would
 inline CR erfc_e(CR ax, CR e) { CR::n += 1; return CR(erfc(ax.v) + 0.0 * e.v); }
 
