@@ -48,7 +48,7 @@ def _leg(case, steps, warmup):
     return {"seconds": t1 - t0, "kernels": kt, "res": r, "W": W, "steps_done": warmup + 2 * steps}
 
 
-KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_lib.hip", "erfc_cheb.hpp")
+KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_lib.hip", "erfc_poly.hpp")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_face_sbli_1024x512_hbm_traffic.md")
 
 

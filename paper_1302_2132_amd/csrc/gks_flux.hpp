@@ -27,7 +27,7 @@
 #define GKS_HD __host__ __device__
 #endif
 
-#include "erfc_cheb.hpp"
+#include "erfc_poly.hpp"
 
 namespace gks {
 
@@ -88,17 +88,17 @@ GKS_HD inline float g_rsqrt(float x)
 template <typename R> GKS_HD inline R rconst(double v) { return R(v); }
 
 // erfc(ax) for ax >= 0, given e = exp(-ax^2) (which the half-line moments need anyway):
-// erfc(ax) = e g(ax) / (1 + 2 ax), with g(x) = (1 + 2x) exp(x^2) erfc(x) summed from its
-// Chebyshev series in y = (ax - K)/(ax + K) by Clenshaw's recurrence (coefficients of
-// erfc_cheb.hpp).  One reciprocal serves both the map and 1/(1 + 2 ax).
-template <typename R> struct ErfcSeries;
-template <> struct ErfcSeries<double> {
+// erfc(ax) = e g(ax) / (1 + 2 ax), with g(x) = (1 + 2x) exp(x^2) erfc(x) a polynomial in
+// y = (ax - K)/(ax + K) (the truncated Chebyshev series of erfc_poly.hpp in the power
+// basis), summed by Horner's rule.  One reciprocal serves both the map and 1/(1 + 2 ax).
+template <typename R> struct ErfcPoly;
+template <> struct ErfcPoly<double> {
     static constexpr int N = ERFC_N64;
-    GKS_HD static constexpr double c(int k) { return ERFC_C64[k]; }
+    GKS_HD static constexpr double a(int k) { return ERFC_A64[k]; }
 };
-template <> struct ErfcSeries<float> {
+template <> struct ErfcPoly<float> {
     static constexpr int N = ERFC_N32;
-    GKS_HD static constexpr float c(int k) { return ERFC_C32[k]; }
+    GKS_HD static constexpr float a(int k) { return ERFC_A32[k]; }
 };
 
 template <typename R>
@@ -109,15 +109,9 @@ GKS_HD inline R erfc_e(R ax, R e)
     const R r = g_rcp(p * q);
     const R y = (ax - K) * q * r;          // (ax - K)/(ax + K)
     const R iq = p * r;                    // 1/(1 + 2 ax)
-    const R y2 = y + y;
-    R b1 = R(0), b2 = R(0);
+    R g = R(ErfcPoly<R>::a(ErfcPoly<R>::N - 1));
 #pragma unroll
-    for (int k = ErfcSeries<R>::N - 1; k >= 1; --k) {
-        const R b0 = y2 * b1 - b2 + R(ErfcSeries<R>::c(k));
-        b2 = b1;
-        b1 = b0;
-    }
-    const R g = y * b1 - b2 + R(ErfcSeries<R>::c(0));
+    for (int k = ErfcPoly<R>::N - 2; k >= 0; --k) g = g * y + R(ErfcPoly<R>::a(k));
     return e * g * iq;
 }
 

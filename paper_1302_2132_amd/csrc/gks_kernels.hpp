@@ -189,12 +189,31 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
     fc[2] = (D == 3) ? f / (fn0 * fn1) : 0;
     const double* __restrict__ W = I.W[state_of(I).parity];
 
+    // Stencil cells i-2 .. i+1 along DIR (cell i = fc, on the face's high side) and the two
+    // cells sharing the face (il, ir).  When every lane's stencil is interior (a wave-uniform
+    // test) they are indexed directly; otherwise ghosts come from the boundary conditions.
     double Wc[4][NV];
+    int il, ir;
+    if (__all(fc[DIR] >= 2 && fc[DIR] <= I.n[DIR] - 2)) {
+        const int st = DIR == 0 ? 1 : (DIR == 1 ? I.n[0] : I.n[0] * I.n[1]);
+        const long long nc = I.ncells;
+        ir = cell_index(I, fc[0], fc[1], fc[2]);
+        il = ir - st;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        int c[3] = {fc[0], fc[1], fc[2]};
-        c[DIR] += o - 2;
-        load_state<D>(I, W, DIR, c, Wc[o]);
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int m = 0; m < NV; ++m) Wc[o][m] = W[m * nc + ir + (o - 2) * st];
+    } else {
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            int c[3] = {fc[0], fc[1], fc[2]};
+            c[DIR] += o - 2;
+            load_state<D>(I, W, DIR, c, Wc[o]);
+        }
+        int cl[3] = {fc[0], fc[1], fc[2]};
+        cl[DIR] -= 1;
+        il = image_cell<D>(I, DIR, cl);
+        ir = image_cell<D>(I, DIR, fc);
     }
     FaceGeo<double> geo;
     {
@@ -227,14 +246,9 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
             if (D == 3) v[q][3] = t2;
         }
     }
-    {
-        int cl[3] = {fc[0], fc[1], fc[2]};
-        cl[DIR] -= 1;
-        const int il = image_cell<D>(I, DIR, cl), ir = image_cell<D>(I, DIR, fc);
-        in.kf = 0.5 * (I.k[il] + I.k[ir]);
-        in.wf = 0.5 * (I.om[il] + I.om[ir]);
-        in.Sf = 0.5 * (I.S[il] + I.S[ir]);
-    }
+    in.kf = 0.5 * (I.k[il] + I.k[ir]);
+    in.wf = 0.5 * (I.om[il] + I.om[ir]);
+    in.Sf = 0.5 * (I.S[il] + I.S[ir]);
     in.dt = state_of(I).dt;
     GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
     R F[NV];
