@@ -168,10 +168,11 @@ gks_status gks_batch_step(gks_batch b, int32_t nsteps);
 /* Capture one step of the batch as a HIP graph; later gks_batch_step calls replay it. */
 gks_status gks_batch_capture(gks_batch b);
 
-/* Launch shape of the batch kernels: kind 0 = strain, 1 = face (2D FP64), 2 = face
- * (2D FP32), 3 = face (3D FP64), 4 = face (3D FP32), 5 = update.  grid = number of
- * persistent workgroups walking the tile table (0 = one per tile).  tile = faces per
- * face-kernel tile and workgroup (64, 128 or 256) for the face kinds, 0 otherwise.
+/* Launch shape of the batch kernels: kind 0 = strain, 1 = fused 2D tile kernel (FP64),
+ * 2 = fused 2D tile kernel (FP32 flux), 3 = face (3D FP64), 4 = face (3D FP32), 5 = update
+ * (3D).  grid = number of persistent workgroups walking the tile table (0 = one per
+ * tile).  tile = faces per face-kernel tile and workgroup (64, 128 or 256) for kinds 3
+ * and 4; 0 otherwise (the 2D tile is fixed: 16 x 15 cells per 256-thread workgroup).
  * Results do not depend on the launch shape (bitwise).  Invalidates a captured graph. */
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile);
 

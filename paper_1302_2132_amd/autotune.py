@@ -3,9 +3,10 @@
 The result of a step does not depend on the launch shape (every face flux and every
 per-tile partial sum is computed the same way whatever workgroup handles it), so the
 tuner times candidate shapes on the live batch: the steps it spends measuring are real
-steps of the solves.  Searched: for each face-kernel class present, faces per tile
-(64 / 128 / 256) times the persistent grid (one workgroup per tile, or 4/8/16 workgroups
-per CU); then the grid of the strain and update kernels.  The winner is cached in a JSON
+steps of the solves.  Searched: for each face-kernel class present, the persistent grid
+(one workgroup per tile, or 4/8/16 workgroups per CU) and, for the 3D classes, faces per
+tile (64 / 128 / 256; the fused 2D kernel has a fixed cell tile); then the grid of the
+strain kernel and, with 3D members, of the update kernel.  The winner is cached in a JSON
 file keyed by device, class mix and problem size, and reused without a search.
 """
 from __future__ import annotations
@@ -16,6 +17,11 @@ import time
 
 KIND_STRAIN, KIND_UPDATE = 0, 5
 TILES = (64, 128, 256)
+
+
+def tiles_of(c: int):
+    """Tile sizes of a face class: none to choose for the fused 2D kernel (classes 0, 1)."""
+    return (0,) if c < 2 else TILES
 
 
 def cls_of(case) -> int:
@@ -33,7 +39,7 @@ def _signature(batch) -> str:
     classes = sorted({cls_of(s.case) for s in batch.solvers})
     cells = sum(s.case.ncells for s in batch.solvers)
     bucket = 1 << max(int(cells).bit_length() - 1, 0)        # power-of-two size class
-    return f"{name}|classes={classes}|cells~{bucket}|members~{len(batch.solvers)}"
+    return f"{name}|classes={classes}|cells~{bucket}|members~{len(batch.solvers)}|fused2d"
 
 
 def _time_steps(batch, n: int) -> float:
@@ -80,7 +86,7 @@ def autotune(batch, steps_per_trial: int = 2, cache_path: str | None = None, use
     shape = {"face": {}, "strain_grid": 8 * cus, "update_grid": 8 * cus}
     for c in classes:
         trials = []
-        for tile in TILES:
+        for tile in tiles_of(c):
             for g in grids:
                 batch.set_launch(1 + c, g, tile)
                 batch.step(1)                       # first launch of a new shape: warm
@@ -89,7 +95,10 @@ def autotune(batch, steps_per_trial: int = 2, cache_path: str | None = None, use
         _, g, tile = min(trials)
         batch.set_launch(1 + c, g, tile)
         shape["face"][str(c)] = [g, tile]
-    for kind, keyname in ((KIND_STRAIN, "strain_grid"), (KIND_UPDATE, "update_grid")):
+    kinds = [(KIND_STRAIN, "strain_grid")]
+    if any(c >= 2 for c in classes):
+        kinds.append((KIND_UPDATE, "update_grid"))
+    for kind, keyname in kinds:
         trials = []
         for g in grids:
             batch.set_launch(kind, g, 0)

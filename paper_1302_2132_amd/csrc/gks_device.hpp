@@ -48,7 +48,7 @@ struct Inst {
     const double* k;
     const double* om;
     double* S;
-    void* F[3];                // face fluxes per axis: [nv][nface[d]], double or float
+    void* F[3];                // 3D face fluxes per axis: [nv][nface[d]], double or float (2D: none)
     const double* xf[3];
     const double* xc[3];
     const double* dx[3];
@@ -57,9 +57,10 @@ struct Inst {
     const double* icd[3];      // 1/(xc[i+1] - xc[i]), i from -2 to n
     const double* fgeo[3];     // per face f in [0, n]: xf-xc[f-1], xc[f]-xf, and their inverses
     const double* bcd[3][2];
-    double* part;              // per-tile partials [ntile_cell][PSTRIDE]
+    double* part;              // per-tile partials [max(ntile_cell, nstep_part)][PSTRIDE]
     State* st;
     int ntile_cell;
+    int nstep_part;            // partial slots written by a step: fused 2D tiles, else update tiles
     int ntile_face[3];
     int ntile_face_all;
     int face_tile;             // faces per face-kernel tile in the table holding this copy

@@ -175,8 +175,65 @@ __device__ inline void strain_cell(cref<Inst> I, int cell)
 // --------------------------------------------------------------------------------------
 // face fluxes
 // --------------------------------------------------------------------------------------
-// One face normal to axis DIR.  The axis is a template parameter so that every stencil
-// index and the rotation to the face-local frame are compile-time (no private arrays).
+// Flux through the face at position i (0..n) along axis DIR from its four stencil cells
+// Wc (i-2 .. i+1, ghosts already synthesised); k, omega and strain rate are averaged over
+// elements il, ir of the arrays kk, ww, ss (HBM or LDS: P is the pointer type).  Fg
+// receives the time-integrated flux with the momentum components in the global axis
+// order.  Returns nonzero for a non-physical state.  The axis is a template parameter so
+// that every index and the rotation to the face-local frame are compile-time (no private
+// arrays).
+template <typename R, int D, int DIR, typename P>
+__device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int i, const double (*Wc)[D + 2],
+                                                               P kk, P ww, P ss, int il, int ir, double dt, R* Fg)
+{
+    constexpr int NV = D + 2;
+    FaceGeo<double> geo;
+    {
+        const double* __restrict__ icd = I.icd[DIR];
+        geo.icd[0] = icd[i - 2];
+        geo.icd[1] = icd[i - 1];
+        geo.icd[2] = icd[i];
+        const double* __restrict__ fg = I.fgeo[DIR] + 4 * i;
+        geo.dl = fg[0];
+        geo.dr = fg[1];
+        geo.idl = fg[2];
+        geo.idr = fg[3];
+    }
+    FaceIn<D, double> in;
+    reconstruct<D, double>(Wc, geo, in);
+
+    // face-local frame: normal momentum first, then the remaining axes in order
+    constexpr int P1 = DIR == 0 ? 1 : 0;             // first tangential axis
+    constexpr int P2 = DIR == 2 ? 1 : 2;             // second tangential axis (3D)
+    if (DIR != 0) {
+        double* v[6] = {in.Wl, in.Wr, in.sl, in.sr, in.Wi, in.Wi1};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double mn = v[q][1 + DIR], t1 = v[q][1 + P1];
+            double t2 = 0.0;
+            if (D == 3) t2 = v[q][1 + P2];
+            v[q][1] = mn;
+            v[q][2] = t1;
+            if (D == 3) v[q][3] = t2;
+        }
+    }
+    in.kf = 0.5 * (kk[il] + kk[ir]);
+    in.wf = 0.5 * (ww[il] + ww[ir]);
+    in.Sf = 0.5 * (ss[il] + ss[ir]);
+    in.dt = dt;
+    GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
+    R F[NV];
+    const int bad = face_flux<R, D, double>(in, gas, F);
+    Fg[0] = F[0];
+    Fg[1 + DIR] = F[1];
+    Fg[1 + P1] = F[2];
+    if (D == 3) Fg[1 + P2] = F[3];
+    Fg[D + 1] = F[D + 1];
+    return bad;
+}
+
+// One face normal to axis DIR, stencil read from the state in HBM, flux written to the
+// axis' face-flux array (structure of arrays).
 template <typename R, int D, int DIR>
 __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int f)
 {
@@ -215,70 +272,32 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
         il = image_cell<D>(I, DIR, cl);
         ir = image_cell<D>(I, DIR, fc);
     }
-    FaceGeo<double> geo;
-    {
-        const int i = fc[DIR];
-        const double* __restrict__ icd = I.icd[DIR];
-        geo.icd[0] = icd[i - 2];
-        geo.icd[1] = icd[i - 1];
-        geo.icd[2] = icd[i];
-        const double* __restrict__ fg = I.fgeo[DIR] + 4 * i;
-        geo.dl = fg[0];
-        geo.dr = fg[1];
-        geo.idl = fg[2];
-        geo.idr = fg[3];
-    }
-    FaceIn<D, double> in;
-    reconstruct<D, double>(Wc, geo, in);
-
-    // face-local frame: normal momentum first, then the remaining axes in order
-    constexpr int P1 = DIR == 0 ? 1 : 0;             // first tangential axis
-    constexpr int P2 = DIR == 2 ? 1 : 2;             // second tangential axis (3D)
-    if (DIR != 0) {
-        double* v[6] = {in.Wl, in.Wr, in.sl, in.sr, in.Wi, in.Wi1};
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const double mn = v[q][1 + DIR], t1 = v[q][1 + P1];
-            double t2 = 0.0;
-            if (D == 3) t2 = v[q][1 + P2];
-            v[q][1] = mn;
-            v[q][2] = t1;
-            if (D == 3) v[q][3] = t2;
-        }
-    }
-    in.kf = 0.5 * (I.k[il] + I.k[ir]);
-    in.wf = 0.5 * (I.om[il] + I.om[ir]);
-    in.Sf = 0.5 * (I.S[il] + I.S[ir]);
-    in.dt = state_of(I).dt;
-    GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
     R F[NV];
-    if (face_flux<R, D, double>(in, gas, F)) atomicOr(&I.st->err, 1);
+    const double* kk = I.k;
+    const double* ww = I.om;
+    const double* ss = I.S;
+    if (face_eval<R, D, DIR>(I, fc[DIR], Wc, kk, ww, ss, il, ir, state_of(I).dt, F)) atomicOr(&I.st->err, 1);
     R* __restrict__ out = (R*)I.F[DIR];
     const long long nf = I.nface[DIR];   // 64-bit: component offsets m * nf may pass 2^31
     out[f] = F[0];
-    out[(long long)(1 + DIR) * nf + f] = F[1];
-    out[(long long)(1 + P1) * nf + f] = F[2];
-    if (D == 3) out[(long long)(1 + P2) * nf + f] = F[3];
+    out[nf + f] = F[1];
+    out[2 * nf + f] = F[2];
+    if (D == 3) out[3 * nf + f] = F[3];
     out[(long long)(D + 1) * nf + f] = F[D + 1];
 }
 
-#ifndef GKS_FACE_WAVES_FP64_2D
-#define GKS_FACE_WAVES_FP64_2D 3
-#endif
-#ifndef GKS_FACE_WAVES_FP64_3D
-#define GKS_FACE_WAVES_FP64_3D 2
+#ifndef GKS_FACE_WAVES_FP64
+#define GKS_FACE_WAVES_FP64 2
 #endif
 #ifndef GKS_FACE_WAVES_FP32
 #define GKS_FACE_WAVES_FP32 4
 #endif
-// Register budget of the face kernel: at least this many waves per SIMD (3 leaves 168
-// VGPRs per lane, enough for the 2D FP64 flux; 2 leaves 256 for the 3D FP64 flux; 4
-// leaves 128 for the FP32 flux).  TILE faces per workgroup (64, 128 or 256: a batch's
-// autotuned shape).
+// Register budget of the face kernel (instantiated for 3D; 2D steps use k_tile2): at least
+// this many waves per SIMD (2 leaves 256 VGPRs per lane for the 3D FP64 flux, 4 leaves 128
+// for the FP32 flux).  TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
 template <typename R, int D, int TILE>
 __global__ __launch_bounds__(TILE)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32
-                                                  : (D == 2 ? GKS_FACE_WAVES_FP64_2D : GKS_FACE_WAVES_FP64_3D))))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_FACE_WAVES_FP64)))
 void k_face(const void* __restrict__ table, int cap, int cls)
 {
     const TabC tv(table, cap);
@@ -323,24 +342,25 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
+// Everything the update of one cell reads: old state, the fluxes through its low and high
+// faces per axis, inverse widths, k and omega.
+template <int D>
+struct CellRead {
+    double old[D + 2], fl[D][D + 2], fh[D][D + 2], idx[D], kc, wc;
+};
+
 template <int D, typename RF>
-__device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2, double& rate, int& bad)
+__device__ inline void update_read(cref<Inst> I, const double* __restrict__ Wo, int cell, CellRead<D>& x)
 {
     constexpr int NV = D + 2;
-    const int cur = state_of(I).parity;
-    const double* __restrict__ Wo = I.W[cur];
-    double* __restrict__ Wn = I.W[cur ^ 1];
     int c[3];
     c[0] = cell % I.n[0];
     c[1] = (cell / I.n[0]) % I.n[1];
     c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
-    // Every read of the cell first: the compiler cannot move a load above a store through
-    // another pointer, so reads interleaved with the stores below would be serialised.
-    double old[NV], fl[D][NV], fh[D][NV], idx_[3];
 #pragma unroll
-    for (int d = 0; d < D; ++d) idx_[d] = I.idx[d][c[d]];
+    for (int d = 0; d < D; ++d) x.idx[d] = I.idx[d][c[d]];
 #pragma unroll
-    for (int m = 0; m < NV; ++m) old[m] = Wo[(long long)m * I.ncells + cell];
+    for (int m = 0; m < NV; ++m) x.old[m] = Wo[(long long)m * I.ncells + cell];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const int fn0 = I.n[0] + (d == 0), fn1 = I.n[1] + (d == 1);
@@ -350,39 +370,233 @@ __device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2
         const RF* __restrict__ F = (const RF*)I.F[d];
 #pragma unroll
         for (int m = 0; m < NV; ++m) {
-            fl[d][m] = double(F[m * nf + lo]);
-            fh[d][m] = double(F[m * nf + hi]);
+            x.fl[d][m] = double(F[m * nf + lo]);
+            x.fh[d][m] = double(F[m * nf + hi]);
         }
     }
-    const double kc = I.k[cell], wc = I.om[cell];
+    x.kc = I.k[cell];
+    x.wc = I.om[cell];
+}
+
+// New state of one cell (stored when `store`), its squared residual components added to
+// r2, its CFL rate folded into `rate` (max), a non-physical state flagged in `bad`.
+template <int D>
+__device__ inline void update_apply(cref<Inst> I, double* __restrict__ Wn, int cell, bool store,
+                                    const CellRead<D>& x, double idt, double* r2, double& rate, int& bad)
+{
+    constexpr int NV = D + 2;
     double w[NV];
-    const double idt = 1.0 / dt;
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
-        double acc = old[m];
+        double acc = x.old[m];
 #pragma unroll
-        for (int d = 0; d < D; ++d) acc -= (fh[d][m] - fl[d][m]) * idx_[d];
+        for (int d = 0; d < D; ++d) acc -= (x.fh[d][m] - x.fl[d][m]) * x.idx[d];
         w[m] = acc;
-        Wn[(long long)m * I.ncells + cell] = acc;
-        const double r = (acc - old[m]) * idt;
-        r2[m] = r * r;
+        if (store) Wn[(long long)m * I.ncells + cell] = acc;
+        const double r = (acc - x.old[m]) * idt;
+        r2[m] += store ? r * r : 0.0;
     }
+    if (!store) return;
     // positivity and the CFL rate of the new state
     double ke = 0.0, U[3];
     const double rho = w[0], irho = 1.0 / rho;
     for (int d = 0; d < D; ++d) { U[d] = w[1 + d] * irho; ke += U[d] * w[1 + d]; }
     const double p = I.two_over_b * (w[D + 1] - 0.5 * ke);
-    if (!(rho > 0.0) || !(p > 0.0) || !(rho < 1e300) || !(p < 1e300)) { bad = 1; rate = 0.0; return; }
+    if (!(rho > 0.0) || !(p > 0.0) || !(rho < 1e300) || !(p < 1e300)) { bad = 1; return; }
     // CFL rate  sum_d (|U_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2
     const double cs = sqrt(I.gamma * p * irho);
     const double fac = fmax(4.0 / 3.0, I.gamma / I.prandtl);
-    const double nu = (I.mu * irho + kc / wc) * fac;
+    const double nu = (I.mu * irho + x.kc / x.wc) * fac;
     double r = 0.0, r2s = 0.0;
     for (int d = 0; d < D; ++d) {
-        r += (fabs(U[d]) + cs) * idx_[d];
-        r2s += idx_[d] * idx_[d];
+        r += (fabs(U[d]) + cs) * x.idx[d];
+        r2s += x.idx[d] * x.idx[d];
     }
-    rate = r + 2.0 * nu * r2s;
+    rate = fmax(rate, r + 2.0 * nu * r2s);
+}
+
+// Update of one cell from the face fluxes in HBM: every read first (the compiler cannot
+// move a load above a store through another pointer), then the stores.
+template <int D, typename RF>
+__device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2, double& rate, int& bad)
+{
+    const int cur = state_of(I).parity;
+    CellRead<D> x;
+    update_read<D, RF>(I, I.W[cur], cell, x);
+    update_apply<D>(I, I.W[cur ^ 1], cell, true, x, 1.0 / dt, r2, rate, bad);
+}
+
+// --------------------------------------------------------------------------------------
+// fused 2D step: a tile's fluxes computed into LDS, then the tile's update
+// --------------------------------------------------------------------------------------
+// A workgroup of T2_THREADS threads owns a tile of T2X x T2Y cells.  It stages the state
+// of the tile and its two-cell halo (no corners: every stencil is one-dimensional) and k,
+// omega, strain rate on a one-cell halo in LDS, synthesising ghosts once; computes the
+// (T2X+1) x T2Y x-faces and T2X x (T2Y+1) y-faces of the tile into LDS (one of each per
+// thread; faces on the tile edge are also computed by the neighbouring tile); then
+// updates its cells from LDS.  Fluxes never go to HBM, and the update needs no launch of
+// its own.  The arithmetic of every face and cell is that of k_face and k_update.
+constexpr int T2X = 16, T2Y = 15, T2_THREADS = 256;
+constexpr int T2_WX = T2X + 4, T2_WY = T2Y + 4;     // state window (two-cell halo)
+constexpr int T2_KX = T2X + 2, T2_KY = T2Y + 2;     // k, omega, strain window (one-cell halo)
+constexpr int T2_NFX = (T2X + 1) * T2Y, T2_NFY = T2X * (T2Y + 1);
+static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_THREADS,
+              "one x-face, one y-face and one cell per thread");
+
+// Register budget: 3 waves per SIMD leave 168 VGPRs per lane, enough for the 2D FP64 flux;
+// the FP32-flux form gets 4 (128 VGPRs).
+#ifndef GKS_TILE2_WAVES_FP64
+#define GKS_TILE2_WAVES_FP64 3
+#endif
+
+template <typename R>
+__global__ __launch_bounds__(T2_THREADS)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_TILE2_WAVES_FP64)))
+void k_tile2(const void* __restrict__ table, int cap, int cls)
+{
+    constexpr int NV = 4;
+    __shared__ double sW[NV][T2_WX * T2_WY];
+    __shared__ double sK[3][T2_KX * T2_KY];
+    __shared__ R sFx[NV][T2_NFX];
+    __shared__ R sFy[NV][T2_NFY];
+    __shared__ double sh_sum[5 * 4];
+    __shared__ double sh_max[4];
+    __shared__ int sh_bad[4];
+    const TabC tv(table, cap);
+    const int count = tv.hdr->ncls[cls];
+    const int total = tv.hdr->total_face[cls];
+    cptr<int> prefix = tv.cls_prefix + cls * (cap + 1);
+    cptr<int> member = tv.cls_member + cls * cap;
+    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+        const int mj = find_member(prefix, count, tile);
+        cref<Inst> I = tv.inst[member[mj]];
+        if (!state_of(I).active) continue;
+        const int lt = tile - prefix[mj];
+        const int n0 = I.n[0], n1 = I.n[1];
+        const int nbx = (n0 + T2X - 1) / T2X;
+        const int x0 = (lt % nbx) * T2X, y0 = (lt / nbx) * T2Y;
+        const int tx = min(T2X, n0 - x0), ty = min(T2Y, n1 - y0);
+        const int cur = state_of(I).parity;
+        const double* __restrict__ W = I.W[cur];
+        const double dt = state_of(I).dt;
+
+        // stage the state window: tile rows with the x halo, tile columns with the y halo
+        for (int e = tid; e < T2_WX * T2_WY; e += T2_THREADS) {
+            const int a = e % T2_WX, b = e / T2_WX;
+            const bool row = b >= 2 && b < ty + 2 && a < tx + 4;
+            const bool col = a >= 2 && a < tx + 2 && b < ty + 4;
+            if (!(row || col)) continue;
+            const int c[3] = {x0 - 2 + a, y0 - 2 + b, 0};
+            const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;     // the ghost axis, if any
+            double w[NV];
+            load_state<2>(I, W, d, c, w);
+#pragma unroll
+            for (int m = 0; m < NV; ++m) sW[m][e] = w[m];
+        }
+        // stage k, omega and strain rate on the one-cell halo
+        for (int e = tid; e < T2_KX * T2_KY; e += T2_THREADS) {
+            const int a = e % T2_KX, b = e / T2_KX;
+            const bool row = b >= 1 && b < ty + 1 && a < tx + 2;
+            const bool col = a >= 1 && a < tx + 1 && b < ty + 2;
+            if (!(row || col)) continue;
+            const int c[3] = {x0 - 1 + a, y0 - 1 + b, 0};
+            const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;
+            const int ic = image_cell<2>(I, d, c);
+            sK[0][e] = I.k[ic];
+            sK[1][e] = I.om[ic];
+            sK[2][e] = I.S[ic];
+        }
+        __syncthreads();
+
+        {   // x-face (i, j): between cells x0+i-1 and x0+i of row y0+j
+            const int i = tid % (T2X + 1), j = tid / (T2X + 1);
+            if (tid < T2_NFX && i <= tx && j < ty) {
+                double Wc[4][NV];
+#pragma unroll
+                for (int o = 0; o < 4; ++o)
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + 2) * T2_WX + i + o];
+                const int kl = (j + 1) * T2_KX + i;
+                R F[NV];
+                if (face_eval<R, 2, 0>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F))
+                    atomicOr(&I.st->err, 1);
+                sFx[0][tid] = F[0];
+                sFx[1][tid] = F[1];
+                sFx[2][tid] = F[2];
+                sFx[3][tid] = F[3];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);      // keep the two passes' registers apart
+        {   // y-face (i, j): between cells y0+j-1 and y0+j of column x0+i
+            const int i = tid % T2X, j = tid / T2X;
+            if (tid < T2_NFY && i < tx && j <= ty) {
+                double Wc[4][NV];
+#pragma unroll
+                for (int o = 0; o < 4; ++o)
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + o) * T2_WX + i + 2];
+                const int kl = j * T2_KX + i + 1;
+                R F[NV];
+                if (face_eval<R, 2, 1>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt, F))
+                    atomicOr(&I.st->err, 1);
+                sFy[0][tid] = F[0];
+                sFy[1][tid] = F[1];
+                sFy[2][tid] = F[2];
+                sFy[3][tid] = F[3];
+            }
+        }
+        __syncthreads();
+
+        // update of cell (i, j) of the tile
+        double r2[5] = {0, 0, 0, 0, 0};
+        double rate = 0.0;
+        int bad = 0;
+        {
+            const int i = tid % T2X, j = tid / T2X;
+            const bool own = tid < T2X * T2Y && i < tx && j < ty;
+            const int ii = own ? i : 0, jj = own ? j : 0;
+            CellRead<2> x;
+            const int ew = (jj + 2) * T2_WX + ii + 2, ek = (jj + 1) * T2_KX + ii + 1;
+            const int fx = jj * (T2X + 1) + ii, fy = jj * T2X + ii;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+                x.old[m] = sW[m][ew];
+                x.fl[0][m] = double(sFx[m][fx]);
+                x.fh[0][m] = double(sFx[m][fx + 1]);
+                x.fl[1][m] = double(sFy[m][fy]);
+                x.fh[1][m] = double(sFy[m][fy + T2X]);
+            }
+            x.idx[0] = I.idx[0][x0 + ii];
+            x.idx[1] = I.idx[1][y0 + jj];
+            x.kc = sK[0][ek];
+            x.wc = sK[1][ek];
+            const int cell = (y0 + jj) * n0 + x0 + ii;
+            update_apply<2>(I, I.W[cur ^ 1], cell, own, x, 1.0 / dt, r2, rate, bad);
+        }
+        // tile partials in a fixed order
+        for (int m = 0; m < NV; ++m) {
+            const double s = wave_sum(r2[m]);
+            if (lane == 0) sh_sum[m * 4 + wv] = s;
+        }
+        {
+            const double mx = wave_max(rate);
+            const int any = __any(bad);
+            if (lane == 0) { sh_max[wv] = mx; sh_bad[wv] = any; }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            State* st = I.st;                    // every workgroup of the solve writes the same values
+            st->fresh = cur ^ 1;
+            st->pending = 1;
+            double* part = I.part + (long long)lt * PSTRIDE;
+            for (int m = 0; m < NV; ++m)
+                part[m] = (sh_sum[m * 4 + 0] + sh_sum[m * 4 + 1]) + (sh_sum[m * 4 + 2] + sh_sum[m * 4 + 3]);
+            part[5] = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
+            if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&I.st->err, 1);
+        }
+        __syncthreads();
+    }
 }
 
 // time step following a state whose max CFL rate is `rate`, and the time it ends at
@@ -410,7 +624,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mi = find_member(tv.cell_prefix, count, tile);
         cref<Inst> I = tv.inst[mi];
-        if (!state_of(I).active) continue;
+        if (I.dim == 2 || !state_of(I).active) continue;   // 2D solves update in k_tile2
         const int lt = tile - tv.cell_prefix[mi];
         const int cell = lt * CELL_TILE + (int)threadIdx.x;
         double r2[5] = {0, 0, 0, 0, 0};
@@ -418,13 +632,8 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
         int bad = 0;
         const double dt = state_of(I).dt;
         if (cell < I.ncells) {
-            if (I.dim == 2) {
-                if (I.precision) update_cell<2, float>(I, cell, dt, r2, rate, bad);
-                else update_cell<2, double>(I, cell, dt, r2, rate, bad);
-            } else {
-                if (I.precision) update_cell<3, float>(I, cell, dt, r2, rate, bad);
-                else update_cell<3, double>(I, cell, dt, r2, rate, bad);
-            }
+            if (I.precision) update_cell<3, float>(I, cell, dt, r2, rate, bad);
+            else update_cell<3, double>(I, cell, dt, r2, rate, bad);
         }
         // workgroup reductions in a fixed order
         for (int m = 0; m < I.nv; ++m) {
@@ -515,7 +724,7 @@ __device__ inline void finish_member(cref<Inst> I, int mode, double* sh)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     State* st = I.st;
     if (mode == 0 && !st->pending) return;
-    const int nv = I.nv, nt = I.ntile_cell;
+    const int nv = I.nv, nt = mode == 0 ? I.nstep_part : I.ntile_cell;
     const int first = mode == 0 ? 0 : 5;    // mode 1 needs the rate only
     double acc[5] = {0, 0, 0, 0, 0}, rmax = 0.0;
     const double* __restrict__ part = I.part;
@@ -602,15 +811,11 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
     }
 }
 
-template __global__ void k_face<double, 2, 64>(const void*, int, int);
-template __global__ void k_face<double, 2, 128>(const void*, int, int);
-template __global__ void k_face<double, 2, 256>(const void*, int, int);
+template __global__ void k_tile2<double>(const void*, int, int);
+template __global__ void k_tile2<float>(const void*, int, int);
 template __global__ void k_face<double, 3, 64>(const void*, int, int);
 template __global__ void k_face<double, 3, 128>(const void*, int, int);
 template __global__ void k_face<double, 3, 256>(const void*, int, int);
-template __global__ void k_face<float, 2, 64>(const void*, int, int);
-template __global__ void k_face<float, 2, 128>(const void*, int, int);
-template __global__ void k_face<float, 2, 256>(const void*, int, int);
 template __global__ void k_face<float, 3, 64>(const void*, int, int);
 template __global__ void k_face<float, 3, 128>(const void*, int, int);
 template __global__ void k_face<float, 3, 256>(const void*, int, int);

@@ -11,6 +11,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -28,7 +29,12 @@ struct Layout {
     long long ncells, nface[3];
     int ntan[3];
     int ntile_cell, ntile_face[3];
+    int ntile2;        // fused 2D tiles (2D only)
+    int nstep_part;    // partial slots of a step
 };
+
+// fused 2D tiles of an n0 x n1 mesh
+static int tiles2(long long n0, long long n1) { return (int)(((n0 + T2X - 1) / T2X) * ((n1 + T2Y - 1) / T2Y)); }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -91,7 +97,7 @@ void layout(const gks_config* c, Layout* L)
         L->nface[d] = L->ncells / n[d] * (n[d] + 1);
         L->ntan[d] = (int)(L->ncells / n[d]);
         L->ntile_face[d] = (int)((L->nface[d] + FACE_TILE - 1) / FACE_TILE);
-        L->F[d] = take(fb * nv * (size_t)L->nface[d]);
+        if (D == 3) L->F[d] = take(fb * nv * (size_t)L->nface[d]);   // 2D fluxes stay in LDS
         L->xf[d] = take(sizeof(double) * (n[d] + 5));
         L->xc[d] = take(sizeof(double) * (n[d] + 4));
         L->dx[d] = take(sizeof(double) * (n[d] + 4));
@@ -105,7 +111,9 @@ void layout(const gks_config* c, Layout* L)
         }
     }
     L->ntile_cell = (int)((L->ncells + CELL_TILE - 1) / CELL_TILE);
-    L->part = take(sizeof(double) * PSTRIDE * (size_t)L->ntile_cell);
+    L->ntile2 = D == 2 ? tiles2(n[0], n[1]) : 0;
+    L->nstep_part = D == 2 ? L->ntile2 : L->ntile_cell;
+    L->part = take(sizeof(double) * PSTRIDE * (size_t)std::max(L->ntile_cell, L->nstep_part));
     L->st = take(sizeof(State));
     L->tab = take(TabView::bytes(1));
     L->total = off;
@@ -240,12 +248,17 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
     for (size_t i = 0; i < members.size(); ++i) {
         tv.inst[i] = *members[i];
         Inst& I = tv.inst[i];
-        const int ft = face_tile[I.cls];
-        I.face_tile = ft;
-        I.ntile_face_all = 0;
-        for (int d = 0; d < 3; ++d) {
-            I.ntile_face[d] = d < I.dim ? (I.nface[d] + ft - 1) / ft : 0;
-            I.ntile_face_all += I.ntile_face[d];
+        if (I.dim == 2) {                        // fused 2D kernel: fixed cell tiles
+            I.face_tile = T2_THREADS;
+            I.ntile_face_all = tiles2(I.n[0], I.n[1]);
+        } else {
+            const int ft = face_tile[I.cls];
+            I.face_tile = ft;
+            I.ntile_face_all = 0;
+            for (int d = 0; d < 3; ++d) {
+                I.ntile_face[d] = d < I.dim ? (I.nface[d] + ft - 1) / ft : 0;
+                I.ntile_face_all += I.ntile_face[d];
+            }
         }
         cells += I.ntile_cell;
         tv.cell_prefix[i + 1] = cells;
@@ -259,13 +272,15 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
     for (int c = 0; c < NCLS; ++c) tv.hdr->total_face[c] = faces[c];
 }
 
+// Kernel of a face class: the fused 2D tile kernel (fixed workgroup of T2_THREADS) for the
+// 2D classes, the 3D face kernel with `tile` faces per workgroup otherwise.
 typedef void (*face_kernel_t)(const void*, int, int);
 template <int T>
 static face_kernel_t face_kernel_t_(int cls)
 {
     switch (cls) {
-    case 0: return k_face<double, 2, T>;
-    case 1: return k_face<float, 2, T>;
+    case 0: return k_tile2<double>;
+    case 1: return k_tile2<float>;
     case 2: return k_face<double, 3, T>;
     default: return k_face<float, 3, T>;
     }
@@ -276,6 +291,7 @@ static face_kernel_t face_kernel(int cls, int tile)
     if (tile == 256) return face_kernel_t_<256>(cls);
     return face_kernel_t_<64>(cls);
 }
+static int face_block(int cls, int tile) { return cls < 2 ? T2_THREADS : tile; }
 static const int kDefaultFaceTiles[NCLS] = {FACE_TILE, FACE_TILE, FACE_TILE, FACE_TILE};
 
 extern "C" {
@@ -382,8 +398,9 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.part = (double*)(ws + L.part);
     I.st = (State*)(ws + L.st);
     I.ntile_cell = L.ntile_cell;
-    I.face_tile = FACE_TILE;
-    I.ntile_face_all = L.ntile_face[0] + L.ntile_face[1] + L.ntile_face[2];
+    I.nstep_part = L.nstep_part;
+    I.face_tile = D == 2 ? T2_THREADS : FACE_TILE;
+    I.ntile_face_all = D == 2 ? L.ntile2 : L.ntile_face[0] + L.ntile_face[1] + L.ntile_face[2];
 
     HIP_TRY(h, hipMemcpyAsync(I.W[0], W, cellb * nv, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipMemcpyAsync((void*)I.k, k, cellb, hipMemcpyHostToDevice, s));
@@ -391,7 +408,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     for (int d = 0; d < D; ++d) {
         std::vector<double> xf, xc, dx, idx, ic2, icd, fgeo;
         metrics(cfg, d, xf, xc, dx, idx, ic2, icd, fgeo);
-        I.F[d] = (void*)(ws + L.F[d]);
+        I.F[d] = L.F[d] ? (void*)(ws + L.F[d]) : nullptr;
         I.xf[d] = (const double*)(ws + L.xf[d]) + 2;
         I.xc[d] = (const double*)(ws + L.xc[d]) + 2;
         I.dx[d] = (const double*)(ws + L.dx[d]) + 2;
@@ -452,42 +469,47 @@ static gks_status next_event(gks_ctx* h, hipEvent_t* ev)
     return GKS_OK;
 }
 
-// Each step is three launches (strain with the previous step's end folded in, face,
-// update); one trailing k_finish ends the last step so the state is complete when the
-// call's work has run.
+// A 3D step is three launches (strain with the previous step's end folded in, face,
+// update); a 2D step two (strain, fused tile kernel).  One trailing k_finish ends the last
+// step so the state is complete when the call's work has run.
 static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
 {
     hipStream_t s = h->stream;
     const void* tab = h->tab;
     face_kernel_t fk = face_kernel(h->cls, FACE_TILE);
+    const dim3 fblock(face_block(h->cls, FACE_TILE));
+    const bool upd = h->cfg.dim == 3;
     const int grid_head = h->grid_cell + 1;
     if (nsteps == 0) return GKS_OK;
     if (!h->timing) {
         for (int i = 0; i < nsteps; ++i) {
             hipLaunchKernelGGL(k_strain, dim3(grid_head), dim3(CELL_TILE), 0, s, tab, 1, 0, 1);
-            hipLaunchKernelGGL(fk, dim3(h->grid_face), dim3(FACE_TILE), 0, s, tab, 1, h->cls);
-            hipLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
+            hipLaunchKernelGGL(fk, dim3(h->grid_face), fblock, 0, s, tab, 1, h->cls);
+            if (upd) hipLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
         }
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, tab, 1, 0);
     } else {
         // timed: the runtime stamps each launch's own start and end into its event pair
-        hipEvent_t ev[8];
+        hipEvent_t ev[6];
         for (int i = 0; i < nsteps; ++i) {
-            for (int q = 0; q < 6; ++q) {
+            for (int q = 0; q < (upd ? 6 : 4); ++q) {
                 gks_status r = next_event(h, &ev[q]);
                 if (r != GKS_OK) return r;
             }
             hipExtLaunchKernelGGL(k_strain, dim3(grid_head), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, 0, 1);
-            hipExtLaunchKernelGGL(fk, dim3(h->grid_face), dim3(FACE_TILE), 0, s, ev[2], ev[3], 0, tab, 1, h->cls);
-            hipExtLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, ev[4], ev[5], 0, tab, 1);
-            h->timed_kind.insert(h->timed_kind.end(), {0, 1, 2});
+            hipExtLaunchKernelGGL(fk, dim3(h->grid_face), fblock, 0, s, ev[2], ev[3], 0, tab, 1, h->cls);
+            h->timed_kind.insert(h->timed_kind.end(), {0, 1});
+            if (upd) {
+                hipExtLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, ev[4], ev[5], 0, tab, 1);
+                h->timed_kind.push_back(2);
+            }
             h->steps_timed += 1;
         }
-        for (int q = 6; q < 8; ++q) {
+        for (int q = 0; q < 2; ++q) {
             gks_status r = next_event(h, &ev[q]);
             if (r != GKS_OK) return r;
         }
-        hipExtLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, ev[6], ev[7], 0, tab, 1, 0);
+        hipExtLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, 0);
         h->timed_kind.push_back(3);
     }
     HIP_TRY(h, hipGetLastError());
@@ -721,9 +743,10 @@ static void batch_launch(gks_batch b, int present)
     hipLaunchKernelGGL(k_strain, dim3(batch_grid(b, 0)), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0, 1);
     for (int c = 0; c < NCLS; ++c)
         if (present & (1 << c))
-            hipLaunchKernelGGL(face_kernel(c, b->face_tile[c]), dim3(batch_grid(b, 1 + c)), dim3(b->face_tile[c]), 0,
-                               b->stream, tab, b->cap, c);
-    hipLaunchKernelGGL(k_update, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
+            hipLaunchKernelGGL(face_kernel(c, b->face_tile[c]), dim3(batch_grid(b, 1 + c)),
+                               dim3(face_block(c, b->face_tile[c])), 0, b->stream, tab, b->cap, c);
+    if (present & ((1 << 2) | (1 << 3)))   // 3D members update in their own launch
+        hipLaunchKernelGGL(k_update, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
 }
 
 gks_status gks_batch_step(gks_batch b, int32_t nsteps)
@@ -767,8 +790,8 @@ gks_status gks_batch_capture(gks_batch b)
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile)
 {
     if (!b || kind < 0 || kind > 5 || grid < 0) return fail_h(nullptr, GKS_ERR_ARG, "bad launch shape");
-    const bool face = kind >= 1 && kind <= 4;
-    if (face ? (tile != 64 && tile != 128 && tile != 256) : (tile != 0 && tile != CELL_TILE))
+    const bool face = kind >= 3 && kind <= 4;        // 3D face kinds; the 2D tile is fixed
+    if (face ? (tile != 64 && tile != 128 && tile != 256) : (tile != 0 && !(kind >= 1 && kind <= 2 && tile == T2_THREADS)))
         return fail_h(nullptr, GKS_ERR_ARG, "unsupported tile size");
     b->grid[kind] = grid;
     if (b->captured) {

@@ -121,7 +121,9 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
             new_classes = {(s.case.dim, s.case.precision) for s in members}
             if batch is None:
                 batch = G.Batch(members, capacity=capacity, device=device, stream=run_stream)
-                for kind in (1, 2, 3, 4):
+                for kind in (1, 2):
+                    batch.set_launch(kind, 8 * cus, 0)
+                for kind in (3, 4):
                     batch.set_launch(kind, 16 * cus, 64)
                 batch.set_launch(0, 8 * cus, 0)
                 batch.set_launch(5, 8 * cus, 0)

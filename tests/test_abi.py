@@ -34,8 +34,8 @@ def test_workspace_bytes_and_validation():
     import paper_1302_2132_amd as P
     c = C.mixing_layer(64)
     nb = P.gks_workspace_bytes(P.config_from_case(c))
-    # two FP64 state buffers + k, omega, strain + x/y face fluxes at least
-    assert nb >= 8 * 64 * 64 * (4 * 2 + 3) + 8 * 4 * 2 * 65 * 64
+    # two FP64 state buffers + k, omega, strain at least (2D fluxes never leave LDS)
+    assert 8 * 64 * 64 * (4 * 2 + 3) <= nb < 8 * 64 * 64 * (4 * 2 + 3) + 8 * 4 * 2 * 65 * 64
     bad = c.copy()
     bad.bc = [["periodic", "outflow"], ["periodic", "periodic"]]
     with pytest.raises(P.GksError) as e:
@@ -49,9 +49,13 @@ def test_workspace_bytes_and_validation():
     bad.gamma = 2.5          # fewer than D total degrees of freedom
     with pytest.raises(P.GksError):
         P.gks_workspace_bytes(P.config_from_case(bad))
-    fp32 = c.copy()
+    c3 = C.isotropic_box(16, precision="fp64")
+    nb3 = P.gks_workspace_bytes(P.config_from_case(c3))
+    # 3D: two state buffers + k, omega, strain + x/y/z face fluxes (FP64) at least
+    assert nb3 >= 8 * 16 ** 3 * (5 * 2 + 3) + 8 * 5 * 3 * 17 * 16 * 16
+    fp32 = c3.copy()
     fp32.precision = "fp32_flux"
-    assert P.gks_workspace_bytes(P.config_from_case(fp32)) < nb
+    assert P.gks_workspace_bytes(P.config_from_case(fp32)) < nb3     # FP32 face fluxes
 
 
 def test_init_validation_before_any_device_call():
