@@ -467,8 +467,13 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
     const int total = tv.hdr->total_face[cls];
     cptr<int> prefix = tv.cls_prefix + cls * (cap + 1);
     cptr<int> member = tv.cls_member + cls * cap;
-    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+        // The thread index is made opaque per tile so that the LDS offsets derived from it
+        // are recomputed (a few integer operations) rather than kept live across the tile
+        // loop, where they would take registers from the flux evaluation.
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63, wv = tid >> 6;
         const int mj = find_member(prefix, count, tile);
         cref<Inst> I = tv.inst[member[mj]];
         if (!state_of(I).active) continue;
