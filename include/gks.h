@@ -144,7 +144,8 @@ gks_status gks_face_flops(int32_t dim, int32_t precision, double* flops);
 /* ---------------------------------------------------------------------------------- */
 typedef struct gks_batch_ctx* gks_batch;
 
-/* Device workspace of a batch table able to hold up to `capacity` solves. */
+/* Device workspace of a batch able to hold up to `capacity` solves: its tile table and a
+ * read-back buffer of `capacity` step states. */
 gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
 
 /* Create a batch over `count` initialised handles (all on the same device).  Batch work
@@ -177,8 +178,9 @@ gks_status gks_batch_capture(gks_batch b);
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile);
 
 /* Synchronise; copy per-member steps done, residual of the last step and of the first
- * step (5 slots per member each), time and status (0 running, 1 done by t_end, 2 error)
- * into host arrays (any NULL). */
+ * step (5 slots per member each), time and status (0 running, 1 done by t_end or
+ * max_steps, 2 error) into host arrays (any NULL).  The states are gathered on the
+ * device after the queued steps and read back in one copy. */
 gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* res_first, double* t,
                             int32_t* state);
 

@@ -816,6 +816,18 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
     }
 }
 
+// Copy of every member's step state into one array, so that a batch's states come back
+// to the host in one read.
+__global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, int cap, State* __restrict__ out)
+{
+    const TabC tv(table, cap);
+    const int count = tv.hdr->count;
+    for (int i = blockIdx.x * blockDim.x + (int)threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const State* __restrict__ st = tv.inst[i].st;
+        out[i] = *st;
+    }
+}
+
 template __global__ void k_tile2<double>(const void*, int, int);
 template __global__ void k_tile2<float>(const void*, int, int);
 template __global__ void k_face<double, 3, 64>(const void*, int, int);

@@ -650,10 +650,15 @@ const char* gks_last_error(gks_handle h)
 // ------------------------------------------------------------------------------------
 // batch
 // ------------------------------------------------------------------------------------
+// Batch workspace: the tile table, then an array of cap step states (the read-back buffer
+// of gks_batch_status).
+static size_t batch_bytes(int cap) { return TabView::bytes(cap) + tab_align(sizeof(State) * (size_t)cap); }
+static State* batch_states(gks_batch b) { return (State*)((char*)b->tab + TabView::bytes(b->cap)); }
+
 gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes)
 {
     if (capacity < 1 || !bytes) return fail_h(nullptr, GKS_ERR_ARG, "bad capacity");
-    *bytes = TabView::bytes(capacity);
+    *bytes = batch_bytes(capacity);
     return GKS_OK;
 }
 
@@ -693,7 +698,7 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
 {
     if (!out || (!hs && count) || count < 0 || capacity < 1 || count > capacity || !dev_workspace)
         return fail_h(nullptr, GKS_ERR_ARG, "bad batch arguments");
-    if (bytes < TabView::bytes(capacity)) return fail_h(nullptr, GKS_ERR_NOMEM, "batch workspace too small");
+    if (bytes < batch_bytes(capacity)) return fail_h(nullptr, GKS_ERR_NOMEM, "batch workspace too small");
     if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
     for (int i = 0; i < count; ++i)
         if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
@@ -707,7 +712,8 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
     const int cus = device_cus();
     b->grid[0] = cus * 8;        // strain: 256-thread workgroups
     b->grid[5] = cus * 8;        // update
-    for (int c = 1; c <= 4; ++c) b->grid[c] = cus * 16;   // face: one-wave workgroups
+    b->grid[1] = b->grid[2] = 0;                       // fused 2D kernel: one workgroup per tile
+    b->grid[3] = b->grid[4] = cus * 16;                // 3D face: one-wave workgroups
     for (int c = 0; c < NCLS; ++c) b->face_tile[c] = FACE_TILE;
     gks_status r = batch_upload(b);
     if (r != GKS_OK) { delete b; return r; }
@@ -810,11 +816,16 @@ gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* re
                             int32_t* state)
 {
     if (!b) return fail_h(nullptr, GKS_ERR_ARG, "NULL batch");
-    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "sync failed");
     std::vector<State> sts(b->members.size());
-    for (size_t i = 0; i < b->members.size(); ++i)
-        if (hipMemcpy(&sts[i], b->members[i]->st, sizeof(State), hipMemcpyDeviceToHost) != hipSuccess)
+    if (!sts.empty()) {
+        // one gather launch and one copy for the whole batch, after the queued steps
+        hipLaunchKernelGGL(k_states, dim3(1), dim3(64), 0, b->stream, (const void*)b->tab, b->cap, batch_states(b));
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(sts.data(), batch_states(b), sizeof(State) * sts.size(), hipMemcpyDeviceToHost,
+                           b->stream) != hipSuccess)
             return fail_h(nullptr, GKS_ERR_DEVICE, "state read failed");
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "sync failed");
     for (size_t i = 0; i < sts.size(); ++i) {
         if (steps) steps[i] = sts[i].steps;
         if (res) for (int m = 0; m < 5; ++m) res[5 * i + m] = sts[i].res[m];

@@ -5,13 +5,22 @@ relative to its first step (max over fields of res_m / res_first_m) or until
 `max_steps`.  The server keeps every admitted solve's state on the device and advances
 all of them together with the persistent batch kernels (one captured graph per step;
 admissions and retirements rewrite the batch table in place).  Requests are admitted in
-arrival order whenever a batch slot and enough HBM (the solve's workspace footprint)
-are free; new solves are initialised on a separate stream so that their set-up overlaps
+arrival order (or, with order="shortest", smallest expected work first: cells x step
+cap) whenever a batch slot and enough HBM (the solve's workspace footprint) are free and
+the cells already in the batch do not saturate the GPU (`sat_cells`: past that point a
+further member only shares the GPU, lengthening every member's time without adding
+throughput); new solves are initialised on a separate stream so that their set-up overlaps
 the running batch.  For comparison `run_fifo` serves the same trace one solve at a time
 with the plain per-solve loop.
 
 Latency of a request = completion time - arrival time (wall clock, arrivals replayed in
 real time from the trace).
+
+Both loops advance their work in quanta of steps sized to about `target_s` of GPU time
+(from the measured time of the previous quantum, at least `quantum` steps), so that the
+per-quantum host work (reading the states back, admitting, retiring) stays a small
+fraction of the GPU time.  A solve stops on the device at its step cap, so a quantum
+that overshoots a solve's end costs no work, only up to one quantum of detection delay.
 """
 from __future__ import annotations
 
@@ -32,6 +41,14 @@ def _converged(res, res_first, steps, tol, max_steps, nv):
     return float(np.max(r[mask] / r0[mask])) <= tol
 
 
+def _next_quantum(q, gpu_ms, quantum, target_s, q_max=4000):
+    """Steps of the next quantum: about target_s of GPU time at the last measured rate."""
+    if gpu_ms <= 0.0:
+        return q
+    per_step = gpu_ms * 1e-3 / q
+    return int(min(q_max, max(quantum, target_s / per_step)))
+
+
 def _summary(lat, cell_updates, makespan, n):
     lat = np.asarray(lat)
     return {
@@ -46,9 +63,10 @@ def _summary(lat, cell_updates, makespan, n):
 
 
 def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=20, keep_fields=False,
-                device="cuda:0"):
+                device="cuda:0", target_s=0.004, log=None, sat_cells=None, order="arrival"):
     """Serve `requests` (dicts with id, arrival [s], max_steps, tol) with continuous
-    batching.  Returns (summary, per-request records).
+    batching.  Returns (summary, per-request records).  `log(msg)`, if given, is called
+    every 16 completions.
 
     Each iteration enqueues the next `quantum` steps of the running batch first, then does
     the host work (building and initialising newly arrived solves on their own stream)
@@ -59,6 +77,8 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
     from . import gks as G
     torch.cuda.set_device(device)
     cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    if sat_cells is None:
+        sat_cells = 8192 * cus          # ~2M cells: a few waves of tiles on every CU
     run_stream = torch.cuda.Stream(device=device)
     init_stream = torch.cuda.Stream(device=device)
     pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
@@ -69,6 +89,11 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
     batch = None
     classes = set()
     cell_updates = 0
+    q = quantum
+    ndone = 0
+    cells_in = 0         # cells of the active and staged solves
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
 
     def now():
@@ -79,15 +104,21 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
         while pending and pending[0]["arrival"] <= t:
             queue.append(pending.popleft())
         if active:
-            batch.step(quantum)                          # GPU works while the host admits
+            ev0.record(run_stream)
+            batch.step(q)                                # GPU works while the host admits
+            ev1.record(run_stream)
         staged = []
         while queue and len(active) + len(staged) < capacity:
-            req = queue[0]
+            if order == "shortest":
+                req = min(queue, key=lambda r: make_case(r).ncells * r["max_steps"])
+            else:
+                req = queue[0]
             case = make_case(req)
             nbytes = G.gks_workspace_bytes(G.config_from_case(case))
-            if used + nbytes > hbm_budget and (active or staged):
-                break                                    # wait for memory to free up
-            queue.popleft()
+            if (used + nbytes > hbm_budget or cells_in + case.ncells > sat_cells) and (active or staged):
+                break                                    # wait for memory or GPU room
+            queue.remove(req)
+            cells_in += case.ncells
             with torch.cuda.stream(init_stream):
                 solver = G.Solver(case, device=device, stream=init_stream)
             used += nbytes
@@ -97,6 +128,7 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
         retired = False
         if active:
             st = batch.status()                          # synchronises the run stream
+            q = _next_quantum(q, ev0.elapsed_time(ev1), quantum, target_s)
             keep = []
             tnow = now()
             for i, item in enumerate(active):
@@ -111,7 +143,11 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
                         rec["fields"] = solver.fields("cons")
                     solver.close()
                     used -= nbytes
+                    cells_in -= rec["cells"]
                     retired = True
+                    ndone += 1
+                    if log is not None and ndone % 16 == 0:
+                        log(f"batched: {ndone}/{len(requests)} done at {tnow:.1f} s, quantum {q}")
                 else:
                     keep.append(item)
             active = keep
@@ -143,7 +179,7 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
     return _summary(lat, cell_updates, makespan, len(records)), records
 
 
-def run_fifo(requests, make_case, quantum=20, keep_fields=False, device="cuda:0"):
+def run_fifo(requests, make_case, quantum=20, keep_fields=False, device="cuda:0", target_s=0.004, log=None):
     """The same trace served one solve at a time with the plain per-solve loop."""
     import torch
 
@@ -152,6 +188,8 @@ def run_fifo(requests, make_case, quantum=20, keep_fields=False, device="cuda:0"
     reqs = sorted(requests, key=lambda r: r["arrival"])
     records = {}
     cell_updates = 0
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     for req in reqs:
         wait = req["arrival"] - (time.perf_counter() - t0)
@@ -159,9 +197,13 @@ def run_fifo(requests, make_case, quantum=20, keep_fields=False, device="cuda:0"
             time.sleep(wait)
         case = make_case(req)
         s = G.Solver(case, device=device)
+        q = quantum
         while True:
-            s.step(quantum)
-            r = s.residual()
+            ev0.record()
+            s.step(q)
+            ev1.record()
+            r = s.residual()                             # synchronises
+            q = _next_quantum(q, ev0.elapsed_time(ev1), quantum, target_s)
             steps = r["steps"]
             if _converged(r["res"], r["res_first"], steps, req["tol"], req["max_steps"], case.nvar):
                 break
@@ -173,6 +215,8 @@ def run_fifo(requests, make_case, quantum=20, keep_fields=False, device="cuda:0"
         cell_updates += steps * case.ncells
         s.close()
         records[req["id"]] = rec
+        if log is not None and len(records) % 16 == 0:
+            log(f"fifo: {len(records)}/{len(reqs)} done at {tnow:.1f} s")
     makespan = time.perf_counter() - t0
     lat = [r["latency"] for r in records.values()]
     return _summary(lat, cell_updates, makespan, len(records)), records
