@@ -83,6 +83,9 @@ def _bind(L):
     _lib.og_moment_solve.argtypes = [C.c_int, C.c_double, dp, dp, dp]
     _lib.og_tau_value.argtypes = [C.c_double] * 11
     _lib.og_tau_value.restype = C.c_double
+    if hasattr(_lib, "og_run_kw"):
+        _lib.og_run_kw.argtypes = [C.c_void_p, dp, dp, dp, C.c_int, C.c_int, dp, dp, dp, C.POINTER(C.c_long)]
+        _lib.og_kw_sources.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
 
 
 def _dp(a):
@@ -144,6 +147,37 @@ def run(case, nsteps=None, nthreads=0, W=None, t0=0.0):
         raise OracleError(st)
     return {"W": Wf.reshape(case.W.shape), "res": res, "dt": float(dt[0]), "t": float(t[0]),
             "steps": int(done.value)}
+
+
+def run_kw(case, nsteps=None, nthreads=0, W=None, k=None, omega=None, t0=0.0):
+    """Like run, with k and omega transported: returns dict(W, k, omega, res, dt, t, steps)."""
+    b = _Bound(case)
+    Wf = _flat(case.W if W is None else W).copy()
+    kf = _flat(case.k if k is None else k).copy()
+    wf = _flat(case.omega if omega is None else omega).copy()
+    res = np.zeros(case.nvar)
+    dt = np.zeros(1)
+    t = np.array([t0], dtype=np.float64)
+    done = C.c_long(0)
+    n = case.steps if nsteps is None else nsteps
+    st = lib().og_run_kw(b.ptr, _dp(Wf), _dp(kf), _dp(wf), int(n), int(nthreads), _dp(res), _dp(dt),
+                         _dp(t), C.byref(done))
+    if st:
+        raise OracleError(st)
+    return {"W": Wf.reshape(case.W.shape), "k": kf.reshape(case.k.shape), "omega": wf.reshape(case.k.shape),
+            "res": res, "dt": float(dt[0]), "t": float(t[0]), "steps": int(done.value)}
+
+
+def kw_sources(case, W=None, k=None, omega=None):
+    """Explicit k-omega sources (Qk, Qw) of every cell."""
+    b = _Bound(case)
+    Wf = _flat(case.W if W is None else W)
+    Qk, Qw = np.zeros(case.ncells), np.zeros(case.ncells)
+    st = lib().og_kw_sources(b.ptr, _dp(Wf), _dp(_flat(case.k if k is None else k)),
+                             _dp(_flat(case.omega if omega is None else omega)), _dp(Qk), _dp(Qw))
+    if st:
+        raise OracleError(st)
+    return Qk.reshape(case.k.shape), Qw.reshape(case.k.shape)
 
 
 def cfl_dt(case, W=None):

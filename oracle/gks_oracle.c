@@ -38,6 +38,14 @@
  *    with T = p0/rho0, eta = S/(C_mu omega), interface state W0.
  *  - Prandtl correction: F_E += (1/Pr - 1) q, q the time-integrated heat flux of the
  *    interface distribution in the frame of U0.
+ *  - k-omega transport (og_run_kw; the "allied equations" of the implementation
+ *    section, with the Wilcox 2006 k-omega model the paper names): conservative rho k,
+ *    rho omega; convection with the GKS time-integrated mass flux, upwind by its sign;
+ *    face diffusion with mu + sigma* rho k/omega and mu + sigma rho k/omega (face means of
+ *    the two cells); production P from the paper's turbulent viscosity
+ *    mu_t = rho k/(omega sqrt(1+eta^2)); cross-diffusion sigma_d (rho/omega) grad k.grad omega
+ *    where that product is positive; the sinks beta* omega rho k and beta omega rho omega
+ *    point-implicit in the step; ghost k and omega take their interior image's values.
  */
 #include <math.h>
 #include <stdio.h>
@@ -644,33 +652,49 @@ static long og_image_cell(const og_grid* gr, long i, long j, long k)
 
 /* Strain-rate magnitude S = sqrt(2 S_ab S_ab), S_ab = (dU_a/dx_b + dU_b/dx_a)/2, with
  * central differences of the cell-averaged velocity over the neighbouring centres. */
-static void og_strain(const og_grid* gr, const double* We, double* S)
+/* Velocity gradient grad[a][b] = dU_a/dx_b of interior cell (i, j, k) by central
+ * differences over the neighbouring centres (ghost-filled state We). */
+static void og_velocity_gradient(const og_grid* gr, const double* We, long i, long j, long k,
+                                 double grad[3][3])
 {
     const int dim = gr->c->dim;
+    long c0[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) grad[a][b] = 0.0;
+    for (int b = 0; b < dim; ++b) {       /* derivative direction */
+        long cp[3] = {i, j, k}, cm[3] = {i, j, k};
+        cp[b] += 1; cm[b] -= 1;
+        long ip = gidx(gr, cp[0], cp[1], cp[2]), im = gidx(gr, cm[0], cm[1], cm[2]);
+        double h = gr->xc[b][c0[b] + 1 + 2] - gr->xc[b][c0[b] - 1 + 2];
+        for (int a = 0; a < dim; ++a) {   /* velocity component */
+            double up = We[(1 + a) * gr->next + ip] / We[ip];
+            double um = We[(1 + a) * gr->next + im] / We[im];
+            grad[a][b] = (up - um) / h;
+        }
+    }
+}
+
+/* S^2 = 2 S_ab S_ab with S_ab the symmetric part of the velocity gradient. */
+static double og_strain_sq(int dim, const double grad[3][3])
+{
+    double ss = 0.0;
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) {
+            double sab = 0.5 * (grad[a][b] + grad[b][a]);
+            ss += sab * sab;
+        }
+    return 2.0 * ss;
+}
+
+static void og_strain(const og_grid* gr, const double* We, double* S)
+{
     const long N = gr->n[0] * gr->n[1] * gr->n[2];
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < N; ++s) {
         long i = s % gr->n[0], j = (s / gr->n[0]) % gr->n[1], k = s / (gr->n[0] * gr->n[1]);
-        long c0[3] = {i, j, k};
-        double grad[3][3] = {{0}};
-        for (int b = 0; b < dim; ++b) {       /* derivative direction */
-            long cp[3] = {i, j, k}, cm[3] = {i, j, k};
-            cp[b] += 1; cm[b] -= 1;
-            long ip = gidx(gr, cp[0], cp[1], cp[2]), im = gidx(gr, cm[0], cm[1], cm[2]);
-            double h = gr->xc[b][c0[b] + 1 + 2] - gr->xc[b][c0[b] - 1 + 2];
-            for (int a = 0; a < dim; ++a) {   /* velocity component */
-                double up = We[(1 + a) * gr->next + ip] / We[ip];
-                double um = We[(1 + a) * gr->next + im] / We[im];
-                grad[a][b] = (up - um) / h;
-            }
-        }
-        double ss = 0.0;
-        for (int a = 0; a < dim; ++a)
-            for (int b = 0; b < dim; ++b) {
-                double sab = 0.5 * (grad[a][b] + grad[b][a]);
-                ss += sab * sab;
-            }
-        S[s] = sqrt(2.0 * ss);
+        double grad[3][3];
+        og_velocity_gradient(gr, We, i, j, k, grad);
+        S[s] = sqrt(og_strain_sq(gr->c->dim, grad));
     }
 }
 
@@ -769,12 +793,36 @@ static int og_face_at(const og_grid* gr, const double* We, const double* kk, con
     return OG_OK;
 }
 
+/* Net time-integrated flux out of cell idx per unit volume, component m of the face
+ * arrays F[d] (component-major, fn[d] faces along each axis). */
+static double og_flux_out(const og_grid* gr, double* const F[3], const long fn[3][3], int m, const long idx[3])
+{
+    double acc = 0.0;
+    for (int d = 0; d < gr->c->dim; ++d) {
+        long nf = fn[d][0] * fn[d][1] * fn[d][2];
+        long lo = (idx[2] * fn[d][1] + idx[1]) * fn[d][0] + idx[0];
+        long hi = lo + (d == 0 ? 1 : (d == 1 ? fn[d][0] : fn[d][0] * fn[d][1]));
+        acc += (F[d][m * nf + hi] - F[d][m * nf + lo]) / gr->dx[d][idx[d] + 2];
+    }
+    return acc;
+}
+
+/* Conservative update of the flow variables of every cell: Wn = W - flux out. */
+static void og_update(const og_grid* gr, const double* W, double* const F[3], const long fn[3][3], double* Wn)
+{
+    const long N = gr->n[0] * gr->n[1] * gr->n[2];
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < N; ++s) {
+        long idx[3] = {s % gr->n[0], (s / gr->n[0]) % gr->n[1], s / (gr->n[0] * gr->n[1])};
+        for (int m = 0; m < gr->nv; ++m) Wn[m * N + s] = W[m * N + s] - og_flux_out(gr, F, fn, m, idx);
+    }
+}
+
 /* One explicit step W -> Wn with step dt.  All faces, then the conservative update. */
 static int og_step(const og_grid* gr, const double* W, const double* kk, const double* om,
                    double dt, double* Wn, double* We, double* S)
 {
     const int dim = gr->c->dim, nv = gr->nv;
-    const long N = gr->n[0] * gr->n[1] * gr->n[2];
     og_fill_W(gr, W, We);
     og_strain(gr, We, S);
     double* F[3] = {NULL, NULL, NULL};
@@ -792,22 +840,7 @@ static int og_step(const og_grid* gr, const double* W, const double* kk, const d
             for (int m = 0; m < nv; ++m) F[d][m * nf + f] = Fl[m];
         }
     }
-    if (!bad) {
-#pragma omp parallel for schedule(static)
-        for (long s = 0; s < N; ++s) {
-            long idx[3] = {s % gr->n[0], (s / gr->n[0]) % gr->n[1], s / (gr->n[0] * gr->n[1])};
-            for (int m = 0; m < nv; ++m) {
-                double acc = W[m * N + s];
-                for (int d = 0; d < dim; ++d) {
-                    long nf = fn[d][0] * fn[d][1] * fn[d][2];
-                    long lo = (idx[2] * fn[d][1] + idx[1]) * fn[d][0] + idx[0];
-                    long hi = lo + (d == 0 ? 1 : (d == 1 ? fn[d][0] : fn[d][0] * fn[d][1]));
-                    acc -= (F[d][m * nf + hi] - F[d][m * nf + lo]) / gr->dx[d][idx[d] + 2];
-                }
-                Wn[m * N + s] = acc;
-            }
-        }
-    }
+    if (!bad) og_update(gr, W, F, fn, Wn);
     for (int d = 0; d < dim; ++d) free(F[d]);
     return bad ? OG_ERR_NONPHYSICAL : OG_OK;
 }
@@ -823,6 +856,127 @@ static int og_check_fields(const og_grid* gr, const double* W, const double* kk,
         if (!(kk[s] >= 0.0) || !isfinite(kk[s]) || !(om[s] > 0.0) || !isfinite(om[s])) return OG_ERR_ARG;
     }
     return OG_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* k-omega transport                                                         */
+/* ------------------------------------------------------------------------ */
+/* constants of the Wilcox (2006) k-omega model */
+#define KW_ALPHA (13.0 / 25.0)
+#define KW_BETA 0.0708
+#define KW_BETA_STAR 0.09
+#define KW_SIGMA 0.5
+#define KW_SIGMA_STAR 0.6
+#define KW_SIGMA_DO 0.125
+
+/* value of a cell field at a (possibly ghost) cell: its interior image's value */
+static double og_kw_at(const og_grid* gr, const double* f, const long* c)
+{
+    return f[og_image_cell(gr, c[0], c[1], c[2])];
+}
+
+/* Explicit sources of one interior cell s at the state We (ghost-filled) and fields k, om:
+ *   Qk = P,  Qw = alpha (omega/k) P + sigma_d (rho/omega) grad k . grad omega,
+ *   P = mu_t (S^2 - 2/3 div^2) - 2/3 rho k div,  mu_t = rho k/(omega sqrt(1+eta^2)),
+ *   S^2 = 2 S_ab S_ab,  eta = S/(C_mu omega),  sigma_d = sigma_do where grad k.grad omega > 0.
+ * alpha (omega/k) P is written as alpha rho ((S^2 - 2/3 div^2)/sqrt(1+eta^2) - 2/3 omega div),
+ * which is the same quantity without the division by k.  Central differences over the
+ * neighbouring centres, as for the strain rate. */
+static void og_kw_source_cell(const og_grid* gr, const double* We, const double* kk, const double* om,
+                              long s, double* Qk, double* Qw)
+{
+    const int dim = gr->c->dim;
+    long i = s % gr->n[0], j = (s / gr->n[0]) % gr->n[1], k = s / (gr->n[0] * gr->n[1]);
+    long c0[3] = {i, j, k};
+    double grad[3][3], gk[3] = {0}, gw[3] = {0};
+    og_velocity_gradient(gr, We, i, j, k, grad);
+    for (int b = 0; b < dim; ++b) {
+        long cp[3] = {i, j, k}, cm[3] = {i, j, k};
+        cp[b] += 1; cm[b] -= 1;
+        double h = gr->xc[b][c0[b] + 1 + 2] - gr->xc[b][c0[b] - 1 + 2];
+        gk[b] = (og_kw_at(gr, kk, cp) - og_kw_at(gr, kk, cm)) / h;
+        gw[b] = (og_kw_at(gr, om, cp) - og_kw_at(gr, om, cm)) / h;
+    }
+    const double s2 = og_strain_sq(dim, grad);
+    double div = 0.0, cross = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        div += grad[a][a];
+        cross += gk[a] * gw[a];
+    }
+    const double rho = We[gidx(gr, i, j, k)];
+    const double kc = kk[s], wc = om[s];
+    const double eta = sqrt(s2) / (gr->c->c_mu * wc);
+    const double root = sqrt(1.0 + eta * eta);
+    const double mut = rho * kc / (wc * root);
+    const double shear = s2 - 2.0 / 3.0 * div * div;
+    *Qk = mut * shear - 2.0 / 3.0 * rho * kc * div;
+    *Qw = KW_ALPHA * rho * (shear / root - 2.0 / 3.0 * wc * div);
+    if (cross > 0.0) *Qw += KW_SIGMA_DO * rho / wc * cross;
+}
+
+/* Time-integrated fluxes of rho k and rho omega through one face (axis d, face coordinates
+ * as in og_face_at), given the face's time-integrated mass flux Frho. */
+static void og_kw_face(const og_grid* gr, const double* We, const double* kk, const double* om, int d,
+                       long fi, long fj, long fk, double Frho, double dt, double* Fk, double* Fw)
+{
+    long cl[3] = {fi, fj, fk}, cr[3] = {fi, fj, fk};
+    cl[d] -= 1;
+    const double kl = og_kw_at(gr, kk, cl), kr = og_kw_at(gr, kk, cr);
+    const double wl = og_kw_at(gr, om, cl), wr = og_kw_at(gr, om, cr);
+    const double rl = We[gidx(gr, cl[0], cl[1], cl[2])], rr = We[gidx(gr, cr[0], cr[1], cr[2])];
+    const double nut = 0.5 * (rl * kl / wl + rr * kr / wr);
+    const double dn = gr->xc[d][cr[d] + 2] - gr->xc[d][cl[d] + 2];
+    const double mu = gr->c->mu;
+    *Fk = Frho * (Frho >= 0.0 ? kl : kr) - dt * (mu + KW_SIGMA_STAR * nut) * (kr - kl) / dn;
+    *Fw = Frho * (Frho >= 0.0 ? wl : wr) - dt * (mu + KW_SIGMA * nut) * (wr - wl) / dn;
+}
+
+/* One explicit step of the flow and of rho k, rho omega (rk, rw: conservative, in/out via
+ * rkn, rwn).  kk, om are rk/rho, rw/rho of the current state. */
+static int og_step_kw(const og_grid* gr, const double* W, const double* kk, const double* om,
+                      const double* rk, const double* rw, double dt, double* Wn, double* rkn, double* rwn,
+                      double* We, double* S)
+{
+    const int dim = gr->c->dim, nv = gr->nv;
+    const long N = gr->n[0] * gr->n[1] * gr->n[2];
+    og_fill_W(gr, W, We);
+    og_strain(gr, We, S);
+    double* F[3] = {NULL, NULL, NULL};
+    double* Fk[3] = {NULL, NULL, NULL};
+    double* Fw[3] = {NULL, NULL, NULL};
+    long fn[3][3];
+    int bad = 0;
+    for (int d = 0; d < dim; ++d) {
+        for (int a = 0; a < 3; ++a) fn[d][a] = gr->n[a] + (a == d ? 1 : 0);
+        long nf = fn[d][0] * fn[d][1] * fn[d][2];
+        F[d] = (double*)malloc(sizeof(double) * nv * nf);
+        Fk[d] = (double*)malloc(sizeof(double) * nf);
+        Fw[d] = (double*)malloc(sizeof(double) * nf);
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
+        for (long f = 0; f < nf; ++f) {
+            long fi = f % fn[d][0], fj = (f / fn[d][0]) % fn[d][1], fk = f / (fn[d][0] * fn[d][1]);
+            double Fl[5];
+            if (og_face_at(gr, We, kk, om, S, d, fi, fj, fk, dt, Fl)) { bad = 1; continue; }
+            for (int m = 0; m < nv; ++m) F[d][m * nf + f] = Fl[m];
+            og_kw_face(gr, We, kk, om, d, fi, fj, fk, Fl[0], dt, &Fk[d][f], &Fw[d][f]);
+        }
+    }
+    if (!bad) {
+        og_update(gr, W, F, fn, Wn);
+#pragma omp parallel for schedule(static) reduction(| : bad)
+        for (long s = 0; s < N; ++s) {
+            long idx[3] = {s % gr->n[0], (s / gr->n[0]) % gr->n[1], s / (gr->n[0] * gr->n[1])};
+            double ak = rk[s] - og_flux_out(gr, Fk, fn, 0, idx);
+            double aw = rw[s] - og_flux_out(gr, Fw, fn, 0, idx);
+            double Qk, Qw;
+            og_kw_source_cell(gr, We, kk, om, s, &Qk, &Qw);
+            rkn[s] = (ak + dt * Qk) / (1.0 + dt * KW_BETA_STAR * om[s]);
+            rwn[s] = (aw + dt * Qw) / (1.0 + dt * KW_BETA * om[s]);
+            if (!(rkn[s] >= 0.0) || !(rwn[s] > 0.0) || !isfinite(rkn[s]) || !isfinite(rwn[s])) bad = 1;
+        }
+    }
+    for (int d = 0; d < dim; ++d) { free(F[d]); free(Fk[d]); free(Fw[d]); }
+    return bad ? OG_ERR_NONPHYSICAL : OG_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -878,6 +1032,75 @@ int og_run(const og_case* c, double* W, const double* kk, const double* om, int 
     if (t_io) *t_io = t;
     if (steps_done) *steps_done = done;
     free(We); free(S); free(Wn);
+    og_grid_free(&gr);
+    return st;
+}
+
+/* og_run with k and omega transported (in/out) instead of frozen.  The residual covers the
+ * flow variables. */
+int og_run_kw(const og_case* c, double* W, double* kk, double* om, int nsteps, int nthreads,
+              double* res, double* dt_last, double* t_io, long* steps_done)
+{
+    og_grid gr;
+    int st = og_grid_init(&gr, c);
+    if (st) { og_grid_free(&gr); return st; }
+    og_threads(nthreads);
+    const long N = gr.n[0] * gr.n[1] * gr.n[2];
+    const int nv = gr.nv;
+    if ((st = og_check_fields(&gr, W, kk, om))) { og_grid_free(&gr); return st; }
+    double* We = (double*)malloc(sizeof(double) * nv * gr.next);
+    double* S = (double*)malloc(sizeof(double) * N);
+    double* Wn = (double*)malloc(sizeof(double) * nv * N);
+    double* rk = (double*)malloc(sizeof(double) * N);
+    double* rw = (double*)malloc(sizeof(double) * N);
+    double* rkn = (double*)malloc(sizeof(double) * N);
+    double* rwn = (double*)malloc(sizeof(double) * N);
+    for (long s = 0; s < N; ++s) { rk[s] = W[s] * kk[s]; rw[s] = W[s] * om[s]; }
+    double t = t_io ? *t_io : 0.0;
+    long done = 0;
+    for (int step = 0; step < nsteps; ++step) {
+        if (c->t_end > 0.0 && t >= c->t_end) break;
+        double rate;
+        if ((st = og_max_rate(&gr, W, kk, om, &rate))) break;
+        double dt = c->cfl / rate, tn = t + dt;
+        if (c->t_end > 0.0 && tn >= c->t_end) { dt = c->t_end - t; tn = c->t_end; }
+        if ((st = og_step_kw(&gr, W, kk, om, rk, rw, dt, Wn, rkn, rwn, We, S))) break;
+        for (int m = 0; m < nv; ++m) {
+            double acc = 0.0;
+            for (long s = 0; s < N; ++s) {
+                double r = (Wn[m * N + s] - W[m * N + s]) / dt;
+                acc += r * r;
+            }
+            if (res) res[m] = sqrt(acc / (double)N);
+        }
+        memcpy(W, Wn, sizeof(double) * nv * N);
+        memcpy(rk, rkn, sizeof(double) * N);
+        memcpy(rw, rwn, sizeof(double) * N);
+        for (long s = 0; s < N; ++s) { kk[s] = rk[s] / W[s]; om[s] = rw[s] / W[s]; }
+        if (dt_last) *dt_last = dt;
+        t = tn;
+        ++done;
+        if ((st = og_check_fields(&gr, W, kk, om))) break;
+    }
+    if (t_io) *t_io = t;
+    if (steps_done) *steps_done = done;
+    free(We); free(S); free(Wn); free(rk); free(rw); free(rkn); free(rwn);
+    og_grid_free(&gr);
+    return st;
+}
+
+/* Explicit k-omega sources Qk, Qw of every interior cell at state W and fields k, omega. */
+int og_kw_sources(const og_case* c, const double* W, const double* kk, const double* om, double* Qk, double* Qw)
+{
+    og_grid gr;
+    int st = og_grid_init(&gr, c);
+    if (!st) {
+        const long N = gr.n[0] * gr.n[1] * gr.n[2];
+        double* We = (double*)malloc(sizeof(double) * gr.nv * gr.next);
+        og_fill_W(&gr, W, We);
+        for (long s = 0; s < N; ++s) og_kw_source_cell(&gr, We, kk, om, s, &Qk[s], &Qw[s]);
+        free(We);
+    }
     og_grid_free(&gr);
     return st;
 }

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_kw as KW
 import test_oracle_pins as P
 
 SRC = oracle.SRC
@@ -39,12 +40,27 @@ MUTANTS = {
                          "ADD_TERM(g0.rho * kw.g[1], 0, R_ALL, p_lin(dim, Ab, &terms[nt].poly));"),
     "wall mirrors normal momentum only": ("if (bc == OG_WALL && m >= 1 && m <= dim) v = -v;",
                                           "if (bc == OG_WALL && m == 1) v = -v;"),
-    "update sign": ("acc -= (F[d][m * nf + hi] - F[d][m * nf + lo]) / gr->dx[d][idx[d] + 2];",
-                    "acc += (F[d][m * nf + hi] - F[d][m * nf + lo]) / gr->dx[d][idx[d] + 2];"),
+    "update sign": ("Wn[m * N + s] = W[m * N + s] - og_flux_out(gr, F, fn, m, idx);",
+                    "Wn[m * N + s] = W[m * N + s] + og_flux_out(gr, F, fn, m, idx);"),
+    "flux difference faces swapped": ("acc += (F[d][m * nf + hi] - F[d][m * nf + lo])",
+                                      "acc += (F[d][m * nf + lo] - F[d][m * nf + hi])"),
     "strain not symmetrised": ("double sab = 0.5 * (grad[a][b] + grad[b][a]);", "double sab = grad[a][b];"),
     "viscous CFL term": ("r += 2.0 * nu * r2;", "r += nu * r2;"),
     "periodic ghost face coordinates": ("gr->xfe[d][2 - m] = xf[0] - (xf[n] - xf[n - m]);",
                                         "gr->xfe[d][2 - m] = xf[0] - (xf[m] - xf[0]);"),
+    "k-omega convection downwind": ("*Fk = Frho * (Frho >= 0.0 ? kl : kr)", "*Fk = Frho * (Frho >= 0.0 ? kr : kl)"),
+    "k-omega diffusion sign": ("*Fk = Frho * (Frho >= 0.0 ? kl : kr) - dt", "*Fk = Frho * (Frho >= 0.0 ? kl : kr) + dt"),
+    "omega diffusion coefficient": ("(mu + KW_SIGMA * nut) * (wr - wl)", "(mu + KW_SIGMA_STAR * nut) * (wr - wl)"),
+    "eddy diffusivity from one side": ("const double nut = 0.5 * (rl * kl / wl + rr * kr / wr);",
+                                       "const double nut = rl * kl / wl;"),
+    "k sink coefficient": ("rkn[s] = (ak + dt * Qk) / (1.0 + dt * KW_BETA_STAR * om[s]);",
+                           "rkn[s] = (ak + dt * Qk) / (1.0 + dt * KW_BETA * om[s]);"),
+    "k flux difference sign": ("double ak = rk[s] - og_flux_out(gr, Fk, fn, 0, idx);",
+                               "double ak = rk[s] + og_flux_out(gr, Fk, fn, 0, idx);"),
+    "eddy viscosity without strain limiter": ("const double mut = rho * kc / (wc * root);",
+                                              "const double mut = rho * kc / wc;"),
+    "omega production without limiter": ("*Qw = KW_ALPHA * rho * (shear / root", "*Qw = KW_ALPHA * rho * (shear"),
+    "cross diffusion regardless of sign": ("if (cross > 0.0) *Qw +=", "if (cross != 0.0) *Qw +="),
 }
 
 
@@ -78,6 +94,16 @@ PINS = [
     lambda: P.test_coefficient_definitions_by_quadrature(2),
     lambda: P.test_p16_flux_bruteforce(2, 1.0),
     _sod_quick,
+    lambda: KW.test_homogeneous_decay_follows_the_point_implicit_recurrence(2),
+    lambda: KW.test_uniform_k_stays_uniform_in_a_density_wave(),
+    lambda: KW.test_rho_k_and_rho_omega_conserved_up_to_their_sources("mixing"),
+    lambda: KW.test_convection_is_upwind(),
+    lambda: KW.test_production_of_a_linear_shear(),
+    lambda: KW.test_cross_diffusion_only_where_gradients_align(-1.0),
+    lambda: KW.test_cross_diffusion_only_where_gradients_align(1.0),
+    lambda: KW.test_diffusion_rate_of_a_sine_mode("k"),
+    lambda: KW.test_diffusion_rate_of_a_sine_mode("omega"),
+    lambda: KW.test_mirror_symmetry(),
 ]
 
 
