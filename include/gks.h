@@ -9,12 +9,18 @@
  * artificial part (Eqs. relaxation time, taua, tautchenadjusted), followed by the
  * conservative finite-volume update on a stretched Cartesian grid (section
  * "Implementation of the turbulent gas-kinetic scheme in a finite-volume solver").
- * k and omega are frozen inputs.
+ * k and omega are frozen inputs, or (turb_transport = 1) advanced with the flow by the
+ * transport equations of the 2006 k-omega model (coefficients beta* = 0.09,
+ * beta = 0.0708, alpha = 13/25, sigma* = 3/5, sigma = 1/2, sigma_do = 1/8): rho k and
+ * rho omega are convected by each face's time-integrated gas-kinetic mass flux (upwind
+ * k, omega), diffused with mu + sigma (mean of the two cells' rho k/omega), take the
+ * model's production and cross-diffusion explicitly and its dissipation point-implicitly.
  *
  * Conventions used by every entry point
  *  - Cells are stored structure-of-arrays, x fastest: field m of cell (i, j, k) is at
  *    m * ncells + (k * ny + j) * nx + i.  Conservative variables are
- *    (rho, rho U, rho V, [rho W], rho E), nvar = dim + 2.
+ *    (rho, rho U, rho V, [rho W], rho E), nvar = dim + 2.  A solve with turb_transport
+ *    stores nvar + 2 fields on the device, rho k and rho omega last.
  *  - Pointers named dev_* are device (HBM) pointers; all other pointers are host memory.
  *    The library copies every host input it needs during the call that receives it.
  *  - The caller owns device memory: it passes a workspace of the size the library asks
@@ -64,8 +70,10 @@ enum { GKS_BC_PERIODIC = 0, GKS_BC_WALL = 1, GKS_BC_DIRICHLET = 2, GKS_BC_PROFIL
 enum { GKS_FP64 = 0, GKS_FP32_FLUX = 1 };
 
 /* Fields for gks_fields. CONS: conservative state (nvar x ncells). PRIM: rho, U, V, [W],
- * p (nvar x ncells). STRAIN: strain-rate magnitude sqrt(2 S_ab S_ab) (ncells). */
-enum { GKS_FIELD_CONS = 0, GKS_FIELD_PRIM = 1, GKS_FIELD_STRAIN = 2 };
+ * p (nvar x ncells). STRAIN: strain-rate magnitude sqrt(2 S_ab S_ab) (ncells). TURB: k
+ * then omega (2 x ncells): those of the current state when transported (computed on the
+ * device from rho k, rho omega), the frozen inputs otherwise. */
+enum { GKS_FIELD_CONS = 0, GKS_FIELD_PRIM = 1, GKS_FIELD_STRAIN = 2, GKS_FIELD_TURB = 3 };
 
 typedef struct {
     int32_t dim;                  /* 2 or 3 */
@@ -82,6 +90,7 @@ typedef struct {
     double t_end;                 /* > 0: clip the last step to land on t_end, then stop */
     int32_t precision;            /* GKS_FP64 or GKS_FP32_FLUX */
     int64_t max_steps;            /* > 0: the solve stops (on the device) after this many steps */
+    int32_t turb_transport;       /* 1: transport k and omega with the flow; 0: frozen inputs */
 } gks_config;
 
 typedef struct gks_ctx* gks_handle;
@@ -92,7 +101,8 @@ gks_status gks_workspace_bytes(const gks_config* cfg, size_t* bytes);
 
 /* Validate cfg and the initial state, copy W (nvar x ncells), k and omega (ncells) from
  * the host into dev_workspace (256-byte aligned, >= gks_workspace_bytes), and compute the
- * first CFL step on `hip_stream` (a hipStream_t; NULL = default stream).  Returns
+ * first CFL step on `hip_stream` (a hipStream_t; NULL = default stream).  With
+ * turb_transport the initial rho k = rho * k and rho omega = rho * omega.  Returns
  * GKS_ERR_ARG for a bad config, k < 0, omega <= 0; GKS_ERR_NONPHYSICAL for rho <= 0 or
  * p <= 0; GKS_ERR_NOMEM if bytes is too small. */
 gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
@@ -100,11 +110,14 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
 
 /* Enqueue nsteps explicit steps (asynchronous; no host synchronisation).  Each step: CFL
  * time step from the current state, strain rate, every face flux, conservative update,
- * residual and next time step, all on the device. */
+ * residual and next time step, all on the device.  With turb_transport the strain pass
+ * also computes k, omega and the k-omega sources, the face pass the fluxes of rho k and
+ * rho omega, and the update advances them; a step whose rho k < 0 or rho omega <= 0 is
+ * non-physical. */
 gks_status gks_step(gks_handle h, int32_t nsteps);
 
 /* Synchronise and report the last step: res[nvar] = sqrt(mean(((W^{n+1}-W^n)/dt)^2)) per
- * field, res_first[nvar] the same for the first step of the solve (for convergence
+ * flow field (rho k and rho omega excluded), res_first[nvar] the same for the first step of the solve (for convergence
  * ratios), the step dt_last, the time t and the number of steps done.  Any pointer may be
  * NULL. */
 gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt_last, double* t,
@@ -113,8 +126,8 @@ gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt
 /* Synchronise and copy a field (GKS_FIELD_*) to host memory. */
 gks_status gks_fields(gks_handle h, int32_t which, double* host_out);
 
-/* Device pointer of the current conservative state (nvar x ncells, FP64). Valid until the
- * next gks_step. */
+/* Device pointer of the current conservative state (nvar x ncells, FP64; nvar + 2 with
+ * turb_transport). Valid until the next gks_step. */
 gks_status gks_state_device_ptr(gks_handle h, const double** dev_W);
 
 /* Synchronise and release the handle (the caller frees the workspace). */
@@ -122,9 +135,10 @@ gks_status gks_destroy(gks_handle h);
 
 /* Per-kernel timing for benchmarks.  While enabled, gks_step launches each kernel with a
  * pair of HIP events on the handle's stream that the runtime stamps with that launch's
- * own start and end (no extra packets between launches).  A step is three launches:
- * strain (which also ends the previous step), face and update; a call adds one trailing
- * end-of-step launch (finish).  gks_kernel_times synchronises and writes the summed
+ * own start and end (no extra packets between launches).  A 3D step is three launches:
+ * strain (which also ends the previous step), face and update; a 2D step two: strain and
+ * the fused tile kernel, which computes the faces and updates (timed as face).  A call
+ * adds one trailing end-of-step launch (finish).  gks_kernel_times synchronises and writes the summed
  * milliseconds of each launch kind since timing was enabled (ms[0..3] = strain, face,
  * update, finish) and the number of steps timed; enabling again resets. */
 gks_status gks_set_timing(gks_handle h, int32_t enable);
@@ -153,7 +167,8 @@ gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
  * captured as a graph.  Creation (and gks_batch_set_members) waits for the members' own
  * streams; afterwards every per-handle call on a member first waits for the batch stream.
  * The table lives in dev_workspace.  Handles stay owned by the caller and must outlive
- * the batch. */
+ * the batch.  Members are frozen-field solves: a handle with turb_transport is refused
+ * (GKS_ERR_ARG), here and in gks_batch_set_members. */
 gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity,
                             void* dev_workspace, size_t bytes, void* hip_stream, gks_batch* out);
 

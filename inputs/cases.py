@@ -47,6 +47,7 @@ class Case:
     steps: int = 100
     precision: str = "fp64"       # "fp64" | "fp32_flux"
     max_steps: int = 0            # > 0: a solver stops after this many steps
+    kw_transport: bool = False    # transport k and omega with the flow (else frozen inputs)
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property

@@ -38,14 +38,16 @@
  *    with T = p0/rho0, eta = S/(C_mu omega), interface state W0.
  *  - Prandtl correction: F_E += (1/Pr - 1) q, q the time-integrated heat flux of the
  *    interface distribution in the frame of U0.
- *  - k-omega transport (og_run_kw; the "allied equations" of the implementation
- *    section, with the Wilcox 2006 k-omega model the paper names): conservative rho k,
+ *  - k-omega transport (og_run_kw; the turbulence-model equations that the implementation
+ *    section solves beside the flow, with the Wilcox 2006 k-omega model the paper names):
+ *    conservative rho k,
  *    rho omega; convection with the GKS time-integrated mass flux, upwind by its sign;
  *    face diffusion with mu + sigma* rho k/omega and mu + sigma rho k/omega (face means of
  *    the two cells); production P from the paper's turbulent viscosity
  *    mu_t = rho k/(omega sqrt(1+eta^2)); cross-diffusion sigma_d (rho/omega) grad k.grad omega
  *    where that product is positive; the sinks beta* omega rho k and beta omega rho omega
- *    point-implicit in the step; ghost k and omega take their interior image's values.
+ *    point-implicit in the step; a ghost cell's k, omega and, in the face diffusion,
+ *    density take their interior image's values.
  */
 #include <math.h>
 #include <stdio.h>
@@ -915,15 +917,16 @@ static void og_kw_source_cell(const og_grid* gr, const double* We, const double*
 }
 
 /* Time-integrated fluxes of rho k and rho omega through one face (axis d, face coordinates
- * as in og_face_at), given the face's time-integrated mass flux Frho. */
-static void og_kw_face(const og_grid* gr, const double* We, const double* kk, const double* om, int d,
+ * as in og_face_at), given the face's time-integrated mass flux Frho.  W: interior state;
+ * a ghost cell's density, k and omega (so its eddy viscosity) are its interior image's. */
+static void og_kw_face(const og_grid* gr, const double* W, const double* kk, const double* om, int d,
                        long fi, long fj, long fk, double Frho, double dt, double* Fk, double* Fw)
 {
     long cl[3] = {fi, fj, fk}, cr[3] = {fi, fj, fk};
     cl[d] -= 1;
     const double kl = og_kw_at(gr, kk, cl), kr = og_kw_at(gr, kk, cr);
     const double wl = og_kw_at(gr, om, cl), wr = og_kw_at(gr, om, cr);
-    const double rl = We[gidx(gr, cl[0], cl[1], cl[2])], rr = We[gidx(gr, cr[0], cr[1], cr[2])];
+    const double rl = og_kw_at(gr, W, cl), rr = og_kw_at(gr, W, cr);
     const double nut = 0.5 * (rl * kl / wl + rr * kr / wr);
     const double dn = gr->xc[d][cr[d] + 2] - gr->xc[d][cl[d] + 2];
     const double mu = gr->c->mu;
@@ -958,7 +961,7 @@ static int og_step_kw(const og_grid* gr, const double* W, const double* kk, cons
             double Fl[5];
             if (og_face_at(gr, We, kk, om, S, d, fi, fj, fk, dt, Fl)) { bad = 1; continue; }
             for (int m = 0; m < nv; ++m) F[d][m * nf + f] = Fl[m];
-            og_kw_face(gr, We, kk, om, d, fi, fj, fk, Fl[0], dt, &Fk[d][f], &Fw[d][f]);
+            og_kw_face(gr, W, kk, om, d, fi, fj, fk, Fl[0], dt, &Fk[d][f], &Fw[d][f]);
         }
     }
     if (!bad) {

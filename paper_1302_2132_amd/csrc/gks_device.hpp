@@ -35,8 +35,13 @@ struct alignas(64) State {
 
 // Device descriptor of one solve.  Extended metric arrays are offset so that index i of
 // axis d (i from -2) reads xf[d][i], xc[d][i], dx[d][i].
+// With k-omega transport (kw = 1) the state holds nv + 2 components, rho k and rho omega
+// after the flow variables; k and om then hold k and omega of the state a step starts
+// from (written by its strain pass), Qk and Qw the explicit sources of that state, nt its
+// rho k / omega.
 struct Inst {
     int dim, nv, precision, cls;
+    int kw;                    // 1: k and omega are transported, else frozen inputs
     int n[3];
     int ntan[3];               // cells in a boundary plane of axis d
     int ncells;                // < 2^29 (validated), so cell and face indices fit in int
@@ -45,10 +50,13 @@ struct Inst {
     double gamma, prandtl, mu, c_a, c_mu, cfl, t_end, b;
     double two_over_b, inv_b, inv_cmu, pfix;   // 2/b, 1/b, 1/C_mu, 1/Pr - 1
     double* W[2];
-    const double* k;
-    const double* om;
+    double* k;
+    double* om;
     double* S;
-    void* F[3];                // 3D face fluxes per axis: [nv][nface[d]], double or float (2D: none)
+    double* Qk;                // transport only: sources of rho k and rho omega per cell,
+    double* Qw;
+    double* nt;                // and the eddy viscosity rho k / omega of the diffusive fluxes
+    void* F[3];                // 3D face fluxes per axis: [nv (+2)][nface[d]], double or float (2D: none)
     const double* xf[3];
     const double* xc[3];
     const double* dx[3];

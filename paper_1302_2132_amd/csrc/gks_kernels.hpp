@@ -17,6 +17,11 @@
 // captured graph) serves any membership.  Workgroup ids are remapped so that consecutive
 // tiles, which share halo cells, land on the same XCD (L2).
 //
+// Solves that transport k and omega (Inst::kw) use the KW = true instantiations: the
+// strain pass also derives k, omega and the model's sources of each cell, the face pass
+// adds the fluxes of rho k and rho omega, and the update advances them with point-implicit
+// sinks.  The KW = false code is the frozen-field scheme, untouched by the transport.
+//
 // The table, the solve descriptors and (outside k_finish) the step state are read
 // through the constant address space: nothing writes them while these kernels run, so
 // their wave-uniform reads compile to scalar loads rather than chains of dependent
@@ -173,6 +178,93 @@ __device__ inline void strain_cell(cref<Inst> I, int cell)
 }
 
 // --------------------------------------------------------------------------------------
+// k-omega transport: sources of a cell, fluxes of a face
+// --------------------------------------------------------------------------------------
+// Coefficients of Wilcox's 2006 k-omega model, the closure whose k and omega enter the
+// turbulent relaxation time of the scheme (section on the turbulent relaxation time).
+constexpr double KW_BETA_STAR = 0.09;
+constexpr double KW_BETA = 0.0708;
+constexpr double KW_ALPHA = 13.0 / 25.0;
+constexpr double KW_SIGMA_STAR = 0.6;
+constexpr double KW_SIGMA = 0.5;
+constexpr double KW_SIGMA_DO = 0.125;
+
+// Strain pass of a transported solve: besides the strain-rate magnitude S (as in
+// strain_cell), k = rho k / rho, omega = rho omega / rho and rho k / omega of the cell,
+// stored for the face and update passes of the step, and the explicit sources
+//   Qk = mu_t (S^2 - 2/3 div^2) - 2/3 rho k div,   mu_t = rho k / (omega sqrt(1 + eta^2)),
+//   Qw = alpha rho ((S^2 - 2/3 div^2)/sqrt(1 + eta^2) - 2/3 omega div)
+//        + sigma_do (rho/omega) grad k . grad omega   (the last term only where positive),
+// eta = S/(C_mu omega): alpha (omega/k) times the production of k, written without the
+// division by k.  Gradients are central differences over the neighbouring centres; a
+// ghost neighbour's k and omega are those of its interior image.
+template <int D>
+__device__ inline void strain_cell_kw(cref<Inst> I, int cell)
+{
+    const double* __restrict__ W = I.W[state_of(I).fresh];
+    const long long nc = I.ncells;
+    int c[3];
+    c[0] = cell % I.n[0];
+    c[1] = (cell / I.n[0]) % I.n[1];
+    c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
+    double g[3][3], gk[3], gw[3];
+    for (int b = 0; b < D; ++b) {
+        double wp[D + 2], wm[D + 2];
+        int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+        cp[b] += 1;
+        cm[b] -= 1;
+        load_state<D>(I, W, b, cp, wp);
+        load_state<D>(I, W, b, cm, wm);
+        const int jp = image_cell<D>(I, b, cp), jm = image_cell<D>(I, b, cm);
+        const double rp = W[jp], rm = W[jm];
+        const double kp = W[(D + 2) * nc + jp] / rp, km = W[(D + 2) * nc + jm] / rm;
+        const double qp = W[(D + 3) * nc + jp] / rp, qm = W[(D + 3) * nc + jm] / rm;
+        const double ip = 1.0 / wp[0], im = 1.0 / wm[0], ih = I.ic2[b][c[b]];
+        for (int a = 0; a < D; ++a) g[a][b] = (wp[1 + a] * ip - wm[1 + a] * im) * ih;
+        gk[b] = (kp - km) * ih;
+        gw[b] = (qp - qm) * ih;
+    }
+    double ss = 0.0, div = 0.0, cross = 0.0;
+    for (int a = 0; a < D; ++a) {
+        div += g[a][a];
+        cross += gk[a] * gw[a];
+        for (int b = 0; b < D; ++b) {
+            const double s = 0.5 * (g[a][b] + g[b][a]);
+            ss += s * s;
+        }
+    }
+    const double s2 = 2.0 * ss, S = sqrt(s2);
+    const double rho = W[cell];
+    const double kc = W[(D + 2) * nc + cell] / rho, wc = W[(D + 3) * nc + cell] / rho;
+    const double eta = S / (I.c_mu * wc);
+    const double root = sqrt(1.0 + eta * eta);
+    const double shear = s2 - (2.0 / 3.0) * div * div;
+    const double mut = rho * kc / (wc * root);
+    double qw = KW_ALPHA * rho * (shear / root - (2.0 / 3.0) * wc * div);
+    if (cross > 0.0) qw += KW_SIGMA_DO * rho / wc * cross;
+    I.S[cell] = S;
+    I.k[cell] = kc;
+    I.om[cell] = wc;
+    I.nt[cell] = rho * kc / wc;
+    I.Qk[cell] = mut * shear - (2.0 / 3.0) * rho * kc * div;
+    I.Qw[cell] = qw;
+}
+
+// Time-integrated fluxes of rho k and rho omega through a face: convection by the face's
+// time-integrated mass flux frho with the upwind cell's k (omega), and diffusion with the
+// coefficient mu + sigma* (sigma for omega) times the mean eddy viscosity rho k/omega
+// (nl, nr) of the two cells, over the centre distance (1/icdn).  A ghost's k, omega and
+// rho k/omega are those of its interior image.
+__device__ inline void kw_face(cref<Inst> I, double frho, double kl, double kr, double wl, double wr, double nl,
+                               double nr, double icdn, double dt, double& Fk, double& Fw)
+{
+    const double nut = 0.5 * (nl + nr);
+    const bool up = frho >= 0.0;
+    Fk = frho * (up ? kl : kr) - dt * (I.mu + KW_SIGMA_STAR * nut) * (kr - kl) * icdn;
+    Fw = frho * (up ? wl : wr) - dt * (I.mu + KW_SIGMA * nut) * (wr - wl) * icdn;
+}
+
+// --------------------------------------------------------------------------------------
 // face fluxes
 // --------------------------------------------------------------------------------------
 // Flux through the face at position i (0..n) along axis DIR from its four stencil cells
@@ -234,7 +326,7 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
 
 // One face normal to axis DIR, stencil read from the state in HBM, flux written to the
 // axis' face-flux array (structure of arrays).
-template <typename R, int D, int DIR>
+template <typename R, int D, int DIR, bool KW>
 __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int f)
 {
     constexpr int NV = D + 2;
@@ -276,7 +368,8 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
     const double* kk = I.k;
     const double* ww = I.om;
     const double* ss = I.S;
-    if (face_eval<R, D, DIR>(I, fc[DIR], Wc, kk, ww, ss, il, ir, state_of(I).dt, F)) atomicOr(&I.st->err, 1);
+    const double dt = state_of(I).dt;
+    if (face_eval<R, D, DIR>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt, F)) atomicOr(&I.st->err, 1);
     R* __restrict__ out = (R*)I.F[DIR];
     const long long nf = I.nface[DIR];   // 64-bit: component offsets m * nf may pass 2^31
     out[f] = F[0];
@@ -284,6 +377,25 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
     out[2 * nf + f] = F[2];
     if (D == 3) out[3 * nf + f] = F[3];
     out[(long long)(D + 1) * nf + f] = F[D + 1];
+    if (KW) {
+        // The two cells' indices are derived again from an opaque copy of the face index,
+        // so that neither they nor the cell values are kept live across the flux.
+        int g = f;
+        asm volatile("" : "+v"(g));
+        int gc[3];
+        gc[0] = g % fn0;
+        gc[1] = (g / fn0) % fn1;
+        gc[2] = (D == 3) ? g / (fn0 * fn1) : 0;
+        const int jr = image_cell<D>(I, DIR, gc);
+        const int fd = gc[DIR];
+        gc[DIR] -= 1;
+        const int jl = image_cell<D>(I, DIR, gc);
+        const double* nt = I.nt;
+        double Fk, Fw;
+        kw_face(I, double(F[0]), kk[jl], kk[jr], ww[jl], ww[jr], nt[jl], nt[jr], I.icd[DIR][fd - 1], dt, Fk, Fw);
+        out[(long long)(D + 2) * nf + f] = R(Fk);
+        out[(long long)(D + 3) * nf + f] = R(Fw);
+    }
 }
 
 #ifndef GKS_FACE_WAVES_FP64
@@ -295,7 +407,7 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
 // Register budget of the face kernel (instantiated for 3D; 2D steps use k_tile2): at least
 // this many waves per SIMD (2 leaves 256 VGPRs per lane for the 3D FP64 flux, 4 leaves 128
 // for the FP32 flux).  TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
-template <typename R, int D, int TILE>
+template <typename R, int D, int TILE, bool KW>
 __global__ __launch_bounds__(TILE)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_FACE_WAVES_FP64)))
 void k_face(const void* __restrict__ table, int cap, int cls)
@@ -312,18 +424,18 @@ void k_face(const void* __restrict__ table, int cap, int cls)
         int lt = tile - prefix[mj];
         if (lt < I.ntile_face[0]) {
             const int f = lt * TILE + (int)threadIdx.x;
-            if (f < I.nface[0]) face_one<R, D, 0>(I, f);
+            if (f < I.nface[0]) face_one<R, D, 0, KW>(I, f);
             continue;
         }
         lt -= I.ntile_face[0];
         if (D == 2 || lt < I.ntile_face[1]) {
             const int f = lt * TILE + (int)threadIdx.x;
-            if (f < I.nface[1]) face_one<R, D, 1>(I, f);
+            if (f < I.nface[1]) face_one<R, D, 1, KW>(I, f);
             continue;
         }
         lt -= I.ntile_face[1];
         const int f = lt * TILE + (int)threadIdx.x;
-        if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1)>(I, f);
+        if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1), KW>(I, f);
     }
 }
 
@@ -343,16 +455,18 @@ __device__ inline double wave_max(double v)
 }
 
 // Everything the update of one cell reads: old state, the fluxes through its low and high
-// faces per axis, inverse widths, k and omega.
-template <int D>
+// faces per axis, inverse widths, k and omega, and with transport (KW) also rho k, rho
+// omega, their face fluxes and their sources qk, qw.
+template <int D, bool KW = false>
 struct CellRead {
-    double old[D + 2], fl[D][D + 2], fh[D][D + 2], idx[D], kc, wc;
+    static constexpr int NX = D + 2 + (KW ? 2 : 0);
+    double old[NX], fl[D][NX], fh[D][NX], idx[D], kc, wc, qk, qw;
 };
 
-template <int D, typename RF>
-__device__ inline void update_read(cref<Inst> I, const double* __restrict__ Wo, int cell, CellRead<D>& x)
+template <int D, typename RF, bool KW = false>
+__device__ inline void update_read(cref<Inst> I, const double* __restrict__ Wo, int cell, CellRead<D, KW>& x)
 {
-    constexpr int NV = D + 2;
+    constexpr int NV = CellRead<D, KW>::NX;
     int c[3];
     c[0] = cell % I.n[0];
     c[1] = (cell / I.n[0]) % I.n[1];
@@ -376,13 +490,22 @@ __device__ inline void update_read(cref<Inst> I, const double* __restrict__ Wo, 
     }
     x.kc = I.k[cell];
     x.wc = I.om[cell];
+    if (KW) {
+        x.qk = I.Qk[cell];
+        x.qw = I.Qw[cell];
+    }
 }
 
 // New state of one cell (stored when `store`), its squared residual components added to
-// r2, its CFL rate folded into `rate` (max), a non-physical state flagged in `bad`.
-template <int D>
+// r2 (flow variables only), its CFL rate folded into `rate` (max), a non-physical state
+// flagged in `bad`.  With transport, rho k and rho omega take their flux differences and
+// sources explicitly and their sinks beta* omega rho k, beta omega rho omega point-
+// implicitly with the omega the step started from:
+//   rho k' = (rho k - flux out + dt Qk) / (1 + dt beta* omega),  likewise for rho omega.
+template <int D, bool KW = false>
 __device__ inline void update_apply(cref<Inst> I, double* __restrict__ Wn, int cell, bool store,
-                                    const CellRead<D>& x, double idt, double* r2, double& rate, int& bad)
+                                    const CellRead<D, KW>& x, double dt, double idt, double* r2, double& rate,
+                                    int& bad)
 {
     constexpr int NV = D + 2;
     double w[NV];
@@ -396,6 +519,22 @@ __device__ inline void update_apply(cref<Inst> I, double* __restrict__ Wn, int c
         const double r = (acc - x.old[m]) * idt;
         r2[m] += store ? r * r : 0.0;
     }
+    double kow = x.kc / x.wc;      // k/omega of the new state, for the CFL rate
+    if (KW) {
+        double ak = x.old[NV], aw = x.old[NV + 1];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ak -= (x.fh[d][NV] - x.fl[d][NV]) * x.idx[d];
+            aw -= (x.fh[d][NV + 1] - x.fl[d][NV + 1]) * x.idx[d];
+        }
+        const double rk = (ak + dt * x.qk) / (1.0 + dt * KW_BETA_STAR * x.wc);
+        const double rw = (aw + dt * x.qw) / (1.0 + dt * KW_BETA * x.wc);
+        if (!store) return;
+        Wn[(long long)NV * I.ncells + cell] = rk;
+        Wn[(long long)(NV + 1) * I.ncells + cell] = rw;
+        if (!(rk >= 0.0) || !(rw > 0.0) || !(rk < 1e300) || !(rw < 1e300)) { bad = 1; return; }
+        kow = rk / rw;
+    }
     if (!store) return;
     // positivity and the CFL rate of the new state
     double ke = 0.0, U[3];
@@ -406,7 +545,7 @@ __device__ inline void update_apply(cref<Inst> I, double* __restrict__ Wn, int c
     // CFL rate  sum_d (|U_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2
     const double cs = sqrt(I.gamma * p * irho);
     const double fac = fmax(4.0 / 3.0, I.gamma / I.prandtl);
-    const double nu = (I.mu * irho + x.kc / x.wc) * fac;
+    const double nu = (I.mu * irho + kow) * fac;
     double r = 0.0, r2s = 0.0;
     for (int d = 0; d < D; ++d) {
         r += (fabs(U[d]) + cs) * x.idx[d];
@@ -417,13 +556,13 @@ __device__ inline void update_apply(cref<Inst> I, double* __restrict__ Wn, int c
 
 // Update of one cell from the face fluxes in HBM: every read first (the compiler cannot
 // move a load above a store through another pointer), then the stores.
-template <int D, typename RF>
+template <int D, typename RF, bool KW>
 __device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2, double& rate, int& bad)
 {
     const int cur = state_of(I).parity;
-    CellRead<D> x;
-    update_read<D, RF>(I, I.W[cur], cell, x);
-    update_apply<D>(I, I.W[cur ^ 1], cell, true, x, 1.0 / dt, r2, rate, bad);
+    CellRead<D, KW> x;
+    update_read<D, RF, KW>(I, I.W[cur], cell, x);
+    update_apply<D, KW>(I, I.W[cur ^ 1], cell, true, x, dt, 1.0 / dt, r2, rate, bad);
 }
 
 // --------------------------------------------------------------------------------------
@@ -449,16 +588,17 @@ static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_TH
 #define GKS_TILE2_WAVES_FP64 3
 #endif
 
-template <typename R>
+template <typename R, bool KW>
 __global__ __launch_bounds__(T2_THREADS)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_TILE2_WAVES_FP64)))
 void k_tile2(const void* __restrict__ table, int cap, int cls)
 {
     constexpr int NV = 4;
+    constexpr int NX = NV + (KW ? 2 : 0);     // with transport: fluxes of rho k, rho omega too
     __shared__ double sW[NV][T2_WX * T2_WY];
-    __shared__ double sK[3][T2_KX * T2_KY];
-    __shared__ R sFx[NV][T2_NFX];
-    __shared__ R sFy[NV][T2_NFY];
+    __shared__ double sK[KW ? 4 : 3][T2_KX * T2_KY];   // k, omega, strain rate (, rho k/omega)
+    __shared__ R sFx[NX][T2_NFX];
+    __shared__ R sFy[NX][T2_NFY];
     __shared__ double sh_sum[5 * 4];
     __shared__ double sh_max[4];
     __shared__ int sh_bad[4];
@@ -511,6 +651,7 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
             sK[0][e] = I.k[ic];
             sK[1][e] = I.om[ic];
             sK[2][e] = I.S[ic];
+            if (KW) sK[KW ? 3 : 0][e] = I.nt[ic];
         }
         __syncthreads();
 
@@ -530,6 +671,15 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                 sFx[1][tid] = F[1];
                 sFx[2][tid] = F[2];
                 sFx[3][tid] = F[3];
+                if (KW) {
+                    int q = kl;                  // reloaded, not kept live across the flux
+                    asm volatile("" : "+v"(q));
+                    double Fk, Fw;
+                    kw_face(I, double(F[0]), sK[0][q], sK[0][q + 1], sK[1][q], sK[1][q + 1], sK[KW ? 3 : 0][q],
+                            sK[KW ? 3 : 0][q + 1], I.icd[0][x0 + i - 1], dt, Fk, Fw);
+                    sFx[NX - 2][tid] = R(Fk);
+                    sFx[NX - 1][tid] = R(Fw);
+                }
             }
         }
         __builtin_amdgcn_sched_barrier(0);      // keep the two passes' registers apart
@@ -549,6 +699,15 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                 sFy[1][tid] = F[1];
                 sFy[2][tid] = F[2];
                 sFy[3][tid] = F[3];
+                if (KW) {
+                    int q = kl;
+                    asm volatile("" : "+v"(q));
+                    double Fk, Fw;
+                    kw_face(I, double(F[0]), sK[0][q], sK[0][q + T2_KX], sK[1][q], sK[1][q + T2_KX],
+                            sK[KW ? 3 : 0][q], sK[KW ? 3 : 0][q + T2_KX], I.icd[1][y0 + j - 1], dt, Fk, Fw);
+                    sFy[NX - 2][tid] = R(Fk);
+                    sFy[NX - 1][tid] = R(Fw);
+                }
             }
         }
         __syncthreads();
@@ -561,12 +720,13 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
             const int i = tid % T2X, j = tid / T2X;
             const bool own = tid < T2X * T2Y && i < tx && j < ty;
             const int ii = own ? i : 0, jj = own ? j : 0;
-            CellRead<2> x;
+            CellRead<2, KW> x;
             const int ew = (jj + 2) * T2_WX + ii + 2, ek = (jj + 1) * T2_KX + ii + 1;
             const int fx = jj * (T2X + 1) + ii, fy = jj * T2X + ii;
+            const int cell = (y0 + jj) * n0 + x0 + ii;
 #pragma unroll
-            for (int m = 0; m < NV; ++m) {
-                x.old[m] = sW[m][ew];
+            for (int m = 0; m < NX; ++m) {
+                x.old[m] = m < NV ? sW[m < NV ? m : 0][ew] : W[(long long)m * I.ncells + cell];
                 x.fl[0][m] = double(sFx[m][fx]);
                 x.fh[0][m] = double(sFx[m][fx + 1]);
                 x.fl[1][m] = double(sFy[m][fy]);
@@ -576,8 +736,11 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
             x.idx[1] = I.idx[1][y0 + jj];
             x.kc = sK[0][ek];
             x.wc = sK[1][ek];
-            const int cell = (y0 + jj) * n0 + x0 + ii;
-            update_apply<2>(I, I.W[cur ^ 1], cell, own, x, 1.0 / dt, r2, rate, bad);
+            if (KW) {
+                x.qk = I.Qk[cell];
+                x.qw = I.Qw[cell];
+            }
+            update_apply<2, KW>(I, I.W[cur ^ 1], cell, own, x, dt, 1.0 / dt, r2, rate, bad);
         }
         // tile partials in a fixed order
         for (int m = 0; m < NV; ++m) {
@@ -617,6 +780,7 @@ __device__ inline void next_step(cref<Inst> I, State* st, double rate, double t)
     st->t_after = ta;
 }
 
+template <bool KW>
 __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ table, int cap)
 {
     const TabC tv(table, cap);
@@ -637,8 +801,8 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
         int bad = 0;
         const double dt = state_of(I).dt;
         if (cell < I.ncells) {
-            if (I.precision) update_cell<3, float>(I, cell, dt, r2, rate, bad);
-            else update_cell<3, double>(I, cell, dt, r2, rate, bad);
+            if (I.precision) update_cell<3, float, KW>(I, cell, dt, r2, rate, bad);
+            else update_cell<3, double, KW>(I, cell, dt, r2, rate, bad);
         }
         // workgroup reductions in a fixed order
         for (int m = 0; m < I.nv; ++m) {
@@ -793,6 +957,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_finish(const void* __restrict__ t
 // Strain pass over every cell tile of the table (of active members unless `force`).
 // With `finish` set, the first `count` work items instead end the pending step of each
 // member (the strain items read W[fresh], which ending a step leaves alone).
+template <bool KW>
 __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ table, int cap, int force, int finish)
 {
     const TabC tv(table, cap);
@@ -811,8 +976,13 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
         if (!force && !state_of(I).active) continue;
         const int cell = (tile - tv.cell_prefix[mi]) * CELL_TILE + (int)threadIdx.x;
         if (cell >= I.ncells) continue;
-        if (I.dim == 2) strain_cell<2>(I, cell);
-        else strain_cell<3>(I, cell);
+        if (KW) {
+            if (I.dim == 2) strain_cell_kw<2>(I, cell);
+            else strain_cell_kw<3>(I, cell);
+        } else {
+            if (I.dim == 2) strain_cell<2>(I, cell);
+            else strain_cell<3>(I, cell);
+        }
     }
 }
 
@@ -828,13 +998,21 @@ __global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, i
     }
 }
 
-template __global__ void k_tile2<double>(const void*, int, int);
-template __global__ void k_tile2<float>(const void*, int, int);
-template __global__ void k_face<double, 3, 64>(const void*, int, int);
-template __global__ void k_face<double, 3, 128>(const void*, int, int);
-template __global__ void k_face<double, 3, 256>(const void*, int, int);
-template __global__ void k_face<float, 3, 64>(const void*, int, int);
-template __global__ void k_face<float, 3, 128>(const void*, int, int);
-template __global__ void k_face<float, 3, 256>(const void*, int, int);
+template __global__ void k_tile2<double, false>(const void*, int, int);
+template __global__ void k_tile2<float, false>(const void*, int, int);
+template __global__ void k_tile2<double, true>(const void*, int, int);
+template __global__ void k_tile2<float, true>(const void*, int, int);
+template __global__ void k_face<double, 3, 64, false>(const void*, int, int);
+template __global__ void k_face<double, 3, 128, false>(const void*, int, int);
+template __global__ void k_face<double, 3, 256, false>(const void*, int, int);
+template __global__ void k_face<float, 3, 64, false>(const void*, int, int);
+template __global__ void k_face<float, 3, 128, false>(const void*, int, int);
+template __global__ void k_face<float, 3, 256, false>(const void*, int, int);
+template __global__ void k_face<double, 3, 64, true>(const void*, int, int);
+template __global__ void k_face<float, 3, 64, true>(const void*, int, int);
+template __global__ void k_update<false>(const void*, int);
+template __global__ void k_update<true>(const void*, int);
+template __global__ void k_strain<false>(const void*, int, int, int);
+template __global__ void k_strain<true>(const void*, int, int, int);
 
 }  // namespace gks

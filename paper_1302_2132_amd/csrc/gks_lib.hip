@@ -25,7 +25,7 @@ namespace {
 thread_local std::string g_last_error;
 
 struct Layout {
-    size_t W[2], k, om, S, F[3], xf[3], xc[3], dx[3], idx[3], ic2[3], icd[3], fgeo[3], bcd[3][2], part, st, tab, total;
+    size_t W[2], k, om, S, Qk, Qw, nt, F[3], xf[3], xc[3], dx[3], idx[3], ic2[3], icd[3], fgeo[3], bcd[3][2], part, st, tab, total;
     long long ncells, nface[3];
     int ntan[3];
     int ntile_cell, ntile_face[3];
@@ -39,6 +39,8 @@ static int tiles2(long long n0, long long n1) { return (int)(((n0 + T2X - 1) / T
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int nvar_of(const gks_config* c) { return c->dim + 2; }
+// components of the stored state: the flow variables, then rho k and rho omega when transported
+int nstate_of(const gks_config* c) { return c->dim + 2 + (c->turb_transport ? 2 : 0); }
 
 bool config_ok(const gks_config* c, std::string* why)
 {
@@ -70,22 +72,26 @@ bool config_ok(const gks_config* c, std::string* why)
         return fail("gas or time-step parameter out of range");
     if (c->precision != GKS_FP64 && c->precision != GKS_FP32_FLUX) return fail("unknown precision");
     if (c->max_steps < 0) return fail("max_steps must be >= 0");
+    if (c->turb_transport != 0 && c->turb_transport != 1) return fail("turb_transport must be 0 or 1");
     return true;
 }
 
 void layout(const gks_config* c, Layout* L)
 {
-    const int nv = nvar_of(c), D = c->dim;
+    const int nv = nvar_of(c), nx = nstate_of(c), D = c->dim;
     long long n[3] = {c->n[0], c->n[1], D == 3 ? c->n[2] : 1};
     L->ncells = n[0] * n[1] * n[2];
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
     const size_t cellb = sizeof(double) * (size_t)L->ncells;
-    L->W[0] = take(cellb * nv);
-    L->W[1] = take(cellb * nv);
+    L->W[0] = take(cellb * nx);
+    L->W[1] = take(cellb * nx);
     L->k = take(cellb);
     L->om = take(cellb);
     L->S = take(cellb);
+    L->Qk = c->turb_transport ? take(cellb) : 0;
+    L->Qw = c->turb_transport ? take(cellb) : 0;
+    L->nt = c->turb_transport ? take(cellb) : 0;
     const size_t fb = c->precision == GKS_FP32_FLUX ? sizeof(float) : sizeof(double);
     for (int d = 0; d < 3; ++d) {
         L->nface[d] = 0;
@@ -97,7 +103,7 @@ void layout(const gks_config* c, Layout* L)
         L->nface[d] = L->ncells / n[d] * (n[d] + 1);
         L->ntan[d] = (int)(L->ncells / n[d]);
         L->ntile_face[d] = (int)((L->nface[d] + FACE_TILE - 1) / FACE_TILE);
-        if (D == 3) L->F[d] = take(fb * nv * (size_t)L->nface[d]);   // 2D fluxes stay in LDS
+        if (D == 3) L->F[d] = take(fb * nx * (size_t)L->nface[d]);   // 2D fluxes stay in LDS
         L->xf[d] = take(sizeof(double) * (n[d] + 5));
         L->xc[d] = take(sizeof(double) * (n[d] + 4));
         L->dx[d] = take(sizeof(double) * (n[d] + 4));
@@ -275,21 +281,23 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
 // Kernel of a face class: the fused 2D tile kernel (fixed workgroup of T2_THREADS) for the
 // 2D classes, the 3D face kernel with `tile` faces per workgroup otherwise.
 typedef void (*face_kernel_t)(const void*, int, int);
-template <int T>
+template <int T, bool KW>
 static face_kernel_t face_kernel_t_(int cls)
 {
     switch (cls) {
-    case 0: return k_tile2<double>;
-    case 1: return k_tile2<float>;
-    case 2: return k_face<double, 3, T>;
-    default: return k_face<float, 3, T>;
+    case 0: return k_tile2<double, KW>;
+    case 1: return k_tile2<float, KW>;
+    case 2: return k_face<double, 3, T, KW>;
+    default: return k_face<float, 3, T, KW>;
     }
 }
-static face_kernel_t face_kernel(int cls, int tile)
+// Transported solves run alone with the default tile; batches hold frozen-field solves.
+static face_kernel_t face_kernel(int cls, int tile, bool kw = false)
 {
-    if (tile == 128) return face_kernel_t_<128>(cls);
-    if (tile == 256) return face_kernel_t_<256>(cls);
-    return face_kernel_t_<64>(cls);
+    if (kw) return face_kernel_t_<FACE_TILE, true>(cls);
+    if (tile == 128) return face_kernel_t_<128, false>(cls);
+    if (tile == 256) return face_kernel_t_<256, false>(cls);
+    return face_kernel_t_<64, false>(cls);
 }
 static int face_block(int cls, int tile) { return cls < 2 ? T2_THREADS : tile; }
 static const int kDefaultFaceTiles[NCLS] = {FACE_TILE, FACE_TILE, FACE_TILE, FACE_TILE};
@@ -369,6 +377,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.nv = nv;
     I.precision = cfg->precision;
     I.cls = h->cls;
+    I.kw = cfg->turb_transport;
     for (int d = 0; d < 3; ++d) {
         I.n[d] = d < D ? (int)cfg->n[d] : 1;
         I.ntan[d] = L.ntan[d];
@@ -392,9 +401,12 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.max_steps = cfg->max_steps;
     I.W[0] = (double*)(ws + L.W[0]);
     I.W[1] = (double*)(ws + L.W[1]);
-    I.k = (const double*)(ws + L.k);
-    I.om = (const double*)(ws + L.om);
+    I.k = (double*)(ws + L.k);
+    I.om = (double*)(ws + L.om);
     I.S = (double*)(ws + L.S);
+    I.Qk = cfg->turb_transport ? (double*)(ws + L.Qk) : nullptr;
+    I.Qw = cfg->turb_transport ? (double*)(ws + L.Qw) : nullptr;
+    I.nt = cfg->turb_transport ? (double*)(ws + L.nt) : nullptr;
     I.part = (double*)(ws + L.part);
     I.st = (State*)(ws + L.st);
     I.ntile_cell = L.ntile_cell;
@@ -405,6 +417,16 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     HIP_TRY(h, hipMemcpyAsync(I.W[0], W, cellb * nv, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipMemcpyAsync((void*)I.k, k, cellb, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipMemcpyAsync((void*)I.om, omega, cellb, hipMemcpyHostToDevice, s));
+    std::vector<double> turb;
+    if (cfg->turb_transport) {
+        // transported: the state carries rho k and rho omega after the flow variables
+        turb.resize(2 * (size_t)N);
+        for (long long i = 0; i < N; ++i) {
+            turb[i] = W[i] * k[i];
+            turb[N + i] = W[i] * omega[i];
+        }
+        HIP_TRY(h, hipMemcpyAsync(I.W[0] + (size_t)nv * N, turb.data(), 2 * cellb, hipMemcpyHostToDevice, s));
+    }
     for (int d = 0; d < D; ++d) {
         std::vector<double> xf, xc, dx, idx, ic2, icd, fgeo;
         metrics(cfg, d, xf, xc, dx, idx, ic2, icd, fgeo);
@@ -476,16 +498,19 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
 {
     hipStream_t s = h->stream;
     const void* tab = h->tab;
-    face_kernel_t fk = face_kernel(h->cls, FACE_TILE);
+    const bool kw = h->cfg.turb_transport != 0;
+    face_kernel_t fk = face_kernel(h->cls, FACE_TILE, kw);
     const dim3 fblock(face_block(h->cls, FACE_TILE));
     const bool upd = h->cfg.dim == 3;
+    void (*ks)(const void*, int, int, int) = kw ? k_strain<true> : k_strain<false>;
+    void (*ku)(const void*, int) = kw ? k_update<true> : k_update<false>;
     const int grid_head = h->grid_cell + 1;
     if (nsteps == 0) return GKS_OK;
     if (!h->timing) {
         for (int i = 0; i < nsteps; ++i) {
-            hipLaunchKernelGGL(k_strain, dim3(grid_head), dim3(CELL_TILE), 0, s, tab, 1, 0, 1);
+            hipLaunchKernelGGL(ks, dim3(grid_head), dim3(CELL_TILE), 0, s, tab, 1, 0, 1);
             hipLaunchKernelGGL(fk, dim3(h->grid_face), fblock, 0, s, tab, 1, h->cls);
-            if (upd) hipLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
+            if (upd) hipLaunchKernelGGL(ku, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
         }
         hipLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, tab, 1, 0);
     } else {
@@ -496,11 +521,11 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
                 gks_status r = next_event(h, &ev[q]);
                 if (r != GKS_OK) return r;
             }
-            hipExtLaunchKernelGGL(k_strain, dim3(grid_head), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, 0, 1);
+            hipExtLaunchKernelGGL(ks, dim3(grid_head), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, 0, 1);
             hipExtLaunchKernelGGL(fk, dim3(h->grid_face), fblock, 0, s, ev[2], ev[3], 0, tab, 1, h->cls);
             h->timed_kind.insert(h->timed_kind.end(), {0, 1});
             if (upd) {
-                hipExtLaunchKernelGGL(k_update, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, ev[4], ev[5], 0, tab, 1);
+                hipExtLaunchKernelGGL(ku, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, ev[4], ev[5], 0, tab, 1);
                 h->timed_kind.push_back(2);
             }
             h->steps_timed += 1;
@@ -556,7 +581,7 @@ gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt
 gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
 {
     if (!h || !host_out) return fail_h(h, GKS_ERR_ARG, "NULL argument");
-    if (which < GKS_FIELD_CONS || which > GKS_FIELD_STRAIN) return fail_h(h, GKS_ERR_ARG, "unknown field");
+    if (which < GKS_FIELD_CONS || which > GKS_FIELD_TURB) return fail_h(h, GKS_ERR_ARG, "unknown field");
     gks_status rs = sync_batch(h);
     if (rs != GKS_OK) return rs;
     State st;
@@ -564,10 +589,20 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const long long N = h->L.ncells;
     const int nv = h->nv, D = h->cfg.dim;
-    if (which == GKS_FIELD_STRAIN) {
-        hipLaunchKernelGGL(k_strain, dim3(h->grid_cell), dim3(CELL_TILE), 0, h->stream, (const void*)h->tab, 1, 1, 0);
+    if (which == GKS_FIELD_STRAIN || (which == GKS_FIELD_TURB && h->cfg.turb_transport)) {
+        // a strain pass over the current state (with transport it also writes k and omega)
+        hipLaunchKernelGGL(h->cfg.turb_transport ? k_strain<true> : k_strain<false>, dim3(h->grid_cell),
+                           dim3(CELL_TILE), 0, h->stream, (const void*)h->tab, 1, 1, 0);
         HIP_TRY(h, hipGetLastError());
+    }
+    if (which == GKS_FIELD_STRAIN) {
         HIP_TRY(h, hipMemcpyAsync(host_out, h->inst.S, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return GKS_OK;
+    }
+    if (which == GKS_FIELD_TURB) {
+        HIP_TRY(h, hipMemcpyAsync(host_out, h->inst.k, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(host_out + N, h->inst.om, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         return GKS_OK;
     }
@@ -700,8 +735,10 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
         return fail_h(nullptr, GKS_ERR_ARG, "bad batch arguments");
     if (bytes < batch_bytes(capacity)) return fail_h(nullptr, GKS_ERR_NOMEM, "batch workspace too small");
     if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
-    for (int i = 0; i < count; ++i)
+    for (int i = 0; i < count; ++i) {
         if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
+        if (hs[i]->cfg.turb_transport) return fail_h(nullptr, GKS_ERR_ARG, "solves with k-omega transport step alone");
+    }
     gks_batch b = new gks_batch_ctx();
     b->members.assign(hs, hs + count);
     b->cap = capacity;
@@ -724,8 +761,10 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
 gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t count)
 {
     if (!b || count < 0 || count > b->cap || (!hs && count)) return fail_h(nullptr, GKS_ERR_ARG, "bad member list");
-    for (int i = 0; i < count; ++i)
+    for (int i = 0; i < count; ++i) {
         if (!hs[i]) return fail_h(nullptr, GKS_ERR_ARG, "NULL member");
+        if (hs[i]->cfg.turb_transport) return fail_h(nullptr, GKS_ERR_ARG, "solves with k-omega transport step alone");
+    }
     b->members.assign(hs, hs + count);
     return batch_upload(b);
 }
@@ -746,13 +785,13 @@ static int batch_grid(gks_batch b, int kind)
 static void batch_launch(gks_batch b, int present)
 {
     const void* tab = b->tab;
-    hipLaunchKernelGGL(k_strain, dim3(batch_grid(b, 0)), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0, 1);
+    hipLaunchKernelGGL(k_strain<false>, dim3(batch_grid(b, 0)), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0, 1);
     for (int c = 0; c < NCLS; ++c)
         if (present & (1 << c))
             hipLaunchKernelGGL(face_kernel(c, b->face_tile[c]), dim3(batch_grid(b, 1 + c)),
                                dim3(face_block(c, b->face_tile[c])), 0, b->stream, tab, b->cap, c);
     if (present & ((1 << 2) | (1 << 3)))   // 3D members update in their own launch
-        hipLaunchKernelGGL(k_update, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
+        hipLaunchKernelGGL(k_update<false>, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
 }
 
 gks_status gks_batch_step(gks_batch b, int32_t nsteps)

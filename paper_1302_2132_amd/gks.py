@@ -17,7 +17,7 @@ GKS_OK, GKS_ERR_ARG, GKS_ERR_NONPHYSICAL, GKS_ERR_NOMEM, GKS_ERR_DEVICE, GKS_ERR
 _NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NONPHYSICAL", 3: "ERR_NOMEM", 4: "ERR_DEVICE", 5: "ERR_STATE"}
 BC = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
-FIELD = {"cons": 0, "prim": 1, "strain": 2}
+FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3}
 
 # every entry point declared in include/gks.h
 EXPORTED = (
@@ -46,6 +46,7 @@ class gks_config(C.Structure):
         ("c_mu", C.c_double), ("cfl", C.c_double), ("t_end", C.c_double),
         ("precision", C.c_int32),
         ("max_steps", C.c_int64),
+        ("turb_transport", C.c_int32),
     ]
 
 
@@ -128,6 +129,7 @@ class _Cfg:
         c.c_mu, c.cfl, c.t_end = case.c_mu, case.cfl, case.t_end
         c.precision = PRECISION[case.precision]
         c.max_steps = int(getattr(case, "max_steps", 0) or 0)
+        c.turb_transport = 1 if getattr(case, "kw_transport", False) else 0
         self.c = c
 
 
@@ -290,7 +292,8 @@ class Solver:
         return gks_residual(self.h, self.nv)
 
     def fields(self, which="cons"):
-        shape = self.case.k.shape if which == "strain" else self.case.W.shape
+        """cons / prim: (nvar, nz, ny, nx); strain: (nz, ny, nx); turb: (2, nz, ny, nx), k and omega."""
+        shape = {"strain": self.case.k.shape, "turb": (2,) + self.case.k.shape}.get(which, self.case.W.shape)
         return gks_fields(self.h, which, shape)
 
     def close(self):
