@@ -6,7 +6,8 @@ Mach-2 inflow, 8-degree oblique shock from the top boundary, adiabatic no-slip w
 frozen seeded k/omega.  A step is one explicit time step of the whole path (CFL time
 step, strain rate, every face flux, conservative update, residual).  The FP64 form is
 the headline `value`; the FP32-flux form (flux arithmetic in FP32, everything else FP64)
-is reported beside it with its error against the FP64 run.
+is reported beside it with its error against the FP64 run, and so is the same workload
+with k and omega transported by the k-omega equations instead of frozen.
 
 Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
 """
@@ -81,7 +82,8 @@ def _roofline(case, leg, steps, flops_face, peak):
     face_s = leg["kernels"]["face_ms"] / 1e3 / steps
     achieved = flops_face * faces / face_s / 1e12
     r = "float" if case.precision == "fp32_flux" else "double"
-    kernel = f"k_tile2<{r}>" if case.dim == 2 else f"k_face<{r},3,64>"
+    kw = "true" if getattr(case, "kw_transport", False) else "false"
+    kernel = f"k_tile2<{r},{kw}>" if case.dim == 2 else f"k_face<{r},3,64,{kw}>"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": _profiled_traffic(kernel),
             "kernel": kernel, "flops_per_face": flops_face, "faces_per_launch": faces,
@@ -235,6 +237,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D isotropic-box leg")
+    ap.add_argument("--no-kw", action="store_true", help="skip the k-omega transport leg")
     ap.add_argument("--serve-full", action="store_true", help="served leg on the full 256-request trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), to calibrate "
@@ -258,7 +261,7 @@ def main():
     import torch
 
     from inputs import cases as C
-    from paper_1302_2132_amd import gks_face_flops
+    from paper_1302_2132_amd import gks_face_flops, gks_kw_face_flops
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
 
     case = C.sbli(1024, 512)
@@ -294,6 +297,18 @@ def main():
             "max_rel_err_vs_fp64_per_field": err, "after_steps": leg32["steps_done"],
             "roofline": _roofline(c32, leg32, K, flops2d, FP32_PEAK_TFLOPS),
             "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg32["kernels"].items() if k != "steps"},
+        }
+    if not args.no_kw:
+        ckw = C.sbli(1024, 512)
+        ckw.kw_transport = True
+        legkw = _leg(ckw, K, Wm)
+        vkw = ckw.ncells * K / legkw["seconds"]
+        out["kw_transport"] = {
+            "workload": "sbli_1024x512 as above, k and omega transported (2006 k-omega model), FP64",
+            "value": vkw, "unit": "cell-updates/s", "ms_per_step": legkw["seconds"] * 1e3 / K,
+            "vs_frozen": vkw / value,
+            "roofline": _roofline(ckw, legkw, K, flops2d + gks_kw_face_flops(), FP64_PEAK_TFLOPS),
+            "kernel_ms_per_step": {k: round(v / K, 4) for k, v in legkw["kernels"].items() if k != "steps"},
         }
     if not args.no_3d:
         out["isotropic_3d"] = _iso_leg()

@@ -152,6 +152,11 @@ const char* gks_last_error(gks_handle h);
  * Counted by running the flux code on the host with a counting number type. */
 gks_status gks_face_flops(int32_t dim, int32_t precision, double* flops);
 
+/* The same count for the fluxes of rho k and rho omega that a transported solve adds to
+ * every face (upwind convection by the mass flux plus diffusion with the mean eddy
+ * viscosity; the mass flux itself is part of gks_face_flops). */
+gks_status gks_kw_face_flops(double* flops);
+
 /* ---------------------------------------------------------------------------------- */
 /* Batched form: many independent solves (any mix of sizes, dims, precisions) advanced  */
 /* by persistent kernels that walk one device tile table per step.                       */

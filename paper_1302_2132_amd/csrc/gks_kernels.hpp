@@ -254,14 +254,22 @@ __device__ inline void strain_cell_kw(cref<Inst> I, int cell)
 // time-integrated mass flux frho with the upwind cell's k (omega), and diffusion with the
 // coefficient mu + sigma* (sigma for omega) times the mean eddy viscosity rho k/omega
 // (nl, nr) of the two cells, over the centre distance (1/icdn).  A ghost's k, omega and
-// rho k/omega are those of its interior image.
+// rho k/omega are those of its interior image.  (A template so that the host can count
+// its operations.)
+template <typename T>
+__host__ __device__ inline void kw_face_t(T mu, T frho, T kl, T kr, T wl, T wr, T nl, T nr, T icdn, T dt, T& Fk,
+                                          T& Fw)
+{
+    const T nut = T(0.5) * (nl + nr);
+    const bool up = frho >= T(0.0);
+    Fk = frho * (up ? kl : kr) - dt * (mu + T(KW_SIGMA_STAR) * nut) * (kr - kl) * icdn;
+    Fw = frho * (up ? wl : wr) - dt * (mu + T(KW_SIGMA) * nut) * (wr - wl) * icdn;
+}
+
 __device__ inline void kw_face(cref<Inst> I, double frho, double kl, double kr, double wl, double wr, double nl,
                                double nr, double icdn, double dt, double& Fk, double& Fw)
 {
-    const double nut = 0.5 * (nl + nr);
-    const bool up = frho >= 0.0;
-    Fk = frho * (up ? kl : kr) - dt * (I.mu + KW_SIGMA_STAR * nut) * (kr - kl) * icdn;
-    Fw = frho * (up ? wl : wr) - dt * (I.mu + KW_SIGMA * nut) * (wr - wl) * icdn;
+    kw_face_t<double>(I.mu, frho, kl, kr, wl, wr, nl, nr, icdn, dt, Fk, Fw);
 }
 
 // --------------------------------------------------------------------------------------

@@ -954,6 +954,16 @@ static double count_face()
     face_flux<CR, D, CR>(in, gas, F);
     return CR::n;
 }
+
+// operations of the rho k / rho omega fluxes of one face (transported solves)
+static double count_kw_face()
+{
+    CR Fk, Fw;
+    CR::n = 0;
+    kw_face_t<CR>(CR(1e-3), CR(0.2), CR(1e-3), CR(2e-3), CR(5.0), CR(6.0), CR(2e-4), CR(3e-4), CR(100.0), CR(1e-3),
+                  Fk, Fw);
+    return CR::n;
+}
 }  // namespace gks
 
 extern "C" gks_status gks_face_flops(int32_t dim, int32_t precision, double* flops)
@@ -961,5 +971,12 @@ extern "C" gks_status gks_face_flops(int32_t dim, int32_t precision, double* flo
     if (!flops || (dim != 2 && dim != 3) || (precision != GKS_FP64 && precision != GKS_FP32_FLUX))
         return fail_h(nullptr, GKS_ERR_ARG, "bad arguments");
     *flops = dim == 2 ? gks::count_face<2>() : gks::count_face<3>();
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_kw_face_flops(double* flops)
+{
+    if (!flops) return fail_h(nullptr, GKS_ERR_ARG, "flops is NULL");
+    *flops = gks::count_kw_face();
     return GKS_OK;
 }

@@ -22,7 +22,7 @@ FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3}
 # every entry point declared in include/gks.h
 EXPORTED = (
     "gks_workspace_bytes", "gks_init", "gks_step", "gks_residual", "gks_fields",
-    "gks_state_device_ptr", "gks_destroy", "gks_last_error", "gks_face_flops",
+    "gks_state_device_ptr", "gks_destroy", "gks_last_error", "gks_face_flops", "gks_kw_face_flops",
     "gks_set_timing", "gks_kernel_times",
     "gks_batch_workspace_bytes", "gks_batch_create", "gks_batch_set_members", "gks_batch_step",
     "gks_batch_capture", "gks_batch_set_launch", "gks_batch_status", "gks_batch_destroy",
@@ -78,6 +78,7 @@ def lib():
         L.gks_last_error.argtypes = [vp]
         L.gks_last_error.restype = C.c_char_p
         L.gks_face_flops.argtypes = [i32, i32, dp]
+        L.gks_kw_face_flops.argtypes = [dp]
         L.gks_set_timing.argtypes = [vp, i32]
         L.gks_kernel_times.argtypes = [vp, dp, C.POINTER(i64)]
         L.gks_batch_workspace_bytes.argtypes = [i32, sz]
@@ -192,6 +193,12 @@ def gks_last_error(h=None):
 def gks_face_flops(dim, precision="fp64"):
     out = C.c_double(0)
     _check(lib().gks_face_flops(int(dim), PRECISION[precision], C.byref(out)))
+    return out.value
+
+
+def gks_kw_face_flops():
+    out = C.c_double(0)
+    _check(lib().gks_kw_face_flops(C.byref(out)))
     return out.value
 
 

@@ -74,6 +74,10 @@ def test_face_flop_count():
     import paper_1302_2132_amd as P
     f2, f3 = P.gks_face_flops(2), P.gks_face_flops(3)
     assert 500 < f2 < f3 < 5000
+    # rho k / rho omega fluxes: face eddy viscosity 0.5 (nl + nr) (2 operations), then per
+    # field frho * k_up, sigma * nut, mu + ., dt * ., (kr - kl), two products and the
+    # difference (8 each)
+    assert P.gks_kw_face_flops() == 18.0
 
 
 def test_binding_loads_torch_runtime_first():
