@@ -48,6 +48,7 @@ class Case:
     precision: str = "fp64"       # "fp64" | "fp32_flux"
     max_steps: int = 0            # > 0: a solver stops after this many steps
     kw_transport: bool = False    # transport k and omega with the flow (else frozen inputs)
+    eps_mode: str = "dt"          # rarefaction in the time weights: "dt" (tau/dt) or "tauhat" (tau/tau_hat)
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property

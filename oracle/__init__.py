@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libgks_oracle.so")
 
 BC_CODE = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 ERRORS = {0: "ok", 1: "bad argument", 2: "nonphysical state"}
-INFO_LEN = 50
+INFO_LEN = 51
+EPS_MODE = {"dt": 0, "tauhat": 1}
 NU = 12
 
 
@@ -42,6 +43,7 @@ class _Case(C.Structure):
         ("bc_data", (C.c_void_p * 2) * 3),
         ("gamma", C.c_double), ("prandtl", C.c_double), ("mu", C.c_double),
         ("c_a", C.c_double), ("c_mu", C.c_double), ("cfl", C.c_double), ("t_end", C.c_double),
+        ("eps_mode", C.c_int),
     ]
 
 
@@ -83,6 +85,9 @@ def _bind(L):
     _lib.og_moment_solve.argtypes = [C.c_int, C.c_double, dp, dp, dp]
     _lib.og_tau_value.argtypes = [C.c_double] * 11
     _lib.og_tau_value.restype = C.c_double
+    if hasattr(_lib, "og_kogan_e"):
+        _lib.og_kogan_e.argtypes = [C.c_double, C.c_double, C.c_double, dp]
+        _lib.og_eps_field.argtypes = [C.c_void_p, dp, dp, dp, dp]
     if hasattr(_lib, "og_run_kw"):
         _lib.og_run_kw.argtypes = [C.c_void_p, dp, dp, dp, C.c_int, C.c_int, dp, dp, dp, C.POINTER(C.c_long)]
         _lib.og_kw_sources.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
@@ -120,6 +125,7 @@ class _Bound:
                     s.bc_data[d][side] = bd.ctypes.data
         s.gamma, s.prandtl, s.mu = case.gamma, case.prandtl, case.mu
         s.c_a, s.c_mu, s.cfl, s.t_end = case.c_a, case.c_mu, case.cfl, case.t_end
+        s.eps_mode = EPS_MODE[getattr(case, "eps_mode", "dt")]
         self.s = s
 
     @property
@@ -227,14 +233,14 @@ def step_cells(case, W, dt, cells, nthreads=0):
 
 
 def face_flux(dim, Wl, Wr, sl, sr, Wi, Wi1, dxl, dxr, kf, wf, Sf, dt,
-              gamma=1.4, prandtl=0.72, mu=1e-3, c_a=0.0, c_mu=0.09):
+              gamma=1.4, prandtl=0.72, mu=1e-3, c_a=0.0, c_mu=0.09, eps_mode="dt"):
     """One interface in the face-local frame (normal velocity first).
 
     Returns dict(F, G, q, info) with info holding W0, a_l, a_r, A_l, A_r, abar_l, abar_r,
-    Abar (5 slots each), tau, gam0..5, c1, c4, c5."""
+    Abar (5 slots each), tau, gam0..5, c1, c4, c5 and eps_hat (= tau/tau_hat)."""
     nv = dim + 2
     arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (Wl, Wr, sl, sr, Wi, Wi1)]
-    params = np.array([gamma, prandtl, mu, c_a, c_mu], dtype=np.float64)
+    params = np.array([gamma, prandtl, mu, c_a, c_mu, EPS_MODE[eps_mode]], dtype=np.float64)
     F, G, q, info = np.zeros(nv), np.zeros(nv), np.zeros(1), np.zeros(INFO_LEN)
     st = lib().og_face_flux(dim, _dp(params), *[_dp(a) for a in arrs], float(dxl), float(dxr),
                             float(kf), float(wf), float(Sf), float(dt), _dp(F), _dp(G), _dp(q), _dp(info))
@@ -242,7 +248,7 @@ def face_flux(dim, Wl, Wr, sl, sr, Wi, Wi1, dxl, dxr, kf, wf, Sf, dt,
         raise OracleError(st)
     names = ["W0", "a_l", "a_r", "A_l", "A_r", "abar_l", "abar_r", "Abar"]
     d = {nm: info[5 * i:5 * i + nv].copy() for i, nm in enumerate(names)}
-    d.update(tau=info[40], gam=info[41:47].copy(), c=info[47:50].copy())
+    d.update(tau=info[40], gam=info[41:47].copy(), c=info[47:50].copy(), eps_hat=info[50])
     return {"F": F, "G": G, "q": float(q[0]), "info": d}
 
 
@@ -256,6 +262,24 @@ def kogan(tau, dt):
     out = np.zeros(9)
     lib().og_kogan(float(tau), float(dt), _dp(out))
     return out
+
+
+def kogan_e(tau, tau_e, dt):
+    """Time weights with decay time tau_e in the exponentials (the tau_hat mode)."""
+    out = np.zeros(9)
+    lib().og_kogan_e(float(tau), float(tau_e), float(dt), _dp(out))
+    return out
+
+
+def eps_field(case, W=None, k=None, omega=None):
+    """eps_hat = tau/tau_hat of every face at the state's CFL step, largest per cell."""
+    b = _Bound(case)
+    out = np.zeros(case.ncells)
+    st = lib().og_eps_field(b.ptr, _dp(_flat(case.W if W is None else W)), _dp(_flat(case.k if k is None else k)),
+                            _dp(_flat(case.omega if omega is None else omega)), _dp(out))
+    if st:
+        raise OracleError(st)
+    return out.reshape(case.k.shape)
 
 
 def moment_solve(dim, gamma, rho, U, lam, r):

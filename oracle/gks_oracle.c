@@ -76,6 +76,7 @@ typedef struct {
     double b;          /* total degrees of freedom 2/(gamma-1) */
     double K;          /* internal degrees of freedom b - dim */
     double gamma, prandtl, mu, c_a, c_mu;
+    int eps_mode;      /* 0: rarefaction eps = tau/dt; 1: eps = tau/tau_hat (see og_face) */
 } og_gas;
 
 typedef struct {       /* face-local frame: U[0] is the face-normal velocity */
@@ -316,6 +317,64 @@ static void og_kogan_weights(double tau, double dt, og_tw* k)
     k->c5 = -s / g0;
 }
 
+/* Time weights with the rarefaction measured against a resolved time scale tau_hat
+ * (Eqs. tautautilde, rarefactionkepsilon, epsilonkomega).  Eq. resultingf, regrouped as in
+ * Eq. resultingf2 but with the slope terms written out exactly, reads
+ *   f = f_c (1 + Abar t) + e^{-t/tau} (f_u - f_c) + t e^{-t/tau} u (abar g0 - a g_{l,r}),
+ *   f_c = g0 (1 - tau (abar u + Abar)),  f_u = g_{l,r} (1 - tau (a u + A)),
+ * and its time average depends on eps = tau/dt only through the averages of e^{-t/tau} and
+ * t e^{-t/tau}.  The tau_hat mode evaluates those with eps = tau/tau_hat, i.e. with the
+ * decay time tau_e = dt tau/tau_hat in the exponentials, while f_c and f_u keep the
+ * physical tau.  With I0 = int_0^dt e^{-t/tau_e} dt and I1 = int_0^dt t e^{-t/tau_e} dt:
+ *   gam0 = dt - I0,  gam1 = -tau gam0 + I1,  gam2 = dt^2/2 - tau gam0,
+ *   gam3 = I0,       gam4 = -tau I0 - I1,    gam5 = -tau I0,
+ * and the integrated compatibility condition keeps its form (gam0 + gam3 = dt), its
+ * coefficients being c_j = gam_j/(tau gam0) (1/2 dt^2 - gam2 = tau gam0).  tau_e = tau
+ * reproduces og_kogan_weights; tau_e = 0 is the hydrodynamic limit f = f_c (1 + Abar t)
+ * (Eq. hydroturbolimit). */
+static void og_time_weights(double tau, double tau_e, double dt, og_tw* k)
+{
+    if (tau <= 0.0) {
+        og_kogan_weights(tau, dt, k);
+        return;
+    }
+    double I0, I1, gam0;
+    if (tau_e <= 0.0) {
+        I0 = 0.0; I1 = 0.0; gam0 = dt;
+    } else {
+        const double x = dt / tau_e;
+        double s, g0, h;   /* s = 1 - e^{-x}, g0 = x - s, h = s - x e^{-x} */
+        if (x < 0.5) {
+            double term = 1.0;
+            s = g0 = h = 0.0;
+            for (int n = 1; n <= 40; ++n) {
+                term *= x / n;
+                double sg = (n % 2) ? 1.0 : -1.0;   /* (-1)^{n+1} */
+                s += sg * term;
+                if (n >= 2) { g0 -= sg * term; h -= sg * (n - 1) * term; }
+                if (term < 1e-300) break;
+            }
+        } else {
+            const double E = exp(-x);
+            s = 1.0 - E;
+            g0 = x - s;
+            h = s - x * E;
+        }
+        I0 = tau_e * s;
+        I1 = tau_e * tau_e * h;
+        gam0 = tau_e * g0;
+    }
+    k->g[0] = gam0;
+    k->g[1] = -tau * gam0 + I1;
+    k->g[2] = 0.5 * dt * dt - tau * gam0;
+    k->g[3] = I0;
+    k->g[4] = -tau * I0 - I1;
+    k->g[5] = -tau * I0;
+    k->c1 = k->g[1] / (tau * gam0);
+    k->c4 = k->g[4] / (tau * gam0);
+    k->c5 = k->g[5] / (tau * gam0);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Relaxation time                                                          */
 /* ------------------------------------------------------------------------ */
@@ -342,8 +401,8 @@ typedef struct {
 } og_term;
 
 /* info layout (doubles): W0[5] a_l[5] a_r[5] A_l[5] A_r[5] abar_l[5] abar_r[5] Abar[5]
- *                        tau gam[6] c1 c4 c5   -> 50 values */
-#define OG_INFO_LEN 50
+ *                        tau gam[6] c1 c4 c5 eps_hat   -> 51 values */
+#define OG_INFO_LEN 51
 
 static int og_face(const og_gas* gas, const double* Wl, const double* Wr,
                    const double* sl, const double* sr, const double* Wi, const double* Wi1,
@@ -399,8 +458,21 @@ static int og_face(const og_gas* gas, const double* Wl, const double* Wr,
     const double p0 = g0.rho / (2.0 * g0.lam);
     const double pl = gl.rho / (2.0 * gl.lam), pr = gr.rho / (2.0 * gr.lam);
     const double tau = og_tau(gas, g0.rho, p0, pl, pr, kf, wf, Sf, dt);
+    /* degree of rarefaction against the resolved time scale tau_hat = rho/|D rho| (Eqs.
+       tautilde, epsilonkomega), D rho the material derivative at the interface along the
+       normal: with the mean of the two one-sided gradients through W0 (those of the
+       equilibrium slopes), D rho = d_t rho + U0 d_x rho = U0 d_x rho - d_x (rho U) by mass
+       conservation.  eps_hat = tau/tau_hat. */
+    double drho = 0.0;
+    {
+        const double grho = 0.5 * ((W0[0] - Wi[0]) / dxl + (Wi1[0] - W0[0]) / dxr);
+        const double gmom = 0.5 * ((W0[1] - Wi[1]) / dxl + (Wi1[1] - W0[1]) / dxr);
+        drho = g0.U[0] * grho - gmom;
+    }
+    const double eps_hat = tau * fabs(drho) / g0.rho;
     og_tw kw;
-    og_kogan_weights(tau, dt, &kw);
+    if (gas->eps_mode) og_time_weights(tau, dt * eps_hat, dt, &kw);
+    else og_kogan_weights(tau, dt, &kw);
 
     /* Abar from the compatibility condition integrated over [0, dt]:
        int_0^dt int (g - f) psi = 0 ; the W0 terms cancel because gam0 + gam3 = dt, leaving
@@ -487,6 +559,7 @@ static int og_face(const og_gas* gas, const double* Wl, const double* Wr,
         info[40] = tau;
         for (int i = 0; i < 6; ++i) info[41 + i] = kw.g[i];
         info[47] = kw.c1; info[48] = kw.c4; info[49] = kw.c5;
+        info[50] = eps_hat;
     }
     return OG_OK;
 }
@@ -501,6 +574,7 @@ typedef struct {
     int bc[3][2];
     const double* bc_data[3][2];
     double gamma, prandtl, mu, c_a, c_mu, cfl, t_end;
+    int eps_mode;      /* 0: eps = tau/dt; 1: eps = tau/tau_hat */
 } og_case;
 
 typedef struct {
@@ -531,6 +605,8 @@ static int og_grid_init(og_grid* gr, const og_case* c)
     if (gr->gas.K < 0.0) return OG_ERR_ARG;
     gr->gas.gamma = c->gamma; gr->gas.prandtl = c->prandtl; gr->gas.mu = c->mu;
     gr->gas.c_a = c->c_a; gr->gas.c_mu = c->c_mu;
+    if (c->eps_mode != 0 && c->eps_mode != 1) return OG_ERR_ARG;
+    gr->gas.eps_mode = c->eps_mode;
     gr->nv = c->dim + 2;
     gr->next = 1;
     for (int d = 0; d < 3; ++d) {
@@ -743,7 +819,8 @@ static int og_max_rate(const og_grid* gr, const double* W, const double* kk, con
 /* Flux through one face.  axis d; (fi, fj, fk) are face coordinates (the face lies on the low
  * side of cell (fi, fj, fk) along d).  Fout in global component order. */
 static int og_face_at(const og_grid* gr, const double* We, const double* kk, const double* om,
-                      const double* S, int d, long fi, long fj, long fk, double dt, double* Fout)
+                      const double* S, int d, long fi, long fj, long fk, double dt, double* Fout,
+                      double* eps_out)
 {
     const int dim = gr->c->dim, nv = gr->nv;
     long base[3] = {fi, fj, fk};
@@ -784,10 +861,11 @@ static int og_face_at(const og_grid* gr, const double* We, const double* kk, con
     double kf = 0.5 * (kk[il] + kk[ir]);
     double wf = 0.5 * (om[il] + om[ir]);
     double Sf = 0.5 * (S[il] + S[ir]);
-    double F[5];
+    double F[5], info[OG_INFO_LEN];
     int st = og_face(&gr->gas, lWL, lWR, lsL, lsR, lWi, lWi1, xface - xcs[1], xcs[2] - xface,
-                     kf, wf, Sf, dt, F, NULL, NULL, NULL);
+                     kf, wf, Sf, dt, F, NULL, NULL, eps_out ? info : NULL);
     if (st) return st;
+    if (eps_out) *eps_out = info[50];
     for (int m = 0; m < nv; ++m) {
         int dst = (m >= 1 && m <= dim) ? 1 + perm[m - 1] : m;
         Fout[dst] = F[m];
@@ -838,7 +916,7 @@ static int og_step(const og_grid* gr, const double* W, const double* kk, const d
         for (long f = 0; f < nf; ++f) {
             long fi = f % fn[d][0], fj = (f / fn[d][0]) % fn[d][1], fk = f / (fn[d][0] * fn[d][1]);
             double Fl[5];
-            if (og_face_at(gr, We, kk, om, S, d, fi, fj, fk, dt, Fl)) { bad = 1; continue; }
+            if (og_face_at(gr, We, kk, om, S, d, fi, fj, fk, dt, Fl, NULL)) { bad = 1; continue; }
             for (int m = 0; m < nv; ++m) F[d][m * nf + f] = Fl[m];
         }
     }
@@ -959,7 +1037,7 @@ static int og_step_kw(const og_grid* gr, const double* W, const double* kk, cons
         for (long f = 0; f < nf; ++f) {
             long fi = f % fn[d][0], fj = (f / fn[d][0]) % fn[d][1], fk = f / (fn[d][0] * fn[d][1]);
             double Fl[5];
-            if (og_face_at(gr, We, kk, om, S, d, fi, fj, fk, dt, Fl)) { bad = 1; continue; }
+            if (og_face_at(gr, We, kk, om, S, d, fi, fj, fk, dt, Fl, NULL)) { bad = 1; continue; }
             for (int m = 0; m < nv; ++m) F[d][m * nf + f] = Fl[m];
             og_kw_face(gr, W, kk, om, d, fi, fj, fk, Fl[0], dt, &Fk[d][f], &Fw[d][f]);
         }
@@ -1173,8 +1251,8 @@ int og_step_cells(const og_case* c, const double* W, const double* kk, const dou
             double Flo[5], Fhi[5];
             long hi[3] = {idx[0], idx[1], idx[2]};
             hi[d] += 1;
-            if (og_face_at(&gr, We, kk, om, S, d, idx[0], idx[1], idx[2], dt, Flo) ||
-                og_face_at(&gr, We, kk, om, S, d, hi[0], hi[1], hi[2], dt, Fhi)) { bad = 1; continue; }
+            if (og_face_at(&gr, We, kk, om, S, d, idx[0], idx[1], idx[2], dt, Flo, NULL) ||
+                og_face_at(&gr, We, kk, om, S, d, hi[0], hi[1], hi[2], dt, Fhi, NULL)) { bad = 1; continue; }
             for (int m = 0; m < nv; ++m) acc[m] -= (Fhi[m] - Flo[m]) / gr.dx[d][idx[d] + 2];
         }
         for (int m = 0; m < nv; ++m) out[q * nv + m] = acc[m];
@@ -1184,7 +1262,7 @@ int og_step_cells(const og_case* c, const double* W, const double* kk, const dou
     return bad ? OG_ERR_NONPHYSICAL : OG_OK;
 }
 
-/* Single interface in the face-local frame.  params: gamma, prandtl, mu, c_a, c_mu.
+/* Single interface in the face-local frame.  params: gamma, prandtl, mu, c_a, c_mu, eps_mode.
  * F, G: nv values; q: heat flux; info: OG_INFO_LEN values (see og_face). */
 int og_face_flux(int dim, const double* params, const double* Wl, const double* Wr,
                  const double* sl, const double* sr, const double* Wi, const double* Wi1,
@@ -1194,7 +1272,7 @@ int og_face_flux(int dim, const double* params, const double* Wl, const double* 
     og_gas gas;
     if (dim != 2 && dim != 3) return OG_ERR_ARG;
     gas.dim = dim; gas.gamma = params[0]; gas.prandtl = params[1]; gas.mu = params[2];
-    gas.c_a = params[3]; gas.c_mu = params[4];
+    gas.c_a = params[3]; gas.c_mu = params[4]; gas.eps_mode = params[5] != 0.0;
     gas.b = 2.0 / (gas.gamma - 1.0); gas.K = gas.b - dim;
     return og_face(&gas, Wl, Wr, sl, sr, Wi, Wi1, dxl, dxr, kf, wf, Sf, dt, F, G, q, info);
 }
@@ -1219,6 +1297,52 @@ int og_kogan(double tau, double dt, double* out)
     for (int i = 0; i < 6; ++i) out[i] = k.g[i];
     out[6] = k.c1; out[7] = k.c4; out[8] = k.c5;
     return OG_OK;
+}
+
+/* gam0..gam5, c1, c4, c5 with the exponential decay time tau_e (og_time_weights). */
+int og_kogan_e(double tau, double tau_e, double dt, double* out)
+{
+    og_tw k;
+    og_time_weights(tau, tau_e, dt, &k);
+    for (int i = 0; i < 6; ++i) out[i] = k.g[i];
+    out[6] = k.c1; out[7] = k.c4; out[8] = k.c5;
+    return OG_OK;
+}
+
+/* Degree of rarefaction eps_hat = tau/tau_hat of every face at state W, with the CFL step
+ * of W, reduced to each cell as the largest over its 2 dim faces. */
+int og_eps_field(const og_case* c, const double* W, const double* kk, const double* om, double* out)
+{
+    og_grid gr;
+    int st = og_grid_init(&gr, c);
+    if (st) { og_grid_free(&gr); return st; }
+    const int dim = c->dim;
+    const long N = gr.n[0] * gr.n[1] * gr.n[2];
+    double rate;
+    if ((st = og_max_rate(&gr, W, kk, om, &rate))) { og_grid_free(&gr); return st; }
+    const double dt = c->cfl / rate;
+    double* We = (double*)malloc(sizeof(double) * gr.nv * gr.next);
+    double* S = (double*)malloc(sizeof(double) * N);
+    og_fill_W(&gr, W, We);
+    og_strain(&gr, We, S);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long s = 0; s < N; ++s) {
+        long idx[3] = {s % gr.n[0], (s / gr.n[0]) % gr.n[1], s / (gr.n[0] * gr.n[1])};
+        double mx = 0.0, F[5];
+        for (int d = 0; d < dim; ++d)
+            for (int side = 0; side < 2; ++side) {
+                long f[3] = {idx[0], idx[1], idx[2]};
+                f[d] += side;
+                double e;
+                if (og_face_at(&gr, We, kk, om, S, d, f[0], f[1], f[2], dt, F, &e)) { bad = 1; continue; }
+                if (e > mx) mx = e;
+            }
+        out[s] = mx;
+    }
+    free(We); free(S);
+    og_grid_free(&gr);
+    return bad ? OG_ERR_NONPHYSICAL : OG_OK;
 }
 
 /* Solve <psi_m psi_n>_g x = r for a Maxwellian given by (rho, U[3], lam); face-local frame. */

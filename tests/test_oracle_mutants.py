@@ -13,6 +13,7 @@ import pytest
 import oracle
 import test_oracle_kw as KW
 import test_oracle_pins as P
+import test_oracle_tauhat as TH
 
 SRC = oracle.SRC
 
@@ -61,6 +62,14 @@ MUTANTS = {
                                               "const double mut = rho * kc / wc;"),
     "omega production without limiter": ("*Qw = KW_ALPHA * rho * (shear / root", "*Qw = KW_ALPHA * rho * (shear"),
     "cross diffusion regardless of sign": ("if (cross > 0.0) *Qw +=", "if (cross != 0.0) *Qw +="),
+    "material derivative sign": ("drho = g0.U[0] * grho - gmom;", "drho = g0.U[0] * grho + gmom;"),
+    "tau_hat from the cell density": ("const double eps_hat = tau * fabs(drho) / g0.rho;",
+                                      "const double eps_hat = tau * fabs(drho) / Wi[0];"),
+    "decay time inverted": ("og_time_weights(tau, dt * eps_hat, dt, &kw)", "og_time_weights(tau, dt / eps_hat, dt, &kw)"),
+    "slope term of gam1": ("k->g[1] = -tau * gam0 + I1;", "k->g[1] = -tau * gam0 - I1;"),
+    "slope term of gam4": ("k->g[4] = -tau * I0 - I1;", "k->g[4] = -tau * I0 + I1;"),
+    "series of t e^{-t/tau_e}": ("h -= sg * (n - 1) * term;", "h -= sg * n * term;"),
+    "hydrodynamic limit keeps the upwind part": ("I0 = 0.0; I1 = 0.0; gam0 = dt;", "I0 = dt; I1 = 0.0; gam0 = 0.0;"),
 }
 
 
@@ -104,6 +113,11 @@ PINS = [
     lambda: KW.test_diffusion_rate_of_a_sine_mode("k"),
     lambda: KW.test_diffusion_rate_of_a_sine_mode("omega"),
     lambda: KW.test_mirror_symmetry(),
+    lambda: [TH.test_time_weights_by_quadrature(x, r) for x in (0.3, 2.0) for r in (0.1, 7.0)],
+    lambda: TH.test_hydrodynamic_limit(),
+    lambda: TH.test_eps_hat_of_a_velocity_gradient(2),
+    lambda: TH.test_eps_hat_of_density_and_velocity_gradients(),
+    lambda: TH.test_continuous_data_navier_stokes_flux_in_tauhat_mode(2),
 ]
 
 
