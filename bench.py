@@ -7,7 +7,11 @@ frozen seeded k/omega.  A step is one explicit time step of the whole path (CFL 
 step, strain rate, every face flux, conservative update, residual).  The FP64 form is
 the headline `value`; the FP32-flux form (flux arithmetic in FP32, everything else FP64)
 is reported beside it with its error against the FP64 run, and so is the same workload
-with k and omega transported by the k-omega equations instead of frozen.
+with k and omega transported by the k-omega equations instead of frozen.  The degree of
+rarefaction eps_hat = tau/tau_hat (the turbulent Knudsen number) of the SBLI run is
+reported as a diagnostic; the mode that puts eps_hat into the time weights is measured on a
+1024^2 mixing layer (it does not stay physical on the SBLI mesh with an explicit global
+step, where it leaves the shock generator's jump with almost no kinetic dissipation).
 
 Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
 """
@@ -25,7 +29,7 @@ FP32_PEAK_TFLOPS = 78.6    # scalar FP32 VALU at the same rate (packed FP32 is n
 HBM_PEAK_GBS = 8000.0
 
 
-def _leg(case, steps, warmup):
+def _leg(case, steps, warmup, eps_field=False):
     """Warm-up, then `steps` plain steps on the clock (the throughput), then the same
     number again with every launch carrying its own start/stop event pair (the per-kernel
     durations).  The state read back has advanced warmup + 2 * steps steps."""
@@ -45,8 +49,9 @@ def _leg(case, steps, warmup):
     gks_set_timing(s.h, False)
     r = s.residual()
     W = s.fields("cons")
+    eps = s.fields("eps") if eps_field else None
     s.close()
-    return {"seconds": t1 - t0, "kernels": kt, "res": r, "W": W, "steps_done": warmup + 2 * steps}
+    return {"seconds": t1 - t0, "kernels": kt, "res": r, "W": W, "steps_done": warmup + 2 * steps, "eps": eps}
 
 
 KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_lib.hip", "erfc_poly.hpp")
@@ -83,7 +88,8 @@ def _roofline(case, leg, steps, flops_face, peak):
     achieved = flops_face * faces / face_s / 1e12
     r = "float" if case.precision == "fp32_flux" else "double"
     kw = "true" if getattr(case, "kw_transport", False) else "false"
-    kernel = f"k_tile2<{r},{kw}>" if case.dim == 2 else f"k_face<{r},3,64,{kw}>"
+    th = "true" if getattr(case, "eps_mode", "dt") == "tauhat" else "false"
+    kernel = f"k_tile2<{r},{kw},{th}>" if case.dim == 2 else f"k_face<{r},3,64,{kw},{th}>"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": _profiled_traffic(kernel),
             "kernel": kernel, "flops_per_face": flops_face, "faces_per_launch": faces,
@@ -238,6 +244,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D isotropic-box leg")
     ap.add_argument("--no-kw", action="store_true", help="skip the k-omega transport leg")
+    ap.add_argument("--no-tauhat", action="store_true", help="skip the tau_hat rarefaction leg")
     ap.add_argument("--serve-full", action="store_true", help="served leg on the full 256-request trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), to calibrate "
@@ -266,7 +273,7 @@ def main():
 
     case = C.sbli(1024, 512)
     K, Wm = args.steps, args.warmup
-    leg64 = _leg(case, K, Wm)
+    leg64 = _leg(case, K, Wm, eps_field=True)
     value = case.ncells * K / leg64["seconds"]
     flops2d = gks_face_flops(2, "fp64")
     out = {
@@ -283,6 +290,9 @@ def main():
                    "cells": case.ncells, "precision": "fp64"},
         "roofline": _roofline(case, leg64, K, flops2d, FP64_PEAK_TFLOPS),
         "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg64["kernels"].items() if k != "steps"},
+        "eps_hat_diagnostic": {"after_steps": leg64["steps_done"], "max": float(leg64["eps"].max()),
+                               "p99": float(np.percentile(leg64["eps"], 99)),
+                               "p50": float(np.percentile(leg64["eps"], 50))},
     }
     if not args.no_fp32:
         c32 = C.sbli(1024, 512, precision="fp32_flux")
@@ -309,6 +319,26 @@ def main():
             "vs_frozen": vkw / value,
             "roofline": _roofline(ckw, legkw, K, flops2d + gks_kw_face_flops(), FP64_PEAK_TFLOPS),
             "kernel_ms_per_step": {k: round(v / K, 4) for k, v in legkw["kernels"].items() if k != "steps"},
+        }
+    if not args.no_tauhat:
+        legs = {}
+        for mode in ("dt", "tauhat"):
+            cm = C.mixing_layer(1024, seed=3)
+            cm.eps_mode = mode
+            legs[mode] = (cm, _leg(cm, K, Wm, eps_field=True))
+        cth, legth = legs["tauhat"]
+        vth = cth.ncells * K / legth["seconds"]
+        vdt = cth.ncells * K / legs["dt"][1]["seconds"]
+        e = legth["eps"]
+        out["tauhat"] = {
+            "workload": "mixing_layer_1024x1024 (periodic double shear layer, Ma 0.3), FP64, rarefaction "
+                        "eps = tau/tau_hat (tau_hat = rho/|D rho|) against eps = tau/dt on the same workload",
+            "value": vth, "unit": "cell-updates/s", "ms_per_step": legth["seconds"] * 1e3 / K,
+            "dt_mode_value": vdt, "vs_dt_mode": vth / vdt,
+            "roofline": _roofline(cth, legth, K, flops2d, FP64_PEAK_TFLOPS),
+            "kernel_ms_per_step": {k: round(v / K, 4) for k, v in legth["kernels"].items() if k != "steps"},
+            "eps_hat_after_steps": legth["steps_done"], "eps_hat_max": float(e.max()),
+            "eps_hat_p99": float(np.percentile(e, 99)),
         }
     if not args.no_3d:
         out["isotropic_3d"] = _iso_leg()

@@ -69,11 +69,24 @@ enum { GKS_BC_PERIODIC = 0, GKS_BC_WALL = 1, GKS_BC_DIRICHLET = 2, GKS_BC_PROFIL
  * update and the time-step/residual reductions stay FP64. */
 enum { GKS_FP64 = 0, GKS_FP32_FLUX = 1 };
 
+/* Degree of rarefaction in the time weights of the flux.
+ *  DT      eps = tau/dt (Eqs. resultingf4, epsilonkepsilon): the exact time integral of the
+ *          Kogan solution over the step;
+ *  TAUHAT  eps = tau/tau_hat (Eqs. tautautilde, tautilde, epsilonkomega): tau_hat =
+ *          rho/|D rho|, D rho = U0 d_x rho - d_x (rho U) the interface material derivative
+ *          along the normal (mean of the one-sided gradients through the interface state).
+ *          The exponential time factors decay with tau_e = dt tau/tau_hat; the
+ *          Chapman-Enskog terms keep the physical tau.  eps -> 0 gives the Navier-Stokes
+ *          limit f_c (1 + Abar dt/2) (Eq. hydroturbolimit). */
+enum { GKS_EPS_DT = 0, GKS_EPS_TAUHAT = 1 };
+
 /* Fields for gks_fields. CONS: conservative state (nvar x ncells). PRIM: rho, U, V, [W],
  * p (nvar x ncells). STRAIN: strain-rate magnitude sqrt(2 S_ab S_ab) (ncells). TURB: k
  * then omega (2 x ncells): those of the current state when transported (computed on the
- * device from rho k, rho omega), the frozen inputs otherwise. */
-enum { GKS_FIELD_CONS = 0, GKS_FIELD_PRIM = 1, GKS_FIELD_STRAIN = 2, GKS_FIELD_TURB = 3 };
+ * device from rho k, rho omega), the frozen inputs otherwise. EPS: eps_hat = tau/tau_hat of
+ * each face at the current state and step, the largest over the cell's faces (ncells; in
+ * either eps_mode, as the "turbulent Knudsen number" diagnostic). */
+enum { GKS_FIELD_CONS = 0, GKS_FIELD_PRIM = 1, GKS_FIELD_STRAIN = 2, GKS_FIELD_TURB = 3, GKS_FIELD_EPS = 4 };
 
 typedef struct {
     int32_t dim;                  /* 2 or 3 */
@@ -91,6 +104,7 @@ typedef struct {
     int32_t precision;            /* GKS_FP64 or GKS_FP32_FLUX */
     int64_t max_steps;            /* > 0: the solve stops (on the device) after this many steps */
     int32_t turb_transport;       /* 1: transport k and omega with the flow; 0: frozen inputs */
+    int32_t eps_mode;             /* GKS_EPS_DT or GKS_EPS_TAUHAT */
 } gks_config;
 
 typedef struct gks_ctx* gks_handle;
@@ -172,8 +186,9 @@ gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
  * captured as a graph.  Creation (and gks_batch_set_members) waits for the members' own
  * streams; afterwards every per-handle call on a member first waits for the batch stream.
  * The table lives in dev_workspace.  Handles stay owned by the caller and must outlive
- * the batch.  Members are frozen-field solves: a handle with turb_transport is refused
- * (GKS_ERR_ARG), here and in gks_batch_set_members. */
+ * the batch.  Members are frozen-field solves in the DT mode: a handle with
+ * turb_transport or GKS_EPS_TAUHAT is refused (GKS_ERR_ARG), here and in
+ * gks_batch_set_members. */
 gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity,
                             void* dev_workspace, size_t bytes, void* hip_stream, gks_batch* out);
 

@@ -283,6 +283,36 @@ GKS_HD inline Kw<R> kogan(R tau, R dt)
     return k;
 }
 
+// Weights when the rarefaction is measured against a resolved time scale tau_hat
+// (Eqs. tautautilde, rarefactionkepsilon, epsilonkomega): the exponentials decay with
+// tau_e = dt tau/tau_hat while the Chapman-Enskog parts keep the physical tau.  With
+// gam'_j, c'_j the Kogan weights at tau_e (kogan(tau_e, dt)) and d = tau_e - tau (the
+// Chapman-Enskog factor tau tau_e = tau_e^2 - d tau_e):
+//   gam0 = gam'0, gam3 = gam'3, gam1 = gam'1 + d gam0, gam2 = gam'2 + d gam0,
+//   gam4 = gam'4 + d gam3, gam5 = -tau gam3,
+//   c1 = (tau_e c'1 + d)/tau, c4 = (tau_e c'4 - d c'5)/tau, c5 = c'5   (c_j = gam_j/(tau gam0)).
+// tau_e = tau gives kogan(tau, dt); tau_e = 0 is the hydrodynamic limit (kogan's tau = 0
+// branch corrected: no upwind part, gam1 = -tau dt, gam2 = dt^2/2 - tau dt, c1 = -1).
+template <typename R>
+GKS_HD inline Kw<R> kogan_e(R tau, R tau_e, R dt)
+{
+    Kw<R> k = kogan(tau_e, dt);
+    if (tau > R(0)) {                                 // tau = 0 implies tau_e = 0: the Euler limit
+        const R d = tau_e - tau, itau = g_rcp(tau);
+        k.g[1] = k.g[1] + d * k.g[0];
+        k.g[2] = k.g[2] + d * k.g[0];
+        k.g[4] = k.g[4] + d * k.g[3];
+        k.g[5] = -tau * k.g[3];
+        k.c1 = (tau_e * k.c1 + d) * itau;
+        k.c4 = (tau_e * k.c4 - d * k.c5) * itau;
+    }
+    return k;
+}
+
+// Flux modes (bits): FLUX_TAUHAT evaluates the time weights with eps = tau/tau_hat;
+// FLUX_EPS_OUT also stores eps_hat = tau/tau_hat in F[D + 2] (the caller provides room).
+enum { FLUX_TAUHAT = 1, FLUX_EPS_OUT = 2 };
+
 // Inputs of one face in the wide type H (FP64 on the device): reconstructed states,
 // minmod slopes, cell averages of the two neighbours, inverse centre-to-face distances,
 // face means of k, omega and strain rate, and the step.
@@ -348,6 +378,22 @@ GKS_HD inline bool prim_wide(const H* W, H two_over_b, H& rho, H& irho, H* U, H&
     return (rho > H(0)) && (p > H(0)) && (p < H(1e300)) && (rho < H(1e300));
 }
 
+// Time weights of a face in a flux mode other than 0.  tau_hat = rho0/|D rho|, with
+// D rho = U0 d_x rho - d_x (rho U) along the normal (mass conservation gives
+// d_t rho = -d_x (rho U)) from the mean of the one-sided gradients through the interface
+// state W0 (rho w00, normal momentum w01); eps_hat = tau/tau_hat.
+template <typename R, int D, typename H, int MODE>
+GKS_HD __attribute__((always_inline)) inline void mode_weights(const FaceIn<D, H>& in, H tau, const R* W0,
+                                                               const H* U0d, H ir0, R dt, R* F, Kw<R>& kw)
+{
+    const H w00 = H(W0[0]), w01 = H(W0[1]);
+    const H grho = H(0.5) * ((w00 - in.Wi[0]) * in.idl + (in.Wi1[0] - w00) * in.idr);
+    const H gmom = H(0.5) * ((w01 - in.Wi[1]) * in.idl + (in.Wi1[1] - w01) * in.idr);
+    const H eps = tau * g_abs(U0d[0] * grho - gmom) * ir0;
+    if (MODE & FLUX_EPS_OUT) F[D + 2] = R(eps);
+    kw = (MODE & FLUX_TAUHAT) ? kogan_e(R(tau), R(in.dt * eps), dt) : kogan(R(tau), dt);
+}
+
 // The flux.  Returns 0, or 1 when a state met is non-physical (then F is meaningless).
 // F receives the time-integrated flux (it already contains dt) in the face-local frame.
 //
@@ -355,7 +401,7 @@ GKS_HD inline bool prim_wide(const H* W, H two_over_b, H& rho, H& irho, H* U, H&
 // the equilibrium-slope terms, then the left side, then the right side are each folded
 // into F and into the right-hand side Rv of the Abar system as soon as their
 // coefficients exist; Abar and the remaining equilibrium terms come last.
-template <typename R, int D, typename H = double>
+template <typename R, int D, typename H = double, int MODE = 0>
 GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
 {
     constexpr int NV = D + 2;
@@ -437,7 +483,9 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         if (gas.c_a > 0.0) tau = tau + H(gas.c_a) * g_abs(pr - pl) * g_rcp(pr + pl) * in.dt;
     }
     const R dt = R(in.dt);
-    const Kw<R> kw = kogan(R(tau), dt);
+    Kw<R> kw;
+    if (MODE) mode_weights<R, D, H, MODE>(in, tau, W0, U0d, ir0, dt, F, kw);
+    else kw = kogan(R(tau), dt);
 
     // Rv accumulates rho0 <psi Abar.psi>_g0 from the time-integrated compatibility condition:
     //   c1 rho0 (<u psi abar_l.psi>_{g0,>0} + <u psi abar_r.psi>_{g0,<0})
@@ -531,7 +579,12 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
     {
         const R pfix = R(gas.pfix);
         R Gv[NV];
-        const R hdt2 = half * dt * dt;
+        R dtq = dt;
+#ifdef __HIP_DEVICE_COMPILE__
+        // in the flux modes the weights' dt/2 would otherwise be kept from there to here
+        if (MODE) asm volatile("" : "+v"(dtq));
+#endif
+        const R hdt2 = half * dtq * dtq;
         for (int m = 0; m < NV; ++m) Gv[m] = dt * W0[m] + hdt2 * Rv[m];
         R uF = R(0), uG = R(0), U2 = R(0);
         for (int d = 0; d < D; ++d) {

@@ -20,7 +20,9 @@
 // Solves that transport k and omega (Inst::kw) use the KW = true instantiations: the
 // strain pass also derives k, omega and the model's sources of each cell, the face pass
 // adds the fluxes of rho k and rho omega, and the update advances them with point-implicit
-// sinks.  The KW = false code is the frozen-field scheme, untouched by the transport.
+// sinks.  Solves whose degree of rarefaction is measured against the resolved time scale
+// tau_hat use the TH = true flux (face_flux with FLUX_TAUHAT).  The KW = TH = false code is
+// the frozen-field scheme, untouched by either.
 //
 // The table, the solve descriptors and (outside k_finish) the step state are read
 // through the constant address space: nothing writes them while these kernels run, so
@@ -30,6 +32,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "gks_device.hpp"
 #include "gks_flux.hpp"
@@ -282,7 +286,7 @@ __device__ inline void kw_face(cref<Inst> I, double frho, double kl, double kr, 
 // order.  Returns nonzero for a non-physical state.  The axis is a template parameter so
 // that every index and the rotation to the face-local frame are compile-time (no private
 // arrays).
-template <typename R, int D, int DIR, typename P>
+template <typename R, int D, int DIR, int MODE, typename P>
 __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int i, const double (*Wc)[D + 2],
                                                                P kk, P ww, P ss, int il, int ir, double dt, R* Fg)
 {
@@ -322,19 +326,20 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
     in.Sf = 0.5 * (ss[il] + ss[ir]);
     in.dt = dt;
     GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
-    R F[NV];
-    const int bad = face_flux<R, D, double>(in, gas, F);
+    R F[NV + ((MODE & FLUX_EPS_OUT) ? 1 : 0)];
+    const int bad = face_flux<R, D, double, MODE>(in, gas, F);
     Fg[0] = F[0];
     Fg[1 + DIR] = F[1];
     Fg[1 + P1] = F[2];
     if (D == 3) Fg[1 + P2] = F[3];
     Fg[D + 1] = F[D + 1];
+    if (MODE & FLUX_EPS_OUT) Fg[D + 2] = F[(MODE & FLUX_EPS_OUT) ? D + 2 : 0];
     return bad;
 }
 
 // One face normal to axis DIR, stencil read from the state in HBM, flux written to the
 // axis' face-flux array (structure of arrays).
-template <typename R, int D, int DIR, bool KW>
+template <typename R, int D, int DIR, bool KW, bool TH>
 __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int f)
 {
     constexpr int NV = D + 2;
@@ -377,7 +382,8 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
     const double* ww = I.om;
     const double* ss = I.S;
     const double dt = state_of(I).dt;
-    if (face_eval<R, D, DIR>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt, F)) atomicOr(&I.st->err, 1);
+    if (face_eval<R, D, DIR, TH ? FLUX_TAUHAT : 0>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt, F))
+        atomicOr(&I.st->err, 1);
     R* __restrict__ out = (R*)I.F[DIR];
     const long long nf = I.nface[DIR];   // 64-bit: component offsets m * nf may pass 2^31
     out[f] = F[0];
@@ -415,7 +421,7 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
 // Register budget of the face kernel (instantiated for 3D; 2D steps use k_tile2): at least
 // this many waves per SIMD (2 leaves 256 VGPRs per lane for the 3D FP64 flux, 4 leaves 128
 // for the FP32 flux).  TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
-template <typename R, int D, int TILE, bool KW>
+template <typename R, int D, int TILE, bool KW, bool TH>
 __global__ __launch_bounds__(TILE)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_FACE_WAVES_FP64)))
 void k_face(const void* __restrict__ table, int cap, int cls)
@@ -432,18 +438,18 @@ void k_face(const void* __restrict__ table, int cap, int cls)
         int lt = tile - prefix[mj];
         if (lt < I.ntile_face[0]) {
             const int f = lt * TILE + (int)threadIdx.x;
-            if (f < I.nface[0]) face_one<R, D, 0, KW>(I, f);
+            if (f < I.nface[0]) face_one<R, D, 0, KW, TH>(I, f);
             continue;
         }
         lt -= I.ntile_face[0];
         if (D == 2 || lt < I.ntile_face[1]) {
             const int f = lt * TILE + (int)threadIdx.x;
-            if (f < I.nface[1]) face_one<R, D, 1, KW>(I, f);
+            if (f < I.nface[1]) face_one<R, D, 1, KW, TH>(I, f);
             continue;
         }
         lt -= I.ntile_face[1];
         const int f = lt * TILE + (int)threadIdx.x;
-        if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1), KW>(I, f);
+        if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1), KW, TH>(I, f);
     }
 }
 
@@ -596,7 +602,7 @@ static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_TH
 #define GKS_TILE2_WAVES_FP64 3
 #endif
 
-template <typename R, bool KW>
+template <typename R, bool KW, bool TH>
 __global__ __launch_bounds__(T2_THREADS)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_TILE2_WAVES_FP64)))
 void k_tile2(const void* __restrict__ table, int cap, int cls)
@@ -673,7 +679,8 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + 2) * T2_WX + i + o];
                 const int kl = (j + 1) * T2_KX + i;
                 R F[NV];
-                if (face_eval<R, 2, 0>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F))
+                if (face_eval<R, 2, 0, TH ? FLUX_TAUHAT : 0>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1,
+                                                            dt, F))
                     atomicOr(&I.st->err, 1);
                 sFx[0][tid] = F[0];
                 sFx[1][tid] = F[1];
@@ -701,7 +708,8 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + o) * T2_WX + i + 2];
                 const int kl = j * T2_KX + i + 1;
                 R F[NV];
-                if (face_eval<R, 2, 1>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt, F))
+                if (face_eval<R, 2, 1, TH ? FLUX_TAUHAT : 0>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl,
+                                                            kl + T2_KX, dt, F))
                     atomicOr(&I.st->err, 1);
                 sFy[0][tid] = F[0];
                 sFy[1][tid] = F[1];
@@ -994,6 +1002,59 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
     }
 }
 
+// Degree of rarefaction eps_hat = tau/tau_hat of the faces of each cell at the current
+// state and step (the strain rate, k and omega of that state already in place), largest
+// over the cell's 2 D faces, into out[cell].  TH selects the solve's time weights, which do
+// not change eps_hat but keep the evaluation that of the step.  A diagnostic: each face is
+// evaluated by both of its cells.
+template <int D, bool TH>
+__device__ inline double cell_eps(cref<Inst> I, int cell)
+{
+    constexpr int NV = D + 2;
+    const double* __restrict__ W = I.W[state_of(I).parity];
+    const double dt = state_of(I).dt;
+    int c[3];
+    c[0] = cell % I.n[0];
+    c[1] = (cell / I.n[0]) % I.n[1];
+    c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
+    double mx = 0.0;
+    auto face = [&](auto dirc, int side) {
+        constexpr int DIR = decltype(dirc)::value;
+        int fc[3] = {c[0], c[1], c[2]};
+        fc[DIR] += side;                               // the face lies on the low side of cell fc
+        double Wc[4][NV];
+        for (int o = 0; o < 4; ++o) {
+            int cc[3] = {fc[0], fc[1], fc[2]};
+            cc[DIR] += o - 2;
+            load_state<D>(I, W, DIR, cc, Wc[o]);
+        }
+        int cl[3] = {fc[0], fc[1], fc[2]};
+        cl[DIR] -= 1;
+        const int il = image_cell<D>(I, DIR, cl), ir = image_cell<D>(I, DIR, fc);
+        double F[NV + 1];
+        if (face_eval<double, D, DIR, FLUX_EPS_OUT | (TH ? FLUX_TAUHAT : 0)>(I, fc[DIR], Wc, I.k, I.om, I.S, il, ir,
+                                                                               dt, F))
+            atomicOr(&I.st->err, 1);
+        mx = fmax(mx, F[NV]);
+    };
+    using D0 = std::integral_constant<int, 0>;
+    using D1 = std::integral_constant<int, 1>;
+    using D2 = std::integral_constant<int, D == 3 ? 2 : 1>;
+    face(D0{}, 0); face(D0{}, 1);
+    face(D1{}, 0); face(D1{}, 1);
+    if (D == 3) { face(D2{}, 0); face(D2{}, 1); }
+    return mx;
+}
+
+template <bool TH>
+__global__ __launch_bounds__(64) void k_eps(const void* __restrict__ table, int cap, double* __restrict__ out)
+{
+    const TabC tv(table, cap);
+    cref<Inst> I = tv.inst[0];
+    for (int cell = blockIdx.x * blockDim.x + (int)threadIdx.x; cell < I.ncells; cell += gridDim.x * blockDim.x)
+        out[cell] = I.dim == 2 ? cell_eps<2, TH>(I, cell) : cell_eps<3, TH>(I, cell);
+}
+
 // Copy of every member's step state into one array, so that a batch's states come back
 // to the host in one read.
 __global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, int cap, State* __restrict__ out)
@@ -1006,18 +1067,28 @@ __global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, i
     }
 }
 
-template __global__ void k_tile2<double, false>(const void*, int, int);
-template __global__ void k_tile2<float, false>(const void*, int, int);
-template __global__ void k_tile2<double, true>(const void*, int, int);
-template __global__ void k_tile2<float, true>(const void*, int, int);
-template __global__ void k_face<double, 3, 64, false>(const void*, int, int);
-template __global__ void k_face<double, 3, 128, false>(const void*, int, int);
-template __global__ void k_face<double, 3, 256, false>(const void*, int, int);
-template __global__ void k_face<float, 3, 64, false>(const void*, int, int);
-template __global__ void k_face<float, 3, 128, false>(const void*, int, int);
-template __global__ void k_face<float, 3, 256, false>(const void*, int, int);
-template __global__ void k_face<double, 3, 64, true>(const void*, int, int);
-template __global__ void k_face<float, 3, 64, true>(const void*, int, int);
+template __global__ void k_tile2<double, false, false>(const void*, int, int);
+template __global__ void k_tile2<float, false, false>(const void*, int, int);
+template __global__ void k_tile2<double, true, false>(const void*, int, int);
+template __global__ void k_tile2<float, true, false>(const void*, int, int);
+template __global__ void k_tile2<double, false, true>(const void*, int, int);
+template __global__ void k_tile2<float, false, true>(const void*, int, int);
+template __global__ void k_tile2<double, true, true>(const void*, int, int);
+template __global__ void k_tile2<float, true, true>(const void*, int, int);
+template __global__ void k_face<double, 3, 64, false, false>(const void*, int, int);
+template __global__ void k_face<double, 3, 128, false, false>(const void*, int, int);
+template __global__ void k_face<double, 3, 256, false, false>(const void*, int, int);
+template __global__ void k_face<float, 3, 64, false, false>(const void*, int, int);
+template __global__ void k_face<float, 3, 128, false, false>(const void*, int, int);
+template __global__ void k_face<float, 3, 256, false, false>(const void*, int, int);
+template __global__ void k_face<double, 3, 64, true, false>(const void*, int, int);
+template __global__ void k_face<float, 3, 64, true, false>(const void*, int, int);
+template __global__ void k_face<double, 3, 64, false, true>(const void*, int, int);
+template __global__ void k_face<float, 3, 64, false, true>(const void*, int, int);
+template __global__ void k_face<double, 3, 64, true, true>(const void*, int, int);
+template __global__ void k_face<float, 3, 64, true, true>(const void*, int, int);
+template __global__ void k_eps<false>(const void*, int, double*);
+template __global__ void k_eps<true>(const void*, int, double*);
 template __global__ void k_update<false>(const void*, int);
 template __global__ void k_update<true>(const void*, int);
 template __global__ void k_strain<false>(const void*, int, int, int);

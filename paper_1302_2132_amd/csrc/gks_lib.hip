@@ -73,6 +73,7 @@ bool config_ok(const gks_config* c, std::string* why)
     if (c->precision != GKS_FP64 && c->precision != GKS_FP32_FLUX) return fail("unknown precision");
     if (c->max_steps < 0) return fail("max_steps must be >= 0");
     if (c->turb_transport != 0 && c->turb_transport != 1) return fail("turb_transport must be 0 or 1");
+    if (c->eps_mode != GKS_EPS_DT && c->eps_mode != GKS_EPS_TAUHAT) return fail("unknown eps_mode");
     return true;
 }
 
@@ -281,23 +282,26 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
 // Kernel of a face class: the fused 2D tile kernel (fixed workgroup of T2_THREADS) for the
 // 2D classes, the 3D face kernel with `tile` faces per workgroup otherwise.
 typedef void (*face_kernel_t)(const void*, int, int);
-template <int T, bool KW>
+template <int T, bool KW, bool TH>
 static face_kernel_t face_kernel_t_(int cls)
 {
     switch (cls) {
-    case 0: return k_tile2<double, KW>;
-    case 1: return k_tile2<float, KW>;
-    case 2: return k_face<double, 3, T, KW>;
-    default: return k_face<float, 3, T, KW>;
+    case 0: return k_tile2<double, KW, TH>;
+    case 1: return k_tile2<float, KW, TH>;
+    case 2: return k_face<double, 3, T, KW, TH>;
+    default: return k_face<float, 3, T, KW, TH>;
     }
 }
-// Transported solves run alone with the default tile; batches hold frozen-field solves.
-static face_kernel_t face_kernel(int cls, int tile, bool kw = false)
+// Solves that transport k and omega or use the tau_hat rarefaction run alone with the
+// default tile; batches hold the plain form.
+static face_kernel_t face_kernel(int cls, int tile, bool kw = false, bool th = false)
 {
-    if (kw) return face_kernel_t_<FACE_TILE, true>(cls);
-    if (tile == 128) return face_kernel_t_<128, false>(cls);
-    if (tile == 256) return face_kernel_t_<256, false>(cls);
-    return face_kernel_t_<64, false>(cls);
+    if (kw && th) return face_kernel_t_<FACE_TILE, true, true>(cls);
+    if (kw) return face_kernel_t_<FACE_TILE, true, false>(cls);
+    if (th) return face_kernel_t_<FACE_TILE, false, true>(cls);
+    if (tile == 128) return face_kernel_t_<128, false, false>(cls);
+    if (tile == 256) return face_kernel_t_<256, false, false>(cls);
+    return face_kernel_t_<64, false, false>(cls);
 }
 static int face_block(int cls, int tile) { return cls < 2 ? T2_THREADS : tile; }
 static const int kDefaultFaceTiles[NCLS] = {FACE_TILE, FACE_TILE, FACE_TILE, FACE_TILE};
@@ -499,7 +503,7 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
     hipStream_t s = h->stream;
     const void* tab = h->tab;
     const bool kw = h->cfg.turb_transport != 0;
-    face_kernel_t fk = face_kernel(h->cls, FACE_TILE, kw);
+    face_kernel_t fk = face_kernel(h->cls, FACE_TILE, kw, h->cfg.eps_mode == GKS_EPS_TAUHAT);
     const dim3 fblock(face_block(h->cls, FACE_TILE));
     const bool upd = h->cfg.dim == 3;
     void (*ks)(const void*, int, int, int) = kw ? k_strain<true> : k_strain<false>;
@@ -581,7 +585,7 @@ gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt
 gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
 {
     if (!h || !host_out) return fail_h(h, GKS_ERR_ARG, "NULL argument");
-    if (which < GKS_FIELD_CONS || which > GKS_FIELD_TURB) return fail_h(h, GKS_ERR_ARG, "unknown field");
+    if (which < GKS_FIELD_CONS || which > GKS_FIELD_EPS) return fail_h(h, GKS_ERR_ARG, "unknown field");
     gks_status rs = sync_batch(h);
     if (rs != GKS_OK) return rs;
     State st;
@@ -589,7 +593,7 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const long long N = h->L.ncells;
     const int nv = h->nv, D = h->cfg.dim;
-    if (which == GKS_FIELD_STRAIN || (which == GKS_FIELD_TURB && h->cfg.turb_transport)) {
+    if (which == GKS_FIELD_STRAIN || which == GKS_FIELD_EPS || (which == GKS_FIELD_TURB && h->cfg.turb_transport)) {
         // a strain pass over the current state (with transport it also writes k and omega)
         hipLaunchKernelGGL(h->cfg.turb_transport ? k_strain<true> : k_strain<false>, dim3(h->grid_cell),
                            dim3(CELL_TILE), 0, h->stream, (const void*)h->tab, 1, 1, 0);
@@ -597,6 +601,17 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
     }
     if (which == GKS_FIELD_STRAIN) {
         HIP_TRY(h, hipMemcpyAsync(host_out, h->inst.S, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return GKS_OK;
+    }
+    if (which == GKS_FIELD_EPS) {
+        // into the older state buffer, which no step reads again before writing it
+        double* out = h->inst.W[st.parity ^ 1];
+        const int grid = (int)std::min<long long>((N + 63) / 64, 1 << 20);
+        hipLaunchKernelGGL(h->cfg.eps_mode == GKS_EPS_TAUHAT ? k_eps<true> : k_eps<false>, dim3(grid), dim3(64), 0,
+                           h->stream, (const void*)h->tab, 1, out);
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(host_out, out, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         return GKS_OK;
     }
@@ -737,7 +752,8 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
     if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
     for (int i = 0; i < count; ++i) {
         if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
-        if (hs[i]->cfg.turb_transport) return fail_h(nullptr, GKS_ERR_ARG, "solves with k-omega transport step alone");
+        if (hs[i]->cfg.turb_transport || hs[i]->cfg.eps_mode != GKS_EPS_DT)
+            return fail_h(nullptr, GKS_ERR_ARG, "solves with k-omega transport or the tau_hat mode step alone");
     }
     gks_batch b = new gks_batch_ctx();
     b->members.assign(hs, hs + count);
@@ -763,7 +779,8 @@ gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t coun
     if (!b || count < 0 || count > b->cap || (!hs && count)) return fail_h(nullptr, GKS_ERR_ARG, "bad member list");
     for (int i = 0; i < count; ++i) {
         if (!hs[i]) return fail_h(nullptr, GKS_ERR_ARG, "NULL member");
-        if (hs[i]->cfg.turb_transport) return fail_h(nullptr, GKS_ERR_ARG, "solves with k-omega transport step alone");
+        if (hs[i]->cfg.turb_transport || hs[i]->cfg.eps_mode != GKS_EPS_DT)
+            return fail_h(nullptr, GKS_ERR_ARG, "solves with k-omega transport or the tau_hat mode step alone");
     }
     b->members.assign(hs, hs + count);
     return batch_upload(b);

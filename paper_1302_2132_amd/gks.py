@@ -17,7 +17,8 @@ GKS_OK, GKS_ERR_ARG, GKS_ERR_NONPHYSICAL, GKS_ERR_NOMEM, GKS_ERR_DEVICE, GKS_ERR
 _NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NONPHYSICAL", 3: "ERR_NOMEM", 4: "ERR_DEVICE", 5: "ERR_STATE"}
 BC = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
-FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3}
+FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3, "eps": 4}
+EPS_MODE = {"dt": 0, "tauhat": 1}
 
 # every entry point declared in include/gks.h
 EXPORTED = (
@@ -47,6 +48,7 @@ class gks_config(C.Structure):
         ("precision", C.c_int32),
         ("max_steps", C.c_int64),
         ("turb_transport", C.c_int32),
+        ("eps_mode", C.c_int32),
     ]
 
 
@@ -131,6 +133,7 @@ class _Cfg:
         c.precision = PRECISION[case.precision]
         c.max_steps = int(getattr(case, "max_steps", 0) or 0)
         c.turb_transport = 1 if getattr(case, "kw_transport", False) else 0
+        c.eps_mode = EPS_MODE[getattr(case, "eps_mode", "dt")]
         self.c = c
 
 
@@ -299,8 +302,9 @@ class Solver:
         return gks_residual(self.h, self.nv)
 
     def fields(self, which="cons"):
-        """cons / prim: (nvar, nz, ny, nx); strain: (nz, ny, nx); turb: (2, nz, ny, nx), k and omega."""
-        shape = {"strain": self.case.k.shape, "turb": (2,) + self.case.k.shape}.get(which, self.case.W.shape)
+        """cons / prim: (nvar, nz, ny, nx); strain, eps: (nz, ny, nx); turb: (2, nz, ny, nx), k and omega."""
+        shape = {"strain": self.case.k.shape, "eps": self.case.k.shape,
+                 "turb": (2,) + self.case.k.shape}.get(which, self.case.W.shape)
         return gks_fields(self.h, which, shape)
 
     def close(self):

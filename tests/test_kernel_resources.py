@@ -2,7 +2,8 @@
 
 The flux kernels must stay spill-free at the occupancy they were designed for: the fused
 2D tile kernel at three waves per SIMD in FP64 and four in the FP32-flux form, the 3D
-face kernel at two (FP64) and four (FP32), each also in its k-omega transport form.  A spill means the flux path stopped being
+face kernel at two (FP64) and four (FP32), each also in its k-omega transport and tau_hat
+forms.  A spill means the flux path stopped being
 inlined or grew (or values derived from the thread index were kept live across the tile
 loop), and costs scratch traffic to HBM on every face."""
 import os
@@ -36,16 +37,16 @@ def remarks(tmp_path_factory):
 
 
 def _face(res, r, d):
-    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks6k_faceI{r}Li{d}ELi\d+ELb[01]EEEvPKvii", k)}
+    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks6k_faceI{r}Li{d}ELi\d+ELb[01]ELb[01]EEEvPKvii", k)}
 
 
 def _tile2(res, r):
-    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks7k_tile2I{r}Lb[01]EEEvPKvii", k)}
+    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks7k_tile2I{r}Lb[01]ELb[01]EEEvPKvii", k)}
 
 
 def test_fused_2d_kernels_occupancy(remarks):
     k64, k32 = _tile2(remarks, "d"), _tile2(remarks, "f")
-    assert len(k64) == 2 and len(k32) == 2         # frozen fields and transport
+    assert len(k64) == 4 and len(k32) == 4         # frozen or transported k-omega, dt or tau_hat
     for k, v in k64.items():
         assert v["ScratchSize"] == 0, (k, v)
         assert v["Occupancy"] >= 3, (k, v)
@@ -57,7 +58,7 @@ def test_fused_2d_kernels_occupancy(remarks):
 def test_3d_face_kernels_fit_without_spill(remarks):
     for r, waves in (("d", 2), ("f", 4)):
         ks = _face(remarks, r, 3)
-        assert len(ks) == 4                         # tiles 64, 128, 256; transport at 64
+        assert len(ks) == 6                         # tiles 64, 128, 256; transport / tau_hat at 64
         for k, v in ks.items():
             assert v["ScratchSize"] == 0, (k, v)
             assert v["Occupancy"] >= waves, (k, v)
@@ -65,5 +66,5 @@ def test_3d_face_kernels_fit_without_spill(remarks):
 
 def test_cell_kernels_do_not_spill(remarks):
     for k, v in remarks.items():
-        if any(s in k for s in ("k_strain", "k_update", "k_finish", "k_rate")):
+        if any(s in k for s in ("k_strain", "k_update", "k_finish", "k_rate", "k_eps")):
             assert v["ScratchSize"] == 0, (k, v)
