@@ -21,6 +21,7 @@ BC_CODE = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 ERRORS = {0: "ok", 1: "bad argument", 2: "nonphysical state"}
 INFO_LEN = 51
 EPS_MODE = {"dt": 0, "tauhat": 1}
+RECON = {"muscl2": 0, "muscl3": 1}
 NU = 12
 
 
@@ -44,6 +45,7 @@ class _Case(C.Structure):
         ("gamma", C.c_double), ("prandtl", C.c_double), ("mu", C.c_double),
         ("c_a", C.c_double), ("c_mu", C.c_double), ("cfl", C.c_double), ("t_end", C.c_double),
         ("eps_mode", C.c_int),
+        ("recon", C.c_int),
     ]
 
 
@@ -85,6 +87,8 @@ def _bind(L):
     _lib.og_moment_solve.argtypes = [C.c_int, C.c_double, dp, dp, dp]
     _lib.og_tau_value.argtypes = [C.c_double] * 11
     _lib.og_tau_value.restype = C.c_double
+    if hasattr(_lib, "og_recon"):
+        _lib.og_recon.argtypes = [C.c_int, dp, dp, C.c_double, dp]
     if hasattr(_lib, "og_kogan_e"):
         _lib.og_kogan_e.argtypes = [C.c_double, C.c_double, C.c_double, dp]
         _lib.og_eps_field.argtypes = [C.c_void_p, dp, dp, dp, dp]
@@ -126,6 +130,7 @@ class _Bound:
         s.gamma, s.prandtl, s.mu = case.gamma, case.prandtl, case.mu
         s.c_a, s.c_mu, s.cfl, s.t_end = case.c_a, case.c_mu, case.cfl, case.t_end
         s.eps_mode = EPS_MODE[getattr(case, "eps_mode", "dt")]
+        s.recon = RECON[getattr(case, "recon", "muscl2")]
         self.s = s
 
     @property
@@ -262,6 +267,15 @@ def kogan(tau, dt):
     out = np.zeros(9)
     lib().og_kogan(float(tau), float(dt), _dp(out))
     return out
+
+
+def reconstruct(recon, w, xc, xf):
+    """One component at one face from cells i-1..i+2 (values w, centres xc), face xf:
+    returns (wl, wr, sl, sr)."""
+    out = np.zeros(4)
+    lib().og_recon(RECON[recon], _dp(np.ascontiguousarray(w, dtype=np.float64)),
+                   _dp(np.ascontiguousarray(xc, dtype=np.float64)), float(xf), _dp(out))
+    return tuple(out)
 
 
 def kogan_e(tau, tau_e, dt):

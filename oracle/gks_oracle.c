@@ -575,6 +575,7 @@ typedef struct {
     const double* bc_data[3][2];
     double gamma, prandtl, mu, c_a, c_mu, cfl, t_end;
     int eps_mode;      /* 0: eps = tau/dt; 1: eps = tau/tau_hat */
+    int recon;         /* 0: second-order MUSCL (minmod); 1: third-order MUSCL (limited kappa = 1/3) */
 } og_case;
 
 typedef struct {
@@ -606,6 +607,7 @@ static int og_grid_init(og_grid* gr, const og_case* c)
     gr->gas.gamma = c->gamma; gr->gas.prandtl = c->prandtl; gr->gas.mu = c->mu;
     gr->gas.c_a = c->c_a; gr->gas.c_mu = c->c_mu;
     if (c->eps_mode != 0 && c->eps_mode != 1) return OG_ERR_ARG;
+    if (c->recon != 0 && c->recon != 1) return OG_ERR_ARG;
     gr->gas.eps_mode = c->eps_mode;
     gr->nv = c->dim + 2;
     gr->next = 1;
@@ -782,6 +784,40 @@ static double og_minmod(double p, double q)
     return (p > 0.0 ? 1.0 : -1.0) * fmin(fabs(p), fabs(q));
 }
 
+/* Limited kappa-scheme (van Leer's MUSCL family) with kappa = 1/3, the third-order member:
+ * the slope towards the face of a cell whose one-sided slopes are `away` (across the far
+ * face) and `toward` (across this face) is
+ *   (1 - kappa)/2 minmod(away, b toward) + (1 + kappa)/2 minmod(toward, b away),
+ * b = (3 - kappa)/(1 - kappa) = 4.  On a uniform grid the face value W_i + slope dx/2 is
+ * exact for the cell averages of a quadratic where neither limiter acts, and it stays
+ * between the averages of the two cells sharing the face (no new extremum). */
+static double og_muscl3(double away, double toward)
+{
+    const double kappa = 1.0 / 3.0, b = (3.0 - kappa) / (1.0 - kappa);
+    return 0.5 * (1.0 - kappa) * og_minmod(away, b * toward) + 0.5 * (1.0 + kappa) * og_minmod(toward, b * away);
+}
+
+/* One component along a face normal: cell values w[0..3] (cells i-1, i, i+1, i+2) with
+ * centres xc[0..3], face at xf between cells i and i+1.  Gradients sl, sr: minmod of the
+ * one-sided slopes on centre distances (both schemes); face values wl, wr from those
+ * (recon 0) or from the limited kappa = 1/3 slopes (recon 1). */
+static void og_reconstruct(int recon, const double* w, const double* xc, double xf, double* wl, double* wr,
+                           double* sl, double* sr)
+{
+    const double d0 = (w[1] - w[0]) / (xc[1] - xc[0]);
+    const double d1 = (w[2] - w[1]) / (xc[2] - xc[1]);
+    const double d2 = (w[3] - w[2]) / (xc[3] - xc[2]);
+    *sl = og_minmod(d0, d1);
+    *sr = og_minmod(d1, d2);
+    if (recon) {
+        *wl = w[1] + og_muscl3(d0, d1) * (xf - xc[1]);
+        *wr = w[2] - og_muscl3(d2, d1) * (xc[2] - xf);
+    } else {
+        *wl = w[1] + *sl * (xf - xc[1]);
+        *wr = w[2] - *sr * (xc[2] - xf);
+    }
+}
+
 /* local rate  sum_d (|U_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2,
  * nu_eff = (mu + rho k/omega)/rho * max(4/3, gamma/Pr);  dt = CFL / max rate */
 static int og_max_rate(const og_grid* gr, const double* W, const double* kk, const double* om,
@@ -834,16 +870,13 @@ static int og_face_at(const og_grid* gr, const double* We, const double* kk, con
         xcs[o] = gr->xc[d][cc[d] + 2];
     }
     const double xface = gr->xfe[d][base[d] + 2];
-    /* minmod slopes of the conservative variables on centre-to-centre distances */
+    /* minmod slopes of the conservative variables on centre-to-centre distances; the face
+       values from them (second order) or from the limited kappa = 1/3 combination of the
+       two one-sided slopes (third-order MUSCL) */
     double sL[5], sR[5], WL[5], WR[5];
     for (int m = 0; m < nv; ++m) {
-        double d0 = (Wc[1][m] - Wc[0][m]) / (xcs[1] - xcs[0]);
-        double d1 = (Wc[2][m] - Wc[1][m]) / (xcs[2] - xcs[1]);
-        double d2 = (Wc[3][m] - Wc[2][m]) / (xcs[3] - xcs[2]);
-        sL[m] = og_minmod(d0, d1);
-        sR[m] = og_minmod(d1, d2);
-        WL[m] = Wc[1][m] + sL[m] * (xface - xcs[1]);
-        WR[m] = Wc[2][m] - sR[m] * (xcs[2] - xface);
+        const double w[4] = {Wc[0][m], Wc[1][m], Wc[2][m], Wc[3][m]};
+        og_reconstruct(gr->c->recon, w, xcs, xface, &WL[m], &WR[m], &sL[m], &sR[m]);
     }
     /* rotate to the face-local frame: normal first, then remaining axes in order */
     int perm[3];
@@ -1296,6 +1329,13 @@ int og_kogan(double tau, double dt, double* out)
     og_kogan_weights(tau, dt, &k);
     for (int i = 0; i < 6; ++i) out[i] = k.g[i];
     out[6] = k.c1; out[7] = k.c4; out[8] = k.c5;
+    return OG_OK;
+}
+
+/* Reconstruction of one component at one face (og_reconstruct): out = wl, wr, sl, sr. */
+int og_recon(int recon, const double* w, const double* xc, double xf, double* out)
+{
+    og_reconstruct(recon, w, xc, xf, &out[0], &out[1], &out[2], &out[3]);
     return OG_OK;
 }
 

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import test_oracle_kw as KW
+import test_oracle_muscl3 as M3
 import test_oracle_pins as P
 import test_oracle_tauhat as TH
 
@@ -70,6 +71,11 @@ MUTANTS = {
     "slope term of gam4": ("k->g[4] = -tau * I0 - I1;", "k->g[4] = -tau * I0 + I1;"),
     "series of t e^{-t/tau_e}": ("h -= sg * (n - 1) * term;", "h -= sg * n * term;"),
     "hydrodynamic limit keeps the upwind part": ("I0 = 0.0; I1 = 0.0; gam0 = dt;", "I0 = dt; I1 = 0.0; gam0 = 0.0;"),
+    "kappa-scheme weights swapped": ("return 0.5 * (1.0 - kappa) * og_minmod(away, b * toward) + 0.5 * (1.0 + kappa) * og_minmod(toward, b * away);",
+                                     "return 0.5 * (1.0 + kappa) * og_minmod(away, b * toward) + 0.5 * (1.0 - kappa) * og_minmod(toward, b * away);"),
+    "kappa-scheme limiter bound": ("b = (3.0 - kappa) / (1.0 - kappa);", "b = (1.0 + kappa) / (1.0 - kappa);"),
+    "third-order right face value from the wrong cell": ("*wr = w[2] - og_muscl3(d2, d1) * (xc[2] - xf);",
+                                                          "*wr = w[2] - og_muscl3(d1, d2) * (xc[2] - xf);"),
 }
 
 
@@ -118,6 +124,9 @@ PINS = [
     lambda: TH.test_eps_hat_of_a_velocity_gradient(2),
     lambda: TH.test_eps_hat_of_density_and_velocity_gradients(),
     lambda: TH.test_continuous_data_navier_stokes_flux_in_tauhat_mode(2),
+    lambda: [M3.test_quadratic_face_values_are_exact_on_a_uniform_grid(s) for s in range(3)],
+    lambda: M3.test_no_new_extrema_on_a_uniform_grid(),
+    lambda: M3.test_quadratic_with_slopes_three_times_apart(),
 ]
 
 
