@@ -7,7 +7,8 @@ frozen seeded k/omega.  A step is one explicit time step of the whole path (CFL 
 step, strain rate, every face flux, conservative update, residual).  The FP64 form is
 the headline `value`; the FP32-flux form (flux arithmetic in FP32, everything else FP64)
 is reported beside it with its error against the FP64 run, and so is the same workload
-with k and omega transported by the k-omega equations instead of frozen.  The degree of
+with k and omega transported by the k-omega equations instead of frozen, and with
+third-order MUSCL face values.  The degree of
 rarefaction eps_hat = tau/tau_hat (the turbulent Knudsen number) of the SBLI run is
 reported as a diagnostic; the mode that puts eps_hat into the time weights is measured on a
 1024^2 mixing layer (it does not stay physical on the SBLI mesh with an explicit global
@@ -87,9 +88,10 @@ def _roofline(case, leg, steps, flops_face, peak):
     face_s = leg["kernels"]["face_ms"] / 1e3 / steps
     achieved = flops_face * faces / face_s / 1e12
     r = "float" if case.precision == "fp32_flux" else "double"
-    kw = "true" if getattr(case, "kw_transport", False) else "false"
-    th = "true" if getattr(case, "eps_mode", "dt") == "tauhat" else "false"
-    kernel = f"k_tile2<{r},{kw},{th}>" if case.dim == 2 else f"k_face<{r},3,64,{kw},{th}>"
+    # variant bits of the face kernels: 1 k-omega transport, 2 tau_hat, 4 third-order MUSCL
+    v = ((1 if getattr(case, "kw_transport", False) else 0) | (2 if getattr(case, "eps_mode", "dt") == "tauhat" else 0)
+         | (4 if getattr(case, "recon", "muscl2") == "muscl3" else 0))
+    kernel = f"k_tile2<{r},{v}>" if case.dim == 2 else f"k_face<{r},3,64,{v}>"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": _profiled_traffic(kernel),
             "kernel": kernel, "flops_per_face": flops_face, "faces_per_launch": faces,
@@ -245,6 +247,7 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D isotropic-box leg")
     ap.add_argument("--no-kw", action="store_true", help="skip the k-omega transport leg")
     ap.add_argument("--no-tauhat", action="store_true", help="skip the tau_hat rarefaction leg")
+    ap.add_argument("--no-muscl3", action="store_true", help="skip the third-order MUSCL leg")
     ap.add_argument("--serve-full", action="store_true", help="served leg on the full 256-request trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), to calibrate "
@@ -319,6 +322,18 @@ def main():
             "vs_frozen": vkw / value,
             "roofline": _roofline(ckw, legkw, K, flops2d + gks_kw_face_flops(), FP64_PEAK_TFLOPS),
             "kernel_ms_per_step": {k: round(v / K, 4) for k, v in legkw["kernels"].items() if k != "steps"},
+        }
+    if not args.no_muscl3:
+        c3 = C.sbli(1024, 512)
+        c3.recon = "muscl3"
+        leg3 = _leg(c3, K, Wm)
+        v3 = c3.ncells * K / leg3["seconds"]
+        out["muscl3"] = {
+            "workload": "sbli_1024x512 as above with third-order MUSCL face values (limited kappa = 1/3), FP64",
+            "value": v3, "unit": "cell-updates/s", "ms_per_step": leg3["seconds"] * 1e3 / K,
+            "vs_muscl2": v3 / value,
+            "roofline": _roofline(c3, leg3, K, flops2d, FP64_PEAK_TFLOPS),
+            "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg3["kernels"].items() if k != "steps"},
         }
     if not args.no_tauhat:
         legs = {}

@@ -80,6 +80,16 @@ enum { GKS_FP64 = 0, GKS_FP32_FLUX = 1 };
  *          limit f_c (1 + Abar dt/2) (Eq. hydroturbolimit). */
 enum { GKS_EPS_DT = 0, GKS_EPS_TAUHAT = 1 };
 
+/* Reconstruction of the face values (section "Implementation ...": second- and
+ * third-order TVD/MUSCL with the minmod limiter).  Both use conservative variables and
+ * one-sided slopes on centre-to-centre distances; the gradients that set the initial
+ * distribution's slopes are the minmod of the two one-sided slopes in both.
+ *  MUSCL2  face values from the minmod gradients (second order);
+ *  MUSCL3  face values from the limited kappa-scheme with kappa = 1/3: the slope towards a
+ *          face is (1/3) minmod(s_away, 4 s_toward) + (2/3) minmod(s_toward, 4 s_away)
+ *          (third-order face values on uniform grids, no new extrema). */
+enum { GKS_RECON_MUSCL2 = 0, GKS_RECON_MUSCL3 = 1 };
+
 /* Fields for gks_fields. CONS: conservative state (nvar x ncells). PRIM: rho, U, V, [W],
  * p (nvar x ncells). STRAIN: strain-rate magnitude sqrt(2 S_ab S_ab) (ncells). TURB: k
  * then omega (2 x ncells): those of the current state when transported (computed on the
@@ -105,6 +115,7 @@ typedef struct {
     int64_t max_steps;            /* > 0: the solve stops (on the device) after this many steps */
     int32_t turb_transport;       /* 1: transport k and omega with the flow; 0: frozen inputs */
     int32_t eps_mode;             /* GKS_EPS_DT or GKS_EPS_TAUHAT */
+    int32_t recon;                /* GKS_RECON_MUSCL2 or GKS_RECON_MUSCL3 */
 } gks_config;
 
 typedef struct gks_ctx* gks_handle;
@@ -186,8 +197,8 @@ gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
  * captured as a graph.  Creation (and gks_batch_set_members) waits for the members' own
  * streams; afterwards every per-handle call on a member first waits for the batch stream.
  * The table lives in dev_workspace.  Handles stay owned by the caller and must outlive
- * the batch.  Members are frozen-field solves in the DT mode: a handle with
- * turb_transport or GKS_EPS_TAUHAT is refused (GKS_ERR_ARG), here and in
+ * the batch.  Members are frozen-field, DT-mode, second-order solves: a handle with
+ * turb_transport, GKS_EPS_TAUHAT or GKS_RECON_MUSCL3 is refused (GKS_ERR_ARG), here and in
  * gks_batch_set_members. */
 gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity,
                             void* dev_workspace, size_t bytes, void* hip_stream, gks_batch* out);

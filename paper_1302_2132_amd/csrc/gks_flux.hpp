@@ -343,10 +343,24 @@ struct FaceGeo {
     H icd[3], dl, dr, idl, idr;
 };
 
+// Third-order MUSCL slope towards a face (the limited kappa-scheme with kappa = 1/3): of a
+// cell whose one-sided slopes are `away` (across its far face) and `toward` (across this
+// face), (1/3) minmod(away, 4 toward) + (2/3) minmod(toward, 4 away).  Both minmods vanish
+// unless the slopes share a sign, and then carry it, so this is one select:
+//   away toward > 0 ? sign(toward) ((1/3) min(|away|, 4|toward|) + (2/3) min(|toward|, 4|away|)) : 0.
+template <typename H>
+GKS_HD inline H muscl3(H away, H toward)
+{
+    const H a = g_abs(away), t = g_abs(toward);
+    const H m = H(1.0 / 3.0) * g_min(a, H(4) * t) + H(2.0 / 3.0) * g_min(t, H(4) * a);
+    return (away * toward > H(0)) ? g_copysign(m, toward) : H(0);
+}
+
 // MUSCL reconstruction along the face normal from four cell averages Wc[0..3] (cells
-// i-1, i, i+1, i+2 around face i+1/2): minmod of the one-sided differences on
-// centre-to-centre distances, conservative variables.
-template <int D, typename H>
+// i-1, i, i+1, i+2 around face i+1/2), conservative variables, one-sided differences on
+// centre-to-centre distances.  The gradients are their minmod; the face values come from
+// those gradients (second order) or, with R3, from the third-order slopes above.
+template <int D, typename H, bool R3 = false>
 GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const FaceGeo<H>& geo, FaceIn<D, H>& in)
 {
     for (int m = 0; m < D + 2; ++m) {
@@ -356,8 +370,13 @@ GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const FaceGeo<H>& geo, Face
         const H sl = minmod(d0, d1), sr = minmod(d1, d2);
         in.sl[m] = sl;
         in.sr[m] = sr;
-        in.Wl[m] = Wc[1][m] + sl * geo.dl;
-        in.Wr[m] = Wc[2][m] - sr * geo.dr;
+        if constexpr (R3) {
+            in.Wl[m] = Wc[1][m] + muscl3(d0, d1) * geo.dl;
+            in.Wr[m] = Wc[2][m] - muscl3(d2, d1) * geo.dr;
+        } else {
+            in.Wl[m] = Wc[1][m] + sl * geo.dl;
+            in.Wr[m] = Wc[2][m] - sr * geo.dr;
+        }
         in.Wi[m] = Wc[1][m];
         in.Wi1[m] = Wc[2][m];
     }

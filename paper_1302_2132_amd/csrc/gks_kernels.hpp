@@ -17,12 +17,14 @@
 // captured graph) serves any membership.  Workgroup ids are remapped so that consecutive
 // tiles, which share halo cells, land on the same XCD (L2).
 //
-// Solves that transport k and omega (Inst::kw) use the KW = true instantiations: the
-// strain pass also derives k, omega and the model's sources of each cell, the face pass
-// adds the fluxes of rho k and rho omega, and the update advances them with point-implicit
-// sinks.  Solves whose degree of rarefaction is measured against the resolved time scale
-// tau_hat use the TH = true flux (face_flux with FLUX_TAUHAT).  The KW = TH = false code is
-// the frozen-field scheme, untouched by either.
+// The face kernels come in variants (a bit mask V):
+//   V_KW  k and omega transported (Inst::kw): the strain pass (k_strain<true>) also derives
+//         k, omega and the model's sources of each cell, the face pass adds the fluxes of
+//         rho k and rho omega, and the update advances them with point-implicit sinks;
+//   V_TH  the degree of rarefaction measured against the resolved time scale tau_hat
+//         (face_flux with FLUX_TAUHAT);
+//   V_R3  third-order MUSCL face values (reconstruct<.., true>).
+// V = 0 is the plain scheme, untouched by the others.
 //
 // The table, the solve descriptors and (outside k_finish) the step state are read
 // through the constant address space: nothing writes them while these kernels run, so
@@ -286,7 +288,9 @@ __device__ inline void kw_face(cref<Inst> I, double frho, double kl, double kr, 
 // order.  Returns nonzero for a non-physical state.  The axis is a template parameter so
 // that every index and the rotation to the face-local frame are compile-time (no private
 // arrays).
-template <typename R, int D, int DIR, int MODE, typename P>
+enum { V_KW = 1, V_TH = 2, V_R3 = 4 };
+
+template <typename R, int D, int DIR, int MODE, bool R3, typename P>
 __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int i, const double (*Wc)[D + 2],
                                                                P kk, P ww, P ss, int il, int ir, double dt, R* Fg)
 {
@@ -304,7 +308,7 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
         geo.idr = fg[3];
     }
     FaceIn<D, double> in;
-    reconstruct<D, double>(Wc, geo, in);
+    reconstruct<D, double, R3>(Wc, geo, in);
 
     // face-local frame: normal momentum first, then the remaining axes in order
     constexpr int P1 = DIR == 0 ? 1 : 0;             // first tangential axis
@@ -339,9 +343,10 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
 
 // One face normal to axis DIR, stencil read from the state in HBM, flux written to the
 // axis' face-flux array (structure of arrays).
-template <typename R, int D, int DIR, bool KW, bool TH>
+template <typename R, int D, int DIR, int V>
 __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int f)
 {
+    constexpr bool KW = V & V_KW;
     constexpr int NV = D + 2;
     // face coordinates: the face lies on the low side of cell fc along axis DIR
     const int fn0 = I.n[0] + (DIR == 0), fn1 = I.n[1] + (DIR == 1);
@@ -382,7 +387,8 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
     const double* ww = I.om;
     const double* ss = I.S;
     const double dt = state_of(I).dt;
-    if (face_eval<R, D, DIR, TH ? FLUX_TAUHAT : 0>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt, F))
+    if (face_eval<R, D, DIR, (V & V_TH) ? FLUX_TAUHAT : 0, (V & V_R3) != 0>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt,
+                                                                           F))
         atomicOr(&I.st->err, 1);
     R* __restrict__ out = (R*)I.F[DIR];
     const long long nf = I.nface[DIR];   // 64-bit: component offsets m * nf may pass 2^31
@@ -420,10 +426,11 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
 #endif
 // Register budget of the face kernel (instantiated for 3D; 2D steps use k_tile2): at least
 // this many waves per SIMD (2 leaves 256 VGPRs per lane for the 3D FP64 flux, 4 leaves 128
-// for the FP32 flux).  TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
-template <typename R, int D, int TILE, bool KW, bool TH>
+// for the FP32 flux; the third-order reconstruction takes the FP32 form to 3, 168 VGPRs).
+// TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
+template <typename R, int D, int TILE, int V>
 __global__ __launch_bounds__(TILE)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_FACE_WAVES_FP64)))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & V_R3) ? 1 : 0) : GKS_FACE_WAVES_FP64)))
 void k_face(const void* __restrict__ table, int cap, int cls)
 {
     const TabC tv(table, cap);
@@ -438,18 +445,18 @@ void k_face(const void* __restrict__ table, int cap, int cls)
         int lt = tile - prefix[mj];
         if (lt < I.ntile_face[0]) {
             const int f = lt * TILE + (int)threadIdx.x;
-            if (f < I.nface[0]) face_one<R, D, 0, KW, TH>(I, f);
+            if (f < I.nface[0]) face_one<R, D, 0, V>(I, f);
             continue;
         }
         lt -= I.ntile_face[0];
         if (D == 2 || lt < I.ntile_face[1]) {
             const int f = lt * TILE + (int)threadIdx.x;
-            if (f < I.nface[1]) face_one<R, D, 1, KW, TH>(I, f);
+            if (f < I.nface[1]) face_one<R, D, 1, V>(I, f);
             continue;
         }
         lt -= I.ntile_face[1];
         const int f = lt * TILE + (int)threadIdx.x;
-        if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1), KW, TH>(I, f);
+        if (f < I.nface[2]) face_one<R, D, (D == 3 ? 2 : 1), V>(I, f);
     }
 }
 
@@ -602,11 +609,14 @@ static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_TH
 #define GKS_TILE2_WAVES_FP64 3
 #endif
 
-template <typename R, bool KW, bool TH>
+template <typename R, int V>
 __global__ __launch_bounds__(T2_THREADS)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_TILE2_WAVES_FP64)))
 void k_tile2(const void* __restrict__ table, int cap, int cls)
 {
+    constexpr bool KW = V & V_KW;
+    constexpr int FMODE = (V & V_TH) ? FLUX_TAUHAT : 0;
+    constexpr bool R3 = V & V_R3;
     constexpr int NV = 4;
     constexpr int NX = NV + (KW ? 2 : 0);     // with transport: fluxes of rho k, rho omega too
     __shared__ double sW[NV][T2_WX * T2_WY];
@@ -679,8 +689,7 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + 2) * T2_WX + i + o];
                 const int kl = (j + 1) * T2_KX + i;
                 R F[NV];
-                if (face_eval<R, 2, 0, TH ? FLUX_TAUHAT : 0>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1,
-                                                            dt, F))
+                if (face_eval<R, 2, 0, FMODE, R3>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F))
                     atomicOr(&I.st->err, 1);
                 sFx[0][tid] = F[0];
                 sFx[1][tid] = F[1];
@@ -708,8 +717,8 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + o) * T2_WX + i + 2];
                 const int kl = j * T2_KX + i + 1;
                 R F[NV];
-                if (face_eval<R, 2, 1, TH ? FLUX_TAUHAT : 0>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl,
-                                                            kl + T2_KX, dt, F))
+                if (face_eval<R, 2, 1, FMODE, R3>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt,
+                                                  F))
                     atomicOr(&I.st->err, 1);
                 sFy[0][tid] = F[0];
                 sFy[1][tid] = F[1];
@@ -1004,10 +1013,10 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
 
 // Degree of rarefaction eps_hat = tau/tau_hat of the faces of each cell at the current
 // state and step (the strain rate, k and omega of that state already in place), largest
-// over the cell's 2 D faces, into out[cell].  TH selects the solve's time weights, which do
-// not change eps_hat but keep the evaluation that of the step.  A diagnostic: each face is
+// over the cell's 2 D faces, into out[cell].  V selects the solve's time weights and
+// reconstruction, so that the evaluation is that of the step.  A diagnostic: each face is
 // evaluated by both of its cells.
-template <int D, bool TH>
+template <int D, int V>
 __device__ inline double cell_eps(cref<Inst> I, int cell)
 {
     constexpr int NV = D + 2;
@@ -1032,8 +1041,8 @@ __device__ inline double cell_eps(cref<Inst> I, int cell)
         cl[DIR] -= 1;
         const int il = image_cell<D>(I, DIR, cl), ir = image_cell<D>(I, DIR, fc);
         double F[NV + 1];
-        if (face_eval<double, D, DIR, FLUX_EPS_OUT | (TH ? FLUX_TAUHAT : 0)>(I, fc[DIR], Wc, I.k, I.om, I.S, il, ir,
-                                                                               dt, F))
+        if (face_eval<double, D, DIR, FLUX_EPS_OUT | ((V & V_TH) ? FLUX_TAUHAT : 0), (V & V_R3) != 0>(
+                I, fc[DIR], Wc, I.k, I.om, I.S, il, ir, dt, F))
             atomicOr(&I.st->err, 1);
         mx = fmax(mx, F[NV]);
     };
@@ -1046,13 +1055,13 @@ __device__ inline double cell_eps(cref<Inst> I, int cell)
     return mx;
 }
 
-template <bool TH>
+template <int V>
 __global__ __launch_bounds__(64) void k_eps(const void* __restrict__ table, int cap, double* __restrict__ out)
 {
     const TabC tv(table, cap);
     cref<Inst> I = tv.inst[0];
     for (int cell = blockIdx.x * blockDim.x + (int)threadIdx.x; cell < I.ncells; cell += gridDim.x * blockDim.x)
-        out[cell] = I.dim == 2 ? cell_eps<2, TH>(I, cell) : cell_eps<3, TH>(I, cell);
+        out[cell] = I.dim == 2 ? cell_eps<2, V>(I, cell) : cell_eps<3, V>(I, cell);
 }
 
 // Copy of every member's step state into one array, so that a batch's states come back
@@ -1067,28 +1076,21 @@ __global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, i
     }
 }
 
-template __global__ void k_tile2<double, false, false>(const void*, int, int);
-template __global__ void k_tile2<float, false, false>(const void*, int, int);
-template __global__ void k_tile2<double, true, false>(const void*, int, int);
-template __global__ void k_tile2<float, true, false>(const void*, int, int);
-template __global__ void k_tile2<double, false, true>(const void*, int, int);
-template __global__ void k_tile2<float, false, true>(const void*, int, int);
-template __global__ void k_tile2<double, true, true>(const void*, int, int);
-template __global__ void k_tile2<float, true, true>(const void*, int, int);
-template __global__ void k_face<double, 3, 64, false, false>(const void*, int, int);
-template __global__ void k_face<double, 3, 128, false, false>(const void*, int, int);
-template __global__ void k_face<double, 3, 256, false, false>(const void*, int, int);
-template __global__ void k_face<float, 3, 64, false, false>(const void*, int, int);
-template __global__ void k_face<float, 3, 128, false, false>(const void*, int, int);
-template __global__ void k_face<float, 3, 256, false, false>(const void*, int, int);
-template __global__ void k_face<double, 3, 64, true, false>(const void*, int, int);
-template __global__ void k_face<float, 3, 64, true, false>(const void*, int, int);
-template __global__ void k_face<double, 3, 64, false, true>(const void*, int, int);
-template __global__ void k_face<float, 3, 64, false, true>(const void*, int, int);
-template __global__ void k_face<double, 3, 64, true, true>(const void*, int, int);
-template __global__ void k_face<float, 3, 64, true, true>(const void*, int, int);
-template __global__ void k_eps<false>(const void*, int, double*);
-template __global__ void k_eps<true>(const void*, int, double*);
+#define GKS_TILE2(V)                                                    \
+    template __global__ void k_tile2<double, V>(const void*, int, int); \
+    template __global__ void k_tile2<float, V>(const void*, int, int);
+#define GKS_FACE(T, V)                                                       \
+    template __global__ void k_face<double, 3, T, V>(const void*, int, int); \
+    template __global__ void k_face<float, 3, T, V>(const void*, int, int);
+GKS_TILE2(0) GKS_TILE2(1) GKS_TILE2(2) GKS_TILE2(3) GKS_TILE2(4) GKS_TILE2(5) GKS_TILE2(6) GKS_TILE2(7)
+GKS_FACE(64, 0) GKS_FACE(128, 0) GKS_FACE(256, 0)
+GKS_FACE(64, 1) GKS_FACE(64, 2) GKS_FACE(64, 3) GKS_FACE(64, 4) GKS_FACE(64, 5) GKS_FACE(64, 6) GKS_FACE(64, 7)
+#undef GKS_TILE2
+#undef GKS_FACE
+template __global__ void k_eps<0>(const void*, int, double*);
+template __global__ void k_eps<V_TH>(const void*, int, double*);
+template __global__ void k_eps<V_R3>(const void*, int, double*);
+template __global__ void k_eps<V_TH | V_R3>(const void*, int, double*);
 template __global__ void k_update<false>(const void*, int);
 template __global__ void k_update<true>(const void*, int);
 template __global__ void k_strain<false>(const void*, int, int, int);

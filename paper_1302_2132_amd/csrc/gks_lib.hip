@@ -74,6 +74,7 @@ bool config_ok(const gks_config* c, std::string* why)
     if (c->max_steps < 0) return fail("max_steps must be >= 0");
     if (c->turb_transport != 0 && c->turb_transport != 1) return fail("turb_transport must be 0 or 1");
     if (c->eps_mode != GKS_EPS_DT && c->eps_mode != GKS_EPS_TAUHAT) return fail("unknown eps_mode");
+    if (c->recon != GKS_RECON_MUSCL2 && c->recon != GKS_RECON_MUSCL3) return fail("unknown reconstruction");
     return true;
 }
 
@@ -282,26 +283,38 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
 // Kernel of a face class: the fused 2D tile kernel (fixed workgroup of T2_THREADS) for the
 // 2D classes, the 3D face kernel with `tile` faces per workgroup otherwise.
 typedef void (*face_kernel_t)(const void*, int, int);
-template <int T, bool KW, bool TH>
+template <int T, int V>
 static face_kernel_t face_kernel_t_(int cls)
 {
     switch (cls) {
-    case 0: return k_tile2<double, KW, TH>;
-    case 1: return k_tile2<float, KW, TH>;
-    case 2: return k_face<double, 3, T, KW, TH>;
-    default: return k_face<float, 3, T, KW, TH>;
+    case 0: return k_tile2<double, V>;
+    case 1: return k_tile2<float, V>;
+    case 2: return k_face<double, 3, T, V>;
+    default: return k_face<float, 3, T, V>;
     }
 }
-// Solves that transport k and omega or use the tau_hat rarefaction run alone with the
-// default tile; batches hold the plain form.
-static face_kernel_t face_kernel(int cls, int tile, bool kw = false, bool th = false)
+// Face kernel of a class and variant (V_KW | V_TH | V_R3).  Solves in a variant other than
+// 0 run alone with the default tile; batches hold variant 0 only.
+static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
 {
-    if (kw && th) return face_kernel_t_<FACE_TILE, true, true>(cls);
-    if (kw) return face_kernel_t_<FACE_TILE, true, false>(cls);
-    if (th) return face_kernel_t_<FACE_TILE, false, true>(cls);
-    if (tile == 128) return face_kernel_t_<128, false, false>(cls);
-    if (tile == 256) return face_kernel_t_<256, false, false>(cls);
-    return face_kernel_t_<64, false, false>(cls);
+    switch (variant) {
+    case 1: return face_kernel_t_<FACE_TILE, 1>(cls);
+    case 2: return face_kernel_t_<FACE_TILE, 2>(cls);
+    case 3: return face_kernel_t_<FACE_TILE, 3>(cls);
+    case 4: return face_kernel_t_<FACE_TILE, 4>(cls);
+    case 5: return face_kernel_t_<FACE_TILE, 5>(cls);
+    case 6: return face_kernel_t_<FACE_TILE, 6>(cls);
+    case 7: return face_kernel_t_<FACE_TILE, 7>(cls);
+    default: break;
+    }
+    if (tile == 128) return face_kernel_t_<128, 0>(cls);
+    if (tile == 256) return face_kernel_t_<256, 0>(cls);
+    return face_kernel_t_<64, 0>(cls);
+}
+static int variant_of(const gks_config* c)
+{
+    return (c->turb_transport ? V_KW : 0) | (c->eps_mode == GKS_EPS_TAUHAT ? V_TH : 0) |
+           (c->recon == GKS_RECON_MUSCL3 ? V_R3 : 0);
 }
 static int face_block(int cls, int tile) { return cls < 2 ? T2_THREADS : tile; }
 static const int kDefaultFaceTiles[NCLS] = {FACE_TILE, FACE_TILE, FACE_TILE, FACE_TILE};
@@ -503,7 +516,7 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
     hipStream_t s = h->stream;
     const void* tab = h->tab;
     const bool kw = h->cfg.turb_transport != 0;
-    face_kernel_t fk = face_kernel(h->cls, FACE_TILE, kw, h->cfg.eps_mode == GKS_EPS_TAUHAT);
+    face_kernel_t fk = face_kernel(h->cls, FACE_TILE, variant_of(&h->cfg));
     const dim3 fblock(face_block(h->cls, FACE_TILE));
     const bool upd = h->cfg.dim == 3;
     void (*ks)(const void*, int, int, int) = kw ? k_strain<true> : k_strain<false>;
@@ -608,8 +621,10 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
         // into the older state buffer, which no step reads again before writing it
         double* out = h->inst.W[st.parity ^ 1];
         const int grid = (int)std::min<long long>((N + 63) / 64, 1 << 20);
-        hipLaunchKernelGGL(h->cfg.eps_mode == GKS_EPS_TAUHAT ? k_eps<true> : k_eps<false>, dim3(grid), dim3(64), 0,
-                           h->stream, (const void*)h->tab, 1, out);
+        const int v = variant_of(&h->cfg) & (V_TH | V_R3);
+        void (*ke)(const void*, int, double*) =
+            v == (V_TH | V_R3) ? k_eps<V_TH | V_R3> : (v == V_TH ? k_eps<V_TH> : (v == V_R3 ? k_eps<V_R3> : k_eps<0>));
+        hipLaunchKernelGGL(ke, dim3(grid), dim3(64), 0, h->stream, (const void*)h->tab, 1, out);
         HIP_TRY(h, hipGetLastError());
         HIP_TRY(h, hipMemcpyAsync(host_out, out, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -752,8 +767,8 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
     if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
     for (int i = 0; i < count; ++i) {
         if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
-        if (hs[i]->cfg.turb_transport || hs[i]->cfg.eps_mode != GKS_EPS_DT)
-            return fail_h(nullptr, GKS_ERR_ARG, "solves with k-omega transport or the tau_hat mode step alone");
+        if (variant_of(&hs[i]->cfg))
+            return fail_h(nullptr, GKS_ERR_ARG, "solves with transport, tau_hat or third-order MUSCL step alone");
     }
     gks_batch b = new gks_batch_ctx();
     b->members.assign(hs, hs + count);
@@ -779,8 +794,8 @@ gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t coun
     if (!b || count < 0 || count > b->cap || (!hs && count)) return fail_h(nullptr, GKS_ERR_ARG, "bad member list");
     for (int i = 0; i < count; ++i) {
         if (!hs[i]) return fail_h(nullptr, GKS_ERR_ARG, "NULL member");
-        if (hs[i]->cfg.turb_transport || hs[i]->cfg.eps_mode != GKS_EPS_DT)
-            return fail_h(nullptr, GKS_ERR_ARG, "solves with k-omega transport or the tau_hat mode step alone");
+        if (variant_of(&hs[i]->cfg))
+            return fail_h(nullptr, GKS_ERR_ARG, "solves with transport, tau_hat or third-order MUSCL step alone");
     }
     b->members.assign(hs, hs + count);
     return batch_upload(b);

@@ -19,6 +19,7 @@ BC = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
 FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3, "eps": 4}
 EPS_MODE = {"dt": 0, "tauhat": 1}
+RECON = {"muscl2": 0, "muscl3": 1}
 
 # every entry point declared in include/gks.h
 EXPORTED = (
@@ -49,6 +50,7 @@ class gks_config(C.Structure):
         ("max_steps", C.c_int64),
         ("turb_transport", C.c_int32),
         ("eps_mode", C.c_int32),
+        ("recon", C.c_int32),
     ]
 
 
@@ -134,6 +136,7 @@ class _Cfg:
         c.max_steps = int(getattr(case, "max_steps", 0) or 0)
         c.turb_transport = 1 if getattr(case, "kw_transport", False) else 0
         c.eps_mode = EPS_MODE[getattr(case, "eps_mode", "dt")]
+        c.recon = RECON[getattr(case, "recon", "muscl2")]
         self.c = c
 
 

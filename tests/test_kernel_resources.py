@@ -2,8 +2,10 @@
 
 The flux kernels must stay spill-free at the occupancy they were designed for: the fused
 2D tile kernel at three waves per SIMD in FP64 and four in the FP32-flux form, the 3D
-face kernel at two (FP64) and four (FP32), each also in its k-omega transport and tau_hat
-forms.  A spill means the flux path stopped being
+face kernel at two (FP64) and four (FP32), in every variant (k-omega transport, tau_hat
+rarefaction, third-order MUSCL face values), except that the third-order FP32 3D form runs
+at three waves and the third-order 2D FP64 tile keeps three waves with a bounded spill of a
+few doubles per face (two waves would cost more).  A spill means the flux path stopped being
 inlined or grew (or values derived from the thread index were kept live across the tile
 loop), and costs scratch traffic to HBM on every face."""
 import os
@@ -37,18 +39,23 @@ def remarks(tmp_path_factory):
 
 
 def _face(res, r, d):
-    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks6k_faceI{r}Li{d}ELi\d+ELb[01]ELb[01]EEEvPKvii", k)}
+    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks6k_faceI{r}Li{d}ELi\d+ELi\dEEEvPKvii", k)}
 
 
 def _tile2(res, r):
-    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks7k_tile2I{r}Lb[01]ELb[01]EEEvPKvii", k)}
+    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks7k_tile2I{r}Li\dEEEvPKvii", k)}
+
+
+def _third_order(name):
+    """Variant bit 4: third-order MUSCL face values."""
+    return bool(int(re.search(r"Li(\d)EEEvPKvii$", name).group(1)) & 4)
 
 
 def test_fused_2d_kernels_occupancy(remarks):
     k64, k32 = _tile2(remarks, "d"), _tile2(remarks, "f")
-    assert len(k64) == 4 and len(k32) == 4         # frozen or transported k-omega, dt or tau_hat
+    assert len(k64) == 8 and len(k32) == 8         # transport x tau_hat x third-order MUSCL
     for k, v in k64.items():
-        assert v["ScratchSize"] == 0, (k, v)
+        assert v["ScratchSize"] <= (40 if _third_order(k) else 0), (k, v)
         assert v["Occupancy"] >= 3, (k, v)
     for k, v in k32.items():
         assert v["ScratchSize"] == 0, (k, v)
@@ -58,10 +65,10 @@ def test_fused_2d_kernels_occupancy(remarks):
 def test_3d_face_kernels_fit_without_spill(remarks):
     for r, waves in (("d", 2), ("f", 4)):
         ks = _face(remarks, r, 3)
-        assert len(ks) == 6                         # tiles 64, 128, 256; transport / tau_hat at 64
+        assert len(ks) == 10                        # variant 0 at tiles 64, 128, 256; variants 1..7 at 64
         for k, v in ks.items():
             assert v["ScratchSize"] == 0, (k, v)
-            assert v["Occupancy"] >= waves, (k, v)
+            assert v["Occupancy"] >= waves - (1 if r == "f" and _third_order(k) else 0), (k, v)
 
 
 def test_cell_kernels_do_not_spill(remarks):
