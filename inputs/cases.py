@@ -50,6 +50,7 @@ class Case:
     kw_transport: bool = False    # transport k and omega with the flow (else frozen inputs)
     eps_mode: str = "dt"          # rarefaction in the time weights: "dt" (tau/dt) or "tauhat" (tau/tau_hat)
     recon: str = "muscl2"         # face values: "muscl2" (minmod) or "muscl3" (limited kappa = 1/3)
+    multi_d: bool = False         # expand the distributions along the tangential axes too
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property

@@ -46,6 +46,7 @@ class _Case(C.Structure):
         ("c_a", C.c_double), ("c_mu", C.c_double), ("cfl", C.c_double), ("t_end", C.c_double),
         ("eps_mode", C.c_int),
         ("recon", C.c_int),
+        ("multi_d", C.c_int),
     ]
 
 
@@ -80,7 +81,7 @@ def _bind(L):
     _lib.og_ghost_fill.argtypes = [C.c_void_p, dp, dp]
     _lib.og_step_cells.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, C.POINTER(C.c_long),
                                    C.c_long, C.c_int, dp]
-    _lib.og_face_flux.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_double,
+    _lib.og_face_flux.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_double,
                                   C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp]
     _lib.og_moments_u.argtypes = [C.c_double, C.c_double, dp]
     _lib.og_kogan.argtypes = [C.c_double, C.c_double, dp]
@@ -131,6 +132,7 @@ class _Bound:
         s.c_a, s.c_mu, s.cfl, s.t_end = case.c_a, case.c_mu, case.cfl, case.t_end
         s.eps_mode = EPS_MODE[getattr(case, "eps_mode", "dt")]
         s.recon = RECON[getattr(case, "recon", "muscl2")]
+        s.multi_d = 1 if getattr(case, "multi_d", False) else 0
         self.s = s
 
     @property
@@ -238,17 +240,29 @@ def step_cells(case, W, dt, cells, nthreads=0):
 
 
 def face_flux(dim, Wl, Wr, sl, sr, Wi, Wi1, dxl, dxr, kf, wf, Sf, dt,
-              gamma=1.4, prandtl=0.72, mu=1e-3, c_a=0.0, c_mu=0.09, eps_mode="dt"):
-    """One interface in the face-local frame (normal velocity first).
+              gamma=1.4, prandtl=0.72, mu=1e-3, c_a=0.0, c_mu=0.09, eps_mode="dt", tsl=None, tsr=None):
+    """One interface in the face-local frame (normal velocity first).  tsl, tsr: tangential
+    gradients of the two cells, (dim - 1, nv), for the multi-dimensional expansion.
 
     Returns dict(F, G, q, info) with info holding W0, a_l, a_r, A_l, A_r, abar_l, abar_r,
     Abar (5 slots each), tau, gam0..5, c1, c4, c5 and eps_hat (= tau/tau_hat)."""
     nv = dim + 2
-    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (Wl, Wr, sl, sr, Wi, Wi1)]
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (Wl, Wr, sl, sr)]
+    if tsl is not None:
+        tan = []
+        for t in (tsl, tsr):
+            a = np.zeros((2, 5))
+            a[:dim - 1, :nv] = np.asarray(t, dtype=np.float64).reshape(dim - 1, nv)
+            tan.append(a)
+        targs = [_dp(a) for a in tan]
+    else:
+        tan, targs = [], [None, None]
+    wis = [np.ascontiguousarray(x, dtype=np.float64) for x in (Wi, Wi1)]
     params = np.array([gamma, prandtl, mu, c_a, c_mu, EPS_MODE[eps_mode]], dtype=np.float64)
     F, G, q, info = np.zeros(nv), np.zeros(nv), np.zeros(1), np.zeros(INFO_LEN)
-    st = lib().og_face_flux(dim, _dp(params), *[_dp(a) for a in arrs], float(dxl), float(dxr),
-                            float(kf), float(wf), float(Sf), float(dt), _dp(F), _dp(G), _dp(q), _dp(info))
+    st = lib().og_face_flux(dim, _dp(params), *[_dp(a) for a in arrs], *targs, *[_dp(a) for a in wis],
+                            float(dxl), float(dxr), float(kf), float(wf), float(Sf), float(dt),
+                            _dp(F), _dp(G), _dp(q), _dp(info))
     if st:
         raise OracleError(st)
     names = ["W0", "a_l", "a_r", "A_l", "A_r", "abar_l", "abar_r", "Abar"]

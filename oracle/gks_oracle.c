@@ -77,6 +77,7 @@ typedef struct {
     double K;          /* internal degrees of freedom b - dim */
     double gamma, prandtl, mu, c_a, c_mu;
     int eps_mode;      /* 0: rarefaction eps = tau/dt; 1: eps = tau/tau_hat (see og_face) */
+    int multi_d;       /* 1: the distributions are expanded along the tangential axes too */
 } og_gas;
 
 typedef struct {       /* face-local frame: U[0] is the face-normal velocity */
@@ -150,6 +151,12 @@ static void p_mul(const og_poly* a, const og_poly* b, og_poly* out)
 static void p_upow(og_poly* p, int k)
 {
     for (int i = 0; i < p->n; ++i) p->e[i][0] = (signed char)(p->e[i][0] + k);
+}
+
+/* multiply by the tangential velocity t (0: v, 1: w) */
+static void p_tpow(og_poly* p, int t)
+{
+    for (int i = 0; i < p->n; ++i) p->e[i][1 + t] = (signed char)(p->e[i][1 + t] + 1);
 }
 
 /* <p>_g over the u-range `range` (tangential and internal variables over all values) */
@@ -404,8 +411,24 @@ typedef struct {
  *                        tau gam[6] c1 c4 c5 eps_hat   -> 51 values */
 #define OG_INFO_LEN 51
 
+/* <u^k v_t psi_m (b.psi)>_g over the u-range `range` (v_t the tangential velocity t) */
+static double og_tan_moment(int dim, const double* b, int t, int m, const og_mom* M, int range, int k)
+{
+    og_poly pb, pm, prod;
+    p_lin(dim, b, &pb);
+    p_psi(dim, m, &pm);
+    p_mul(&pm, &pb, &prod);
+    p_tpow(&prod, t);
+    p_upow(&prod, k);
+    return p_expect(&prod, M, range);
+}
+
+/* tsl, tsr: tangential gradients of the conservative variables of the two cells,
+ * [(dim - 1) x 5] in the face-local frame (tangential axis t, component m at t*5 + m), used
+ * when gas->multi_d; NULL otherwise. */
 static int og_face(const og_gas* gas, const double* Wl, const double* Wr,
-                   const double* sl, const double* sr, const double* Wi, const double* Wi1,
+                   const double* sl, const double* sr, const double* tsl, const double* tsr,
+                   const double* Wi, const double* Wi1,
                    double dxl, double dxr, double kf, double wf, double Sf, double dt,
                    double* F, double* G, double* qout, double* info)
 {
@@ -434,17 +457,34 @@ static int og_face(const og_gas* gas, const double* Wl, const double* Wr,
     for (int m = 0; m < nv; ++m) r[m] = sr[m] / gr.rho;
     if ((st = og_solve_moment_system(gas, &Mr, r, a_r))) return st;
 
+    /* multi-dimensional expansion (the alternative the implementation section mentions):
+       tangential slopes b of each side from its tangential gradients, and of the interface
+       state from the mean of the two, <psi (b.psi)>_g = dW/dy / rho per tangential axis */
+    const int ntan = (gas->multi_d && tsl && tsr) ? dim - 1 : 0;
+    double b_l[2][5], b_r[2][5], b_0[2][5];
+    for (int t = 0; t < ntan; ++t) {
+        for (int m = 0; m < nv; ++m) r[m] = tsl[t * 5 + m] / gl.rho;
+        if ((st = og_solve_moment_system(gas, &Ml, r, b_l[t]))) return st;
+        for (int m = 0; m < nv; ++m) r[m] = tsr[t * 5 + m] / gr.rho;
+        if ((st = og_solve_moment_system(gas, &Mr, r, b_r[t]))) return st;
+        for (int m = 0; m < nv; ++m) r[m] = 0.5 * (tsl[t * 5 + m] + tsr[t * 5 + m]) / g0.rho;
+        if ((st = og_solve_moment_system(gas, &M0, r, b_0[t]))) return st;
+    }
+
     /* time slopes from the compatibility condition at t = 0: <psi (a u + A)>_g = 0 */
+    /* (with the expansion: <psi (a u + b.v_t + A)>_g = 0) */
     p_lin(dim, a_l, &pa);
     for (int m = 0; m < nv; ++m) {
         p_psi(dim, m, &pm); p_mul(&pm, &pa, &prod); p_upow(&prod, 1);
         r[m] = -p_expect(&prod, &Ml, R_ALL);
+        for (int t = 0; t < ntan; ++t) r[m] -= og_tan_moment(dim, b_l[t], t, m, &Ml, R_ALL, 0);
     }
     if ((st = og_solve_moment_system(gas, &Ml, r, A_l))) return st;
     p_lin(dim, a_r, &pa);
     for (int m = 0; m < nv; ++m) {
         p_psi(dim, m, &pm); p_mul(&pm, &pa, &prod); p_upow(&prod, 1);
         r[m] = -p_expect(&prod, &Mr, R_ALL);
+        for (int t = 0; t < ntan; ++t) r[m] -= og_tan_moment(dim, b_r[t], t, m, &Mr, R_ALL, 0);
     }
     if ((st = og_solve_moment_system(gas, &Mr, r, A_r))) return st;
 
@@ -493,13 +533,18 @@ static int og_face(const og_gas* gas, const double* Wl, const double* Wr,
             p_mul(&pm, &q_ar, &prod); p_upow(&prod, 1); x4 += gr.rho * p_expect(&prod, &Mr, R_NEG);
             p_mul(&pm, &q_Al, &prod); x5 = gl.rho * p_expect(&prod, &Ml, R_POS);
             p_mul(&pm, &q_Ar, &prod); x5 += gr.rho * p_expect(&prod, &Mr, R_NEG);
+            for (int t = 0; t < ntan; ++t) {      /* the tangential slopes enter like the normal ones */
+                x1 += og_tan_moment(dim, b_0[t], t, m, &M0, R_ALL, 0);
+                x4 += gl.rho * og_tan_moment(dim, b_l[t], t, m, &Ml, R_POS, 0);
+                x4 += gr.rho * og_tan_moment(dim, b_r[t], t, m, &Mr, R_NEG, 0);
+            }
             r[m] = (kw.c1 * g0.rho * x1 + kw.c4 * x4 + kw.c5 * x5) / g0.rho;
         }
         if ((st = og_solve_moment_system(gas, &M0, r, Ab))) return st;
     }
 
     /* time-integrated distribution at the interface, term by term (Eq. resultingf) */
-    static __thread og_term terms[10];
+    static __thread og_term terms[16];
     int nt = 0;
 #define ADD_TERM(W_, WH_, R_, POLYSET_) do { terms[nt].w = (W_); terms[nt].which = (WH_); \
         terms[nt].range = (R_); POLYSET_; ++nt; } while (0)
@@ -513,6 +558,11 @@ static int og_face(const og_gas* gas, const double* Wl, const double* Wr,
     ADD_TERM(gr.rho * kw.g[3], 2, R_NEG, p_const(&terms[nt].poly, 1.0));
     ADD_TERM(gr.rho * kw.g[4], 2, R_NEG, (p_lin(dim, a_r, &terms[nt].poly), p_upow(&terms[nt].poly, 1)));
     ADD_TERM(gr.rho * kw.g[5], 2, R_NEG, p_lin(dim, A_r, &terms[nt].poly));
+    for (int t = 0; t < ntan; ++t) {   /* tangential slopes: as the normal ones, v_t in place of u */
+        ADD_TERM(g0.rho * kw.g[1], 0, R_ALL, (p_lin(dim, b_0[t], &terms[nt].poly), p_tpow(&terms[nt].poly, t)));
+        ADD_TERM(gl.rho * kw.g[4], 1, R_POS, (p_lin(dim, b_l[t], &terms[nt].poly), p_tpow(&terms[nt].poly, t)));
+        ADD_TERM(gr.rho * kw.g[4], 2, R_NEG, (p_lin(dim, b_r[t], &terms[nt].poly), p_tpow(&terms[nt].poly, t)));
+    }
 #undef ADD_TERM
     const og_mom* Ms[3] = {&M0, &Ml, &Mr};
 
@@ -576,6 +626,7 @@ typedef struct {
     double gamma, prandtl, mu, c_a, c_mu, cfl, t_end;
     int eps_mode;      /* 0: eps = tau/dt; 1: eps = tau/tau_hat */
     int recon;         /* 0: second-order MUSCL (minmod); 1: third-order MUSCL (limited kappa = 1/3) */
+    int multi_d;       /* 1: multi-dimensional expansion (tangential slopes) */
 } og_case;
 
 typedef struct {
@@ -608,6 +659,8 @@ static int og_grid_init(og_grid* gr, const og_case* c)
     gr->gas.c_a = c->c_a; gr->gas.c_mu = c->c_mu;
     if (c->eps_mode != 0 && c->eps_mode != 1) return OG_ERR_ARG;
     if (c->recon != 0 && c->recon != 1) return OG_ERR_ARG;
+    if (c->multi_d != 0 && c->multi_d != 1) return OG_ERR_ARG;
+    gr->gas.multi_d = c->multi_d;
     gr->gas.eps_mode = c->eps_mode;
     gr->nv = c->dim + 2;
     gr->next = 1;
@@ -890,12 +943,38 @@ static int og_face_at(const og_grid* gr, const double* We, const double* kk, con
     }
     long cl[3] = {fi, fj, fk}, cr[3] = {fi, fj, fk};
     cl[d] -= 1;
+    /* tangential gradients of the two cells (multi-dimensional expansion): minmod of the
+       one-sided differences along each tangential axis on centre distances, from the
+       ghost-filled state (a cell beyond the boundary along the normal takes its ghost
+       neighbours, corners filled axis by axis as everywhere) */
+    double tsl[10] = {0}, tsr[10] = {0};
+    if (gr->gas.multi_d) {
+        for (int t = 1; t < dim; ++t) {
+            const int a = perm[t];
+            for (int side = 0; side < 2; ++side) {
+                const long* c = side ? cr : cl;
+                double* out = side ? tsr : tsl;
+                long cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+                cp[a] += 1; cm[a] -= 1;
+                const long i0 = gidx(gr, c[0], c[1], c[2]);
+                const long ip = gidx(gr, cp[0], cp[1], cp[2]), im = gidx(gr, cm[0], cm[1], cm[2]);
+                const double hp = gr->xc[a][c[a] + 1 + 2] - gr->xc[a][c[a] + 2];
+                const double hm = gr->xc[a][c[a] + 2] - gr->xc[a][c[a] - 1 + 2];
+                for (int m = 0; m < nv; ++m) {
+                    const int src = (m >= 1 && m <= dim) ? 1 + perm[m - 1] : m;
+                    const double dp = (We[src * gr->next + ip] - We[src * gr->next + i0]) / hp;
+                    const double dm = (We[src * gr->next + i0] - We[src * gr->next + im]) / hm;
+                    out[(t - 1) * 5 + m] = og_minmod(dm, dp);
+                }
+            }
+        }
+    }
     long il = og_image_cell(gr, cl[0], cl[1], cl[2]), ir = og_image_cell(gr, cr[0], cr[1], cr[2]);
     double kf = 0.5 * (kk[il] + kk[ir]);
     double wf = 0.5 * (om[il] + om[ir]);
     double Sf = 0.5 * (S[il] + S[ir]);
     double F[5], info[OG_INFO_LEN];
-    int st = og_face(&gr->gas, lWL, lWR, lsL, lsR, lWi, lWi1, xface - xcs[1], xcs[2] - xface,
+    int st = og_face(&gr->gas, lWL, lWR, lsL, lsR, tsl, tsr, lWi, lWi1, xface - xcs[1], xcs[2] - xface,
                      kf, wf, Sf, dt, F, NULL, NULL, eps_out ? info : NULL);
     if (st) return st;
     if (eps_out) *eps_out = info[50];
@@ -1296,9 +1375,11 @@ int og_step_cells(const og_case* c, const double* W, const double* kk, const dou
 }
 
 /* Single interface in the face-local frame.  params: gamma, prandtl, mu, c_a, c_mu, eps_mode.
+ * tsl, tsr: tangential gradients [(dim - 1) x 5] (multi-dimensional expansion) or NULL.
  * F, G: nv values; q: heat flux; info: OG_INFO_LEN values (see og_face). */
 int og_face_flux(int dim, const double* params, const double* Wl, const double* Wr,
-                 const double* sl, const double* sr, const double* Wi, const double* Wi1,
+                 const double* sl, const double* sr, const double* tsl, const double* tsr,
+                 const double* Wi, const double* Wi1,
                  double dxl, double dxr, double kf, double wf, double Sf, double dt,
                  double* F, double* G, double* q, double* info)
 {
@@ -1306,8 +1387,9 @@ int og_face_flux(int dim, const double* params, const double* Wl, const double* 
     if (dim != 2 && dim != 3) return OG_ERR_ARG;
     gas.dim = dim; gas.gamma = params[0]; gas.prandtl = params[1]; gas.mu = params[2];
     gas.c_a = params[3]; gas.c_mu = params[4]; gas.eps_mode = params[5] != 0.0;
+    gas.multi_d = tsl && tsr;
     gas.b = 2.0 / (gas.gamma - 1.0); gas.K = gas.b - dim;
-    return og_face(&gas, Wl, Wr, sl, sr, Wi, Wi1, dxl, dxr, kf, wf, Sf, dt, F, G, q, info);
+    return og_face(&gas, Wl, Wr, sl, sr, tsl, tsr, Wi, Wi1, dxl, dxr, kf, wf, Sf, dt, F, G, q, info);
 }
 
 /* Moments <u^n> (n < OG_NU) of one Maxwellian for the three u ranges; out: 3*OG_NU values. */

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import test_oracle_kw as KW
+import test_oracle_multid as MD
 import test_oracle_muscl3 as M3
 import test_oracle_pins as P
 import test_oracle_tauhat as TH
@@ -27,8 +28,8 @@ MUTANTS = {
     "interface state half lines swapped": (
         "W0[m] = gl.rho * p_expect(&pm, &Ml, R_POS) + gr.rho * p_expect(&pm, &Mr, R_NEG);",
         "W0[m] = gl.rho * p_expect(&pm, &Ml, R_NEG) + gr.rho * p_expect(&pm, &Mr, R_POS);"),
-    "compatibility sign": ("        r[m] = -p_expect(&prod, &Ml, R_ALL);\n    }\n    if ((st = og_solve_moment_system(gas, &Ml, r, A_l))) return st;",
-                           "        r[m] = p_expect(&prod, &Ml, R_ALL);\n    }\n    if ((st = og_solve_moment_system(gas, &Ml, r, A_l))) return st;"),
+    "compatibility sign": ("        r[m] = -p_expect(&prod, &Ml, R_ALL);\n        for (int t = 0; t < ntan; ++t) r[m] -= og_tan_moment(dim, b_l",
+                           "        r[m] = p_expect(&prod, &Ml, R_ALL);\n        for (int t = 0; t < ntan; ++t) r[m] -= og_tan_moment(dim, b_l"),
     "time weight gam1": ("g1 = 2.0 * s - x * (1.0 + E);", "g1 = 2.0 * s - x * (1.0 - E);"),
     "time weight c5 sign": ("k->c5 = -s / g0;", "k->c5 = s / g0;"),
     "turbulent tau without strain": ("tau += (kf / wf) / ((p0 / rho0) * sqrt(1.0 + eta * eta));",
@@ -76,6 +77,16 @@ MUTANTS = {
     "kappa-scheme limiter bound": ("b = (3.0 - kappa) / (1.0 - kappa);", "b = (1.0 + kappa) / (1.0 - kappa);"),
     "third-order right face value from the wrong cell": ("*wr = w[2] - og_muscl3(d2, d1) * (xc[2] - xf);",
                                                           "*wr = w[2] - og_muscl3(d1, d2) * (xc[2] - xf);"),
+    "interface tangential slope from one side": ("r[m] = 0.5 * (tsl[t * 5 + m] + tsr[t * 5 + m]) / g0.rho;",
+                                                 "r[m] = tsl[t * 5 + m] / g0.rho;"),
+    "tangential terms of A with the wrong sign": ("r[m] -= og_tan_moment(dim, b_l[t], t, m, &Ml, R_ALL, 0);",
+                                                  "r[m] += og_tan_moment(dim, b_l[t], t, m, &Ml, R_ALL, 0);"),
+    "tangential Abar term dropped": ("x1 += og_tan_moment(dim, b_0[t], t, m, &M0, R_ALL, 0);",
+                                     "x1 += 0.0 * og_tan_moment(dim, b_0[t], t, m, &M0, R_ALL, 0);"),
+    "tangential flux term on the normal velocity": (
+        "ADD_TERM(g0.rho * kw.g[1], 0, R_ALL, (p_lin(dim, b_0[t], &terms[nt].poly), p_tpow(&terms[nt].poly, t)));",
+        "ADD_TERM(g0.rho * kw.g[1], 0, R_ALL, (p_lin(dim, b_0[t], &terms[nt].poly), p_upow(&terms[nt].poly, 1)));"),
+    "one-sided tangential slope": ("out[(t - 1) * 5 + m] = og_minmod(dm, dp);", "out[(t - 1) * 5 + m] = dp;"),
 }
 
 
@@ -127,6 +138,11 @@ PINS = [
     lambda: [M3.test_quadratic_face_values_are_exact_on_a_uniform_grid(s) for s in range(3)],
     lambda: M3.test_no_new_extrema_on_a_uniform_grid(),
     lambda: M3.test_quadratic_with_slopes_three_times_apart(),
+    lambda: MD.test_continuous_data_full_navier_stokes_flux(2),
+    lambda: MD.test_continuous_data_full_navier_stokes_flux(3),
+    lambda: MD.test_transposed_data_give_the_transposed_solution(),
+    lambda: MD.test_mirror_in_the_tangential_direction(),
+    lambda: MD.test_free_stream_and_conservation_with_the_expansion(),
 ]
 
 
