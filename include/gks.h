@@ -90,6 +90,19 @@ enum { GKS_EPS_DT = 0, GKS_EPS_TAUHAT = 1 };
  *          (third-order face values on uniform grids, no new extrema). */
 enum { GKS_RECON_MUSCL2 = 0, GKS_RECON_MUSCL3 = 1 };
 
+/* Multi-dimensional expansion (multi_d = 1; section "Implementation ...": the distribution
+ * expanded along all axes rather than only along the face normal).  The initial
+ * distribution of each side and the equilibrium also carry tangential slopes b:
+ *  - b of each side from the tangential gradients of its cell (minmod of the one-sided
+ *    differences along each tangential axis on centre distances, from the ghost-filled
+ *    states; a cell beyond a boundary takes its ghost neighbours, corner ghosts being
+ *    filled axis by axis: the later axis' rule on the earlier axis' ghost);
+ *  - b of the interface state from the mean of the two cells' tangential gradients;
+ *  - A from <psi (a u + b.v_t + A)> = 0 and Abar from the time-integrated compatibility
+ *    condition with the b terms; in the flux b.v_t enters beside a u.
+ * Continuous linear data then give the Navier-Stokes flux with the full velocity-gradient
+ * tensor. */
+
 /* Fields for gks_fields. CONS: conservative state (nvar x ncells). PRIM: rho, U, V, [W],
  * p (nvar x ncells). STRAIN: strain-rate magnitude sqrt(2 S_ab S_ab) (ncells). TURB: k
  * then omega (2 x ncells): those of the current state when transported (computed on the
@@ -116,6 +129,8 @@ typedef struct {
     int32_t turb_transport;       /* 1: transport k and omega with the flow; 0: frozen inputs */
     int32_t eps_mode;             /* GKS_EPS_DT or GKS_EPS_TAUHAT */
     int32_t recon;                /* GKS_RECON_MUSCL2 or GKS_RECON_MUSCL3 */
+    int32_t multi_d;              /* 1: multi-dimensional expansion (on its own: with
+                                     turb_transport = 0, GKS_EPS_DT and GKS_RECON_MUSCL2) */
 } gks_config;
 
 typedef struct gks_ctx* gks_handle;
@@ -182,6 +197,9 @@ gks_status gks_face_flops(int32_t dim, int32_t precision, double* flops);
  * viscosity; the mass flux itself is part of gks_face_flops). */
 gks_status gks_kw_face_flops(double* flops);
 
+/* The same count for the flux with the multi-dimensional expansion (multi_d). */
+gks_status gks_face_flops_multid(int32_t dim, double* flops);
+
 /* ---------------------------------------------------------------------------------- */
 /* Batched form: many independent solves (any mix of sizes, dims, precisions) advanced  */
 /* by persistent kernels that walk one device tile table per step.                       */
@@ -198,8 +216,8 @@ gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
  * streams; afterwards every per-handle call on a member first waits for the batch stream.
  * The table lives in dev_workspace.  Handles stay owned by the caller and must outlive
  * the batch.  Members are frozen-field, DT-mode, second-order solves: a handle with
- * turb_transport, GKS_EPS_TAUHAT or GKS_RECON_MUSCL3 is refused (GKS_ERR_ARG), here and in
- * gks_batch_set_members. */
+ * turb_transport, GKS_EPS_TAUHAT, GKS_RECON_MUSCL3 or multi_d is refused (GKS_ERR_ARG),
+ * here and in gks_batch_set_members. */
 gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity,
                             void* dev_workspace, size_t bytes, void* hip_stream, gks_batch* out);
 

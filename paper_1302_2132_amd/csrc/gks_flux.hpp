@@ -170,6 +170,40 @@ GKS_HD inline void tmom(const Mx<R, D>& g, const R* mk, const R* a, R bt, R* T)
     T[D + 1] = half * (P2 + g.q * P0 + mk[0] * X);
 }
 
+// Tv = <u^k v_s psi (a.psi)> for a tangential velocity v_s (s = 1 .. D-1 in the face-local
+// frame), from the same u-moments.  The Maxwellian's v_s-factor obeys v_s g = V_s g +
+// h dg/dV_s, and psi (a.psi) does not depend on V_s, so Tv = V_s T + h dT/dV_s with T from
+// tmom; with e = a_s + a_E V_s (= dc0/dV_s), dP_j/dV_s = e <u^{k+j}>:
+//   dT_rho = e <u^k>, dT_u = e <u^{k+1}>,
+//   dT_t = V_t e <u^k> + [t = s] (P_0 + <u^k> a_E h),
+//   dT_E = (e <u^{k+2}> + 2 V_s P_0 + q e <u^k> + <u^k> 2h (a_s + 2 a_E V_s)) / 2.
+template <typename R, int D>
+GKS_HD inline void tvmom(const Mx<R, D>& g, const R* mk, const R* a, R bt, int s, R* Tv)
+{
+    const R aE = a[D + 1];
+    R aV = R(0);
+    for (int t = 1; t < D; ++t) aV = aV + a[1 + t] * g.U[t];
+    const R half = R(0.5);
+    const R c0 = a[0] + aV + half * aE * g.q;
+    const R P0 = c0 * mk[0] + a[1] * mk[1] + half * aE * mk[2];
+    const R P1 = c0 * mk[1] + a[1] * mk[2] + half * aE * mk[3];
+    const R P2 = c0 * mk[2] + a[1] * mk[3] + half * aE * mk[4];
+    const R X = R(2) * g.h * (aV + aE * g.vt2) + aE * bt * g.h * g.h;
+    const R Vs = g.U[s], h = g.h;
+    const R e = a[1 + s] + aE * Vs;
+    Tv[0] = Vs * P0 + h * e * mk[0];
+    Tv[1] = Vs * P1 + h * e * mk[1];
+    for (int t = 1; t < D; ++t) {
+        const R T = g.U[t] * P0 + mk[0] * (a[1 + t] + aE * g.U[t]) * h;
+        R dT = g.U[t] * e * mk[0];
+        if (t == s) dT = dT + P0 + mk[0] * aE * h;
+        Tv[1 + t] = Vs * T + h * dT;
+    }
+    const R TE = half * (P2 + g.q * P0 + mk[0] * X);
+    const R dTE = half * (e * mk[2] + R(2) * Vs * P0 + g.q * e * mk[0] + mk[0] * R(2) * h * (a[1 + s] + R(2) * aE * Vs));
+    Tv[D + 1] = Vs * TE + h * dTE;
+}
+
 // <u^k psi> (a = unit vector on the density slot)
 template <typename R, int D>
 GKS_HD inline void tmom1(const Mx<R, D>& g, const R* mk, R* T)
@@ -310,8 +344,9 @@ GKS_HD inline Kw<R> kogan_e(R tau, R tau_e, R dt)
 }
 
 // Flux modes (bits): FLUX_TAUHAT evaluates the time weights with eps = tau/tau_hat;
-// FLUX_EPS_OUT also stores eps_hat = tau/tau_hat in F[D + 2] (the caller provides room).
-enum { FLUX_TAUHAT = 1, FLUX_EPS_OUT = 2 };
+// FLUX_EPS_OUT also stores eps_hat = tau/tau_hat in F[D + 2] (the caller provides room);
+// FLUX_MULTID expands the distributions along the tangential axes too (FaceIn::tl, tr).
+enum { FLUX_TAUHAT = 1, FLUX_EPS_OUT = 2, FLUX_MULTID = 4 };
 
 // Inputs of one face in the wide type H (FP64 on the device): reconstructed states,
 // minmod slopes, cell averages of the two neighbours, inverse centre-to-face distances,
@@ -320,6 +355,7 @@ template <int D, typename H = double>
 struct FaceIn {
     H Wl[D + 2], Wr[D + 2], sl[D + 2], sr[D + 2], Wi[D + 2], Wi1[D + 2];
     H idl, idr, kf, wf, Sf, dt;
+    H tl[D - 1][D + 2], tr[D - 1][D + 2];   // tangential gradients of the two cells (FLUX_MULTID)
 };
 
 // Per-solve constants; the reciprocals are formed once on the host.
@@ -503,7 +539,7 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
     }
     const R dt = R(in.dt);
     Kw<R> kw;
-    if (MODE) mode_weights<R, D, H, MODE>(in, tau, W0, U0d, ir0, dt, F, kw);
+    if (MODE & (FLUX_TAUHAT | FLUX_EPS_OUT)) mode_weights<R, D, H, MODE>(in, tau, W0, U0d, ir0, dt, F, kw);
     else kw = kogan(R(tau), dt);
 
     // Rv accumulates rho0 <psi Abar.psi>_g0 from the time-integrated compatibility condition:
@@ -540,12 +576,28 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         for (int m = 0; m < NV; ++m) Rv[m] = kw.c1 * g0.rho * (T1[m] + T3[m]);
         tmom(g0, m0n + 2, ab, bt, T3);
         for (int m = 0; m < NV; ++m) F[m] = g0.rho * kw.g[1] * (T2[m] + T3[m]);
+        if constexpr ((MODE & FLUX_MULTID) != 0) {
+            // tangential slopes of the interface state, from the mean tangential gradients:
+            // b_bar v_t enters like abar u, over all u
+            R m0f[7];
+            for (int n = 0; n < 7; ++n) m0f[n] = m0p[n] + m0n[n];
+            for (int s = 1; s < D; ++s) {
+                for (int m = 0; m < NV; ++m) r[m] = R(H(0.5) * (in.tl[s - 1][m] + in.tr[s - 1][m]) * ir0);
+                solve(g0, r, b, inv_b, ab);
+                tvmom(g0, m0f, ab, bt, s, T1);
+                tvmom(g0, m0f + 1, ab, bt, s, T2);
+                for (int m = 0; m < NV; ++m) {
+                    Rv[m] = Rv[m] + kw.c1 * g0.rho * T1[m];
+                    F[m] = F[m] + g0.rho * kw.g[1] * T2[m];
+                }
+            }
+        }
     }
 
     // --- one side of the initial distribution (Eq. initialf0): slopes a from dW/dx,
     //     time coefficients A from the compatibility condition at t = 0, then the
     //     gam3..gam5 flux terms and the c4, c5 terms of Rv -------------------------
-    auto side = [&](const Mx<R, D>& g, const R* m01, const H* slope, H irho) {
+    auto side = [&](const Mx<R, D>& g, const R* m01, const H* slope, const H (*tslope)[D + 2], H irho) {
         R r[NV], a[NV], A[NV], T[NV], mf[8], mh[8];
         const R ir = R(irho);
         for (int m = 0; m < NV; ++m) r[m] = R(slope[m]) * ir;
@@ -554,26 +606,60 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         mf[1] = g.U[0];
         urec(mf, g.U[0], g.h, 5);
         tmom(g, mf + 1, a, bt, T);                     // <u psi (a.psi)> over all u
-        for (int m = 0; m < NV; ++m) T[m] = -T[m];
-        solve(g, T, b, inv_b, A);
-        mh[0] = m01[0];
-        mh[1] = m01[1];
-        urec(mh, g.U[0], g.h, 6);
-        const R rg = g.rho;
-        R acc[NV];
-        tmom1(g, mh + 1, T);
-        for (int m = 0; m < NV; ++m) acc[m] = kw.g[3] * T[m];
-        tmom(g, mh + 2, a, bt, T);
-        for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[4] * T[m];
-        tmom(g, mh + 1, A, bt, T);
-        for (int m = 0; m < NV; ++m) F[m] = F[m] + rg * (acc[m] + kw.g[5] * T[m]);
-        tmom(g, mh + 1, a, bt, T);
-        for (int m = 0; m < NV; ++m) acc[m] = kw.c4 * T[m];
-        tmom(g, mh, A, bt, T);
-        for (int m = 0; m < NV; ++m) Rv[m] = Rv[m] + rg * (acc[m] + kw.c5 * T[m]);
+        if constexpr ((MODE & FLUX_MULTID) != 0) {
+            // tangential slopes b_s: <psi (a u + b.v_t + A)> = 0 over all u, and the flux and
+            // compatibility terms of b v_t beside those of a u (half line)
+            mh[0] = m01[0];
+            mh[1] = m01[1];
+            urec(mh, g.U[0], g.h, 6);
+            R bs[NV], Tv[NV], acc[NV], tacc[NV];
+            for (int m = 0; m < NV; ++m) { acc[m] = R(0); tacc[m] = R(0); }
+            for (int s = 1; s < D; ++s) {
+                for (int m = 0; m < NV; ++m) r[m] = R(tslope[s - 1][m]) * ir;
+                solve(g, r, b, inv_b, bs);
+                tvmom(g, mf, bs, bt, s, Tv);
+                for (int m = 0; m < NV; ++m) T[m] = T[m] + Tv[m];
+                tvmom(g, mh + 1, bs, bt, s, Tv);
+                for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[4] * Tv[m];
+                tvmom(g, mh, bs, bt, s, Tv);
+                for (int m = 0; m < NV; ++m) tacc[m] = tacc[m] + kw.c4 * Tv[m];
+            }
+            for (int m = 0; m < NV; ++m) T[m] = -T[m];
+            solve(g, T, b, inv_b, A);
+            const R rg = g.rho;
+            tmom1(g, mh + 1, T);
+            for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[3] * T[m];
+            tmom(g, mh + 2, a, bt, T);
+            for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[4] * T[m];
+            tmom(g, mh + 1, A, bt, T);
+            for (int m = 0; m < NV; ++m) F[m] = F[m] + rg * (acc[m] + kw.g[5] * T[m]);
+            tmom(g, mh + 1, a, bt, T);
+            for (int m = 0; m < NV; ++m) tacc[m] = tacc[m] + kw.c4 * T[m];
+            tmom(g, mh, A, bt, T);
+            for (int m = 0; m < NV; ++m) Rv[m] = Rv[m] + rg * (tacc[m] + kw.c5 * T[m]);
+        } else {
+            (void)tslope;
+            for (int m = 0; m < NV; ++m) T[m] = -T[m];
+            solve(g, T, b, inv_b, A);
+            mh[0] = m01[0];
+            mh[1] = m01[1];
+            urec(mh, g.U[0], g.h, 6);
+            const R rg = g.rho;
+            R acc[NV];
+            tmom1(g, mh + 1, T);
+            for (int m = 0; m < NV; ++m) acc[m] = kw.g[3] * T[m];
+            tmom(g, mh + 2, a, bt, T);
+            for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[4] * T[m];
+            tmom(g, mh + 1, A, bt, T);
+            for (int m = 0; m < NV; ++m) F[m] = F[m] + rg * (acc[m] + kw.g[5] * T[m]);
+            tmom(g, mh + 1, a, bt, T);
+            for (int m = 0; m < NV; ++m) acc[m] = kw.c4 * T[m];
+            tmom(g, mh, A, bt, T);
+            for (int m = 0; m < NV; ++m) Rv[m] = Rv[m] + rg * (acc[m] + kw.c5 * T[m]);
+        }
     };
-    side(gl, ml01, in.sl, irl);
-    side(gr, mr01, in.sr, irr);
+    side(gl, ml01, in.sl, in.tl, irl);
+    side(gr, mr01, in.sr, in.tr, irr);
 
     // --- Abar, then the gam0 and gam2 equilibrium terms ------------------------------
     {
@@ -601,7 +687,7 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         R dtq = dt;
 #ifdef __HIP_DEVICE_COMPILE__
         // in the flux modes the weights' dt/2 would otherwise be kept from there to here
-        if (MODE) asm volatile("" : "+v"(dtq));
+        if (MODE & (FLUX_TAUHAT | FLUX_EPS_OUT)) asm volatile("" : "+v"(dtq));
 #endif
         const R hdt2 = half * dtq * dtq;
         for (int m = 0; m < NV; ++m) Gv[m] = dt * W0[m] + hdt2 * Rv[m];

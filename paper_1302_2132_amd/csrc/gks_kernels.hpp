@@ -23,7 +23,9 @@
 //         rho k and rho omega, and the update advances them with point-implicit sinks;
 //   V_TH  the degree of rarefaction measured against the resolved time scale tau_hat
 //         (face_flux with FLUX_TAUHAT);
-//   V_R3  third-order MUSCL face values (reconstruct<.., true>).
+//   V_R3  third-order MUSCL face values (reconstruct<.., true>);
+//   V_MD  the multi-dimensional expansion (face_flux with FLUX_MULTID): tangential
+//         gradients of the two cells of every face enter the flux (on its own only).
 // V = 0 is the plain scheme, untouched by the others.
 //
 // The table, the solve descriptors and (outside k_finish) the step state are read
@@ -150,6 +152,52 @@ __device__ inline int image_cell(cref<Inst> I, int d, const int* c)
     const int bc0 = I.bc[d][0], bc1 = I.bc[d][1];
     cc[d] = image_index(cc[d] < 0 ? bc0 : bc1, cc[d], I.n[d]);
     return cell_index(I, cc[0], cc[1], cc[2]);
+}
+
+// State of a cell that may be a ghost along two axes (a corner cell: a tangential
+// neighbour of a cell beyond the boundary).  Ghost layers are filled axis by axis: the
+// later axis' rule applies to the earlier axis' ghost at the later axis' image (a fixed
+// profile indexed by the cell's position clamped into the boundary plane).
+template <int D>
+__device__ inline void load_state_c(cref<Inst> I, const double* __restrict__ W, const int* c, double* w)
+{
+    constexpr int NV = D + 2;
+    int ga = -1, gb = -1;
+    for (int d = 0; d < D; ++d)
+        if (c[d] < 0 || c[d] >= I.n[d]) {
+            if (ga < 0) ga = d;
+            else gb = d;
+        }
+    if (gb < 0) {
+        load_state<D>(I, W, ga < 0 ? 0 : ga, c, w);
+        return;
+    }
+    const bool hi = c[gb] >= I.n[gb];
+    const int bc = I.bc[gb][hi ? 1 : 0];
+    int ci[3] = {c[0], c[1], D == 3 ? c[2] : 0};
+    ci[gb] = image_index(bc, c[gb], I.n[gb]);
+    load_state<D>(I, W, ga, ci, w);
+    if (bc == BC_WALL) {
+        for (int m = 1; m <= D; ++m) w[m] = -w[m];
+    } else if (bc == BC_DIRICHLET) {
+        for (int m = 0; m < NV; ++m) w[m] = I.bcd[gb][hi ? 1 : 0][m];
+    } else if (bc == BC_PROFILE) {
+        int t = 0, stride = 1;
+        for (int a = 0; a < D; ++a) {
+            if (a == gb) continue;
+            t += min(max(c[a], 0), I.n[a] - 1) * stride;
+            stride *= I.n[a];
+        }
+        for (int m = 0; m < NV; ++m) w[m] = I.bcd[gb][hi ? 1 : 0][(long long)m * I.ntan[gb] + t];
+    }
+}
+
+// Tangential gradient of one component of a cell from its neighbours along that axis
+// (multi-dimensional expansion): minmod of the one-sided differences on centre distances
+// (icm, icp: inverse distances to the lower and upper neighbour).
+__device__ inline double tgrad(double wm, double w0, double wp, double icm, double icp)
+{
+    return minmod((w0 - wm) * icm, (wp - w0) * icp);
 }
 
 // --------------------------------------------------------------------------------------
@@ -288,11 +336,15 @@ __device__ inline void kw_face(cref<Inst> I, double frho, double kl, double kr, 
 // order.  Returns nonzero for a non-physical state.  The axis is a template parameter so
 // that every index and the rotation to the face-local frame are compile-time (no private
 // arrays).
-enum { V_KW = 1, V_TH = 2, V_R3 = 4 };
+enum { V_KW = 1, V_TH = 2, V_R3 = 4, V_MD = 8 };
 
+// tg_l, tg_r: with FLUX_MULTID, the tangential gradients of the two cells, [(D-1) x (D+2)]
+// in the global component order, tangential axes in increasing order.
 template <typename R, int D, int DIR, int MODE, bool R3, typename P>
 __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int i, const double (*Wc)[D + 2],
-                                                               P kk, P ww, P ss, int il, int ir, double dt, R* Fg)
+                                                               P kk, P ww, P ss, int il, int ir, double dt, R* Fg,
+                                                               const double* tg_l = nullptr,
+                                                               const double* tg_r = nullptr)
 {
     constexpr int NV = D + 2;
     FaceGeo<double> geo;
@@ -324,6 +376,14 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
             v[q][2] = t1;
             if (D == 3) v[q][3] = t2;
         }
+    }
+    if constexpr ((MODE & FLUX_MULTID) != 0) {
+        for (int s = 0; s < D - 1; ++s)
+            for (int m = 0; m < NV; ++m) {
+                const int src = (m == 1) ? 1 + DIR : (m == 2 ? 1 + P1 : (m == 3 && D == 3 ? 1 + P2 : m));
+                in.tl[s][m] = tg_l[s * NV + src];
+                in.tr[s][m] = tg_r[s * NV + src];
+            }
     }
     in.kf = 0.5 * (kk[il] + kk[ir]);
     in.wf = 0.5 * (ww[il] + ww[ir]);
@@ -387,8 +447,28 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
     const double* ww = I.om;
     const double* ss = I.S;
     const double dt = state_of(I).dt;
-    if (face_eval<R, D, DIR, (V & V_TH) ? FLUX_TAUHAT : 0, (V & V_R3) != 0>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt,
-                                                                           F))
+    constexpr int FMODE = ((V & V_TH) ? FLUX_TAUHAT : 0) | ((V & V_MD) ? FLUX_MULTID : 0);
+    double tg[2][(D - 1) * NV];
+    if constexpr ((V & V_MD) != 0) {
+        // tangential gradients of the two cells from their neighbours along each
+        // tangential axis (ghosts, corners included, from the boundary conditions)
+        for (int side = 0; side < 2; ++side) {
+            int cc[3] = {fc[0], fc[1], fc[2]};
+            cc[DIR] -= 1 - side;
+            for (int s = 0; s < D - 1; ++s) {
+                const int a = s == 0 ? (DIR == 0 ? 1 : 0) : (DIR == 2 ? 1 : 2);
+                int cp[3] = {cc[0], cc[1], cc[2]}, cm[3] = {cc[0], cc[1], cc[2]};
+                cp[a] += 1;
+                cm[a] -= 1;
+                double wp[NV], wm[NV];
+                load_state_c<D>(I, W, cp, wp);
+                load_state_c<D>(I, W, cm, wm);
+                const double icm = I.icd[a][cc[a] - 1], icp = I.icd[a][cc[a]];
+                for (int m = 0; m < NV; ++m) tg[side][s * NV + m] = tgrad(wm[m], Wc[1 + side][m], wp[m], icm, icp);
+            }
+        }
+    }
+    if (face_eval<R, D, DIR, FMODE, (V & V_R3) != 0>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt, F, tg[0], tg[1]))
         atomicOr(&I.st->err, 1);
     R* __restrict__ out = (R*)I.F[DIR];
     const long long nf = I.nface[DIR];   // 64-bit: component offsets m * nf may pass 2^31
@@ -426,11 +506,14 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
 #endif
 // Register budget of the face kernel (instantiated for 3D; 2D steps use k_tile2): at least
 // this many waves per SIMD (2 leaves 256 VGPRs per lane for the 3D FP64 flux, 4 leaves 128
-// for the FP32 flux; the third-order reconstruction takes the FP32 form to 3, 168 VGPRs).
+// for the FP32 flux; the third-order reconstruction takes the FP32 form to 3, 168 VGPRs,
+// the multi-dimensional expansion to 2; its FP64 form keeps 2 with a spill of a few
+// values per face, as its tangential gradients stay live through the flux).
 // TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
 template <typename R, int D, int TILE, int V>
 __global__ __launch_bounds__(TILE)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & V_R3) ? 1 : 0) : GKS_FACE_WAVES_FP64)))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & V_MD) ? 2 : ((V & V_R3) ? 1 : 0))
+                                                   : GKS_FACE_WAVES_FP64)))
 void k_face(const void* __restrict__ table, int cap, int cls)
 {
     const TabC tv(table, cap);
@@ -611,11 +694,13 @@ static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_TH
 
 template <typename R, int V>
 __global__ __launch_bounds__(T2_THREADS)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 : GKS_TILE2_WAVES_FP64)))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & V_MD) ? 1 : 0)
+                                                   : GKS_TILE2_WAVES_FP64 - ((V & V_MD) ? 1 : 0))))
 void k_tile2(const void* __restrict__ table, int cap, int cls)
 {
     constexpr bool KW = V & V_KW;
-    constexpr int FMODE = (V & V_TH) ? FLUX_TAUHAT : 0;
+    constexpr bool MD = V & V_MD;
+    constexpr int FMODE = ((V & V_TH) ? FLUX_TAUHAT : 0) | (MD ? FLUX_MULTID : 0);
     constexpr bool R3 = V & V_R3;
     constexpr int NV = 4;
     constexpr int NX = NV + (KW ? 2 : 0);     // with transport: fluxes of rho k, rho omega too
@@ -651,15 +736,22 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
         const double dt = state_of(I).dt;
 
         // stage the state window: tile rows with the x halo, tile columns with the y halo
+        // (with the multi-dimensional expansion also the four diagonal neighbours of the
+        // tile's corner cells, for the tangential gradients of the edge faces' cells)
         for (int e = tid; e < T2_WX * T2_WY; e += T2_THREADS) {
             const int a = e % T2_WX, b = e / T2_WX;
             const bool row = b >= 2 && b < ty + 2 && a < tx + 4;
             const bool col = a >= 2 && a < tx + 2 && b < ty + 4;
-            if (!(row || col)) continue;
+            const bool corner = MD && (a == 1 || a == tx + 2) && (b == 1 || b == ty + 2);
+            if (!(row || col || corner)) continue;
             const int c[3] = {x0 - 2 + a, y0 - 2 + b, 0};
-            const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;     // the ghost axis, if any
             double w[NV];
-            load_state<2>(I, W, d, c, w);
+            if (corner) {
+                load_state_c<2>(I, W, c, w);
+            } else {
+                const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;     // the ghost axis, if any
+                load_state<2>(I, W, d, c, w);
+            }
 #pragma unroll
             for (int m = 0; m < NV; ++m) sW[m][e] = w[m];
         }
@@ -688,8 +780,19 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
 #pragma unroll
                     for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + 2) * T2_WX + i + o];
                 const int kl = (j + 1) * T2_KX + i;
+                double tg[2][NV];
+                if constexpr (MD) {      // y gradients of the two cells of the x-face
+                    const double icm = I.icd[1][y0 + j - 1], icp = I.icd[1][y0 + j];
+                    for (int side = 0; side < 2; ++side) {
+                        const int e0 = (j + 2) * T2_WX + i + 1 + side;
+#pragma unroll
+                        for (int m = 0; m < NV; ++m)
+                            tg[side][m] = tgrad(sW[m][e0 - T2_WX], sW[m][e0], sW[m][e0 + T2_WX], icm, icp);
+                    }
+                }
                 R F[NV];
-                if (face_eval<R, 2, 0, FMODE, R3>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F))
+                if (face_eval<R, 2, 0, FMODE, R3>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F,
+                                                  tg[0], tg[1]))
                     atomicOr(&I.st->err, 1);
                 sFx[0][tid] = F[0];
                 sFx[1][tid] = F[1];
@@ -716,9 +819,18 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
 #pragma unroll
                     for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + o) * T2_WX + i + 2];
                 const int kl = j * T2_KX + i + 1;
+                double tg[2][NV];
+                if constexpr (MD) {      // x gradients of the two cells of the y-face
+                    const double icm = I.icd[0][x0 + i - 1], icp = I.icd[0][x0 + i];
+                    for (int side = 0; side < 2; ++side) {
+                        const int e0 = (j + 1 + side) * T2_WX + i + 2;
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) tg[side][m] = tgrad(sW[m][e0 - 1], sW[m][e0], sW[m][e0 + 1], icm, icp);
+                    }
+                }
                 R F[NV];
                 if (face_eval<R, 2, 1, FMODE, R3>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt,
-                                                  F))
+                                                  F, tg[0], tg[1]))
                     atomicOr(&I.st->err, 1);
                 sFy[0][tid] = F[0];
                 sFy[1][tid] = F[1];
@@ -1085,6 +1197,7 @@ __global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, i
 GKS_TILE2(0) GKS_TILE2(1) GKS_TILE2(2) GKS_TILE2(3) GKS_TILE2(4) GKS_TILE2(5) GKS_TILE2(6) GKS_TILE2(7)
 GKS_FACE(64, 0) GKS_FACE(128, 0) GKS_FACE(256, 0)
 GKS_FACE(64, 1) GKS_FACE(64, 2) GKS_FACE(64, 3) GKS_FACE(64, 4) GKS_FACE(64, 5) GKS_FACE(64, 6) GKS_FACE(64, 7)
+GKS_TILE2(8) GKS_FACE(64, 8)
 #undef GKS_TILE2
 #undef GKS_FACE
 template __global__ void k_eps<0>(const void*, int, double*);

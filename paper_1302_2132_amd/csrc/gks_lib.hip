@@ -75,6 +75,9 @@ bool config_ok(const gks_config* c, std::string* why)
     if (c->turb_transport != 0 && c->turb_transport != 1) return fail("turb_transport must be 0 or 1");
     if (c->eps_mode != GKS_EPS_DT && c->eps_mode != GKS_EPS_TAUHAT) return fail("unknown eps_mode");
     if (c->recon != GKS_RECON_MUSCL2 && c->recon != GKS_RECON_MUSCL3) return fail("unknown reconstruction");
+    if (c->multi_d != 0 && c->multi_d != 1) return fail("multi_d must be 0 or 1");
+    if (c->multi_d && (c->turb_transport || c->eps_mode != GKS_EPS_DT || c->recon != GKS_RECON_MUSCL2))
+        return fail("the multi-dimensional expansion runs on its own (no transport, tau_hat or third-order MUSCL)");
     return true;
 }
 
@@ -293,8 +296,8 @@ static face_kernel_t face_kernel_t_(int cls)
     default: return k_face<float, 3, T, V>;
     }
 }
-// Face kernel of a class and variant (V_KW | V_TH | V_R3).  Solves in a variant other than
-// 0 run alone with the default tile; batches hold variant 0 only.
+// Face kernel of a class and variant (V_KW | V_TH | V_R3, or V_MD alone).  Solves in a
+// variant other than 0 run alone with the default tile; batches hold variant 0 only.
 static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
 {
     switch (variant) {
@@ -305,6 +308,7 @@ static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
     case 5: return face_kernel_t_<FACE_TILE, 5>(cls);
     case 6: return face_kernel_t_<FACE_TILE, 6>(cls);
     case 7: return face_kernel_t_<FACE_TILE, 7>(cls);
+    case V_MD: return face_kernel_t_<FACE_TILE, V_MD>(cls);
     default: break;
     }
     if (tile == 128) return face_kernel_t_<128, 0>(cls);
@@ -314,7 +318,7 @@ static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
 static int variant_of(const gks_config* c)
 {
     return (c->turb_transport ? V_KW : 0) | (c->eps_mode == GKS_EPS_TAUHAT ? V_TH : 0) |
-           (c->recon == GKS_RECON_MUSCL3 ? V_R3 : 0);
+           (c->recon == GKS_RECON_MUSCL3 ? V_R3 : 0) | (c->multi_d ? V_MD : 0);
 }
 static int face_block(int cls, int tile) { return cls < 2 ? T2_THREADS : tile; }
 static const int kDefaultFaceTiles[NCLS] = {FACE_TILE, FACE_TILE, FACE_TILE, FACE_TILE};
@@ -768,7 +772,8 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
     for (int i = 0; i < count; ++i) {
         if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
         if (variant_of(&hs[i]->cfg))
-            return fail_h(nullptr, GKS_ERR_ARG, "solves with transport, tau_hat or third-order MUSCL step alone");
+            return fail_h(nullptr, GKS_ERR_ARG,
+                          "solves with transport, tau_hat, third-order MUSCL or the multi-dimensional expansion step alone");
     }
     gks_batch b = new gks_batch_ctx();
     b->members.assign(hs, hs + count);
@@ -795,7 +800,8 @@ gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t coun
     for (int i = 0; i < count; ++i) {
         if (!hs[i]) return fail_h(nullptr, GKS_ERR_ARG, "NULL member");
         if (variant_of(&hs[i]->cfg))
-            return fail_h(nullptr, GKS_ERR_ARG, "solves with transport, tau_hat or third-order MUSCL step alone");
+            return fail_h(nullptr, GKS_ERR_ARG,
+                          "solves with transport, tau_hat, third-order MUSCL or the multi-dimensional expansion step alone");
     }
     b->members.assign(hs, hs + count);
     return batch_upload(b);
@@ -953,7 +959,7 @@ inline CR g_rsqrt(CR a) { CR::n += 2; return CR(1.0 / sqrt(a.v)); }   // a squar
 // the erfc evaluation counts as one operation, as a library erfc call would
 inline CR erfc_e(CR ax, CR e) { CR::n += 1; return CR(erfc(ax.v) + 0.0 * e.v); }
 
-template <int D>
+template <int D, int MODE = 0>
 static double count_face()
 {
     constexpr int NV = D + 2;
@@ -980,10 +986,15 @@ static double count_face()
     in.wf = CR(10.0);
     in.Sf = CR(5.0);
     in.dt = CR(3e-3);
+    for (int t = 0; t < D - 1; ++t)              // tangential gradients (multi-dimensional mode)
+        for (int m = 0; m < NV; ++m) {
+            in.tl[t][m] = CR(0.3 * (m + 1) * (t + 1));
+            in.tr[t][m] = CR(-0.2 * (m + 2) * (t + 1));
+        }
     const double b = 2.0 / (gamma - 1.0);
     GasC gas{1e-3, 0.1, b, 2.0 / b, 1.0 / b, 1.0 / 0.09, 1.0 / 0.72 - 1.0};
     CR F[NV];
-    face_flux<CR, D, CR>(in, gas, F);
+    face_flux<CR, D, CR, MODE>(in, gas, F);
     return CR::n;
 }
 
@@ -1003,6 +1014,13 @@ extern "C" gks_status gks_face_flops(int32_t dim, int32_t precision, double* flo
     if (!flops || (dim != 2 && dim != 3) || (precision != GKS_FP64 && precision != GKS_FP32_FLUX))
         return fail_h(nullptr, GKS_ERR_ARG, "bad arguments");
     *flops = dim == 2 ? gks::count_face<2>() : gks::count_face<3>();
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_face_flops_multid(int32_t dim, double* flops)
+{
+    if (!flops || (dim != 2 && dim != 3)) return fail_h(nullptr, GKS_ERR_ARG, "bad arguments");
+    *flops = dim == 2 ? gks::count_face<2, gks::FLUX_MULTID>() : gks::count_face<3, gks::FLUX_MULTID>();
     return GKS_OK;
 }
 

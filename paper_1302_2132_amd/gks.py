@@ -25,6 +25,7 @@ RECON = {"muscl2": 0, "muscl3": 1}
 EXPORTED = (
     "gks_workspace_bytes", "gks_init", "gks_step", "gks_residual", "gks_fields",
     "gks_state_device_ptr", "gks_destroy", "gks_last_error", "gks_face_flops", "gks_kw_face_flops",
+    "gks_face_flops_multid",
     "gks_set_timing", "gks_kernel_times",
     "gks_batch_workspace_bytes", "gks_batch_create", "gks_batch_set_members", "gks_batch_step",
     "gks_batch_capture", "gks_batch_set_launch", "gks_batch_status", "gks_batch_destroy",
@@ -51,6 +52,7 @@ class gks_config(C.Structure):
         ("turb_transport", C.c_int32),
         ("eps_mode", C.c_int32),
         ("recon", C.c_int32),
+        ("multi_d", C.c_int32),
     ]
 
 
@@ -83,6 +85,7 @@ def lib():
         L.gks_last_error.restype = C.c_char_p
         L.gks_face_flops.argtypes = [i32, i32, dp]
         L.gks_kw_face_flops.argtypes = [dp]
+        L.gks_face_flops_multid.argtypes = [i32, dp]
         L.gks_set_timing.argtypes = [vp, i32]
         L.gks_kernel_times.argtypes = [vp, dp, C.POINTER(i64)]
         L.gks_batch_workspace_bytes.argtypes = [i32, sz]
@@ -137,6 +140,7 @@ class _Cfg:
         c.turb_transport = 1 if getattr(case, "kw_transport", False) else 0
         c.eps_mode = EPS_MODE[getattr(case, "eps_mode", "dt")]
         c.recon = RECON[getattr(case, "recon", "muscl2")]
+        c.multi_d = 1 if getattr(case, "multi_d", False) else 0
         self.c = c
 
 
@@ -199,6 +203,12 @@ def gks_last_error(h=None):
 def gks_face_flops(dim, precision="fp64"):
     out = C.c_double(0)
     _check(lib().gks_face_flops(int(dim), PRECISION[precision], C.byref(out)))
+    return out.value
+
+
+def gks_face_flops_multid(dim):
+    out = C.c_double(0)
+    _check(lib().gks_face_flops_multid(int(dim), C.byref(out)))
     return out.value
 
 

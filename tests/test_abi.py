@@ -78,6 +78,9 @@ def test_face_flop_count():
     # field frho * k_up, sigma * nut, mu + ., dt * ., (kr - kl), two products and the
     # difference (8 each)
     assert P.gks_kw_face_flops() == 18.0
+    # the multi-dimensional expansion adds the tangential slopes' solves and moments
+    assert f2 < P.gks_face_flops_multid(2) < P.gks_face_flops_multid(3)
+    assert P.gks_face_flops_multid(3) - f3 > P.gks_face_flops_multid(2) - f2
 
 
 def test_binding_loads_torch_runtime_first():
