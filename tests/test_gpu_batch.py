@@ -79,6 +79,27 @@ def test_batch_membership_change_keeps_graph():
         s.close()
 
 
+def test_two_dimensional_batch_then_a_three_dimensional_member():
+    """Admitting a 3D member into a captured batch of 2D members brings a new launch class
+    (the graph is dropped and the 3D face and update launches join), and every member,
+    old and new, still matches its solve alone, bitwise."""
+    from paper_1302_2132_amd import Batch, Solver
+    a, bcase, ccase = C.mixing_layer(36, seed=3), C.sbli(40, 20, precision="fp32_flux"), C.isotropic_box(8, precision="fp64")
+    ref_a, ref_b, ref_c = _alone(a, 9), _alone(bcase, 9), _alone(ccase, 5)
+    sa, sb, sc = Solver(a), Solver(bcase), Solver(ccase)
+    b = Batch([sa, sb], capacity=4)
+    b.capture()
+    b.step(4)
+    b.set_members([sa, sb, sc])
+    b.step(5)
+    for s, r in ((sa, ref_a), (sb, ref_b), (sc, ref_c)):
+        assert np.array_equal(s.fields("cons"), r[0])
+        assert np.array_equal(s.residual()["res"], r[1]["res"])
+    b.close()
+    for s in (sa, sb, sc):
+        s.close()
+
+
 def test_launch_shapes_do_not_change_results():
     """Every tile size (3D face kernels) and persistent grid gives the same fields, bitwise."""
     from paper_1302_2132_amd import Batch, Solver
