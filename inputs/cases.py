@@ -49,7 +49,7 @@ class Case:
     max_steps: int = 0            # > 0: a solver stops after this many steps
     kw_transport: bool = False    # transport k and omega with the flow (else frozen inputs)
     eps_mode: str = "dt"          # rarefaction in the time weights: "dt" (tau/dt) or "tauhat" (tau/tau_hat)
-    recon: str = "muscl2"         # face values: "muscl2" (minmod) or "muscl3" (limited kappa = 1/3)
+    recon: str = "muscl2"         # face values: "muscl2" (minmod), "muscl3" (limited kappa = 1/3) or "weno5"
     multi_d: bool = False         # expand the distributions along the tangential axes too
     meta: dict = dataclasses.field(default_factory=dict)
 

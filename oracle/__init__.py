@@ -21,7 +21,7 @@ BC_CODE = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 ERRORS = {0: "ok", 1: "bad argument", 2: "nonphysical state"}
 INFO_LEN = 51
 EPS_MODE = {"dt": 0, "tauhat": 1}
-RECON = {"muscl2": 0, "muscl3": 1}
+RECON = {"muscl2": 0, "muscl3": 1, "weno5": 2}
 NU = 12
 
 
@@ -90,6 +90,9 @@ def _bind(L):
     _lib.og_tau_value.restype = C.c_double
     if hasattr(_lib, "og_recon"):
         _lib.og_recon.argtypes = [C.c_int, dp, dp, C.c_double, dp]
+    if hasattr(_lib, "og_weno5_value"):
+        _lib.og_weno5_value.argtypes = [dp]
+        _lib.og_weno5_value.restype = C.c_double
     if hasattr(_lib, "og_kogan_e"):
         _lib.og_kogan_e.argtypes = [C.c_double, C.c_double, C.c_double, dp]
         _lib.og_eps_field.argtypes = [C.c_void_p, dp, dp, dp, dp]
@@ -216,7 +219,8 @@ def strain(case, W=None):
 def ghost_fill(case, W=None):
     b = _Bound(case)
     Wf = _flat(case.W if W is None else W)
-    g = [2 if d < case.dim else 0 for d in range(3)]
+    width = 3 if getattr(case, "recon", "muscl2") == "weno5" else 2
+    g = [width if d < case.dim else 0 for d in range(3)]
     ext = [case.n[d] + 2 * g[d] if d < case.dim else 1 for d in range(3)]
     We = np.zeros(case.nvar * ext[0] * ext[1] * ext[2])
     st = lib().og_ghost_fill(b.ptr, _dp(Wf), _dp(We))
@@ -284,12 +288,25 @@ def kogan(tau, dt):
 
 
 def reconstruct(recon, w, xc, xf):
-    """One component at one face from cells i-1..i+2 (values w, centres xc), face xf:
-    returns (wl, wr, sl, sr)."""
+    """One component at one face between cells i and i+1: values w of cells i-1..i+2
+    (i-2..i+3 for "weno5"), centres xc of cells i-1..i+2, face xf.  Returns (wl, wr, sl, sr)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if w.shape != ((6,) if recon == "weno5" else (4,)):
+        raise ValueError("reconstruct: wrong number of cell values")
     out = np.zeros(4)
-    lib().og_recon(RECON[recon], _dp(np.ascontiguousarray(w, dtype=np.float64)),
-                   _dp(np.ascontiguousarray(xc, dtype=np.float64)), float(xf), _dp(out))
+    st = lib().og_recon(RECON[recon], _dp(w), _dp(np.ascontiguousarray(xc, dtype=np.float64)), float(xf), _dp(out))
+    if st:
+        raise OracleError(st)
     return tuple(out)
+
+
+def weno5(v):
+    """Fifth-order WENO value at the face between the third and fourth of five cell
+    averages v (upwind side first)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    if v.shape != (5,):
+        raise ValueError("weno5: five cell averages")
+    return float(lib().og_weno5_value(_dp(v)))
 
 
 def kogan_e(tau, tau_e, dt):

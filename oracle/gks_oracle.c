@@ -48,6 +48,12 @@
  *    where that product is positive; the sinks beta* omega rho k and beta omega rho omega
  *    point-implicit in the step; a ghost cell's k, omega and, in the face diffusion,
  *    density take their interior image's values.
+ *  - Reconstruction (the paper names second- and third-order TVD/MUSCL and fifth-order
+ *    WENO, with minmod on the variables and their gradients): the gradients are always
+ *    the minmod of the one-sided slopes; the face values come from them, from the limited
+ *    kappa = 1/3 slopes, or from Jiang and Shu's WENO5 applied to the conservative
+ *    variables in index space (uniform-grid coefficients on stretched meshes too), which
+ *    needs three ghost layers and at least three cells per axis.
  */
 #include <math.h>
 #include <stdio.h>
@@ -625,7 +631,8 @@ typedef struct {
     const double* bc_data[3][2];
     double gamma, prandtl, mu, c_a, c_mu, cfl, t_end;
     int eps_mode;      /* 0: eps = tau/dt; 1: eps = tau/tau_hat */
-    int recon;         /* 0: second-order MUSCL (minmod); 1: third-order MUSCL (limited kappa = 1/3) */
+    int recon;         /* 0: second-order MUSCL (minmod); 1: third-order MUSCL (limited kappa = 1/3);
+                          2: fifth-order WENO face values (minmod gradients) */
     int multi_d;       /* 1: multi-dimensional expansion (tangential slopes) */
 } og_case;
 
@@ -633,11 +640,11 @@ typedef struct {
     const og_case* c;
     og_gas gas;
     int nv;
-    long n[3], g[3], e[3];    /* interior cells, ghost width, extended size per axis */
+    long n[3], g[3], e[3];    /* interior cells, ghost width of the state, extended size per axis */
     long next;                /* extended cell count */
-    double* xfe[3];           /* extended face coordinates, index i + g (i from -g .. n+g) */
-    double* xc[3];            /* extended centres, index i + g */
-    double* dx[3];            /* extended widths, index i + g */
+    double* xfe[3];           /* extended face coordinates, index i + 2 (i from -2 .. n+2) */
+    double* xc[3];            /* extended centres, index i + 2 (two ghost layers) */
+    double* dx[3];            /* extended widths, index i + 2 */
 } og_grid;
 
 static long gidx(const og_grid* gr, long i, long j, long k)
@@ -658,7 +665,7 @@ static int og_grid_init(og_grid* gr, const og_case* c)
     gr->gas.gamma = c->gamma; gr->gas.prandtl = c->prandtl; gr->gas.mu = c->mu;
     gr->gas.c_a = c->c_a; gr->gas.c_mu = c->c_mu;
     if (c->eps_mode != 0 && c->eps_mode != 1) return OG_ERR_ARG;
-    if (c->recon != 0 && c->recon != 1) return OG_ERR_ARG;
+    if (c->recon < 0 || c->recon > 2) return OG_ERR_ARG;
     if (c->multi_d != 0 && c->multi_d != 1) return OG_ERR_ARG;
     gr->gas.multi_d = c->multi_d;
     gr->gas.eps_mode = c->eps_mode;
@@ -667,7 +674,9 @@ static int og_grid_init(og_grid* gr, const og_case* c)
     for (int d = 0; d < 3; ++d) {
         gr->n[d] = (d < c->dim) ? c->n[d] : 1;
         if (gr->n[d] < 1) return OG_ERR_ARG;
-        gr->g[d] = (d < c->dim) ? 2 : 0;
+        /* the fifth-order stencil reaches a third cell beyond the boundary */
+        gr->g[d] = (d < c->dim) ? (c->recon == 2 ? 3 : 2) : 0;
+        if (d < c->dim && c->recon == 2 && gr->n[d] < 3) return OG_ERR_ARG;
         gr->e[d] = gr->n[d] + 2 * gr->g[d];
         gr->next *= gr->e[d];
     }
@@ -850,10 +859,39 @@ static double og_muscl3(double away, double toward)
     return 0.5 * (1.0 - kappa) * og_minmod(away, b * toward) + 0.5 * (1.0 + kappa) * og_minmod(toward, b * away);
 }
 
+/* Fifth-order WENO value (Jiang and Shu's weighted ENO, 1996) at the face between cells
+ * c and d of five consecutive cell averages a, b, c, d, e, the upwind side being a..c:
+ * the three third-order candidates of the stencils {a,b,c}, {b,c,d}, {c,d,e}, each the
+ * face value of the parabola with those cell averages, weighted by
+ *   alpha_k = d_k / (eps + beta_k)^2,  (d_0, d_1, d_2) = (1/10, 6/10, 3/10),  eps = 1e-6,
+ * beta_k the smoothness indicator of candidate k: the sum over its first and second
+ * derivatives of dx^(2l-1) times the integral of the squared l-th derivative over cell c.
+ * With all beta_k equal the weights are the linear ones, which combine the candidates
+ * into the fifth-order upwind interpolation.  Index space: the cell widths do not enter. */
+static double og_weno5(double a, double b, double c, double d, double e)
+{
+    const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+    const double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+    const double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+    const double s0 = a - 2.0 * b + c, t0 = a - 4.0 * b + 3.0 * c;
+    const double s1 = b - 2.0 * c + d, t1 = b - d;
+    const double s2 = c - 2.0 * d + e, t2 = 3.0 * c - 4.0 * d + e;
+    const double beta0 = 13.0 / 12.0 * s0 * s0 + 0.25 * t0 * t0;
+    const double beta1 = 13.0 / 12.0 * s1 * s1 + 0.25 * t1 * t1;
+    const double beta2 = 13.0 / 12.0 * s2 * s2 + 0.25 * t2 * t2;
+    const double eps = 1e-6;
+    const double al0 = 0.1 / ((eps + beta0) * (eps + beta0));
+    const double al1 = 0.6 / ((eps + beta1) * (eps + beta1));
+    const double al2 = 0.3 / ((eps + beta2) * (eps + beta2));
+    return (al0 * q0 + al1 * q1 + al2 * q2) / (al0 + al1 + al2);
+}
+
 /* One component along a face normal: cell values w[0..3] (cells i-1, i, i+1, i+2) with
- * centres xc[0..3], face at xf between cells i and i+1.  Gradients sl, sr: minmod of the
- * one-sided slopes on centre distances (both schemes); face values wl, wr from those
- * (recon 0) or from the limited kappa = 1/3 slopes (recon 1). */
+ * centres xc[0..3], face at xf between cells i and i+1; for recon 2 also w[-1] and w[4]
+ * (cells i-2, i+3).  Gradients sl, sr: minmod of the one-sided slopes on centre
+ * distances (every scheme); face values wl, wr from those (recon 0), from the limited
+ * kappa = 1/3 slopes (recon 1), or the fifth-order WENO values of cells i-2 .. i+2 and,
+ * mirrored, i+3 .. i-1 (recon 2). */
 static void og_reconstruct(int recon, const double* w, const double* xc, double xf, double* wl, double* wr,
                            double* sl, double* sr)
 {
@@ -862,7 +900,10 @@ static void og_reconstruct(int recon, const double* w, const double* xc, double 
     const double d2 = (w[3] - w[2]) / (xc[3] - xc[2]);
     *sl = og_minmod(d0, d1);
     *sr = og_minmod(d1, d2);
-    if (recon) {
+    if (recon == 2) {
+        *wl = og_weno5(w[-1], w[0], w[1], w[2], w[3]);
+        *wr = og_weno5(w[4], w[3], w[2], w[1], w[0]);
+    } else if (recon == 1) {
         *wl = w[1] + og_muscl3(d0, d1) * (xf - xc[1]);
         *wr = w[2] - og_muscl3(d2, d1) * (xc[2] - xf);
     } else {
@@ -913,23 +954,28 @@ static int og_face_at(const og_grid* gr, const double* We, const double* kk, con
 {
     const int dim = gr->c->dim, nv = gr->nv;
     long base[3] = {fi, fj, fk};
-    double Wc[4][5];
+    /* cells base-3 .. base+2 along d (the outer two for the fifth-order stencil only) */
+    double Wx[6][5];
     double xcs[4];
-    for (int o = 0; o < 4; ++o) {
+    const int wide = gr->c->recon == 2;
+    for (int o = -1; o < 5; ++o) {
+        if (!wide && (o < 0 || o > 3)) continue;
         long cc[3] = {base[0], base[1], base[2]};
         cc[d] += o - 2;
         long gi = gidx(gr, cc[0], cc[1], cc[2]);
-        for (int m = 0; m < nv; ++m) Wc[o][m] = We[m * gr->next + gi];
-        xcs[o] = gr->xc[d][cc[d] + 2];
+        for (int m = 0; m < nv; ++m) Wx[o + 1][m] = We[m * gr->next + gi];
+        if (o >= 0 && o <= 3) xcs[o] = gr->xc[d][cc[d] + 2];
     }
+    double (*Wc)[5] = Wx + 1;                        /* Wc[o]: cell base-2+o */
     const double xface = gr->xfe[d][base[d] + 2];
     /* minmod slopes of the conservative variables on centre-to-centre distances; the face
        values from them (second order) or from the limited kappa = 1/3 combination of the
        two one-sided slopes (third-order MUSCL) */
     double sL[5], sR[5], WL[5], WR[5];
     for (int m = 0; m < nv; ++m) {
-        const double w[4] = {Wc[0][m], Wc[1][m], Wc[2][m], Wc[3][m]};
-        og_reconstruct(gr->c->recon, w, xcs, xface, &WL[m], &WR[m], &sL[m], &sR[m]);
+        double w[6] = {0.0, Wc[0][m], Wc[1][m], Wc[2][m], Wc[3][m], 0.0};
+        if (wide) { w[0] = Wx[0][m]; w[5] = Wx[5][m]; }
+        og_reconstruct(gr->c->recon, w + 1, xcs, xface, &WL[m], &WR[m], &sL[m], &sR[m]);
     }
     /* rotate to the face-local frame: normal first, then remaining axes in order */
     int perm[3];
@@ -1414,12 +1460,18 @@ int og_kogan(double tau, double dt, double* out)
     return OG_OK;
 }
 
-/* Reconstruction of one component at one face (og_reconstruct): out = wl, wr, sl, sr. */
+/* Reconstruction of one component at one face (og_reconstruct): out = wl, wr, sl, sr.
+ * w holds cells i-1 .. i+2 (recon 0, 1) or i-2 .. i+3 (recon 2); xc the centres of cells
+ * i-1 .. i+2. */
 int og_recon(int recon, const double* w, const double* xc, double xf, double* out)
 {
-    og_reconstruct(recon, w, xc, xf, &out[0], &out[1], &out[2], &out[3]);
+    if (recon < 0 || recon > 2) return OG_ERR_ARG;
+    og_reconstruct(recon, recon == 2 ? w + 1 : w, xc, xf, &out[0], &out[1], &out[2], &out[3]);
     return OG_OK;
 }
+
+/* Fifth-order WENO face value of five cell averages (og_weno5). */
+double og_weno5_value(const double* v) { return og_weno5(v[0], v[1], v[2], v[3], v[4]); }
 
 /* gam0..gam5, c1, c4, c5 with the exponential decay time tau_e (og_time_weights). */
 int og_kogan_e(double tau, double tau_e, double dt, double* out)

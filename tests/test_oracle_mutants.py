@@ -16,6 +16,7 @@ import test_oracle_multid as MD
 import test_oracle_muscl3 as M3
 import test_oracle_pins as P
 import test_oracle_tauhat as TH
+import test_oracle_weno5 as W5
 
 SRC = oracle.SRC
 
@@ -87,6 +88,17 @@ MUTANTS = {
         "ADD_TERM(g0.rho * kw.g[1], 0, R_ALL, (p_lin(dim, b_0[t], &terms[nt].poly), p_tpow(&terms[nt].poly, t)));",
         "ADD_TERM(g0.rho * kw.g[1], 0, R_ALL, (p_lin(dim, b_0[t], &terms[nt].poly), p_upow(&terms[nt].poly, 1)));"),
     "one-sided tangential slope": ("out[(t - 1) * 5 + m] = og_minmod(dm, dp);", "out[(t - 1) * 5 + m] = dp;"),
+    "WENO candidate coefficient": ("const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;",
+                                   "const double q0 = (2.0 * a - 7.0 * b + 10.0 * c) / 6.0;"),
+    "WENO linear weight": ("const double al0 = 0.1 / ((eps + beta0) * (eps + beta0));",
+                           "const double al0 = 0.3 / ((eps + beta0) * (eps + beta0));"),
+    "WENO smoothness coefficient": ("const double beta1 = 13.0 / 12.0 * s1 * s1 + 0.25 * t1 * t1;",
+                                    "const double beta1 = 13.0 / 12.0 * s1 * s1 + 0.5 * t1 * t1;"),
+    "WENO weight exponent": ("const double al2 = 0.3 / ((eps + beta2) * (eps + beta2));",
+                             "const double al2 = 0.3 / (eps + beta2);"),
+    "WENO epsilon": ("const double eps = 1e-6;", "const double eps = 1e-40;"),
+    "WENO right value not mirrored": ("*wr = og_weno5(w[4], w[3], w[2], w[1], w[0]);",
+                                      "*wr = og_weno5(w[-1], w[0], w[1], w[2], w[3]);"),
 }
 
 
@@ -143,6 +155,10 @@ PINS = [
     lambda: MD.test_transposed_data_give_the_transposed_solution(),
     lambda: MD.test_mirror_in_the_tangential_direction(),
     lambda: MD.test_free_stream_and_conservation_with_the_expansion(),
+    lambda: W5.test_quadratics_are_exact(0),
+    lambda: W5.test_closed_forms_match_the_definition(1.0),
+    lambda: W5.test_epsilon_matters_for_nearly_linear_data(),
+    lambda: W5.test_mirror_and_minmod_gradients(),
 ]
 
 
