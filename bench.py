@@ -8,7 +8,8 @@ step, strain rate, every face flux, conservative update, residual).  The FP64 fo
 the headline `value`; the FP32-flux form (flux arithmetic in FP32, everything else FP64)
 is reported beside it with its error against the FP64 run, and so is the same workload
 with k and omega transported by the k-omega equations instead of frozen, with
-third-order MUSCL face values, and with the multi-dimensional expansion.  The degree of
+third-order MUSCL face values, with fifth-order WENO face values, and with the
+multi-dimensional expansion.  The degree of
 rarefaction eps_hat = tau/tau_hat (the turbulent Knudsen number) of the SBLI run is
 reported as a diagnostic; the mode that puts eps_hat into the time weights is measured on a
 1024^2 mixing layer (it does not stay physical on the SBLI mesh with an explicit global
@@ -89,9 +90,11 @@ def _roofline(case, leg, steps, flops_face, peak):
     achieved = flops_face * faces / face_s / 1e12
     r = "float" if case.precision == "fp32_flux" else "double"
     # variant bits of the face kernels: 1 k-omega transport, 2 tau_hat, 4 third-order MUSCL,
-    # 8 multi-dimensional expansion
+    # 8 multi-dimensional expansion, 16 WENO5 face values
+    recon = getattr(case, "recon", "muscl2")
     v = ((1 if getattr(case, "kw_transport", False) else 0) | (2 if getattr(case, "eps_mode", "dt") == "tauhat" else 0)
-         | (4 if getattr(case, "recon", "muscl2") == "muscl3" else 0) | (8 if getattr(case, "multi_d", False) else 0))
+         | (4 if recon == "muscl3" else 0) | (8 if getattr(case, "multi_d", False) else 0)
+         | (16 if recon == "weno5" else 0))
     kernel = f"k_tile2<{r},{v}>" if case.dim == 2 else f"k_face<{r},3,64,{v}>"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": _profiled_traffic(kernel),
@@ -250,6 +253,7 @@ def main():
     ap.add_argument("--no-tauhat", action="store_true", help="skip the tau_hat rarefaction leg")
     ap.add_argument("--no-muscl3", action="store_true", help="skip the third-order MUSCL leg")
     ap.add_argument("--no-multid", action="store_true", help="skip the multi-dimensional expansion leg")
+    ap.add_argument("--no-weno5", action="store_true", help="skip the WENO5 leg")
     ap.add_argument("--serve-full", action="store_true", help="served leg on the full 256-request trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), to calibrate "
@@ -273,7 +277,7 @@ def main():
     import torch
 
     from inputs import cases as C
-    from paper_1302_2132_amd import gks_face_flops, gks_face_flops_multid, gks_kw_face_flops
+    from paper_1302_2132_amd import gks_face_flops, gks_face_flops_multid, gks_face_flops_recon, gks_kw_face_flops
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
 
     case = C.sbli(1024, 512)
@@ -334,8 +338,20 @@ def main():
             "workload": "sbli_1024x512 as above with third-order MUSCL face values (limited kappa = 1/3), FP64",
             "value": v3, "unit": "cell-updates/s", "ms_per_step": leg3["seconds"] * 1e3 / K,
             "vs_muscl2": v3 / value,
-            "roofline": _roofline(c3, leg3, K, flops2d, FP64_PEAK_TFLOPS),
+            "roofline": _roofline(c3, leg3, K, gks_face_flops_recon(2, "muscl3"), FP64_PEAK_TFLOPS),
             "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg3["kernels"].items() if k != "steps"},
+        }
+    if not args.no_weno5:
+        c5 = C.sbli(1024, 512)
+        c5.recon = "weno5"
+        leg5 = _leg(c5, K, Wm)
+        v5 = c5.ncells * K / leg5["seconds"]
+        out["weno5"] = {
+            "workload": "sbli_1024x512 as above with fifth-order WENO face values (index space), FP64",
+            "value": v5, "unit": "cell-updates/s", "ms_per_step": leg5["seconds"] * 1e3 / K,
+            "vs_muscl2": v5 / value,
+            "roofline": _roofline(c5, leg5, K, gks_face_flops_recon(2, "weno5"), FP64_PEAK_TFLOPS),
+            "kernel_ms_per_step": {k: round(v / K, 4) for k, v in leg5["kernels"].items() if k != "steps"},
         }
     if not args.no_multid:
         cmd = C.sbli(1024, 512)

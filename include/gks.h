@@ -81,14 +81,19 @@ enum { GKS_FP64 = 0, GKS_FP32_FLUX = 1 };
 enum { GKS_EPS_DT = 0, GKS_EPS_TAUHAT = 1 };
 
 /* Reconstruction of the face values (section "Implementation ...": second- and
- * third-order TVD/MUSCL with the minmod limiter).  Both use conservative variables and
- * one-sided slopes on centre-to-centre distances; the gradients that set the initial
- * distribution's slopes are the minmod of the two one-sided slopes in both.
+ * third-order TVD/MUSCL with the minmod limiter, and fifth-order WENO).  All use
+ * conservative variables; the gradients that set the initial distribution's slopes are
+ * the minmod of the two one-sided slopes on centre-to-centre distances in every scheme.
  *  MUSCL2  face values from the minmod gradients (second order);
  *  MUSCL3  face values from the limited kappa-scheme with kappa = 1/3: the slope towards a
  *          face is (1/3) minmod(s_away, 4 s_toward) + (2/3) minmod(s_toward, 4 s_away)
- *          (third-order face values on uniform grids, no new extrema). */
-enum { GKS_RECON_MUSCL2 = 0, GKS_RECON_MUSCL3 = 1 };
+ *          (third-order face values on uniform grids, no new extrema);
+ *  WENO5   face values by Jiang and Shu's fifth-order WENO (three-cell candidates of the
+ *          five cells upwind-biased to each side, smoothness-indicator weights with
+ *          eps = 1e-6) in index space, the cell widths not entering; it reads three cells
+ *          on each side of a face, so it needs three ghost layers and at least three cells
+ *          per axis, and runs on its own (turb_transport = 0, GKS_EPS_DT, multi_d = 0). */
+enum { GKS_RECON_MUSCL2 = 0, GKS_RECON_MUSCL3 = 1, GKS_RECON_WENO5 = 2 };
 
 /* Multi-dimensional expansion (multi_d = 1; section "Implementation ...": the distribution
  * expanded along all axes rather than only along the face normal).  The initial
@@ -128,7 +133,7 @@ typedef struct {
     int64_t max_steps;            /* > 0: the solve stops (on the device) after this many steps */
     int32_t turb_transport;       /* 1: transport k and omega with the flow; 0: frozen inputs */
     int32_t eps_mode;             /* GKS_EPS_DT or GKS_EPS_TAUHAT */
-    int32_t recon;                /* GKS_RECON_MUSCL2 or GKS_RECON_MUSCL3 */
+    int32_t recon;                /* GKS_RECON_MUSCL2, GKS_RECON_MUSCL3 or GKS_RECON_WENO5 */
     int32_t multi_d;              /* 1: multi-dimensional expansion (on its own: with
                                      turb_transport = 0, GKS_EPS_DT and GKS_RECON_MUSCL2) */
 } gks_config;
@@ -200,6 +205,10 @@ gks_status gks_kw_face_flops(double* flops);
 /* The same count for the flux with the multi-dimensional expansion (multi_d). */
 gks_status gks_face_flops_multid(int32_t dim, double* flops);
 
+/* The same count (FP64) with the face values of the given reconstruction (GKS_RECON_*);
+ * GKS_RECON_MUSCL2 gives gks_face_flops. */
+gks_status gks_face_flops_recon(int32_t dim, int32_t recon, double* flops);
+
 /* ---------------------------------------------------------------------------------- */
 /* Batched form: many independent solves (any mix of sizes, dims, precisions) advanced  */
 /* by persistent kernels that walk one device tile table per step.                       */
@@ -216,7 +225,7 @@ gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
  * streams; afterwards every per-handle call on a member first waits for the batch stream.
  * The table lives in dev_workspace.  Handles stay owned by the caller and must outlive
  * the batch.  Members are frozen-field, DT-mode, second-order solves: a handle with
- * turb_transport, GKS_EPS_TAUHAT, GKS_RECON_MUSCL3 or multi_d is refused (GKS_ERR_ARG),
+ * turb_transport, GKS_EPS_TAUHAT, GKS_RECON_MUSCL3, GKS_RECON_WENO5 or multi_d is refused (GKS_ERR_ARG),
  * here and in gks_batch_set_members. */
 gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity,
                             void* dev_workspace, size_t bytes, void* hip_stream, gks_batch* out);

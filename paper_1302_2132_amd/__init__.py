@@ -9,6 +9,7 @@ from .gks import (  # noqa: F401
     GKS_OK, GKS_ERR_ARG, GKS_ERR_NONPHYSICAL, GKS_ERR_NOMEM, GKS_ERR_DEVICE, GKS_ERR_STATE,
     GksError, lib, lib_path, config_from_case, gks_workspace_bytes, gks_init, gks_step,
     gks_residual, gks_fields, gks_destroy, gks_last_error, gks_face_flops, gks_kw_face_flops, gks_face_flops_multid,
+    gks_face_flops_recon,
     gks_state_device_ptr,
     gks_set_timing, gks_kernel_times,
     gks_batch_workspace_bytes, gks_batch_create, gks_batch_set_members, gks_batch_step,

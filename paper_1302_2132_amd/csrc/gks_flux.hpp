@@ -392,11 +392,37 @@ GKS_HD inline H muscl3(H away, H toward)
     return (away * toward > H(0)) ? g_copysign(m, toward) : H(0);
 }
 
-// MUSCL reconstruction along the face normal from four cell averages Wc[0..3] (cells
-// i-1, i, i+1, i+2 around face i+1/2), conservative variables, one-sided differences on
-// centre-to-centre distances.  The gradients are their minmod; the face values come from
-// those gradients (second order) or, with R3, from the third-order slopes above.
-template <int D, typename H, bool R3 = false>
+// Fifth-order WENO value (Jiang and Shu) at the face between cells c and d of the five
+// cell averages a..e, upwind side a..c, in index space: third-order candidates q_k of the
+// stencils {a,b,c}, {b,c,d}, {c,d,e}, smoothness indicators beta_k, linear weights
+// (1/10, 6/10, 3/10) and weights d_k/(eps + beta_k)^2 with eps = 1e-6.  With
+// P_k = (eps + beta_k)^2 the weighted mean is written over the common denominator,
+//   (d0 q0 P1 P2 + d1 q1 P0 P2 + d2 q2 P0 P1) / (d0 P1 P2 + d1 P0 P2 + d2 P0 P1),
+// one reciprocal instead of four.
+template <typename H>
+GKS_HD inline H weno5(H a, H b, H c, H d, H e)
+{
+    const H sixth = H(1.0 / 6.0), c13 = H(13.0 / 12.0), qt = H(0.25), eps = H(1e-6);
+    const H q0 = (H(2) * a - H(7) * b + H(11) * c) * sixth;
+    const H q1 = (H(5) * c - b + H(2) * d) * sixth;
+    const H q2 = (H(2) * c + H(5) * d - e) * sixth;
+    const H s0 = a - H(2) * b + c, t0 = a - H(4) * b + H(3) * c;
+    const H s1 = b - H(2) * c + d, t1 = b - d;
+    const H s2 = c - H(2) * d + e, t2 = H(3) * c - H(4) * d + e;
+    const H e0 = eps + (c13 * s0 * s0 + qt * t0 * t0);
+    const H e1 = eps + (c13 * s1 * s1 + qt * t1 * t1);
+    const H e2 = eps + (c13 * s2 * s2 + qt * t2 * t2);
+    const H p0 = e0 * e0, p1 = e1 * e1, p2 = e2 * e2;
+    const H w0 = H(0.1) * (p1 * p2), w1 = H(0.6) * (p0 * p2), w2 = H(0.3) * (p0 * p1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) * g_rcp(w0 + w1 + w2);
+}
+
+// Reconstruction along the face normal from the cell averages Wc[0..3] (cells i-1, i,
+// i+1, i+2 around face i+1/2; with RK = 2 also Wc[-1] and Wc[4], cells i-2 and i+3),
+// conservative variables, one-sided differences on centre-to-centre distances.  The
+// gradients are their minmod; the face values come from those gradients (RK = 0, second
+// order), from the third-order slopes above (RK = 1) or are the WENO5 values (RK = 2).
+template <int D, typename H, int RK = 0>
 GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const FaceGeo<H>& geo, FaceIn<D, H>& in)
 {
     for (int m = 0; m < D + 2; ++m) {
@@ -406,7 +432,10 @@ GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const FaceGeo<H>& geo, Face
         const H sl = minmod(d0, d1), sr = minmod(d1, d2);
         in.sl[m] = sl;
         in.sr[m] = sr;
-        if constexpr (R3) {
+        if constexpr (RK == 2) {
+            in.Wl[m] = weno5(Wc[-1][m], Wc[0][m], Wc[1][m], Wc[2][m], Wc[3][m]);
+            in.Wr[m] = weno5(Wc[4][m], Wc[3][m], Wc[2][m], Wc[1][m], Wc[0][m]);
+        } else if constexpr (RK == 1) {
             in.Wl[m] = Wc[1][m] + muscl3(d0, d1) * geo.dl;
             in.Wr[m] = Wc[2][m] - muscl3(d2, d1) * geo.dr;
         } else {

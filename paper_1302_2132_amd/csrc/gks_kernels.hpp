@@ -23,9 +23,11 @@
 //         rho k and rho omega, and the update advances them with point-implicit sinks;
 //   V_TH  the degree of rarefaction measured against the resolved time scale tau_hat
 //         (face_flux with FLUX_TAUHAT);
-//   V_R3  third-order MUSCL face values (reconstruct<.., true>);
+//   V_R3  third-order MUSCL face values (reconstruct<.., 1>);
 //   V_MD  the multi-dimensional expansion (face_flux with FLUX_MULTID): tangential
-//         gradients of the two cells of every face enter the flux (on its own only).
+//         gradients of the two cells of every face enter the flux (on its own only);
+//   V_W5  fifth-order WENO face values (reconstruct<.., 2>): six stencil cells per face,
+//         three ghost layers (on its own only).
 // V = 0 is the plain scheme, untouched by the others.
 //
 // The table, the solve descriptors and (outside k_finish) the step state are read
@@ -336,11 +338,16 @@ __device__ inline void kw_face(cref<Inst> I, double frho, double kl, double kr, 
 // order.  Returns nonzero for a non-physical state.  The axis is a template parameter so
 // that every index and the rotation to the face-local frame are compile-time (no private
 // arrays).
-enum { V_KW = 1, V_TH = 2, V_R3 = 4, V_MD = 8 };
+enum { V_KW = 1, V_TH = 2, V_R3 = 4, V_MD = 8, V_W5 = 16 };
+
+// reconstruction of a variant (0 second-order MUSCL, 1 third-order MUSCL, 2 WENO5) and the
+// number of stencil cells on each side of a face (three for WENO5, else two)
+template <int V> constexpr int recon_of() { return (V & V_W5) ? 2 : ((V & V_R3) ? 1 : 0); }
+template <int V> constexpr int halo_of() { return (V & V_W5) ? 3 : 2; }
 
 // tg_l, tg_r: with FLUX_MULTID, the tangential gradients of the two cells, [(D-1) x (D+2)]
 // in the global component order, tangential axes in increasing order.
-template <typename R, int D, int DIR, int MODE, bool R3, typename P>
+template <typename R, int D, int DIR, int MODE, int RK, typename P>
 __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int i, const double (*Wc)[D + 2],
                                                                P kk, P ww, P ss, int il, int ir, double dt, R* Fg,
                                                                const double* tg_l = nullptr,
@@ -360,7 +367,7 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
         geo.idr = fg[3];
     }
     FaceIn<D, double> in;
-    reconstruct<D, double, R3>(Wc, geo, in);
+    reconstruct<D, double, RK>(Wc, geo, in);
 
     // face-local frame: normal momentum first, then the remaining axes in order
     constexpr int P1 = DIR == 0 ? 1 : 0;             // first tangential axis
@@ -416,26 +423,29 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
     fc[2] = (D == 3) ? f / (fn0 * fn1) : 0;
     const double* __restrict__ W = I.W[state_of(I).parity];
 
-    // Stencil cells i-2 .. i+1 along DIR (cell i = fc, on the face's high side) and the two
-    // cells sharing the face (il, ir).  When every lane's stencil is interior (a wave-uniform
-    // test) they are indexed directly; otherwise ghosts come from the boundary conditions.
-    double Wc[4][NV];
+    // Stencil cells i-NS .. i+NS-1 along DIR (cell i = fc, on the face's high side; NS = 2,
+    // or 3 for WENO5) and the two cells sharing the face (il, ir).  When every lane's
+    // stencil is interior (a wave-uniform test) they are indexed directly; otherwise ghosts
+    // come from the boundary conditions.  Wc points at cell i-2.
+    constexpr int NS = halo_of<V>();
+    double Wx[2 * NS][NV];
+    const double(*Wc)[NV] = Wx + (NS - 2);
     int il, ir;
-    if (__all(fc[DIR] >= 2 && fc[DIR] <= I.n[DIR] - 2)) {
+    if (__all(fc[DIR] >= NS && fc[DIR] <= I.n[DIR] - NS)) {
         const int st = DIR == 0 ? 1 : (DIR == 1 ? I.n[0] : I.n[0] * I.n[1]);
         const long long nc = I.ncells;
         ir = cell_index(I, fc[0], fc[1], fc[2]);
         il = ir - st;
 #pragma unroll
-        for (int o = 0; o < 4; ++o)
+        for (int o = 0; o < 2 * NS; ++o)
 #pragma unroll
-            for (int m = 0; m < NV; ++m) Wc[o][m] = W[m * nc + ir + (o - 2) * st];
+            for (int m = 0; m < NV; ++m) Wx[o][m] = W[m * nc + ir + (o - NS) * st];
     } else {
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
+        for (int o = 0; o < 2 * NS; ++o) {
             int c[3] = {fc[0], fc[1], fc[2]};
-            c[DIR] += o - 2;
-            load_state<D>(I, W, DIR, c, Wc[o]);
+            c[DIR] += o - NS;
+            load_state<D>(I, W, DIR, c, Wx[o]);
         }
         int cl[3] = {fc[0], fc[1], fc[2]};
         cl[DIR] -= 1;
@@ -468,7 +478,7 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
             }
         }
     }
-    if (face_eval<R, D, DIR, FMODE, (V & V_R3) != 0>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt, F, tg[0], tg[1]))
+    if (face_eval<R, D, DIR, FMODE, recon_of<V>()>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt, F, tg[0], tg[1]))
         atomicOr(&I.st->err, 1);
     R* __restrict__ out = (R*)I.F[DIR];
     const long long nf = I.nface[DIR];   // 64-bit: component offsets m * nf may pass 2^31
@@ -506,13 +516,13 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
 #endif
 // Register budget of the face kernel (instantiated for 3D; 2D steps use k_tile2): at least
 // this many waves per SIMD (2 leaves 256 VGPRs per lane for the 3D FP64 flux, 4 leaves 128
-// for the FP32 flux; the third-order reconstruction takes the FP32 form to 3, 168 VGPRs,
-// the multi-dimensional expansion to 2; its FP64 form keeps 2 with a spill of a few
-// values per face, as its tangential gradients stay live through the flux).
+// for the FP32 flux; the third-order and WENO5 reconstructions take the FP32 form to 3,
+// 168 VGPRs, the multi-dimensional expansion to 2; its FP64 form keeps 2 with a spill of a
+// few values per face, as its tangential gradients stay live through the flux).
 // TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
 template <typename R, int D, int TILE, int V>
 __global__ __launch_bounds__(TILE)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & V_MD) ? 2 : ((V & V_R3) ? 1 : 0))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & V_MD) ? 2 : ((V & (V_R3 | V_W5)) ? 1 : 0))
                                                    : GKS_FACE_WAVES_FP64)))
 void k_face(const void* __restrict__ table, int cap, int cls)
 {
@@ -673,14 +683,14 @@ __device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2
 // fused 2D step: a tile's fluxes computed into LDS, then the tile's update
 // --------------------------------------------------------------------------------------
 // A workgroup of T2_THREADS threads owns a tile of T2X x T2Y cells.  It stages the state
-// of the tile and its two-cell halo (no corners: every stencil is one-dimensional) and k,
+// of the tile and its two-cell halo (three with WENO5; no corners: every stencil is
+// one-dimensional, except the corner cells the multi-dimensional expansion reads) and k,
 // omega, strain rate on a one-cell halo in LDS, synthesising ghosts once; computes the
 // (T2X+1) x T2Y x-faces and T2X x (T2Y+1) y-faces of the tile into LDS (one of each per
 // thread; faces on the tile edge are also computed by the neighbouring tile); then
 // updates its cells from LDS.  Fluxes never go to HBM, and the update needs no launch of
 // its own.  The arithmetic of every face and cell is that of k_face and k_update.
 constexpr int T2X = 16, T2Y = 15, T2_THREADS = 256;
-constexpr int T2_WX = T2X + 4, T2_WY = T2Y + 4;     // state window (two-cell halo)
 constexpr int T2_KX = T2X + 2, T2_KY = T2Y + 2;     // k, omega, strain window (one-cell halo)
 constexpr int T2_NFX = (T2X + 1) * T2Y, T2_NFY = T2X * (T2Y + 1);
 static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_THREADS,
@@ -701,10 +711,12 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
     constexpr bool KW = V & V_KW;
     constexpr bool MD = V & V_MD;
     constexpr int FMODE = ((V & V_TH) ? FLUX_TAUHAT : 0) | (MD ? FLUX_MULTID : 0);
-    constexpr bool R3 = V & V_R3;
+    constexpr int RK = recon_of<V>();
+    constexpr int HW = halo_of<V>();             // halo of the state window (3 for WENO5)
+    constexpr int WX = T2X + 2 * HW, WY = T2Y + 2 * HW;
     constexpr int NV = 4;
     constexpr int NX = NV + (KW ? 2 : 0);     // with transport: fluxes of rho k, rho omega too
-    __shared__ double sW[NV][T2_WX * T2_WY];
+    __shared__ double sW[NV][WX * WY];
     __shared__ double sK[KW ? 4 : 3][T2_KX * T2_KY];   // k, omega, strain rate (, rho k/omega)
     __shared__ R sFx[NX][T2_NFX];
     __shared__ R sFy[NX][T2_NFY];
@@ -738,13 +750,13 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
         // stage the state window: tile rows with the x halo, tile columns with the y halo
         // (with the multi-dimensional expansion also the four diagonal neighbours of the
         // tile's corner cells, for the tangential gradients of the edge faces' cells)
-        for (int e = tid; e < T2_WX * T2_WY; e += T2_THREADS) {
-            const int a = e % T2_WX, b = e / T2_WX;
-            const bool row = b >= 2 && b < ty + 2 && a < tx + 4;
-            const bool col = a >= 2 && a < tx + 2 && b < ty + 4;
-            const bool corner = MD && (a == 1 || a == tx + 2) && (b == 1 || b == ty + 2);
+        for (int e = tid; e < WX * WY; e += T2_THREADS) {
+            const int a = e % WX, b = e / WX;
+            const bool row = b >= HW && b < ty + HW && a < tx + 2 * HW;
+            const bool col = a >= HW && a < tx + HW && b < ty + 2 * HW;
+            const bool corner = MD && (a == HW - 1 || a == tx + HW) && (b == HW - 1 || b == ty + HW);
             if (!(row || col || corner)) continue;
-            const int c[3] = {x0 - 2 + a, y0 - 2 + b, 0};
+            const int c[3] = {x0 - HW + a, y0 - HW + b, 0};
             double w[NV];
             if (corner) {
                 load_state_c<2>(I, W, c, w);
@@ -774,24 +786,25 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
         {   // x-face (i, j): between cells x0+i-1 and x0+i of row y0+j
             const int i = tid % (T2X + 1), j = tid / (T2X + 1);
             if (tid < T2_NFX && i <= tx && j < ty) {
-                double Wc[4][NV];
+                double Wx[2 * HW][NV];               // cells x0+i-HW .. x0+i+HW-1
 #pragma unroll
-                for (int o = 0; o < 4; ++o)
+                for (int o = 0; o < 2 * HW; ++o)
 #pragma unroll
-                    for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + 2) * T2_WX + i + o];
+                    for (int m = 0; m < NV; ++m) Wx[o][m] = sW[m][(j + HW) * WX + i + o];
+                const double(*Wc)[NV] = Wx + (HW - 2);
                 const int kl = (j + 1) * T2_KX + i;
                 double tg[2][NV];
                 if constexpr (MD) {      // y gradients of the two cells of the x-face
                     const double icm = I.icd[1][y0 + j - 1], icp = I.icd[1][y0 + j];
                     for (int side = 0; side < 2; ++side) {
-                        const int e0 = (j + 2) * T2_WX + i + 1 + side;
+                        const int e0 = (j + HW) * WX + i + HW - 1 + side;
 #pragma unroll
                         for (int m = 0; m < NV; ++m)
-                            tg[side][m] = tgrad(sW[m][e0 - T2_WX], sW[m][e0], sW[m][e0 + T2_WX], icm, icp);
+                            tg[side][m] = tgrad(sW[m][e0 - WX], sW[m][e0], sW[m][e0 + WX], icm, icp);
                     }
                 }
                 R F[NV];
-                if (face_eval<R, 2, 0, FMODE, R3>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F,
+                if (face_eval<R, 2, 0, FMODE, RK>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F,
                                                   tg[0], tg[1]))
                     atomicOr(&I.st->err, 1);
                 sFx[0][tid] = F[0];
@@ -813,23 +826,24 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
         {   // y-face (i, j): between cells y0+j-1 and y0+j of column x0+i
             const int i = tid % T2X, j = tid / T2X;
             if (tid < T2_NFY && i < tx && j <= ty) {
-                double Wc[4][NV];
+                double Wx[2 * HW][NV];               // cells y0+j-HW .. y0+j+HW-1
 #pragma unroll
-                for (int o = 0; o < 4; ++o)
+                for (int o = 0; o < 2 * HW; ++o)
 #pragma unroll
-                    for (int m = 0; m < NV; ++m) Wc[o][m] = sW[m][(j + o) * T2_WX + i + 2];
+                    for (int m = 0; m < NV; ++m) Wx[o][m] = sW[m][(j + o) * WX + i + HW];
+                const double(*Wc)[NV] = Wx + (HW - 2);
                 const int kl = j * T2_KX + i + 1;
                 double tg[2][NV];
                 if constexpr (MD) {      // x gradients of the two cells of the y-face
                     const double icm = I.icd[0][x0 + i - 1], icp = I.icd[0][x0 + i];
                     for (int side = 0; side < 2; ++side) {
-                        const int e0 = (j + 1 + side) * T2_WX + i + 2;
+                        const int e0 = (j + HW - 1 + side) * WX + i + HW;
 #pragma unroll
                         for (int m = 0; m < NV; ++m) tg[side][m] = tgrad(sW[m][e0 - 1], sW[m][e0], sW[m][e0 + 1], icm, icp);
                     }
                 }
                 R F[NV];
-                if (face_eval<R, 2, 1, FMODE, R3>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt,
+                if (face_eval<R, 2, 1, FMODE, RK>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt,
                                                   F, tg[0], tg[1]))
                     atomicOr(&I.st->err, 1);
                 sFy[0][tid] = F[0];
@@ -858,7 +872,7 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
             const bool own = tid < T2X * T2Y && i < tx && j < ty;
             const int ii = own ? i : 0, jj = own ? j : 0;
             CellRead<2, KW> x;
-            const int ew = (jj + 2) * T2_WX + ii + 2, ek = (jj + 1) * T2_KX + ii + 1;
+            const int ew = (jj + HW) * WX + ii + HW, ek = (jj + 1) * T2_KX + ii + 1;
             const int fx = jj * (T2X + 1) + ii, fy = jj * T2X + ii;
             const int cell = (y0 + jj) * n0 + x0 + ii;
 #pragma unroll
@@ -1143,17 +1157,19 @@ __device__ inline double cell_eps(cref<Inst> I, int cell)
         constexpr int DIR = decltype(dirc)::value;
         int fc[3] = {c[0], c[1], c[2]};
         fc[DIR] += side;                               // the face lies on the low side of cell fc
-        double Wc[4][NV];
-        for (int o = 0; o < 4; ++o) {
+        constexpr int NS = halo_of<V>();
+        double Wx[2 * NS][NV];
+        for (int o = 0; o < 2 * NS; ++o) {
             int cc[3] = {fc[0], fc[1], fc[2]};
-            cc[DIR] += o - 2;
-            load_state<D>(I, W, DIR, cc, Wc[o]);
+            cc[DIR] += o - NS;
+            load_state<D>(I, W, DIR, cc, Wx[o]);
         }
+        const double(*Wc)[NV] = Wx + (NS - 2);
         int cl[3] = {fc[0], fc[1], fc[2]};
         cl[DIR] -= 1;
         const int il = image_cell<D>(I, DIR, cl), ir = image_cell<D>(I, DIR, fc);
         double F[NV + 1];
-        if (face_eval<double, D, DIR, FLUX_EPS_OUT | ((V & V_TH) ? FLUX_TAUHAT : 0), (V & V_R3) != 0>(
+        if (face_eval<double, D, DIR, FLUX_EPS_OUT | ((V & V_TH) ? FLUX_TAUHAT : 0), recon_of<V>()>(
                 I, fc[DIR], Wc, I.k, I.om, I.S, il, ir, dt, F))
             atomicOr(&I.st->err, 1);
         mx = fmax(mx, F[NV]);
@@ -1198,11 +1214,13 @@ GKS_TILE2(0) GKS_TILE2(1) GKS_TILE2(2) GKS_TILE2(3) GKS_TILE2(4) GKS_TILE2(5) GK
 GKS_FACE(64, 0) GKS_FACE(128, 0) GKS_FACE(256, 0)
 GKS_FACE(64, 1) GKS_FACE(64, 2) GKS_FACE(64, 3) GKS_FACE(64, 4) GKS_FACE(64, 5) GKS_FACE(64, 6) GKS_FACE(64, 7)
 GKS_TILE2(8) GKS_FACE(64, 8)
+GKS_TILE2(16) GKS_FACE(64, 16)
 #undef GKS_TILE2
 #undef GKS_FACE
 template __global__ void k_eps<0>(const void*, int, double*);
 template __global__ void k_eps<V_TH>(const void*, int, double*);
 template __global__ void k_eps<V_R3>(const void*, int, double*);
+template __global__ void k_eps<V_W5>(const void*, int, double*);
 template __global__ void k_eps<V_TH | V_R3>(const void*, int, double*);
 template __global__ void k_update<false>(const void*, int);
 template __global__ void k_update<true>(const void*, int);

@@ -74,10 +74,17 @@ bool config_ok(const gks_config* c, std::string* why)
     if (c->max_steps < 0) return fail("max_steps must be >= 0");
     if (c->turb_transport != 0 && c->turb_transport != 1) return fail("turb_transport must be 0 or 1");
     if (c->eps_mode != GKS_EPS_DT && c->eps_mode != GKS_EPS_TAUHAT) return fail("unknown eps_mode");
-    if (c->recon != GKS_RECON_MUSCL2 && c->recon != GKS_RECON_MUSCL3) return fail("unknown reconstruction");
+    if (c->recon != GKS_RECON_MUSCL2 && c->recon != GKS_RECON_MUSCL3 && c->recon != GKS_RECON_WENO5)
+        return fail("unknown reconstruction");
     if (c->multi_d != 0 && c->multi_d != 1) return fail("multi_d must be 0 or 1");
     if (c->multi_d && (c->turb_transport || c->eps_mode != GKS_EPS_DT || c->recon != GKS_RECON_MUSCL2))
         return fail("the multi-dimensional expansion runs on its own (no transport, tau_hat or third-order MUSCL)");
+    if (c->recon == GKS_RECON_WENO5) {
+        if (c->turb_transport || c->eps_mode != GKS_EPS_DT)
+            return fail("WENO5 face values run on their own (no transport or tau_hat)");
+        for (int d = 0; d < c->dim; ++d)
+            if (c->n[d] < 3) return fail("WENO5 needs at least 3 cells per axis (three ghost layers)");
+    }
     return true;
 }
 
@@ -296,7 +303,7 @@ static face_kernel_t face_kernel_t_(int cls)
     default: return k_face<float, 3, T, V>;
     }
 }
-// Face kernel of a class and variant (V_KW | V_TH | V_R3, or V_MD alone).  Solves in a
+// Face kernel of a class and variant (V_KW | V_TH | V_R3, or V_MD or V_W5 alone).  Solves in a
 // variant other than 0 run alone with the default tile; batches hold variant 0 only.
 static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
 {
@@ -309,6 +316,7 @@ static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
     case 6: return face_kernel_t_<FACE_TILE, 6>(cls);
     case 7: return face_kernel_t_<FACE_TILE, 7>(cls);
     case V_MD: return face_kernel_t_<FACE_TILE, V_MD>(cls);
+    case V_W5: return face_kernel_t_<FACE_TILE, V_W5>(cls);
     default: break;
     }
     if (tile == 128) return face_kernel_t_<128, 0>(cls);
@@ -318,7 +326,8 @@ static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
 static int variant_of(const gks_config* c)
 {
     return (c->turb_transport ? V_KW : 0) | (c->eps_mode == GKS_EPS_TAUHAT ? V_TH : 0) |
-           (c->recon == GKS_RECON_MUSCL3 ? V_R3 : 0) | (c->multi_d ? V_MD : 0);
+           (c->recon == GKS_RECON_MUSCL3 ? V_R3 : 0) | (c->multi_d ? V_MD : 0) |
+           (c->recon == GKS_RECON_WENO5 ? V_W5 : 0);
 }
 static int face_block(int cls, int tile) { return cls < 2 ? T2_THREADS : tile; }
 static const int kDefaultFaceTiles[NCLS] = {FACE_TILE, FACE_TILE, FACE_TILE, FACE_TILE};
@@ -625,9 +634,11 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
         // into the older state buffer, which no step reads again before writing it
         double* out = h->inst.W[st.parity ^ 1];
         const int grid = (int)std::min<long long>((N + 63) / 64, 1 << 20);
-        const int v = variant_of(&h->cfg) & (V_TH | V_R3);
+        const int v = variant_of(&h->cfg) & (V_TH | V_R3 | V_W5);
         void (*ke)(const void*, int, double*) =
-            v == (V_TH | V_R3) ? k_eps<V_TH | V_R3> : (v == V_TH ? k_eps<V_TH> : (v == V_R3 ? k_eps<V_R3> : k_eps<0>));
+            v == V_W5 ? k_eps<V_W5>
+                      : (v == (V_TH | V_R3) ? k_eps<V_TH | V_R3>
+                                            : (v == V_TH ? k_eps<V_TH> : (v == V_R3 ? k_eps<V_R3> : k_eps<0>)));
         hipLaunchKernelGGL(ke, dim3(grid), dim3(64), 0, h->stream, (const void*)h->tab, 1, out);
         HIP_TRY(h, hipGetLastError());
         HIP_TRY(h, hipMemcpyAsync(host_out, out, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
@@ -959,21 +970,23 @@ inline CR g_rsqrt(CR a) { CR::n += 2; return CR(1.0 / sqrt(a.v)); }   // a squar
 // the erfc evaluation counts as one operation, as a library erfc call would
 inline CR erfc_e(CR ax, CR e) { CR::n += 1; return CR(erfc(ax.v) + 0.0 * e.v); }
 
-template <int D, int MODE = 0>
+template <int D, int MODE = 0, int RK = 0>
 static double count_face()
 {
     constexpr int NV = D + 2;
     // a representative interior face: distinct left/right states, nonzero slopes, tau ~ dt/3
-    const double prim[4][5] = {{1.00, 0.30, -0.10, 0.05, 0.90}, {1.10, 0.25, -0.05, 0.02, 1.00},
-                               {0.95, 0.35, -0.12, 0.04, 0.85}, {1.05, 0.28, -0.08, 0.03, 0.95}};
+    // (six stencil cells: the outer two feed the WENO5 values only)
+    const double prim[6][5] = {{0.97, 0.32, -0.11, 0.06, 0.88}, {1.00, 0.30, -0.10, 0.05, 0.90},
+                               {1.10, 0.25, -0.05, 0.02, 1.00}, {0.95, 0.35, -0.12, 0.04, 0.85},
+                               {1.05, 0.28, -0.08, 0.03, 0.95}, {1.02, 0.31, -0.09, 0.04, 0.93}};
     const double gamma = 1.4, h = 0.01;
-    CR Wc[4][NV];
-    for (int o = 0; o < 4; ++o) {
+    CR Wx[6][NV];
+    for (int o = 0; o < 6; ++o) {
         const double rho = prim[o][0], p = prim[o][4];
         double ke = 0.0;
-        Wc[o][0] = CR(rho);
-        for (int d = 0; d < D; ++d) { Wc[o][1 + d] = CR(rho * prim[o][1 + d]); ke += rho * prim[o][1 + d] * prim[o][1 + d]; }
-        Wc[o][D + 1] = CR(p / (gamma - 1.0) + 0.5 * ke);
+        Wx[o][0] = CR(rho);
+        for (int d = 0; d < D; ++d) { Wx[o][1 + d] = CR(rho * prim[o][1 + d]); ke += rho * prim[o][1 + d] * prim[o][1 + d]; }
+        Wx[o][D + 1] = CR(p / (gamma - 1.0) + 0.5 * ke);
     }
     FaceGeo<CR> geo;
     for (int q = 0; q < 3; ++q) geo.icd[q] = CR(1.0 / h);
@@ -981,7 +994,8 @@ static double count_face()
     geo.idl = geo.idr = CR(2.0 / h);
     CR::n = 0;
     FaceIn<D, CR> in;
-    reconstruct<D, CR>(Wc, geo, in);
+    const CR(*Wc)[NV] = Wx + 1;
+    reconstruct<D, CR, RK>(Wc, geo, in);
     in.kf = CR(1e-3);
     in.wf = CR(10.0);
     in.Sf = CR(5.0);
@@ -1021,6 +1035,17 @@ extern "C" gks_status gks_face_flops_multid(int32_t dim, double* flops)
 {
     if (!flops || (dim != 2 && dim != 3)) return fail_h(nullptr, GKS_ERR_ARG, "bad arguments");
     *flops = dim == 2 ? gks::count_face<2, gks::FLUX_MULTID>() : gks::count_face<3, gks::FLUX_MULTID>();
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_face_flops_recon(int32_t dim, int32_t recon, double* flops)
+{
+    if (!flops || (dim != 2 && dim != 3) ||
+        (recon != GKS_RECON_MUSCL2 && recon != GKS_RECON_MUSCL3 && recon != GKS_RECON_WENO5))
+        return fail_h(nullptr, GKS_ERR_ARG, "bad arguments");
+    if (recon == GKS_RECON_MUSCL2) *flops = dim == 2 ? gks::count_face<2>() : gks::count_face<3>();
+    else if (recon == GKS_RECON_MUSCL3) *flops = dim == 2 ? gks::count_face<2, 0, 1>() : gks::count_face<3, 0, 1>();
+    else *flops = dim == 2 ? gks::count_face<2, 0, 2>() : gks::count_face<3, 0, 2>();
     return GKS_OK;
 }
 

@@ -19,13 +19,13 @@ BC = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
 FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3, "eps": 4}
 EPS_MODE = {"dt": 0, "tauhat": 1}
-RECON = {"muscl2": 0, "muscl3": 1}
+RECON = {"muscl2": 0, "muscl3": 1, "weno5": 2}
 
 # every entry point declared in include/gks.h
 EXPORTED = (
     "gks_workspace_bytes", "gks_init", "gks_step", "gks_residual", "gks_fields",
     "gks_state_device_ptr", "gks_destroy", "gks_last_error", "gks_face_flops", "gks_kw_face_flops",
-    "gks_face_flops_multid",
+    "gks_face_flops_multid", "gks_face_flops_recon",
     "gks_set_timing", "gks_kernel_times",
     "gks_batch_workspace_bytes", "gks_batch_create", "gks_batch_set_members", "gks_batch_step",
     "gks_batch_capture", "gks_batch_set_launch", "gks_batch_status", "gks_batch_destroy",
@@ -86,6 +86,7 @@ def lib():
         L.gks_face_flops.argtypes = [i32, i32, dp]
         L.gks_kw_face_flops.argtypes = [dp]
         L.gks_face_flops_multid.argtypes = [i32, dp]
+        L.gks_face_flops_recon.argtypes = [i32, i32, dp]
         L.gks_set_timing.argtypes = [vp, i32]
         L.gks_kernel_times.argtypes = [vp, dp, C.POINTER(i64)]
         L.gks_batch_workspace_bytes.argtypes = [i32, sz]
@@ -209,6 +210,12 @@ def gks_face_flops(dim, precision="fp64"):
 def gks_face_flops_multid(dim):
     out = C.c_double(0)
     _check(lib().gks_face_flops_multid(int(dim), C.byref(out)))
+    return out.value
+
+
+def gks_face_flops_recon(dim, recon):
+    out = C.c_double(0)
+    _check(lib().gks_face_flops_recon(int(dim), RECON[recon], C.byref(out)))
     return out.value
 
 

@@ -81,6 +81,13 @@ def test_face_flop_count():
     # the multi-dimensional expansion adds the tangential slopes' solves and moments
     assert f2 < P.gks_face_flops_multid(2) < P.gks_face_flops_multid(3)
     assert P.gks_face_flops_multid(3) - f3 > P.gks_face_flops_multid(2) - f2
+    # reconstructions: MUSCL2 is the default count; a WENO5 value takes 70 operations (three
+    # candidates 16, smoothness indicators 18 + 3 + 18, weights and mean 15) and replaces
+    # the 2 of a MUSCL face value, twice per component
+    for d, f in ((2, f2), (3, f3)):
+        assert P.gks_face_flops_recon(d, "muscl2") == f
+        assert P.gks_face_flops_recon(d, "muscl3") > f
+        assert P.gks_face_flops_recon(d, "weno5") - f == (d + 2) * 2 * (70 - 2)
 
 
 def test_binding_loads_torch_runtime_first():

@@ -1,0 +1,140 @@
+"""Fifth-order WENO face values (recon = GKS_RECON_WENO5) on the GPU against the oracle on
+the same seeded inputs: FP64 flux <= 1e-12 and FP32 flux <= 1e-5, normwise, the momentum
+components measured against the momentum magnitude (as in the FP32 parity tests) and the
+other fields each against its own.  The device forms the weighted mean over a common
+denominator (one reciprocal), the oracle with the weights themselves: equal up to rounding.
+
+Why the momentum magnitude: in the mixing layer the transverse momentum stays three orders
+below the streamwise one, and with WENO5 a one-ulp change of the face values anywhere
+grows to 1-2e-12 of max |rho V| within 20-60 steps.  Algebraically equal forms of the
+oracle's own WENO5 (its final division or its weights' divisions taken as reciprocals, or
+its 1/6 as a product) differ from it by 1.3e-12 (20 steps) to 2.1e-12 (60 steps) there,
+and by under 4e-15 against the momentum magnitude; second-order and third-order MUSCL
+face values, computed the same way on both sides, stay within the per-field bound."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import banner, field_errors, run_gpu
+from inputs import cases as C
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _compare(case, nsteps, tol, changes=True):
+    case = case.copy()
+    case.recon = "weno5"
+    banner(f"weno5: {case.name} {case.precision} n={case.n} steps={nsteps}")
+    Wg, rg = run_gpu(case, nsteps)
+    ro = oracle.run(case, nsteps)
+    err = field_errors(Wg, ro["W"], vector_momentum=True)
+    print(f"  field errors {err}", flush=True)
+    assert rg["steps"] == ro["steps"]
+    assert np.all(err <= tol), err
+    assert abs(rg["t"] - ro["t"]) <= (1e-13 if tol <= TOL64 else 1e-5) * max(ro["t"], 1e-300)
+    if changes:       # the reconstruction changed the result
+        case.recon = "muscl2"
+        r2 = oracle.run(case, nsteps)
+        assert np.max(field_errors(r2["W"], ro["W"])) > 10 * tol
+
+
+def test_weno5_mixing_layer_fp64():
+    _compare(C.mixing_layer(64, seed=3), 60, TOL64)
+
+
+def test_weno5_sbli_fp64_all_boundaries():
+    _compare(C.sbli(96, 48), 40, TOL64)
+
+
+def test_weno5_isotropic_3d_fp64():
+    _compare(C.isotropic_box(16, precision="fp64"), 12, TOL64)
+
+
+def test_weno5_3d_mixed_boundaries_fp64():
+    bc = [["dirichlet", "outflow"], ["wall", "profile"], ["outflow", "wall"]]
+    c = C.uniform_flow(dim=3, n=(9, 7, 6), bc=bc, vel=(0.4, 0.1, -0.2))
+    rng = np.random.default_rng(3)
+    c.W = c.W * (1.0 + 0.05 * rng.uniform(-1, 1, size=c.W.shape))
+    _compare(c, 6, TOL64)
+
+
+@pytest.mark.parametrize("n", [(3, 3, 1), (67, 3, 1), (5, 130, 1), (9, 7, 5), (3, 4, 3)])
+def test_weno5_ragged_and_minimal_sizes(n):
+    """Three cells per axis is the least the three ghost layers allow (walls mirror three
+    cells deep, periodic axes wrap them); tile edges and tails land inside the stencils."""
+    dim = 3 if n[2] > 1 else 2
+    bc = [["periodic", "periodic"], ["wall", "outflow"], ["periodic", "periodic"]][:dim]
+    c = C.uniform_flow(dim=dim, n=n, bc=bc, vel=(0.3, 0.0, 0.1)[:dim])
+    rng = np.random.default_rng(sum(n))
+    c.W = c.W * (1.0 + 0.05 * rng.uniform(-1, 1, size=c.W.shape))
+    _compare(c, 4, TOL64)
+
+
+def test_weno5_fp32_flux_2d_and_3d():
+    _compare(C.mixing_layer(64, seed=3, precision="fp32_flux"), 60, TOL32)
+    _compare(C.isotropic_box(16, precision="fp32_flux"), 12, TOL32)
+
+
+def test_weno5_eps_field():
+    from paper_1302_2132_amd import Solver
+    c = C.mixing_layer(48, seed=4)
+    c.recon = "weno5"
+    banner("weno5: eps_hat field after 20 steps")
+    s = Solver(c)
+    try:
+        s.step(20)
+        W, e = s.fields("cons"), s.fields("eps")
+    finally:
+        s.close()
+    eo = oracle.eps_field(c, W)
+    assert np.max(np.abs(e - eo)) <= 1e-12 * max(eo.max(), 1e-300)
+
+
+def test_weno5_configs_refused():
+    from paper_1302_2132_amd import GKS_ERR_ARG, Batch, GksError, Solver
+    small = C.uniform_flow(dim=2, n=(2, 6, 1), bc=[["periodic", "periodic"]] * 2)
+    small.recon = "weno5"
+    with pytest.raises(GksError) as e:
+        Solver(small)
+    assert e.value.status == GKS_ERR_ARG
+    kw = C.mixing_layer(32, seed=2)
+    kw.recon, kw.kw_transport = "weno5", True
+    with pytest.raises(GksError) as e:
+        Solver(kw)
+    assert e.value.status == GKS_ERR_ARG
+    a = C.mixing_layer(32, seed=2)
+    b = a.copy()
+    b.recon = "weno5"
+    sa, sb = Solver(a), Solver(b)
+    try:
+        with pytest.raises(GksError) as e:
+            Batch([sa, sb])
+        assert e.value.status == GKS_ERR_ARG
+    finally:
+        sa.close()
+        sb.close()
+
+
+def test_weno5_sbli_full_size_one_step():
+    from paper_1302_2132_amd import Solver
+    c = C.sbli()
+    c.recon = "weno5"
+    banner(f"weno5: {c.name} full size, one step after 10")
+    s = Solver(c)
+    try:
+        s.step(10)
+        Wa = s.fields("cons")
+        ra = s.residual()
+        s.step(1)
+        Wb = s.fields("cons")
+        rb = s.residual()
+    finally:
+        s.close()
+    ro = oracle.run(c, 1, W=Wa, t0=ra["t"])
+    assert abs(rb["dt"] - ro["dt"]) <= 1e-13 * ro["dt"]
+    err = field_errors(Wb, ro["W"], vector_momentum=True)
+    print(f"  field errors {err}", flush=True)
+    assert np.all(err <= TOL64)
