@@ -92,7 +92,8 @@ enum { GKS_EPS_DT = 0, GKS_EPS_TAUHAT = 1 };
  *          five cells upwind-biased to each side, smoothness-indicator weights with
  *          eps = 1e-6) in index space, the cell widths not entering; it reads three cells
  *          on each side of a face, so it needs three ghost layers and at least three cells
- *          per axis, and runs on its own (turb_transport = 0, GKS_EPS_DT, multi_d = 0). */
+ *          per axis.
+ * Each combines with turb_transport and either eps_mode; MUSCL3 and WENO5 not with multi_d. */
 enum { GKS_RECON_MUSCL2 = 0, GKS_RECON_MUSCL3 = 1, GKS_RECON_WENO5 = 2 };
 
 /* Multi-dimensional expansion (multi_d = 1; section "Implementation ...": the distribution

@@ -27,7 +27,7 @@
 //   V_MD  the multi-dimensional expansion (face_flux with FLUX_MULTID): tangential
 //         gradients of the two cells of every face enter the flux (on its own only);
 //   V_W5  fifth-order WENO face values (reconstruct<.., 2>): six stencil cells per face,
-//         three ghost layers (on its own only).
+//         three ghost layers (with V_KW and V_TH as V_R3 is).
 // V = 0 is the plain scheme, untouched by the others.
 //
 // The table, the solve descriptors and (outside k_finish) the step state are read
@@ -1214,13 +1214,15 @@ GKS_TILE2(0) GKS_TILE2(1) GKS_TILE2(2) GKS_TILE2(3) GKS_TILE2(4) GKS_TILE2(5) GK
 GKS_FACE(64, 0) GKS_FACE(128, 0) GKS_FACE(256, 0)
 GKS_FACE(64, 1) GKS_FACE(64, 2) GKS_FACE(64, 3) GKS_FACE(64, 4) GKS_FACE(64, 5) GKS_FACE(64, 6) GKS_FACE(64, 7)
 GKS_TILE2(8) GKS_FACE(64, 8)
-GKS_TILE2(16) GKS_FACE(64, 16)
+GKS_TILE2(16) GKS_TILE2(17) GKS_TILE2(18) GKS_TILE2(19)
+GKS_FACE(64, 16) GKS_FACE(64, 17) GKS_FACE(64, 18) GKS_FACE(64, 19)
 #undef GKS_TILE2
 #undef GKS_FACE
 template __global__ void k_eps<0>(const void*, int, double*);
 template __global__ void k_eps<V_TH>(const void*, int, double*);
 template __global__ void k_eps<V_R3>(const void*, int, double*);
 template __global__ void k_eps<V_W5>(const void*, int, double*);
+template __global__ void k_eps<V_TH | V_W5>(const void*, int, double*);
 template __global__ void k_eps<V_TH | V_R3>(const void*, int, double*);
 template __global__ void k_update<false>(const void*, int);
 template __global__ void k_update<true>(const void*, int);

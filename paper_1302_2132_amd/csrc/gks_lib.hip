@@ -78,10 +78,8 @@ bool config_ok(const gks_config* c, std::string* why)
         return fail("unknown reconstruction");
     if (c->multi_d != 0 && c->multi_d != 1) return fail("multi_d must be 0 or 1");
     if (c->multi_d && (c->turb_transport || c->eps_mode != GKS_EPS_DT || c->recon != GKS_RECON_MUSCL2))
-        return fail("the multi-dimensional expansion runs on its own (no transport, tau_hat or third-order MUSCL)");
+        return fail("the multi-dimensional expansion runs on its own (no transport, tau_hat, third-order MUSCL or WENO5)");
     if (c->recon == GKS_RECON_WENO5) {
-        if (c->turb_transport || c->eps_mode != GKS_EPS_DT)
-            return fail("WENO5 face values run on their own (no transport or tau_hat)");
         for (int d = 0; d < c->dim; ++d)
             if (c->n[d] < 3) return fail("WENO5 needs at least 3 cells per axis (three ghost layers)");
     }
@@ -303,7 +301,7 @@ static face_kernel_t face_kernel_t_(int cls)
     default: return k_face<float, 3, T, V>;
     }
 }
-// Face kernel of a class and variant (V_KW | V_TH | V_R3, or V_MD or V_W5 alone).  Solves in a
+// Face kernel of a class and variant (V_KW | V_TH with V_R3 or V_W5, or V_MD alone).  Solves in a
 // variant other than 0 run alone with the default tile; batches hold variant 0 only.
 static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
 {
@@ -317,6 +315,9 @@ static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
     case 7: return face_kernel_t_<FACE_TILE, 7>(cls);
     case V_MD: return face_kernel_t_<FACE_TILE, V_MD>(cls);
     case V_W5: return face_kernel_t_<FACE_TILE, V_W5>(cls);
+    case V_W5 | V_KW: return face_kernel_t_<FACE_TILE, V_W5 | V_KW>(cls);
+    case V_W5 | V_TH: return face_kernel_t_<FACE_TILE, V_W5 | V_TH>(cls);
+    case V_W5 | V_KW | V_TH: return face_kernel_t_<FACE_TILE, V_W5 | V_KW | V_TH>(cls);
     default: break;
     }
     if (tile == 128) return face_kernel_t_<128, 0>(cls);
@@ -635,10 +636,15 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
         double* out = h->inst.W[st.parity ^ 1];
         const int grid = (int)std::min<long long>((N + 63) / 64, 1 << 20);
         const int v = variant_of(&h->cfg) & (V_TH | V_R3 | V_W5);
-        void (*ke)(const void*, int, double*) =
-            v == V_W5 ? k_eps<V_W5>
-                      : (v == (V_TH | V_R3) ? k_eps<V_TH | V_R3>
-                                            : (v == V_TH ? k_eps<V_TH> : (v == V_R3 ? k_eps<V_R3> : k_eps<0>)));
+        void (*ke)(const void*, int, double*) = k_eps<0>;
+        switch (v) {
+        case V_TH: ke = k_eps<V_TH>; break;
+        case V_R3: ke = k_eps<V_R3>; break;
+        case V_TH | V_R3: ke = k_eps<V_TH | V_R3>; break;
+        case V_W5: ke = k_eps<V_W5>; break;
+        case V_TH | V_W5: ke = k_eps<V_TH | V_W5>; break;
+        default: break;
+        }
         hipLaunchKernelGGL(ke, dim3(grid), dim3(64), 0, h->stream, (const void*)h->tab, 1, out);
         HIP_TRY(h, hipGetLastError());
         HIP_TRY(h, hipMemcpyAsync(host_out, out, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));

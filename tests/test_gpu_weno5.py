@@ -93,6 +93,36 @@ def test_weno5_eps_field():
     assert np.max(np.abs(e - eo)) <= 1e-12 * max(eo.max(), 1e-300)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", ["dt", "tauhat"])
+def test_weno5_with_transport(dim, mode):
+    from paper_1302_2132_amd import Solver
+    c = C.mixing_layer(48, seed=4) if dim == 2 else C.isotropic_box(12, precision="fp64")
+    c.recon, c.eps_mode, c.kw_transport = "weno5", mode, True
+    n = 30 if dim == 2 else 8
+    banner(f"weno5 + k-omega transport, eps_mode {mode}: {c.name} steps={n}")
+    s = Solver(c)
+    try:
+        s.step(n)
+        W, kw, e = s.fields("cons"), s.fields("turb"), s.fields("eps")
+    finally:
+        s.close()
+    ro = oracle.run_kw(c, n)
+    err = field_errors(W, ro["W"], vector_momentum=True)
+    ek = np.max(np.abs(kw[0] - ro["k"])) / np.max(np.abs(ro["k"]))
+    ew = np.max(np.abs(kw[1] - ro["omega"])) / np.max(np.abs(ro["omega"]))
+    print(f"  flow errors {err}  k {ek:.3e}  omega {ew:.3e}", flush=True)
+    assert np.all(err <= TOL64) and ek <= TOL64 and ew <= TOL64
+    eo = oracle.eps_field(c, W, kw[0], kw[1])
+    assert np.max(np.abs(e - eo)) <= 1e-12 * max(eo.max(), 1e-300)
+
+
+def test_weno5_with_tauhat_frozen():
+    c = C.mixing_layer(48, seed=6)
+    c.eps_mode = "tauhat"
+    _compare(c, 30, TOL64)
+
+
 def test_weno5_configs_refused():
     from paper_1302_2132_amd import GKS_ERR_ARG, Batch, GksError, Solver
     small = C.uniform_flow(dim=2, n=(2, 6, 1), bc=[["periodic", "periodic"]] * 2)
@@ -100,10 +130,10 @@ def test_weno5_configs_refused():
     with pytest.raises(GksError) as e:
         Solver(small)
     assert e.value.status == GKS_ERR_ARG
-    kw = C.mixing_layer(32, seed=2)
-    kw.recon, kw.kw_transport = "weno5", True
+    md = C.mixing_layer(32, seed=2)
+    md.recon, md.multi_d = "weno5", True
     with pytest.raises(GksError) as e:
-        Solver(kw)
+        Solver(md)
     assert e.value.status == GKS_ERR_ARG
     a = C.mixing_layer(32, seed=2)
     b = a.copy()
