@@ -107,7 +107,8 @@ enum { GKS_RECON_MUSCL2 = 0, GKS_RECON_MUSCL3 = 1, GKS_RECON_WENO5 = 2 };
  *  - A from <psi (a u + b.v_t + A)> = 0 and Abar from the time-integrated compatibility
  *    condition with the b terms; in the flux b.v_t enters beside a u.
  * Continuous linear data then give the Navier-Stokes flux with the full velocity-gradient
- * tensor. */
+ * tensor.  It combines with turb_transport and either eps_mode (with GKS_EPS_TAUHAT the
+ * rarefaction measure keeps its normal-direction form), not with MUSCL3 or WENO5. */
 
 /* Fields for gks_fields. CONS: conservative state (nvar x ncells). PRIM: rho, U, V, [W],
  * p (nvar x ncells). STRAIN: strain-rate magnitude sqrt(2 S_ab S_ab) (ncells). TURB: k
@@ -135,8 +136,8 @@ typedef struct {
     int32_t turb_transport;       /* 1: transport k and omega with the flow; 0: frozen inputs */
     int32_t eps_mode;             /* GKS_EPS_DT or GKS_EPS_TAUHAT */
     int32_t recon;                /* GKS_RECON_MUSCL2, GKS_RECON_MUSCL3 or GKS_RECON_WENO5 */
-    int32_t multi_d;              /* 1: multi-dimensional expansion (on its own: with
-                                     turb_transport = 0, GKS_EPS_DT and GKS_RECON_MUSCL2) */
+    int32_t multi_d;              /* 1: multi-dimensional expansion (with GKS_RECON_MUSCL2;
+                                     combines with turb_transport and either eps_mode) */
 } gks_config;
 
 typedef struct gks_ctx* gks_handle;

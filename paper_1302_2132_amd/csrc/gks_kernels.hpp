@@ -25,7 +25,8 @@
 //         (face_flux with FLUX_TAUHAT);
 //   V_R3  third-order MUSCL face values (reconstruct<.., 1>);
 //   V_MD  the multi-dimensional expansion (face_flux with FLUX_MULTID): tangential
-//         gradients of the two cells of every face enter the flux (on its own only);
+//         gradients of the two cells of every face enter the flux (with V_KW and V_TH,
+//         not with the higher-order face values);
 //   V_W5  fifth-order WENO face values (reconstruct<.., 2>): six stencil cells per face,
 //         three ghost layers (with V_KW and V_TH as V_R3 is).
 // V = 0 is the plain scheme, untouched by the others.
@@ -1213,7 +1214,8 @@ __global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, i
 GKS_TILE2(0) GKS_TILE2(1) GKS_TILE2(2) GKS_TILE2(3) GKS_TILE2(4) GKS_TILE2(5) GKS_TILE2(6) GKS_TILE2(7)
 GKS_FACE(64, 0) GKS_FACE(128, 0) GKS_FACE(256, 0)
 GKS_FACE(64, 1) GKS_FACE(64, 2) GKS_FACE(64, 3) GKS_FACE(64, 4) GKS_FACE(64, 5) GKS_FACE(64, 6) GKS_FACE(64, 7)
-GKS_TILE2(8) GKS_FACE(64, 8)
+GKS_TILE2(8) GKS_TILE2(9) GKS_TILE2(10) GKS_TILE2(11)
+GKS_FACE(64, 8) GKS_FACE(64, 9) GKS_FACE(64, 10) GKS_FACE(64, 11)
 GKS_TILE2(16) GKS_TILE2(17) GKS_TILE2(18) GKS_TILE2(19)
 GKS_FACE(64, 16) GKS_FACE(64, 17) GKS_FACE(64, 18) GKS_FACE(64, 19)
 #undef GKS_TILE2

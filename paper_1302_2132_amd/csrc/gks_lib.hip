@@ -77,8 +77,8 @@ bool config_ok(const gks_config* c, std::string* why)
     if (c->recon != GKS_RECON_MUSCL2 && c->recon != GKS_RECON_MUSCL3 && c->recon != GKS_RECON_WENO5)
         return fail("unknown reconstruction");
     if (c->multi_d != 0 && c->multi_d != 1) return fail("multi_d must be 0 or 1");
-    if (c->multi_d && (c->turb_transport || c->eps_mode != GKS_EPS_DT || c->recon != GKS_RECON_MUSCL2))
-        return fail("the multi-dimensional expansion runs on its own (no transport, tau_hat, third-order MUSCL or WENO5)");
+    if (c->multi_d && c->recon != GKS_RECON_MUSCL2)
+        return fail("the multi-dimensional expansion takes second-order MUSCL face values");
     if (c->recon == GKS_RECON_WENO5) {
         for (int d = 0; d < c->dim; ++d)
             if (c->n[d] < 3) return fail("WENO5 needs at least 3 cells per axis (three ghost layers)");
@@ -301,7 +301,7 @@ static face_kernel_t face_kernel_t_(int cls)
     default: return k_face<float, 3, T, V>;
     }
 }
-// Face kernel of a class and variant (V_KW | V_TH with V_R3 or V_W5, or V_MD alone).  Solves in a
+// Face kernel of a class and variant (V_KW and V_TH with one of V_R3, V_W5, V_MD).  Solves in a
 // variant other than 0 run alone with the default tile; batches hold variant 0 only.
 static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
 {
@@ -314,6 +314,9 @@ static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
     case 6: return face_kernel_t_<FACE_TILE, 6>(cls);
     case 7: return face_kernel_t_<FACE_TILE, 7>(cls);
     case V_MD: return face_kernel_t_<FACE_TILE, V_MD>(cls);
+    case V_MD | V_KW: return face_kernel_t_<FACE_TILE, V_MD | V_KW>(cls);
+    case V_MD | V_TH: return face_kernel_t_<FACE_TILE, V_MD | V_TH>(cls);
+    case V_MD | V_KW | V_TH: return face_kernel_t_<FACE_TILE, V_MD | V_KW | V_TH>(cls);
     case V_W5: return face_kernel_t_<FACE_TILE, V_W5>(cls);
     case V_W5 | V_KW: return face_kernel_t_<FACE_TILE, V_W5 | V_KW>(cls);
     case V_W5 | V_TH: return face_kernel_t_<FACE_TILE, V_W5 | V_TH>(cls);

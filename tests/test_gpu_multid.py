@@ -74,16 +74,10 @@ def test_multid_fp32_flux_2d_and_3d():
     _compare(C.isotropic_box(16, precision="fp32_flux"), 8, TOL32)
 
 
-def test_multid_is_refused_with_other_options_and_in_batches():
+def test_multid_is_refused_in_batches():
     from paper_1302_2132_amd import GKS_ERR_ARG, Batch, GksError, Solver
     c = C.mixing_layer(32, seed=2)
     c.multi_d = True
-    for opt in ("kw_transport", "eps_mode", "recon"):
-        d = c.copy()
-        setattr(d, opt, {"kw_transport": True, "eps_mode": "tauhat", "recon": "muscl3"}[opt])
-        with pytest.raises(GksError) as e:
-            Solver(d)
-        assert e.value.status == GKS_ERR_ARG
     a = C.mixing_layer(32, seed=2)
     sa, sb = Solver(a), Solver(c)
     try:
@@ -115,3 +109,46 @@ def test_multid_sbli_full_size_one_step():
     err = field_errors(Wb, ro["W"])
     print(f"  field errors {err}", flush=True)
     assert np.all(err <= TOL64)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", ["dt", "tauhat"])
+def test_multid_with_transport(dim, mode):
+    """The expansion with k and omega transported, in either eps_mode, against the oracle's
+    transport run; the eps_hat field of the same state."""
+    from paper_1302_2132_amd import Solver
+    c = C.mixing_layer(48, seed=4) if dim == 2 else C.isotropic_box(12, precision="fp64")
+    c.multi_d, c.eps_mode, c.kw_transport = True, mode, True
+    n = 30 if dim == 2 else 6
+    banner(f"multi-d + k-omega transport, eps_mode {mode}: {c.name} steps={n}")
+    s = Solver(c)
+    try:
+        s.step(n)
+        W, kw, e = s.fields("cons"), s.fields("turb"), s.fields("eps")
+    finally:
+        s.close()
+    ro = oracle.run_kw(c, n)
+    err = field_errors(W, ro["W"])
+    ek = np.max(np.abs(kw[0] - ro["k"])) / np.max(np.abs(ro["k"]))
+    ew = np.max(np.abs(kw[1] - ro["omega"])) / np.max(np.abs(ro["omega"]))
+    print(f"  flow errors {err}  k {ek:.3e}  omega {ew:.3e}", flush=True)
+    assert np.all(err <= TOL64) and ek <= TOL64 and ew <= TOL64
+    eo = oracle.eps_field(c, W, kw[0], kw[1])
+    assert np.max(np.abs(e - eo)) <= 1e-12 * max(eo.max(), 1e-300)
+
+
+def test_multid_with_tauhat_frozen():
+    c = C.mixing_layer(48, seed=6)
+    c.eps_mode = "tauhat"
+    _compare(c, 30, TOL64)
+
+
+def test_multid_with_higher_order_face_values_refused():
+    from paper_1302_2132_amd import GKS_ERR_ARG, GksError, Solver
+    for recon in ("muscl3", "weno5"):
+        c = C.mixing_layer(32, seed=2)
+        c.multi_d, c.recon = True, recon
+        with pytest.raises(GksError) as e:
+            Solver(c)
+        assert e.value.status == GKS_ERR_ARG
+
