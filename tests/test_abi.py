@@ -58,6 +58,43 @@ def test_workspace_bytes_and_validation():
     assert P.gks_workspace_bytes(P.config_from_case(fp32)) < nb3     # FP32 face fluxes
 
 
+def test_option_combinations_validated():
+    """WENO5 needs three cells per axis; the multi-dimensional expansion takes second-order
+    face values; every reconstruction and the expansion combine with transport and tau_hat."""
+    import paper_1302_2132_amd as P
+
+    def cfg(**kw):
+        c = C.uniform_flow(dim=2, n=kw.pop("n", (8, 6, 1)), bc=[["periodic", "periodic"]] * 2)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        return P.config_from_case(c)
+
+    for bad in (dict(recon="weno5", n=(2, 6, 1)), dict(recon="weno5", n=(8, 2, 1)),
+                dict(multi_d=True, recon="muscl3"), dict(multi_d=True, recon="weno5")):
+        with pytest.raises(P.GksError) as e:
+            P.gks_workspace_bytes(cfg(**bad))
+        assert e.value.status == P.GKS_ERR_ARG, bad
+    for good in (dict(recon="weno5", n=(3, 3, 1)), dict(recon="weno5", kw_transport=True, eps_mode="tauhat"),
+                 dict(recon="muscl3", kw_transport=True), dict(multi_d=True, kw_transport=True, eps_mode="tauhat")):
+        assert P.gks_workspace_bytes(cfg(**good)) > 0, good
+
+
+def test_missing_library_fails_loudly():
+    """Without a built libgks.so the binding raises; nothing runs on the CPU instead."""
+    import subprocess
+    import sys
+    code = ("import paper_1302_2132_amd.gks as G\n"
+            "G.lib_path = '/nonexistent/libgks.so'\n"
+            "from inputs import cases as C\n"
+            "try:\n"
+            "    G.Solver(C.mixing_layer(16))\n"
+            "except RuntimeError as e:\n"
+            "    print('raised', 'not found' in str(e))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert r.stdout.strip() == "raised True", (r.stdout, r.stderr[-2000:])
+
+
 def test_init_validation_before_any_device_call():
     import paper_1302_2132_amd as P
     c = C.mixing_layer(16)
