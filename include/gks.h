@@ -226,9 +226,10 @@ gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes);
  * captured as a graph.  Creation (and gks_batch_set_members) waits for the members' own
  * streams; afterwards every per-handle call on a member first waits for the batch stream.
  * The table lives in dev_workspace.  Handles stay owned by the caller and must outlive
- * the batch.  Members are frozen-field, DT-mode, second-order solves: a handle with
- * turb_transport, GKS_EPS_TAUHAT, GKS_RECON_MUSCL3, GKS_RECON_WENO5 or multi_d is refused (GKS_ERR_ARG),
- * here and in gks_batch_set_members. */
+ * the batch.  Members may carry any options (transport, eps_mode, reconstruction,
+ * multi_d): a step launches the face kernel of each (dimension, precision, options) group
+ * present, and the transported form's strain and 3D update passes when a member transports
+ * k and omega; each member's result equals its solve stepped alone, bitwise. */
 gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity,
                             void* dev_workspace, size_t bytes, void* hip_stream, gks_batch* out);
 
@@ -248,7 +249,8 @@ gks_status gks_batch_capture(gks_batch b);
  * 2 = fused 2D tile kernel (FP32 flux), 3 = face (3D FP64), 4 = face (3D FP32), 5 = update
  * (3D).  grid = number of persistent workgroups walking the tile table (0 = one per
  * tile).  tile = faces per face-kernel tile and workgroup (64, 128 or 256) for kinds 3
- * and 4; 0 otherwise (the 2D tile is fixed: 16 x 15 cells per 256-thread workgroup).
+ * and 4, used by the members without options (the others keep 64); 0 otherwise (the 2D
+ * tile is fixed: 16 x 15 cells per 256-thread workgroup).
  * Results do not depend on the launch shape (bitwise).  Invalidates a captured graph. */
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile);
 

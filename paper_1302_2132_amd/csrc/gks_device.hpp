@@ -42,6 +42,7 @@ struct alignas(64) State {
 struct Inst {
     int dim, nv, precision, cls;
     int kw;                    // 1: k and omega are transported, else frozen inputs
+    int variant;               // the solve's face-kernel variant (bits of its options)
     int n[3];
     int ntan[3];               // cells in a boundary plane of axis d
     int ncells;                // < 2^29 (validated), so cell and face indices fit in int

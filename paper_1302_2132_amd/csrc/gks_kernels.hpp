@@ -535,7 +535,8 @@ void k_face(const void* __restrict__ table, int cap, int cls)
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mj = find_member(prefix, count, tile);
         cref<Inst> I = tv.inst[member[mj]];
-        if (!state_of(I).active) continue;
+        // a batch launches each variant present over its class; other variants' tiles pass
+        if (I.variant != V || !state_of(I).active) continue;
         int lt = tile - prefix[mj];
         if (lt < I.ntile_face[0]) {
             const int f = lt * TILE + (int)threadIdx.x;
@@ -738,7 +739,7 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
         const int lane = tid & 63, wv = tid >> 6;
         const int mj = find_member(prefix, count, tile);
         cref<Inst> I = tv.inst[member[mj]];
-        if (!state_of(I).active) continue;
+        if (I.variant != V || !state_of(I).active) continue;   // another variant's tile (batches)
         const int lt = tile - prefix[mj];
         const int n0 = I.n[0], n1 = I.n[1];
         const int nbx = (n0 + T2X - 1) / T2X;
@@ -945,7 +946,8 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mi = find_member(tv.cell_prefix, count, tile);
         cref<Inst> I = tv.inst[mi];
-        if (I.dim == 2 || !state_of(I).active) continue;   // 2D solves update in k_tile2
+        // 2D solves update in k_tile2; a batch launches the transported form separately
+        if (I.dim == 2 || I.kw != (KW ? 1 : 0) || !state_of(I).active) continue;
         const int lt = tile - tv.cell_prefix[mi];
         const int cell = lt * CELL_TILE + (int)threadIdx.x;
         double r2[5] = {0, 0, 0, 0, 0};
@@ -1125,7 +1127,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
         const int tile = item - head;
         const int mi = find_member(tv.cell_prefix, count, tile);
         cref<Inst> I = tv.inst[mi];
-        if (!force && !state_of(I).active) continue;
+        if (I.kw != (KW ? 1 : 0) || (!force && !state_of(I).active)) continue;   // the other form's solves
         const int cell = (tile - tv.cell_prefix[mi]) * CELL_TILE + (int)threadIdx.x;
         if (cell >= I.ncells) continue;
         if (KW) {

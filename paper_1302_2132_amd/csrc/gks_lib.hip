@@ -3,6 +3,8 @@
 // Device memory is the caller's: every solve lives in one workspace laid out by
 // `layout()`; a batch keeps only its tile table in its own workspace.  Nothing here
 // calls hipMalloc.  Host inputs are validated and copied during gks_init.
+#include <bitset>
+
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -203,6 +205,19 @@ struct gks_ctx {
     long long steps_timed;
 };
 
+// What a batch step launches: the face kernel of each (class, variant) pair among the
+// members, and the strain and 3D update passes of the frozen and transported forms.
+struct Present {
+    std::bitset<NCLS * 32> face;      // bit cls * 32 + variant
+    bool strain[2] = {false, false};  // frozen, transported
+    bool update[2] = {false, false};  // 3D frozen, 3D transported
+    bool covers(const Present& o) const
+    {
+        return (o.face & ~face).none() && (strain[0] || !o.strain[0]) && (strain[1] || !o.strain[1]) &&
+               (update[0] || !o.update[0]) && (update[1] || !o.update[1]);
+    }
+};
+
 struct gks_batch_ctx {
     std::vector<gks_handle> members;
     int cap;
@@ -213,7 +228,7 @@ struct gks_batch_ctx {
     bool captured;
     hipGraph_t graph;
     hipGraphExec_t exec;
-    int cls_present;
+    Present present;                  // launches the current (or captured) step makes
     std::vector<char> host_tab;
     std::string err;
 };
@@ -301,8 +316,8 @@ static face_kernel_t face_kernel_t_(int cls)
     default: return k_face<float, 3, T, V>;
     }
 }
-// Face kernel of a class and variant (V_KW and V_TH with one of V_R3, V_W5, V_MD).  Solves in a
-// variant other than 0 run alone with the default tile; batches hold variant 0 only.
+// Face kernel of a class and variant (V_KW and V_TH with one of V_R3, V_W5, V_MD).  Variants
+// other than 0 use the default tile, alone and in batches.
 static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
 {
     switch (variant) {
@@ -412,6 +427,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.precision = cfg->precision;
     I.cls = h->cls;
     I.kw = cfg->turb_transport;
+    I.variant = variant_of(cfg);
     for (int d = 0; d < 3; ++d) {
         I.n[d] = d < D ? (int)cfg->n[d] : 1;
         I.ntan[d] = L.ntan[d];
@@ -754,7 +770,7 @@ gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes)
 static gks_status batch_upload(gks_batch b)
 {
     std::vector<const Inst*> mem;
-    int present = 0;
+    Present present;
     for (gks_handle h : b->members) {
         // work the member enqueued on its own stream must finish before batch work starts
         if (h->stream != b->stream && hipStreamSynchronize(h->stream) != hipSuccess) {
@@ -764,7 +780,10 @@ static gks_status batch_upload(gks_batch b)
         }
         h->batch_stream = b->stream;
         mem.push_back(&h->inst);
-        present |= 1 << h->cls;
+        const int kw = h->cfg.turb_transport ? 1 : 0;
+        present.face.set(h->cls * 32 + variant_of(&h->cfg));
+        present.strain[kw] = true;
+        if (h->cfg.dim == 3) present.update[kw] = true;
     }
     build_table(b->host_tab, b->cap, mem, b->face_tile);
     if (hipMemcpyAsync(b->tab, b->host_tab.data(), b->host_tab.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
@@ -773,12 +792,13 @@ static gks_status batch_upload(gks_batch b)
         g_last_error = b->err;
         return GKS_ERR_DEVICE;
     }
-    if (b->captured && (present & ~b->cls_present)) {
+    // a captured step graph stays valid while it launches every kernel the members need
+    if (b->captured && !b->present.covers(present)) {
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);
         b->captured = false;
     }
-    if (!b->captured) b->cls_present = present;
+    if (!b->captured) b->present = present;
     return GKS_OK;
 }
 
@@ -789,19 +809,14 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
         return fail_h(nullptr, GKS_ERR_ARG, "bad batch arguments");
     if (bytes < batch_bytes(capacity)) return fail_h(nullptr, GKS_ERR_NOMEM, "batch workspace too small");
     if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
-    for (int i = 0; i < count; ++i) {
+    for (int i = 0; i < count; ++i)
         if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
-        if (variant_of(&hs[i]->cfg))
-            return fail_h(nullptr, GKS_ERR_ARG,
-                          "solves with transport, tau_hat, third-order MUSCL or the multi-dimensional expansion step alone");
-    }
     gks_batch b = new gks_batch_ctx();
     b->members.assign(hs, hs + count);
     b->cap = capacity;
     b->stream = (hipStream_t)hip_stream;
     b->tab = dev_workspace;
     b->captured = false;
-    b->cls_present = 0;
     const int cus = device_cus();
     b->grid[0] = cus * 8;        // strain: 256-thread workgroups
     b->grid[5] = cus * 8;        // update
@@ -817,12 +832,8 @@ gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacit
 gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t count)
 {
     if (!b || count < 0 || count > b->cap || (!hs && count)) return fail_h(nullptr, GKS_ERR_ARG, "bad member list");
-    for (int i = 0; i < count; ++i) {
-        if (!hs[i]) return fail_h(nullptr, GKS_ERR_ARG, "NULL member");
-        if (variant_of(&hs[i]->cfg))
-            return fail_h(nullptr, GKS_ERR_ARG,
-                          "solves with transport, tau_hat, third-order MUSCL or the multi-dimensional expansion step alone");
-    }
+    for (int i = 0; i < count; ++i)
+        if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
     b->members.assign(hs, hs + count);
     return batch_upload(b);
 }
@@ -840,16 +851,28 @@ static int batch_grid(gks_batch b, int kind)
     return tiles > 0 ? tiles : 1;
 }
 
-static void batch_launch(gks_batch b, int present)
+// One batch step: the frozen-form strain pass, which also ends every member's previous
+// step, and the transported form's if any member transports k and omega; the face kernel
+// of each (class, variant) pair present (walking its class's tiles, passing the other
+// variants' tiles; variant 0 with the class's tuned tile, the others with the default);
+// the 3D update of each form present.
+static void batch_launch(gks_batch b, const Present& present)
 {
     const void* tab = b->tab;
     hipLaunchKernelGGL(k_strain<false>, dim3(batch_grid(b, 0)), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0, 1);
+    if (present.strain[1])
+        hipLaunchKernelGGL(k_strain<true>, dim3(batch_grid(b, 0)), dim3(CELL_TILE), 0, b->stream, tab, b->cap, 0, 0);
     for (int c = 0; c < NCLS; ++c)
-        if (present & (1 << c))
-            hipLaunchKernelGGL(face_kernel(c, b->face_tile[c]), dim3(batch_grid(b, 1 + c)),
-                               dim3(face_block(c, b->face_tile[c])), 0, b->stream, tab, b->cap, c);
-    if (present & ((1 << 2) | (1 << 3)))   // 3D members update in their own launch
+        for (int v = 0; v < 32; ++v)
+            if (present.face.test(c * 32 + v)) {
+                const int tile = v == 0 ? b->face_tile[c] : FACE_TILE;
+                hipLaunchKernelGGL(face_kernel(c, tile, v), dim3(batch_grid(b, 1 + c)), dim3(face_block(c, tile)), 0,
+                                   b->stream, tab, b->cap, c);
+            }
+    if (present.update[0])   // 3D members update in their own launch
         hipLaunchKernelGGL(k_update<false>, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
+    if (present.update[1])
+        hipLaunchKernelGGL(k_update<true>, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
 }
 
 gks_status gks_batch_step(gks_batch b, int32_t nsteps)
@@ -859,7 +882,7 @@ gks_status gks_batch_step(gks_batch b, int32_t nsteps)
         if (b->captured) {
             if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "graph launch failed");
         } else {
-            batch_launch(b, b->cls_present);
+            batch_launch(b, b->present);
         }
     }
     // end of the last step (outside the captured step graph)
@@ -879,7 +902,7 @@ gks_status gks_batch_capture(gks_batch b)
     }
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail_h(nullptr, GKS_ERR_DEVICE, "begin capture failed");
-    batch_launch(b, b->cls_present);
+    batch_launch(b, b->present);
     if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess)
         return fail_h(nullptr, GKS_ERR_DEVICE, "end capture failed");
     if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {

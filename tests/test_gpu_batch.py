@@ -1,5 +1,5 @@
 """Batched form: every solve gives the same result alone and inside a persistent batch
-(mixed sizes, dimensions and precisions; with and without a captured graph)."""
+(mixed sizes, dimensions, precisions and options; with and without a captured graph)."""
 import numpy as np
 import pytest
 
@@ -97,6 +97,84 @@ def test_two_dimensional_batch_then_a_three_dimensional_member():
         assert np.array_equal(s.residual()["res"], r[1]["res"])
     b.close()
     for s in (sa, sb, sc):
+        s.close()
+
+
+def _option_cases():
+    """Solves with every option and combination class: frozen and transported k-omega, both
+    eps modes, the three reconstructions, the multi-dimensional expansion; 2D and 3D, FP64
+    and FP32 flux."""
+    out = []
+
+    def add(case, **kw):
+        for k, v in kw.items():
+            setattr(case, k, v)
+        out.append(case)
+
+    add(C.mixing_layer(40, seed=11))
+    add(C.mixing_layer(36, seed=12), kw_transport=True)
+    add(C.mixing_layer(33, seed=13), eps_mode="tauhat")
+    add(C.sbli(96, 48, precision="fp32_flux"), recon="muscl3")
+    add(C.mixing_layer(34, seed=14), recon="weno5", kw_transport=True)
+    add(C.sbli(40, 20), multi_d=True)
+    add(C.isotropic_box(10, precision="fp32_flux"), kw_transport=True)
+    add(C.isotropic_box(9, precision="fp64"), recon="weno5")
+    add(C.isotropic_box(8, precision="fp64"), multi_d=True, eps_mode="tauhat")
+    add(C.isotropic_box(10, precision="fp64"))
+    return out
+
+
+def _alone_full(case, n):
+    from paper_1302_2132_amd import Solver
+    s = Solver(case)
+    s.step(n)
+    out = (s.fields("cons"), s.residual(), s.fields("turb"))
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_with_every_option_equals_alone_bitwise(graph):
+    """Members of every option share one batch: a face launch per (class, variant) pair
+    present, the transported form's strain and update passes beside the frozen form's; each
+    member's state, residual, time and k, omega equal its solve alone, bitwise."""
+    from paper_1302_2132_amd import Batch, Solver
+    n = 12
+    cases = _option_cases()
+    ref = [_alone_full(c, n) for c in cases]
+    banner(f"batch of {len(cases)} solves with options, graph={graph}")
+    solvers = [Solver(c) for c in cases]
+    b = Batch(solvers, capacity=12)
+    if graph:
+        b.capture()
+    b.step(n)
+    for i, (c, s) in enumerate(zip(cases, solvers)):
+        W, r, kw = s.fields("cons"), s.residual(), s.fields("turb")
+        assert np.array_equal(W, ref[i][0]), (i, c.name)
+        assert np.array_equal(r["res"], ref[i][1]["res"]), (i, c.name)
+        assert r["t"] == ref[i][1]["t"] and r["steps"] == ref[i][1]["steps"], (i, c.name)
+        assert np.array_equal(kw, ref[i][2]), (i, c.name)
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_admitting_a_new_variant_drops_the_graph():
+    from paper_1302_2132_amd import Batch, Solver
+    a, w5 = C.mixing_layer(24, seed=1), C.mixing_layer(30, seed=2)
+    w5.recon, w5.kw_transport = "weno5", True
+    ref_a, ref_w = _alone_full(a, 9), _alone_full(w5, 5)
+    sa, sw = Solver(a), Solver(w5)
+    b = Batch([sa], capacity=4)
+    b.capture()
+    b.step(4)
+    b.set_members([sa, sw])          # a new (class, variant) pair and the transported form
+    b.step(5)
+    assert np.array_equal(sa.fields("cons"), ref_a[0])
+    assert np.array_equal(sw.fields("cons"), ref_w[0])
+    assert np.array_equal(sw.fields("turb"), ref_w[2])
+    b.close()
+    for s in (sa, sw):
         s.close()
 
 

@@ -131,26 +131,6 @@ def test_turb_field_of_a_frozen_solve_is_the_input():
     assert np.array_equal(kw[0], c.k) and np.array_equal(kw[1], c.omega)
 
 
-def test_batch_refuses_a_transported_solve():
-    from paper_1302_2132_amd import GKS_ERR_ARG, Batch, GksError, Solver
-    a = C.mixing_layer(32, seed=2)
-    b = a.copy()
-    b.kw_transport = True
-    sa, sb = Solver(a), Solver(b)
-    try:
-        with pytest.raises(GksError) as e:
-            Batch([sa, sb])
-        assert e.value.status == GKS_ERR_ARG
-        bt = Batch([sa])
-        with pytest.raises(GksError) as e:
-            bt.set_members([sa, sb])
-        assert e.value.status == GKS_ERR_ARG
-        bt.close()
-    finally:
-        sa.close()
-        sb.close()
-
-
 def test_kw_sbli_full_size_one_step():
     """SBLI at 1024 x 512 with transport: after 10 steps on the GPU, the next step from the
     GPU's state (flow, k, omega) compared over the whole mesh with one oracle step."""

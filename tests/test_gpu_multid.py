@@ -74,21 +74,6 @@ def test_multid_fp32_flux_2d_and_3d():
     _compare(C.isotropic_box(16, precision="fp32_flux"), 8, TOL32)
 
 
-def test_multid_is_refused_in_batches():
-    from paper_1302_2132_amd import GKS_ERR_ARG, Batch, GksError, Solver
-    c = C.mixing_layer(32, seed=2)
-    c.multi_d = True
-    a = C.mixing_layer(32, seed=2)
-    sa, sb = Solver(a), Solver(c)
-    try:
-        with pytest.raises(GksError) as e:
-            Batch([sa, sb])
-        assert e.value.status == GKS_ERR_ARG
-    finally:
-        sa.close()
-        sb.close()
-
-
 def test_multid_sbli_full_size_one_step():
     from paper_1302_2132_amd import Solver
     c = C.sbli()
@@ -151,4 +136,3 @@ def test_multid_with_higher_order_face_values_refused():
         with pytest.raises(GksError) as e:
             Solver(c)
         assert e.value.status == GKS_ERR_ARG
-

@@ -90,21 +90,6 @@ def test_muscl3_with_transport_and_tauhat(dim):
     assert np.max(np.abs(e - eo)) <= 1e-12 * max(eo.max(), 1e-300)
 
 
-def test_batch_refuses_a_muscl3_solve():
-    from paper_1302_2132_amd import GKS_ERR_ARG, Batch, GksError, Solver
-    a = C.mixing_layer(32, seed=2)
-    b = a.copy()
-    b.recon = "muscl3"
-    sa, sb = Solver(a), Solver(b)
-    try:
-        with pytest.raises(GksError) as e:
-            Batch([sa, sb])
-        assert e.value.status == GKS_ERR_ARG
-    finally:
-        sa.close()
-        sb.close()
-
-
 def test_muscl3_sbli_full_size_one_step():
     from paper_1302_2132_amd import Solver
     c = C.sbli()

@@ -128,21 +128,6 @@ def test_eps_field_then_steps_continue_unchanged():
     assert np.array_equal(Wa, Wb)
 
 
-def test_batch_refuses_a_tauhat_solve():
-    from paper_1302_2132_amd import GKS_ERR_ARG, Batch, GksError, Solver
-    a = C.mixing_layer(32, seed=2)
-    b = a.copy()
-    b.eps_mode = "tauhat"
-    sa, sb = Solver(a), Solver(b)
-    try:
-        with pytest.raises(GksError) as e:
-            Batch([sa, sb])
-        assert e.value.status == GKS_ERR_ARG
-    finally:
-        sa.close()
-        sb.close()
-
-
 def test_tauhat_sbli_full_size_one_step():
     from paper_1302_2132_amd import Solver
     c = C.sbli()

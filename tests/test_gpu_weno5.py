@@ -124,7 +124,7 @@ def test_weno5_with_tauhat_frozen():
 
 
 def test_weno5_configs_refused():
-    from paper_1302_2132_amd import GKS_ERR_ARG, Batch, GksError, Solver
+    from paper_1302_2132_amd import GKS_ERR_ARG, GksError, Solver
     small = C.uniform_flow(dim=2, n=(2, 6, 1), bc=[["periodic", "periodic"]] * 2)
     small.recon = "weno5"
     with pytest.raises(GksError) as e:
@@ -135,17 +135,6 @@ def test_weno5_configs_refused():
     with pytest.raises(GksError) as e:
         Solver(md)
     assert e.value.status == GKS_ERR_ARG
-    a = C.mixing_layer(32, seed=2)
-    b = a.copy()
-    b.recon = "weno5"
-    sa, sb = Solver(a), Solver(b)
-    try:
-        with pytest.raises(GksError) as e:
-            Batch([sa, sb])
-        assert e.value.status == GKS_ERR_ARG
-    finally:
-        sa.close()
-        sb.close()
 
 
 def test_weno5_sbli_full_size_one_step():
