@@ -249,8 +249,8 @@ gks_status gks_batch_capture(gks_batch b);
  * 2 = fused 2D tile kernel (FP32 flux), 3 = face (3D FP64), 4 = face (3D FP32), 5 = update
  * (3D).  grid = number of persistent workgroups walking the tile table (0 = one per
  * tile).  tile = faces per face-kernel tile and workgroup (64, 128 or 256) for kinds 3
- * and 4, used by the members without options (the others keep 64); 0 otherwise (the 2D
- * tile is fixed: 16 x 15 cells per 256-thread workgroup).
+ * and 4 (a class that holds a member with options keeps 64); 0 otherwise (the 2D tile is
+ * fixed: 16 x 15 cells per 256-thread workgroup).
  * Results do not depend on the launch shape (bitwise).  Invalidates a captured graph. */
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile);
 

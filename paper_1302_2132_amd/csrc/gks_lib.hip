@@ -211,8 +211,11 @@ struct Present {
     std::bitset<NCLS * 32> face;      // bit cls * 32 + variant
     bool strain[2] = {false, false};  // frozen, transported
     bool update[2] = {false, false};  // 3D frozen, 3D transported
+    int tile[NCLS] = {0, 0, 0, 0};    // faces per tile of each class in the table
     bool covers(const Present& o) const
     {
+        for (int c = 0; c < NCLS; ++c)
+            if (tile[c] != o.tile[c]) return false;
         return (o.face & ~face).none() && (strain[0] || !o.strain[0]) && (strain[1] || !o.strain[1]) &&
                (update[0] || !o.update[0]) && (update[1] || !o.update[1]);
     }
@@ -785,7 +788,14 @@ static gks_status batch_upload(gks_batch b)
         present.strain[kw] = true;
         if (h->cfg.dim == 3) present.update[kw] = true;
     }
-    build_table(b->host_tab, b->cap, mem, b->face_tile);
+    // The 3D face kernels with options exist at the default tile only, and a class's table
+    // has one tile size: a 3D class with such a member keeps the default.
+    for (int c = 0; c < NCLS; ++c) {
+        present.tile[c] = b->face_tile[c];
+        for (int v = 1; v < 32; ++v)
+            if (c >= 2 && present.face.test(c * 32 + v)) present.tile[c] = FACE_TILE;
+    }
+    build_table(b->host_tab, b->cap, mem, present.tile);
     if (hipMemcpyAsync(b->tab, b->host_tab.data(), b->host_tab.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
         b->err = "table upload failed";
@@ -854,7 +864,7 @@ static int batch_grid(gks_batch b, int kind)
 // One batch step: the frozen-form strain pass, which also ends every member's previous
 // step, and the transported form's if any member transports k and omega; the face kernel
 // of each (class, variant) pair present (walking its class's tiles, passing the other
-// variants' tiles; variant 0 with the class's tuned tile, the others with the default);
+// variants' tiles, at the class's tile size);
 // the 3D update of each form present.
 static void batch_launch(gks_batch b, const Present& present)
 {
@@ -865,7 +875,7 @@ static void batch_launch(gks_batch b, const Present& present)
     for (int c = 0; c < NCLS; ++c)
         for (int v = 0; v < 32; ++v)
             if (present.face.test(c * 32 + v)) {
-                const int tile = v == 0 ? b->face_tile[c] : FACE_TILE;
+                const int tile = present.tile[c];
                 hipLaunchKernelGGL(face_kernel(c, tile, v), dim3(batch_grid(b, 1 + c)), dim3(face_block(c, tile)), 0,
                                    b->stream, tab, b->cap, c);
             }
