@@ -51,3 +51,34 @@ def test_served_equals_standalone():
         s.close()
         assert np.array_equal(rec["fields"], W), r
         assert np.array_equal(frecs[r["id"]]["fields"], W), r
+
+
+def _make_with_options(req):
+    """The same requests carrying options: WENO5 with transport (mixing layers), the
+    multi-dimensional expansion with transport (SBLI), and the multi-dimensional expansion
+    in the tau_hat mode (isotropic boxes)."""
+    c = _make(req)
+    opts = [dict(recon="weno5", kw_transport=True), dict(multi_d=True, kw_transport=True),
+            dict(multi_d=True, eps_mode="tauhat")][req["family"]]
+    for k, v in opts.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_served_with_options_equals_standalone():
+    from paper_1302_2132_amd import Solver, gks_workspace_bytes, config_from_case
+    from paper_1302_2132_amd.serve import run_batched
+    reqs = _trace()
+    biggest = max(gks_workspace_bytes(config_from_case(_make_with_options(r))) for r in reqs)
+    banner("serving 7 requests with options, budget 2 solves")
+    summ, recs = run_batched(reqs, _make_with_options, hbm_budget=2 * biggest, capacity=4, quantum=6,
+                             keep_fields=True)
+    assert summ["requests"] == len(reqs)
+    for r in reqs:
+        rec = recs[r["id"]]
+        assert rec["steps"] == r["max_steps"]
+        s = Solver(_make_with_options(r))
+        s.step(r["max_steps"])
+        W = s.fields("cons")
+        s.close()
+        assert np.array_equal(rec["fields"], W), r
