@@ -15,7 +15,7 @@ reported as a diagnostic; the mode that puts eps_hat into the time weights is me
 1024^2 mixing layer (it does not stay physical on the SBLI mesh with an explicit global
 step, where it leaves the shock generator's jump with almost no kinetic dissipation).
 
-Prints one JSON line.  --gpus above 1 is refused: this build measures one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark measures one GPU.
 """
 import argparse
 import json
@@ -269,8 +269,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "repeats": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(multi-GPU sharding is a design note only).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(sharding a solve over several GPUs is designed, not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
