@@ -57,26 +57,29 @@ def _leg(case, steps, warmup, eps_field=False):
 
 
 KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_lib.hip", "erfc_poly.hpp")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tile2_sbli_1024x512_hbm_traffic.md")
+TRAFFIC_SUMMARIES = (os.path.join(ROOT, "profiles", "k_tile2_sbli_1024x512_hbm_traffic.md"),
+                     os.path.join(ROOT, "profiles", "k_face_isotropic_256_trace_and_traffic.md"))
 
 
 def _profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when the kernel sources have changed since those counters were taken."""
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summaries, or
+    None when it was not profiled or the kernel sources have changed since its counters
+    were taken."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1302_2132_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    try:
-        text = open(TRAFFIC_SUMMARY).read().splitlines()
-    except OSError:
-        return None
-    vals = dict(line.split(": ", 1) for line in text if ": " in line and not line.startswith(("|", "#")))
-    if vals.get("kernel_sources_sha", "").strip() != h.hexdigest()[:16]:
-        return None
-    v = vals.get(f"traffic_bytes_per_launch {kernel}")
-    return float(v) if v else None
+    for path in TRAFFIC_SUMMARIES:
+        try:
+            text = open(path).read().splitlines()
+        except OSError:
+            continue
+        vals = dict(line.split(": ", 1) for line in text if ": " in line and not line.startswith(("|", "#")))
+        v = vals.get(f"traffic_bytes_per_launch {kernel}")
+        if v and vals.get("kernel_sources_sha", "").strip() == h.hexdigest()[:16]:
+            return float(v)
+    return None
 
 
 def _roofline(case, leg, steps, flops_face, peak):
@@ -121,7 +124,6 @@ def _iso_leg(steps=20, warmup=3):
                      "roofline": _roofline(c, leg, steps, gks_face_flops(3, prec), FP64_PEAK_TFLOPS),
                      "kernel_ms_per_step": {k: round(v / steps, 4) for k, v in leg["kernels"].items()
                                             if k != "steps"}}
-        out[prec]["roofline"]["traffic"] = None
     W32, W64 = legs["fp32_flux"]["W"], legs["fp64"]["W"]
     mom = np.sqrt(sum(W64[1 + d] ** 2 for d in range(3)))
     err = []

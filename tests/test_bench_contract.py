@@ -30,7 +30,7 @@ def test_traffic_reported_only_for_the_profiled_sources(tmp_path, monkeypatch):
     summary = tmp_path / "traffic.md"
     summary.write_text("# traffic\n\ntraffic_bytes_per_launch k_tile2<double,0>: 48587070\n"
                        f"kernel_sources_sha: {_sources_sha()}\n")
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summary))
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARIES", (str(tmp_path / "missing.md"), str(summary)))
     assert bench._profiled_traffic("k_tile2<double,0>") == 48587070.0
     assert bench._profiled_traffic("k_tile2<double,4>") is None          # not profiled
     summary.write_text("traffic_bytes_per_launch k_tile2<double,0>: 48587070\nkernel_sources_sha: 0123456789abcdef\n")
