@@ -15,6 +15,7 @@ import test_oracle_kw as KW
 import test_oracle_multid as MD
 import test_oracle_muscl3 as M3
 import test_oracle_pins as P
+import test_oracle_step_cells as SC
 import test_oracle_tauhat as TH
 import test_oracle_weno5 as W5
 
@@ -99,6 +100,10 @@ MUTANTS = {
     "WENO epsilon": ("const double eps = 1e-6;", "const double eps = 1e-40;"),
     "WENO right value not mirrored": ("*wr = og_weno5(w[4], w[3], w[2], w[1], w[0]);",
                                       "*wr = og_weno5(w[-1], w[0], w[1], w[2], w[3]);"),
+    "sampled-cell flux difference sign": ("acc[m] -= (Fhi[m] - Flo[m]) / gr.dx[d][idx[d] + 2];",
+                                          "acc[m] -= (Flo[m] - Fhi[m]) / gr.dx[d][idx[d] + 2];"),
+    "sampled-cell width of the wrong cell": ("acc[m] -= (Fhi[m] - Flo[m]) / gr.dx[d][idx[d] + 2];",
+                                             "acc[m] -= (Fhi[m] - Flo[m]) / gr.dx[d][idx[d] + 3];"),
 }
 
 
@@ -159,6 +164,8 @@ PINS = [
     lambda: W5.test_closed_forms_match_the_definition(1.0),
     lambda: W5.test_epsilon_matters_for_nearly_linear_data(),
     lambda: W5.test_mirror_and_minmod_gradients(),
+    lambda: SC.step_cells_matches_run("2d_mixed_bc"),
+    lambda: SC.step_cells_matches_run("3d_mixed_bc"),
 ]
 
 
