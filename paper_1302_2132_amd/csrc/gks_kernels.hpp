@@ -984,6 +984,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
 }
 
 // Max CFL rate of the current state of each member (first step at init).
+#ifdef GKS_LIB_UNIT   // defined in the library unit only
 __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ table, int cap)
 {
     const TabC tv(table, cap);
@@ -1035,6 +1036,9 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
         __syncthreads();
     }
 }
+#else
+extern __global__ void k_rate(const void* __restrict__ table, int cap);
+#endif
 
 // End of a step (mode 0) or of the initial rate pass (mode 1) of one member, by one
 // workgroup: residual from the per-tile partial sums and the CFL rate from the per-tile
@@ -1100,6 +1104,7 @@ __device__ inline void finish_member(cref<Inst> I, int mode, double* sh)
     __syncthreads();
 }
 
+#ifdef GKS_LIB_UNIT   // defined in the library unit only
 __global__ __launch_bounds__(CELL_TILE) void k_finish(const void* __restrict__ table, int cap, int mode)
 {
     const TabC tv(table, cap);
@@ -1107,6 +1112,9 @@ __global__ __launch_bounds__(CELL_TILE) void k_finish(const void* __restrict__ t
     __shared__ double sh[6 * 4];
     for (int mi = blockIdx.x; mi < count; mi += gridDim.x) finish_member(tv.inst[mi], mode, sh);
 }
+#else
+extern __global__ void k_finish(const void* __restrict__ table, int cap, int mode);
+#endif
 
 // Strain pass over every cell tile of the table (of active members unless `force`).
 // With `finish` set, the first `count` work items instead end the pending step of each
@@ -1197,6 +1205,7 @@ __global__ __launch_bounds__(64) void k_eps(const void* __restrict__ table, int 
 
 // Copy of every member's step state into one array, so that a batch's states come back
 // to the host in one read.
+#ifdef GKS_LIB_UNIT   // defined in the library unit only
 __global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, int cap, State* __restrict__ out)
 {
     const TabC tv(table, cap);
@@ -1206,31 +1215,26 @@ __global__ __launch_bounds__(64) void k_states(const void* __restrict__ table, i
         out[i] = *st;
     }
 }
+#else
+extern __global__ void k_states(const void* __restrict__ table, int cap, State* __restrict__ out);
+#endif
 
-#define GKS_TILE2(V)                                                    \
-    template __global__ void k_tile2<double, V>(const void*, int, int); \
-    template __global__ void k_tile2<float, V>(const void*, int, int);
-#define GKS_FACE(T, V)                                                       \
-    template __global__ void k_face<double, 3, T, V>(const void*, int, int); \
-    template __global__ void k_face<float, 3, T, V>(const void*, int, int);
-GKS_TILE2(0) GKS_TILE2(1) GKS_TILE2(2) GKS_TILE2(3) GKS_TILE2(4) GKS_TILE2(5) GKS_TILE2(6) GKS_TILE2(7)
-GKS_FACE(64, 0) GKS_FACE(128, 0) GKS_FACE(256, 0)
-GKS_FACE(64, 1) GKS_FACE(64, 2) GKS_FACE(64, 3) GKS_FACE(64, 4) GKS_FACE(64, 5) GKS_FACE(64, 6) GKS_FACE(64, 7)
-GKS_TILE2(8) GKS_TILE2(9) GKS_TILE2(10) GKS_TILE2(11)
-GKS_FACE(64, 8) GKS_FACE(64, 9) GKS_FACE(64, 10) GKS_FACE(64, 11)
-GKS_TILE2(16) GKS_TILE2(17) GKS_TILE2(18) GKS_TILE2(19)
-GKS_FACE(64, 16) GKS_FACE(64, 17) GKS_FACE(64, 18) GKS_FACE(64, 19)
-#undef GKS_TILE2
-#undef GKS_FACE
-template __global__ void k_eps<0>(const void*, int, double*);
-template __global__ void k_eps<V_TH>(const void*, int, double*);
-template __global__ void k_eps<V_R3>(const void*, int, double*);
-template __global__ void k_eps<V_W5>(const void*, int, double*);
-template __global__ void k_eps<V_TH | V_W5>(const void*, int, double*);
-template __global__ void k_eps<V_TH | V_R3>(const void*, int, double*);
-template __global__ void k_update<false>(const void*, int);
-template __global__ void k_update<true>(const void*, int);
-template __global__ void k_strain<false>(const void*, int, int, int);
-template __global__ void k_strain<true>(const void*, int, int, int);
+// The face-kernel instantiations are defined in the gks_inst_*.hip units, which the build
+// compiles in parallel; every other unit sees these declarations only.  GKS_TILE2_VARIANTS
+// and GKS_FACE_VARIANTS list every (tile, variant) pair the library launches.
+#define GKS_TILE2_VARIANTS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(16) X(17) X(18) X(19)
+#define GKS_FACE_VARIANTS(X)                                                                         \
+    X(64, 0) X(128, 0) X(256, 0) X(64, 1) X(64, 2) X(64, 3) X(64, 4) X(64, 5) X(64, 6) X(64, 7) X(64, 8) \
+        X(64, 9) X(64, 10) X(64, 11) X(64, 16) X(64, 17) X(64, 18) X(64, 19)
+#define GKS_TILE2_DECL(V)                                                      \
+    extern template __global__ void k_tile2<double, V>(const void*, int, int); \
+    extern template __global__ void k_tile2<float, V>(const void*, int, int);
+#define GKS_FACE_DECL(T, V)                                                           \
+    extern template __global__ void k_face<double, 3, T, V>(const void*, int, int); \
+    extern template __global__ void k_face<float, 3, T, V>(const void*, int, int);
+GKS_TILE2_VARIANTS(GKS_TILE2_DECL)
+GKS_FACE_VARIANTS(GKS_FACE_DECL)
+#undef GKS_TILE2_DECL
+#undef GKS_FACE_DECL
 
 }  // namespace gks

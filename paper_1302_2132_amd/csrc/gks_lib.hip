@@ -14,13 +14,28 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/gks.h"
+#define GKS_LIB_UNIT
 #include "gks_kernels.hpp"
 
 using namespace gks;
+
+namespace gks {
+template __global__ void k_eps<0>(const void*, int, double*);
+template __global__ void k_eps<V_TH>(const void*, int, double*);
+template __global__ void k_eps<V_R3>(const void*, int, double*);
+template __global__ void k_eps<V_W5>(const void*, int, double*);
+template __global__ void k_eps<V_TH | V_W5>(const void*, int, double*);
+template __global__ void k_eps<V_TH | V_R3>(const void*, int, double*);
+template __global__ void k_update<false>(const void*, int);
+template __global__ void k_update<true>(const void*, int);
+template __global__ void k_strain<false>(const void*, int, int, int);
+template __global__ void k_strain<true>(const void*, int, int, int);
+}  // namespace gks
 
 namespace {
 
@@ -402,7 +417,9 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
                 }
         }
 
-    gks_ctx* h = new gks_ctx();
+    // owned until the call succeeds: every early return below frees the context
+    std::unique_ptr<gks_ctx> owner(new gks_ctx());
+    gks_ctx* h = owner.get();
     h->cfg = *cfg;
     for (int d = 0; d < 3; ++d) {
         h->cfg.xf[d] = nullptr;
@@ -525,11 +542,8 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     State st;
     HIP_TRY(h, hipMemcpyAsync(&st, I.st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
-    if (st.err) {
-        delete h;
-        return fail_h(nullptr, GKS_ERR_NONPHYSICAL, "initial state is not physical");
-    }
-    *out = h;
+    if (st.err) return fail_h(nullptr, GKS_ERR_NONPHYSICAL, "initial state is not physical");
+    *out = owner.release();
     return GKS_OK;
 }
 

@@ -138,3 +138,31 @@ def test_binding_loads_torch_runtime_first():
     assert r.returncode == 0, r.stderr[-1000:]
     paths = eval(r.stdout.strip().splitlines()[-1])
     assert len(paths) == 1, paths
+
+
+def test_failed_init_frees_its_context():
+    """A gks_init that fails after creating its context (here: the first device copy, on
+    a host without a device or with a bogus workspace pointer) frees it: repeating the
+    failure does not grow the process (each context holds ~1.5 KB)."""
+    import subprocess
+    import sys
+    code = ("import ctypes\n"
+            "import paper_1302_2132_amd as P\n"
+            "from inputs import cases as C\n"
+            "P.lib()\n"
+            "n = ctypes.c_int(-1)\n"
+            "ctypes.CDLL('libamdhip64.so.7').hipGetDeviceCount(ctypes.byref(n))\n"
+            "assert n.value <= 0, 'a device is visible: the bogus workspace must never reach one'\n"
+            "c = C.mixing_layer(4); cfg = P.config_from_case(c)\n"
+            "def rss(): return int(open('/proc/self/statm').read().split()[1]) * 4096\n"
+            "def fail(n):\n"
+            "    for _ in range(n):\n"
+            "        try: P.gks_init(cfg, 256, 1 << 30, 0, c.W, c.k, c.omega)\n"
+            "        except P.GksError as e: assert e.status == P.GKS_ERR_DEVICE, e\n"
+            "fail(500); r0 = rss(); fail(20000)\n"
+            "print('growth', (rss() - r0) / 1e6)\n")
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="-1", ROCR_VISIBLE_DEVICES="-1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    growth = float(r.stdout.split()[-1])
+    assert growth < 5.0, growth          # 20000 leaked contexts would be ~30 MB

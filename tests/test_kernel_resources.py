@@ -14,7 +14,6 @@ inlined or grew (or values derived from the thread index were kept live across t
 loop), and costs scratch traffic to HBM on every face."""
 import os
 import re
-import subprocess
 
 import pytest
 
@@ -23,14 +22,18 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 @pytest.fixture(scope="module")
 def remarks(tmp_path_factory):
+    import concurrent.futures as cf
+
     from paper_1302_2132_amd import build as B
-    out = tmp_path_factory.mktemp("res") / "libgks_res.so"
-    cmd = [B.HIPCC] + B.FLAGS + ["-Rpass-analysis=kernel-resource-usage", "-o", str(out),
-                                 os.path.join(B.CSRC, "gks_lib.hip")]
-    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
-    assert r.returncode == 0, r.stderr[-2000:]
+    out = tmp_path_factory.mktemp("res")
+    units = B.units()
+    with cf.ThreadPoolExecutor(max_workers=min(len(units), os.cpu_count() or 1)) as ex:
+        runs = list(ex.map(lambda u: B.compile_unit(u[0], u[1], str(out / u[2]),
+                                                     ["-Rpass-analysis=kernel-resource-usage"]), units))
+    for r in runs:
+        assert r.returncode == 0, r.stderr[-2000:]
     res, name = {}, None
-    for line in r.stderr.splitlines():
+    for line in "\n".join(r.stderr for r in runs).splitlines():
         m = re.search(r"Function Name: (\S+)", line)
         if m:
             name = m.group(1)
