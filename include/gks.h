@@ -263,6 +263,24 @@ gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* re
 
 gks_status gks_batch_destroy(gks_batch b);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gks_batch_create without a workspace.
+ * The batch's scratch -- its tile table and the read-back array of its members' step
+ * states -- lives in a static device array of the library (one per device, ~0.2 MB,
+ * held by each device the library runs on until the process ends), sized for up to
+ * GKS_BATCH_STATIC_CAPACITY members.  The members' own workspaces are still the caller's.
+ * The call allocates nothing (no hipMalloc, no allocating library routine); it fills the
+ * table with one host-to-device copy on `hip_stream` and waits for it.
+ * Limits and errors: capacity > GKS_BATCH_STATIC_CAPACITY -> GKS_ERR_ARG; at most one
+ * such batch exists per device at a time: a second call on a device whose array serves a
+ * live batch returns GKS_ERR_STATE until gks_batch_destroy of the first releases it.  The
+ * array keeps the last batch's contents; every batch rewrites all of it that it reads.
+ * Calls on one such batch from several threads at once race, as for any batch.  The
+ * batch is then used with every gks_batch_* call like one made by gks_batch_create. */
+enum { GKS_BATCH_STATIC_CAPACITY = 256 };
+gks_status gks_batch_create_static(const gks_handle* hs, int32_t count, int32_t capacity, void* hip_stream,
+                                   gks_batch* out);
+
 #ifdef __cplusplus
 }
 #endif

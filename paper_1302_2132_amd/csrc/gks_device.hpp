@@ -84,7 +84,7 @@ struct TabHdr {
     int total_face[NCLS];
 };
 
-__host__ __device__ inline size_t tab_align(size_t x) { return (x + 255) & ~size_t(255); }
+__host__ __device__ constexpr size_t tab_align(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct TabView {
     TabHdr* hdr;
@@ -105,7 +105,7 @@ struct TabView {
         off += sizeof(int) * (size_t)NCLS * cap;
         cls_prefix = (int*)(p + off);
     }
-    __host__ __device__ static size_t bytes(int cap)
+    __host__ __device__ static constexpr size_t bytes(int cap)
     {
         size_t off = tab_align(sizeof(TabHdr));
         off = tab_align(off + sizeof(Inst) * (size_t)cap);

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -249,6 +250,7 @@ struct gks_batch_ctx {
     Present present;                  // launches the current (or captured) step makes
     std::vector<char> host_tab;
     std::string err;
+    int static_dev = -1;              // device whose static scratch holds the table, or -1
 };
 
 static gks_status fail_h(gks_ctx* h, gks_status s, const std::string& msg)
@@ -774,7 +776,58 @@ const char* gks_last_error(gks_handle h)
 // ------------------------------------------------------------------------------------
 // Batch workspace: the tile table, then an array of cap step states (the read-back buffer
 // of gks_batch_status).
-static size_t batch_bytes(int cap) { return TabView::bytes(cap) + tab_align(sizeof(State) * (size_t)cap); }
+static constexpr size_t batch_bytes(int cap) { return TabView::bytes(cap) + tab_align(sizeof(State) * (size_t)cap); }
+
+// Scratch of the workspace-free batch (gks_batch_create_static): the tile table and the
+// read-back array of one batch of up to GKS_BATCH_STATIC_CAPACITY members per device, in a
+// file-scope device array that each device holds until the process ends.  In host code
+// `scratch` names a host-side stand-in: its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current and kept in g_static[dev].ptr, and only
+// that address is ever handed to kernels or copies.
+constexpr size_t kStaticScratchBytes = batch_bytes(GKS_BATCH_STATIC_CAPACITY);
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct StaticSlot {
+    void* ptr = nullptr;   // device address of `scratch` on this device
+    bool busy = false;     // a workspace-free batch exists on this device
+};
+std::mutex g_static_mu;
+StaticSlot g_static[kMaxDevices];
+}  // namespace
+
+// Claim the current device's scratch for one batch: its device address (looked up on the
+// first claim) or an error when the device's scratch already serves a live batch.
+static gks_status claim_static(int* dev_out, void** ptr_out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail_h(nullptr, GKS_ERR_DEVICE, "no current HIP device");
+    if (dev >= kMaxDevices) return fail_h(nullptr, GKS_ERR_ARG, "device ordinal beyond the library's static table");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticSlot& slot = g_static[dev];
+    if (slot.busy)
+        return fail_h(nullptr, GKS_ERR_STATE,
+                      "a workspace-free batch already exists on this device (destroy it first)");
+    if (!slot.ptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail_h(nullptr, GKS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        slot.ptr = p;
+    }
+    slot.busy = true;
+    *dev_out = dev;
+    *ptr_out = slot.ptr;
+    return GKS_OK;
+}
+
+static void release_static(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[dev].busy = false;
+}
 static State* batch_states(gks_batch b) { return (State*)((char*)b->tab + TabView::bytes(b->cap)); }
 
 gks_status gks_batch_workspace_bytes(int32_t capacity, size_t* bytes)
@@ -826,31 +879,66 @@ static gks_status batch_upload(gks_batch b)
     return GKS_OK;
 }
 
-gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity, void* dev_workspace, size_t bytes,
-                            void* hip_stream, gks_batch* out)
+// A batch over `hs` whose table lives at `tab` (a caller workspace or a device's scratch).
+static gks_status batch_make(const gks_handle* hs, int32_t count, int32_t capacity, void* tab, void* hip_stream,
+                             int static_dev, gks_batch* out)
 {
-    if (!out || (!hs && count) || count < 0 || capacity < 1 || count > capacity || !dev_workspace)
-        return fail_h(nullptr, GKS_ERR_ARG, "bad batch arguments");
-    if (bytes < batch_bytes(capacity)) return fail_h(nullptr, GKS_ERR_NOMEM, "batch workspace too small");
-    if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
-    for (int i = 0; i < count; ++i)
-        if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
     gks_batch b = new gks_batch_ctx();
     b->members.assign(hs, hs + count);
     b->cap = capacity;
     b->stream = (hipStream_t)hip_stream;
-    b->tab = dev_workspace;
+    b->tab = tab;
     b->captured = false;
+    b->static_dev = static_dev;
     const int cus = device_cus();
     b->grid[0] = cus * 8;        // strain: 256-thread workgroups
     b->grid[5] = cus * 8;        // update
     b->grid[1] = b->grid[2] = 0;                       // fused 2D kernel: one workgroup per tile
     b->grid[3] = b->grid[4] = cus * 16;                // 3D face: one-wave workgroups
     for (int c = 0; c < NCLS; ++c) b->face_tile[c] = FACE_TILE;
+    // the whole table image (zeros included) is written before any kernel reads it, so a
+    // reused scratch needs no clearing; the read-back array is written by k_states first
     gks_status r = batch_upload(b);
     if (r != GKS_OK) { delete b; return r; }
     *out = b;
     return GKS_OK;
+}
+
+static gks_status batch_args_ok(const gks_handle* hs, int32_t count, int32_t capacity)
+{
+    if ((!hs && count) || count < 0 || capacity < 1 || count > capacity)
+        return fail_h(nullptr, GKS_ERR_ARG, "bad batch arguments");
+    for (int i = 0; i < count; ++i)
+        if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
+    return GKS_OK;
+}
+
+gks_status gks_batch_create(const gks_handle* hs, int32_t count, int32_t capacity, void* dev_workspace, size_t bytes,
+                            void* hip_stream, gks_batch* out)
+{
+    if (!out || !dev_workspace) return fail_h(nullptr, GKS_ERR_ARG, "bad batch arguments");
+    gks_status r = batch_args_ok(hs, count, capacity);
+    if (r != GKS_OK) return r;
+    if (bytes < batch_bytes(capacity)) return fail_h(nullptr, GKS_ERR_NOMEM, "batch workspace too small");
+    if (((uintptr_t)dev_workspace) & 255) return fail_h(nullptr, GKS_ERR_ARG, "workspace must be 256-byte aligned");
+    return batch_make(hs, count, capacity, dev_workspace, hip_stream, -1, out);
+}
+
+gks_status gks_batch_create_static(const gks_handle* hs, int32_t count, int32_t capacity, void* hip_stream,
+                                   gks_batch* out)
+{
+    if (!out) return fail_h(nullptr, GKS_ERR_ARG, "out is NULL");
+    gks_status r = batch_args_ok(hs, count, capacity);
+    if (r != GKS_OK) return r;
+    if (capacity > GKS_BATCH_STATIC_CAPACITY)
+        return fail_h(nullptr, GKS_ERR_ARG, "capacity exceeds GKS_BATCH_STATIC_CAPACITY (256) members");
+    int dev = -1;
+    void* ptr = nullptr;
+    r = claim_static(&dev, &ptr);
+    if (r != GKS_OK) return r;
+    r = batch_make(hs, count, capacity, ptr, hip_stream, dev, out);
+    if (r != GKS_OK) release_static(dev);
+    return r;
 }
 
 gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t count)
@@ -989,6 +1077,7 @@ gks_status gks_batch_destroy(gks_batch b)
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);
     }
+    if (b->static_dev >= 0) release_static(b->static_dev);
     delete b;
     return GKS_OK;
 }

@@ -29,7 +29,9 @@ EXPORTED = (
     "gks_set_timing", "gks_kernel_times",
     "gks_batch_workspace_bytes", "gks_batch_create", "gks_batch_set_members", "gks_batch_step",
     "gks_batch_capture", "gks_batch_set_launch", "gks_batch_status", "gks_batch_destroy",
+    "gks_batch_create_static",
 )
+GKS_BATCH_STATIC_CAPACITY = 256
 
 
 class GksError(RuntimeError):
@@ -97,6 +99,7 @@ def lib():
         L.gks_batch_set_launch.argtypes = [vp, i32, i32, i32]
         L.gks_batch_status.argtypes = [vp, C.POINTER(i64), dp, dp, dp, C.POINTER(i32)]
         L.gks_batch_destroy.argtypes = [vp]
+        L.gks_batch_create_static.argtypes = [C.POINTER(vp), i32, i32, vp, C.POINTER(vp)]
         for nm in EXPORTED:
             if nm != "gks_last_error":
                 getattr(L, nm).restype = C.c_int
@@ -256,6 +259,13 @@ def gks_batch_create(hs, capacity, workspace_ptr, nbytes, stream_ptr):
     return b
 
 
+def gks_batch_create_static(hs, capacity, stream_ptr):
+    b = C.c_void_p()
+    _check(lib().gks_batch_create_static(_handles(hs), len(hs), int(capacity), C.c_void_p(stream_ptr),
+                                         C.byref(b)))
+    return b
+
+
 def gks_batch_set_members(b, hs):
     _check(lib().gks_batch_set_members(b, _handles(hs), len(hs)))
 
@@ -342,20 +352,26 @@ class Solver:
 
 
 class Batch:
-    """Persistent-kernel batch over existing Solvers (their handles and workspaces)."""
+    """Persistent-kernel batch over existing Solvers (their handles and workspaces).  With
+    static=True the batch takes no workspace of its own (gks_batch_create_static)."""
 
-    def __init__(self, solvers, capacity=None, device="cuda:0", stream=None):
+    def __init__(self, solvers, capacity=None, device="cuda:0", stream=None, static=False):
         import torch
         self.solvers = list(solvers)
         self.capacity = capacity or max(len(self.solvers), 1)
-        nbytes = gks_batch_workspace_bytes(self.capacity)
         with torch.cuda.device(device):
             # a stream of its own: the null stream cannot be captured into a graph
             if stream is None:
                 stream = torch.cuda.Stream(device=device)
             self.stream, sp = _torch_stream(stream)
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-            self.b = gks_batch_create([s.h for s in self.solvers], self.capacity, self.ws.data_ptr(), nbytes, sp)
+            if static:
+                self.ws = None
+                self.b = gks_batch_create_static([s.h for s in self.solvers], self.capacity, sp)
+            else:
+                nbytes = gks_batch_workspace_bytes(self.capacity)
+                self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+                self.b = gks_batch_create([s.h for s in self.solvers], self.capacity, self.ws.data_ptr(), nbytes,
+                                          sp)
 
     def set_members(self, solvers):
         self.solvers = list(solvers)
