@@ -64,9 +64,16 @@ typedef enum {
  * (wrapped for PERIODIC, mirrored for WALL, nearest boundary cell otherwise). */
 enum { GKS_BC_PERIODIC = 0, GKS_BC_WALL = 1, GKS_BC_DIRICHLET = 2, GKS_BC_PROFILE = 3, GKS_BC_OUTFLOW = 4 };
 
-/* Arithmetic of the flux evaluation.  FP32_FLUX evaluates moments, coefficients and the
- * time-integrated flux in FP32; reconstruction, primitive recovery, the conservative
- * update and the time-step/residual reductions stay FP64. */
+/* Arithmetic of the flux evaluation.  FP32_FLUX evaluates the non-equilibrium part of the
+ * flux in FP32: the slopes of the initial and equilibrium distributions (Eqs. initialf0,
+ * eqlgform), the time coefficients A and Abar, and their time-weighted moment
+ * contractions (the gam1, gam2, gam4, gam5 terms of Eq. fluxesf).  Everything of the size
+ * of the pressure flux p dt stays FP64: the half-space moments of the two sides, the
+ * interface state W0 (Eq. intermediatestate), the time weights, the Euler flux of W0 over
+ * gam0 and the collisionless flux of the two sides over gam3, and the heat-flux
+ * correction; so do the reconstruction, primitive recovery, the face fluxes as stored, the
+ * conservative update and the time-step/residual reductions.  FP32 rounding therefore
+ * scales with the viscous and slope terms, not with p dt. */
 enum { GKS_FP64 = 0, GKS_FP32_FLUX = 1 };
 
 /* Degree of rarefaction in the time weights of the flux.
@@ -138,6 +145,10 @@ typedef struct {
     int32_t recon;                /* GKS_RECON_MUSCL2, GKS_RECON_MUSCL3 or GKS_RECON_WENO5 */
     int32_t multi_d;              /* 1: multi-dimensional expansion (with GKS_RECON_MUSCL2;
                                      combines with turb_transport and either eps_mode) */
+    double res_tol;               /* > 0: the solve stops (on the device) at the end of the first
+                                     step n >= 2 with max_m res_m / res_first_m <= res_tol over
+                                     the flow fields whose first-step residual is > 0 (the
+                                     residual-fall criterion of a converging solve); 0: never */
 } gks_config;
 
 typedef struct gks_ctx* gks_handle;
@@ -255,8 +266,8 @@ gks_status gks_batch_capture(gks_batch b);
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile);
 
 /* Synchronise; copy per-member steps done, residual of the last step and of the first
- * step (5 slots per member each), time and status (0 running, 1 done by t_end or
- * max_steps, 2 error) into host arrays (any NULL).  The states are gathered on the
+ * step (5 slots per member each), time and status (0 running, 1 done by t_end, max_steps
+ * or res_tol, 2 error) into host arrays (any NULL).  The states are gathered on the
  * device after the queued steps and read back in one copy. */
 gks_status gks_batch_status(gks_batch b, int64_t* steps, double* res, double* res_first, double* t,
                             int32_t* state);

@@ -47,6 +47,7 @@ class Case:
     steps: int = 100
     precision: str = "fp64"       # "fp64" | "fp32_flux"
     max_steps: int = 0            # > 0: a solver stops after this many steps
+    res_tol: float = 0.0          # > 0: a solver stops once max_m res_m / res_first_m <= res_tol
     kw_transport: bool = False    # transport k and omega with the flow (else frozen inputs)
     eps_mode: str = "dt"          # rarefaction in the time weights: "dt" (tau/dt) or "tauhat" (tau/tau_hat)
     recon: str = "muscl2"         # face values: "muscl2" (minmod), "muscl3" (limited kappa = 1/3) or "weno5"
@@ -449,6 +450,7 @@ def request_case(req) -> Case:
         c = isotropic_box(side, seed=seed, steps=req["max_steps"], precision="fp32_flux")
     c.name = f"req{req['id']}_{c.name}"
     c.max_steps = int(req["max_steps"])
+    c.res_tol = float(req["tol"])
     return c
 
 

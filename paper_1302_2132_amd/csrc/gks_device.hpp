@@ -57,7 +57,7 @@ struct Inst {
     double* Qk;                // transport only: sources of rho k and rho omega per cell,
     double* Qw;
     double* nt;                // and the eddy viscosity rho k / omega of the diffusive fluxes
-    void* F[3];                // 3D face fluxes per axis: [nv (+2)][nface[d]], double or float (2D: none)
+    void* F[3];                // 3D face fluxes per axis: [nv (+2)][nface[d]], FP64 (2D: none)
     const double* xf[3];
     const double* xc[3];
     const double* dx[3];
@@ -74,6 +74,7 @@ struct Inst {
     int ntile_face_all;
     int face_tile;             // faces per face-kernel tile in the table holding this copy
     long long max_steps;       // > 0: deactivate after this many steps
+    double res_tol;            // > 0: deactivate once max_m res_m / res_first_m <= res_tol (steps >= 2)
 };
 
 // Tile table header; arrays follow at offsets computed by TabView.

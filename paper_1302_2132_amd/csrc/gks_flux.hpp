@@ -27,6 +27,8 @@
 #define GKS_HD __host__ __device__
 #endif
 
+#include <type_traits>
+
 #include "erfc_poly.hpp"
 
 namespace gks {
@@ -462,93 +464,122 @@ GKS_HD inline bool prim_wide(const H* W, H two_over_b, H& rho, H& irho, H* U, H&
     return (rho > H(0)) && (p > H(0)) && (p < H(1e300)) && (rho < H(1e300));
 }
 
-// Time weights of a face in a flux mode other than 0.  tau_hat = rho0/|D rho|, with
-// D rho = U0 d_x rho - d_x (rho U) along the normal (mass conservation gives
-// d_t rho = -d_x (rho U)) from the mean of the one-sided gradients through the interface
-// state W0 (rho w00, normal momentum w01); eps_hat = tau/tau_hat.
-template <typename R, int D, typename H, int MODE>
-GKS_HD __attribute__((always_inline)) inline void mode_weights(const FaceIn<D, H>& in, H tau, const R* W0,
-                                                               const H* U0d, H ir0, R dt, R* F, Kw<R>& kw)
+// Time weights of a face in a flux mode other than 0, in the wide type.  tau_hat =
+// rho0/|D rho|, with D rho = U0 d_x rho - d_x (rho U) along the normal (mass conservation
+// gives d_t rho = -d_x (rho U)) from the mean of the one-sided gradients through the
+// interface state W0 (rho w00, normal momentum w01); eps_hat = tau/tau_hat, stored in
+// Fout[D + 2] with FLUX_EPS_OUT.
+template <int D, typename H, int MODE>
+GKS_HD __attribute__((always_inline)) inline Kw<H> mode_weights(const FaceIn<D, H>& in, H tau, const H* W0,
+                                                               const H* U0d, H ir0, H* Fout)
 {
-    const H w00 = H(W0[0]), w01 = H(W0[1]);
+    const H w00 = W0[0], w01 = W0[1];
     const H grho = H(0.5) * ((w00 - in.Wi[0]) * in.idl + (in.Wi1[0] - w00) * in.idr);
     const H gmom = H(0.5) * ((w01 - in.Wi[1]) * in.idl + (in.Wi1[1] - w01) * in.idr);
     const H eps = tau * g_abs(U0d[0] * grho - gmom) * ir0;
-    if (MODE & FLUX_EPS_OUT) F[D + 2] = R(eps);
-    kw = (MODE & FLUX_TAUHAT) ? kogan_e(R(tau), R(in.dt * eps), dt) : kogan(R(tau), dt);
+    if (MODE & FLUX_EPS_OUT) Fout[D + 2] = eps;
+    return (MODE & FLUX_TAUHAT) ? kogan_e(tau, in.dt * eps, in.dt) : kogan(tau, in.dt);
 }
 
-// The flux.  Returns 0, or 1 when a state met is non-physical (then F is meaningless).
-// F receives the time-integrated flux (it already contains dt) in the face-local frame.
+template <typename R, typename H>
+GKS_HD inline Kw<R> kw_narrow(const Kw<H>& k)
+{
+    Kw<R> r;
+    for (int j = 0; j < 6; ++j) r.g[j] = R(k.g[j]);
+    r.c1 = R(k.c1);
+    r.c4 = R(k.c4);
+    r.c5 = R(k.c5);
+    return r;
+}
+
+// Narrow copy of a wide Maxwellian (vt2 and q formed in the narrow type).
+template <typename R, typename H, int D>
+GKS_HD inline void mx_narrow(Mx<R, D>& g, const Mx<H, D>& w, R bt)
+{
+    R u[D];
+    for (int d = 0; d < D; ++d) u[d] = R(w.U[d]);
+    mx_set(g, R(w.rho), u, R(w.lam), R(w.h), bt);
+}
+
+// The flux.  Returns 0, or 1 when a state met is non-physical (then Fout is meaningless).
+// Fout receives the time-integrated flux (it already contains dt) in the face-local frame,
+// in the wide type H.
+//
+// R is the arithmetic of the flux; H (FP64 on the device) that of the reconstructed
+// states.  When R is narrower than H (the FP32-flux form), every part of the flux of size
+// p dt is kept in H: the half-line moments of the two sides, the interface state W0, the
+// time weights, and the two terms that hold the Euler-like part of the flux,
+//   gam0 rho0 <u psi>_g0  (the Euler flux of W0)  and
+//   gam3 (rho_l <u psi>_{l,>0} + rho_r <u psi>_{r,<0})  (the collisionless flux),
+// with gam0 + gam3 = dt.  R then carries only the non-equilibrium terms (the slopes a, A,
+// abar, Abar and their gam1, gam2, gam4, gam5 contractions), which are smaller than p dt by
+// about tau |grad W|/W, so the FP32 rounding no longer sets an absolute error floor of
+// order eps_32 p dt in the normal-momentum flux; the heat-flux correction is assembled in
+// H as well.  When R = H the evaluation is a single pass in R.
 //
 // Evaluation order keeps few values live: after the interface state and tau are known,
 // the equilibrium-slope terms, then the left side, then the right side are each folded
 // into F and into the right-hand side Rv of the Abar system as soon as their
 // coefficients exist; Abar and the remaining equilibrium terms come last.
 template <typename R, int D, typename H = double, int MODE = 0>
-GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, R* F)
+GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, H* Fout)
 {
     constexpr int NV = D + 2;
+    constexpr bool SPLIT = !std::is_same<R, H>::value;
     const R b = R(gas.b), inv_b = R(gas.inv_b), bt = R(gas.b - 1.0);
+    const H btw = H(gas.b - 1.0);
     const R half = R(0.5);
-    const R rsqpi_half = R(0.28209479177387814);   // 1/(2 sqrt(pi))
+    const H rsqpi_half = H(0.28209479177387814);   // 1/(2 sqrt(pi))
     const H bw = H(gas.two_over_b);
 
-    // --- left / right Maxwellians (wide primitive recovery) -------------------------
+    // --- left / right Maxwellians (wide primitive recovery; narrow copies) ------------
     H rl, irl, Ul[D], pl, rr, irr, Ur[D], pr;
     if (!prim_wide<D>(in.Wl, bw, rl, irl, Ul, pl) || !prim_wide<D>(in.Wr, bw, rr, irr, Ur, pr)) return 1;
+    Mx<H, D> glw, grw;
+    mx_set(glw, rl, Ul, H(0.5) * rl * g_rcp(pl), pl * irl, btw);   // 1/(2 lambda) = p/rho
+    mx_set(grw, rr, Ur, H(0.5) * rr * g_rcp(pr), pr * irr, btw);
     Mx<R, D> gl, gr;
-    {
-        R u[D];
-        const H hl = pl * irl, hr = pr * irr;        // 1/(2 lambda) = p/rho
-        for (int d = 0; d < D; ++d) u[d] = R(Ul[d]);
-        mx_set(gl, R(rl), u, R(H(0.5) * rl * g_rcp(pl)), R(hl), bt);
-        for (int d = 0; d < D; ++d) u[d] = R(Ur[d]);
-        mx_set(gr, R(rr), u, R(H(0.5) * rr * g_rcp(pr)), R(hr), bt);
-    }
+    mx_narrow(gl, glw, bt);
+    mx_narrow(gr, grw, bt);
 
-    // --- half-line u-moments: left over u>0, right over u<0.  Only <u^0>, <u^1> are
-    //     kept; higher ones are regenerated by the recurrence where they are used. ----
+    // --- half-line u-moments: left over u>0, right over u<0 (wide).  Only <u^0>, <u^1>
+    //     are kept; higher ones are regenerated by the recurrence where they are used. --
     //     <u^0>_{>0} = erfc(-sqrt(lambda) U)/2, <u^0>_{<0} = erfc(sqrt(lambda) U)/2; the
     //     exp(-lambda U^2) of the first moment also scales the erfc evaluation.
-    R ml01[2], mr01[2];
+    H ml01[2], mr01[2];
     {
-        const R isq = g_rsqrt(gl.lam);                // 1/sqrt(lambda)
-        const R U = gl.U[0];
-        const R x = -gl.lam * isq * U;
-        const R e = g_exp(-gl.lam * U * U);
-        const R hs = half * erfc_e(g_abs(x), e);
-        ml01[0] = x >= R(0) ? hs : R(1) - hs;
+        const H isq = g_rsqrt(glw.lam);               // 1/sqrt(lambda)
+        const H U = glw.U[0];
+        const H x = -glw.lam * isq * U;
+        const H e = g_exp(-glw.lam * U * U);
+        const H hs = H(0.5) * erfc_e(g_abs(x), e);
+        ml01[0] = x >= H(0) ? hs : H(1) - hs;
         ml01[1] = U * ml01[0] + e * rsqpi_half * isq;
     }
     {
-        const R isq = g_rsqrt(gr.lam);
-        const R U = gr.U[0];
-        const R x = gr.lam * isq * U;
-        const R e = g_exp(-gr.lam * U * U);
-        const R hs = half * erfc_e(g_abs(x), e);
-        mr01[0] = x >= R(0) ? hs : R(1) - hs;
+        const H isq = g_rsqrt(grw.lam);
+        const H U = grw.U[0];
+        const H x = grw.lam * isq * U;
+        const H e = g_exp(-grw.lam * U * U);
+        const H hs = H(0.5) * erfc_e(g_abs(x), e);
+        mr01[0] = x >= H(0) ? hs : H(1) - hs;
         mr01[1] = U * mr01[0] - e * rsqpi_half * isq;
     }
 
-    // --- interface equilibrium state W0 (Eq. intermediatestate) ---------------------
-    R W0[NV];
+    // --- interface equilibrium state W0 (Eq. intermediatestate), wide ----------------
+    H W0[NV];
     {
-        R tl[NV], tr[NV], m3[3];
+        H tl[NV], tr[NV], m3[3];
         m3[0] = ml01[0]; m3[1] = ml01[1];
-        urec(m3, gl.U[0], gl.h, 2);
-        tmom1(gl, m3, tl);
+        urec(m3, glw.U[0], glw.h, 2);
+        tmom1(glw, m3, tl);
         m3[0] = mr01[0]; m3[1] = mr01[1];
-        urec(m3, gr.U[0], gr.h, 2);
-        tmom1(gr, m3, tr);
-        for (int m = 0; m < NV; ++m) W0[m] = gl.rho * tl[m] + gr.rho * tr[m];
+        urec(m3, grw.U[0], grw.h, 2);
+        tmom1(grw, m3, tr);
+        for (int m = 0; m < NV; ++m) W0[m] = glw.rho * tl[m] + grw.rho * tr[m];
     }
     H r0, ir0, U0d[D], p0;
-    {
-        H w0[NV];
-        for (int m = 0; m < NV; ++m) w0[m] = H(W0[m]);
-        if (!prim_wide<D>(w0, bw, r0, ir0, U0d, p0)) return 1;
-    }
+    if (!prim_wide<D>(W0, bw, r0, ir0, U0d, p0)) return 1;
     const H h0 = p0 * ir0, ip0 = g_rcp(p0);
     Mx<R, D> g0;
     {
@@ -566,10 +597,44 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         tau = ip0 * (H(gas.mu) + in.kf * r0 * g_rsqrt(in.wf * in.wf + sc * sc));
         if (gas.c_a > 0.0) tau = tau + H(gas.c_a) * g_abs(pr - pl) * g_rcp(pr + pl) * in.dt;
     }
-    const R dt = R(in.dt);
-    Kw<R> kw;
-    if (MODE & (FLUX_TAUHAT | FLUX_EPS_OUT)) mode_weights<R, D, H, MODE>(in, tau, W0, U0d, ir0, dt, F, kw);
-    else kw = kogan(R(tau), dt);
+    Kw<H> kwh;
+    if (MODE & (FLUX_TAUHAT | FLUX_EPS_OUT)) kwh = mode_weights<D, H, MODE>(in, tau, W0, U0d, ir0, Fout);
+    else kwh = kogan(tau, in.dt);
+    const Kw<R> kw = kw_narrow<R>(kwh);
+
+    // --- wide part of a split evaluation: the gam0 Euler flux of W0 and the gam3
+    //     collisionless flux of the two half-Maxwellians -----------------------------
+    // With the heat-flux correction linear in F and in G = dt W0 + dt^2/2 Rv (below), the
+    // wide part's share of q is formed here: qw = q(Fw) - U0_n dt (W0_E - U0.W0_m +
+    // |U0|^2 rho0/2), where the last bracket is the internal energy b p0/2 of W0.
+    [[maybe_unused]] H Fw[NV];
+    [[maybe_unused]] H qw = H(0);
+    if constexpr (SPLIT) {
+        H m[4], T[NV];
+        Mx<H, D> g0w;
+        mx_set(g0w, r0, U0d, H(0.5) * r0 * ip0, h0, btw);
+        m[0] = H(1);
+        m[1] = U0d[0];
+        urec(m, U0d[0], h0, 3);
+        tmom1(g0w, m + 1, T);                          // <u psi>_g0 over all u
+        for (int q = 0; q < NV; ++q) Fw[q] = kwh.g[0] * r0 * T[q];
+        m[0] = ml01[0]; m[1] = ml01[1];
+        urec(m, glw.U[0], glw.h, 3);
+        tmom1(glw, m + 1, T);                          // <u psi>_{g_l, u>0}
+        for (int q = 0; q < NV; ++q) Fw[q] = Fw[q] + kwh.g[3] * rl * T[q];
+        m[0] = mr01[0]; m[1] = mr01[1];
+        urec(m, grw.U[0], grw.h, 3);
+        tmom1(grw, m + 1, T);                          // <u psi>_{g_r, u<0}
+        for (int q = 0; q < NV; ++q) Fw[q] = Fw[q] + kwh.g[3] * rr * T[q];
+        H uF = H(0), U2 = H(0);
+        for (int d = 0; d < D; ++d) {
+            uF = uF + U0d[d] * Fw[1 + d];
+            U2 = U2 + U0d[d] * U0d[d];
+        }
+        qw = (Fw[D + 1] - uF + H(0.5) * U2 * Fw[0]) - U0d[0] * in.dt * (H(0.5) * H(gas.b) * p0);
+    }
+    const R ml01n[2] = {R(ml01[0]), R(ml01[1])}, mr01n[2] = {R(mr01[0]), R(mr01[1])};
+    R F[NV];
 
     // Rv accumulates rho0 <psi Abar.psi>_g0 from the time-integrated compatibility condition:
     //   c1 rho0 (<u psi abar_l.psi>_{g0,>0} + <u psi abar_r.psi>_{g0,<0})
@@ -584,7 +649,7 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         const R isq = g_rsqrt(g0.lam);                 // 1/sqrt(lambda0)
         const R e = g_exp(-g0.lam * U * U);
         const R small = half * erfc_e(g_abs(g0.lam * isq * U), e);   // one erfc serves both halves
-        const R tail = e * rsqpi_half * isq;
+        const R tail = e * R(rsqpi_half) * isq;
         const bool upos = U >= R(0);
         m0p[0] = upos ? R(1) - small : small;
         m0n[0] = upos ? small : R(1) - small;
@@ -594,11 +659,11 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         urec(m0n, U, g0.h, 6);
         R r[NV], ab[NV], T1[NV], T2[NV];
         const H il = ir0 * in.idl, ir = ir0 * in.idr;
-        for (int m = 0; m < NV; ++m) r[m] = R((H(W0[m]) - in.Wi[m]) * il);
+        for (int m = 0; m < NV; ++m) r[m] = R((W0[m] - in.Wi[m]) * il);
         solve(g0, r, b, inv_b, ab);
         tmom(g0, m0p + 1, ab, bt, T1);                 // <u psi abar_l.psi>_{g0,>0}
         tmom(g0, m0p + 2, ab, bt, T2);                 // <u^2 psi abar_l.psi>_{g0,>0}
-        for (int m = 0; m < NV; ++m) r[m] = R((in.Wi1[m] - H(W0[m])) * ir);
+        for (int m = 0; m < NV; ++m) r[m] = R((in.Wi1[m] - W0[m]) * ir);
         solve(g0, r, b, inv_b, ab);
         R T3[NV];
         tmom(g0, m0n + 1, ab, bt, T3);
@@ -625,7 +690,8 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
 
     // --- one side of the initial distribution (Eq. initialf0): slopes a from dW/dx,
     //     time coefficients A from the compatibility condition at t = 0, then the
-    //     gam3..gam5 flux terms and the c4, c5 terms of Rv -------------------------
+    //     gam3..gam5 flux terms (gam3 in the wide part when split) and the c4, c5 terms
+    //     of Rv -------------------------------------------------------------------------
     auto side = [&](const Mx<R, D>& g, const R* m01, const H* slope, const H (*tslope)[D + 2], H irho) {
         R r[NV], a[NV], A[NV], T[NV], mf[8], mh[8];
         const R ir = R(irho);
@@ -656,8 +722,10 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
             for (int m = 0; m < NV; ++m) T[m] = -T[m];
             solve(g, T, b, inv_b, A);
             const R rg = g.rho;
-            tmom1(g, mh + 1, T);
-            for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[3] * T[m];
+            if constexpr (!SPLIT) {
+                tmom1(g, mh + 1, T);
+                for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[3] * T[m];
+            }
             tmom(g, mh + 2, a, bt, T);
             for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[4] * T[m];
             tmom(g, mh + 1, A, bt, T);
@@ -675,10 +743,15 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
             urec(mh, g.U[0], g.h, 6);
             const R rg = g.rho;
             R acc[NV];
-            tmom1(g, mh + 1, T);
-            for (int m = 0; m < NV; ++m) acc[m] = kw.g[3] * T[m];
-            tmom(g, mh + 2, a, bt, T);
-            for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[4] * T[m];
+            if constexpr (SPLIT) {
+                tmom(g, mh + 2, a, bt, T);
+                for (int m = 0; m < NV; ++m) acc[m] = kw.g[4] * T[m];
+            } else {
+                tmom1(g, mh + 1, T);
+                for (int m = 0; m < NV; ++m) acc[m] = kw.g[3] * T[m];
+                tmom(g, mh + 2, a, bt, T);
+                for (int m = 0; m < NV; ++m) acc[m] = acc[m] + kw.g[4] * T[m];
+            }
             tmom(g, mh + 1, A, bt, T);
             for (int m = 0; m < NV; ++m) F[m] = F[m] + rg * (acc[m] + kw.g[5] * T[m]);
             tmom(g, mh + 1, a, bt, T);
@@ -687,10 +760,10 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
             for (int m = 0; m < NV; ++m) Rv[m] = Rv[m] + rg * (acc[m] + kw.c5 * T[m]);
         }
     };
-    side(gl, ml01, in.sl, in.tl, irl);
-    side(gr, mr01, in.sr, in.tr, irr);
+    side(gl, ml01n, in.sl, in.tl, irl);
+    side(gr, mr01n, in.sr, in.tr, irr);
 
-    // --- Abar, then the gam0 and gam2 equilibrium terms ------------------------------
+    // --- Abar, then the gam2 (and, unsplit, gam0) equilibrium terms ------------------
     {
         R m0[8], r[NV], Ab[NV], T[NV];
         const R i0 = R(ir0);
@@ -699,35 +772,55 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         m0[0] = R(1);
         m0[1] = g0.U[0];
         urec(m0, g0.U[0], g0.h, 5);
-        R acc[NV];
-        tmom1(g0, m0 + 1, T);
-        for (int m = 0; m < NV; ++m) acc[m] = kw.g[0] * T[m];
-        tmom(g0, m0 + 1, Ab, bt, T);
-        for (int m = 0; m < NV; ++m) F[m] = F[m] + g0.rho * (acc[m] + kw.g[2] * T[m]);
+        if constexpr (SPLIT) {
+            tmom(g0, m0 + 1, Ab, bt, T);
+            for (int m = 0; m < NV; ++m) F[m] = F[m] + g0.rho * (kw.g[2] * T[m]);
+        } else {
+            R acc[NV];
+            tmom1(g0, m0 + 1, T);
+            for (int m = 0; m < NV; ++m) acc[m] = kw.g[0] * T[m];
+            tmom(g0, m0 + 1, Ab, bt, T);
+            for (int m = 0; m < NV; ++m) F[m] = F[m] + g0.rho * (acc[m] + kw.g[2] * T[m]);
+        }
+    }
+    for (int m = 0; m < NV; ++m) {
+        if constexpr (SPLIT) Fout[m] = Fw[m] + H(F[m]);
+        else Fout[m] = F[m];
     }
 
     // --- Prandtl-number correction of the energy flux -------------------------------
     // q = int int (u - U0)(|u - U0|^2 + xi^2)/2 f
     //   = (F_E - U0.F_m + |U0|^2 F_rho/2) - U0_n (G_E - U0.G_m + |U0|^2 G_rho/2),
     // with G = int int psi f = dt W0 + dt^2/2 Rv (the integrated compatibility condition).
-    {
-        const R pfix = R(gas.pfix);
-        R Gv[NV];
-        R dtq = dt;
+    // Split: q = qw + the same expression over the narrow F and dt^2/2 Rv alone.
+    if constexpr (SPLIT) {
+        const R dt = R(in.dt), hdt2 = half * dt * dt;
+        R uF = R(0), uR = R(0), U2 = R(0);
+        for (int d = 0; d < D; ++d) {
+            uF = uF + g0.U[d] * F[1 + d];
+            uR = uR + g0.U[d] * Rv[1 + d];
+            U2 = U2 + g0.U[d] * g0.U[d];
+        }
+        const R qn = (F[D + 1] - uF + half * U2 * F[0]) - g0.U[0] * hdt2 * (Rv[D + 1] - uR + half * U2 * Rv[0]);
+        Fout[D + 1] = Fout[D + 1] + H(gas.pfix) * (qw + H(qn));
+    } else {
+        const H pfix = H(gas.pfix);
+        H Gv[NV];
+        H dtq = in.dt;
 #ifdef __HIP_DEVICE_COMPILE__
         // in the flux modes the weights' dt/2 would otherwise be kept from there to here
         if (MODE & (FLUX_TAUHAT | FLUX_EPS_OUT)) asm volatile("" : "+v"(dtq));
 #endif
-        const R hdt2 = half * dtq * dtq;
-        for (int m = 0; m < NV; ++m) Gv[m] = dt * W0[m] + hdt2 * Rv[m];
-        R uF = R(0), uG = R(0), U2 = R(0);
+        const H hdt2 = H(0.5) * dtq * dtq;
+        for (int m = 0; m < NV; ++m) Gv[m] = in.dt * W0[m] + hdt2 * H(Rv[m]);
+        H uF = H(0), uG = H(0), U2 = H(0);
         for (int d = 0; d < D; ++d) {
-            uF = uF + g0.U[d] * F[1 + d];
-            uG = uG + g0.U[d] * Gv[1 + d];
-            U2 = U2 + g0.U[d] * g0.U[d];
+            uF = uF + U0d[d] * Fout[1 + d];
+            uG = uG + U0d[d] * Gv[1 + d];
+            U2 = U2 + U0d[d] * U0d[d];
         }
-        const R q = (F[D + 1] - uF + half * U2 * F[0]) - g0.U[0] * (Gv[D + 1] - uG + half * U2 * Gv[0]);
-        F[D + 1] = F[D + 1] + pfix * q;
+        const H q = (Fout[D + 1] - uF + H(0.5) * U2 * Fout[0]) - U0d[0] * (Gv[D + 1] - uG + H(0.5) * U2 * Gv[0]);
+        Fout[D + 1] = Fout[D + 1] + pfix * q;
     }
     return 0;
 }

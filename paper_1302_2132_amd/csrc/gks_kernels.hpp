@@ -336,9 +336,10 @@ __device__ inline void kw_face(cref<Inst> I, double frho, double kl, double kr, 
 // Wc (i-2 .. i+1, ghosts already synthesised); k, omega and strain rate are averaged over
 // elements il, ir of the arrays kk, ww, ss (HBM or LDS: P is the pointer type).  Fg
 // receives the time-integrated flux with the momentum components in the global axis
-// order.  Returns nonzero for a non-physical state.  The axis is a template parameter so
-// that every index and the rotation to the face-local frame are compile-time (no private
-// arrays).
+// order, in FP64 in both precision forms (the FP32-flux form keeps the parts of size
+// p dt in FP64, see face_flux).  Returns nonzero for a non-physical state.  The axis is a
+// template parameter so that every index and the rotation to the face-local frame are
+// compile-time (no private arrays).
 enum { V_KW = 1, V_TH = 2, V_R3 = 4, V_MD = 8, V_W5 = 16 };
 
 // reconstruction of a variant (0 second-order MUSCL, 1 third-order MUSCL, 2 WENO5) and the
@@ -350,7 +351,7 @@ template <int V> constexpr int halo_of() { return (V & V_W5) ? 3 : 2; }
 // in the global component order, tangential axes in increasing order.
 template <typename R, int D, int DIR, int MODE, int RK, typename P>
 __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int i, const double (*Wc)[D + 2],
-                                                               P kk, P ww, P ss, int il, int ir, double dt, R* Fg,
+                                                               P kk, P ww, P ss, int il, int ir, double dt, double* Fg,
                                                                const double* tg_l = nullptr,
                                                                const double* tg_r = nullptr)
 {
@@ -398,7 +399,7 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
     in.Sf = 0.5 * (ss[il] + ss[ir]);
     in.dt = dt;
     GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
-    R F[NV + ((MODE & FLUX_EPS_OUT) ? 1 : 0)];
+    double F[NV + ((MODE & FLUX_EPS_OUT) ? 1 : 0)];
     const int bad = face_flux<R, D, double, MODE>(in, gas, F);
     Fg[0] = F[0];
     Fg[1 + DIR] = F[1];
@@ -453,7 +454,7 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
         il = image_cell<D>(I, DIR, cl);
         ir = image_cell<D>(I, DIR, fc);
     }
-    R F[NV];
+    double F[NV];
     const double* kk = I.k;
     const double* ww = I.om;
     const double* ss = I.S;
@@ -481,7 +482,7 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
     }
     if (face_eval<R, D, DIR, FMODE, recon_of<V>()>(I, fc[DIR], Wc, kk, ww, ss, il, ir, dt, F, tg[0], tg[1]))
         atomicOr(&I.st->err, 1);
-    R* __restrict__ out = (R*)I.F[DIR];
+    double* __restrict__ out = (double*)I.F[DIR];
     const long long nf = I.nface[DIR];   // 64-bit: component offsets m * nf may pass 2^31
     out[f] = F[0];
     out[nf + f] = F[1];
@@ -503,9 +504,9 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
         const int jl = image_cell<D>(I, DIR, gc);
         const double* nt = I.nt;
         double Fk, Fw;
-        kw_face(I, double(F[0]), kk[jl], kk[jr], ww[jl], ww[jr], nt[jl], nt[jr], I.icd[DIR][fd - 1], dt, Fk, Fw);
-        out[(long long)(D + 2) * nf + f] = R(Fk);
-        out[(long long)(D + 3) * nf + f] = R(Fw);
+        kw_face(I, F[0], kk[jl], kk[jr], ww[jl], ww[jr], nt[jl], nt[jr], I.icd[DIR][fd - 1], dt, Fk, Fw);
+        out[(long long)(D + 2) * nf + f] = Fk;
+        out[(long long)(D + 3) * nf + f] = Fw;
     }
 }
 
@@ -513,17 +514,18 @@ __device__ __attribute__((always_inline)) inline void face_one(cref<Inst> I, int
 #define GKS_FACE_WAVES_FP64 2
 #endif
 #ifndef GKS_FACE_WAVES_FP32
-#define GKS_FACE_WAVES_FP32 4
+#define GKS_FACE_WAVES_FP32 3
 #endif
 // Register budget of the face kernel (instantiated for 3D; 2D steps use k_tile2): at least
-// this many waves per SIMD (2 leaves 256 VGPRs per lane for the 3D FP64 flux, 4 leaves 128
-// for the FP32 flux; the third-order and WENO5 reconstructions take the FP32 form to 3,
-// 168 VGPRs, the multi-dimensional expansion to 2; its FP64 form keeps 2 with a spill of a
-// few values per face, as its tangential gradients stay live through the flux).
-// TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
+// this many waves per SIMD (2 leaves 256 VGPRs per lane for the 3D FP64 flux, 3 leaves 168
+// for the FP32 flux, whose FP64 share -- interface state, Euler and collisionless parts --
+// needs more than 128; the third-order and WENO5 reconstructions and the
+// multi-dimensional expansion take the FP32 form to 2; the multi-dimensional FP64 form
+// keeps 2 with a spill of a few values per face, as its tangential gradients stay live
+// through the flux).  TILE faces per workgroup (64, 128 or 256: a batch's autotuned shape).
 template <typename R, int D, int TILE, int V>
 __global__ __launch_bounds__(TILE)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & V_MD) ? 2 : ((V & (V_R3 | V_W5)) ? 1 : 0))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & (V_MD | V_R3 | V_W5)) ? 1 : 0)
                                                    : GKS_FACE_WAVES_FP64)))
 void k_face(const void* __restrict__ table, int cap, int cls)
 {
@@ -699,14 +701,19 @@ static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_TH
               "one x-face, one y-face and one cell per thread");
 
 // Register budget: 3 waves per SIMD leave 168 VGPRs per lane, enough for the 2D FP64 flux;
-// the FP32-flux form gets 4 (128 VGPRs).
+// the plain FP32-flux form gets 4 (128 VGPRs), its variants 3 (the transported ones are
+// held to 3 by their LDS, six FP64 flux components per face), and the multi-dimensional
+// expansion one wave less in both forms.
 #ifndef GKS_TILE2_WAVES_FP64
 #define GKS_TILE2_WAVES_FP64 3
+#endif
+#ifndef GKS_TILE2_WAVES_FP32
+#define GKS_TILE2_WAVES_FP32 4
 #endif
 
 template <typename R, int V>
 __global__ __launch_bounds__(T2_THREADS)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_FACE_WAVES_FP32 - ((V & V_MD) ? 1 : 0)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (V == 0 ? GKS_TILE2_WAVES_FP32 : 3) - ((V & V_MD) ? 1 : 0)
                                                    : GKS_TILE2_WAVES_FP64 - ((V & V_MD) ? 1 : 0))))
 void k_tile2(const void* __restrict__ table, int cap, int cls)
 {
@@ -720,8 +727,8 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
     constexpr int NX = NV + (KW ? 2 : 0);     // with transport: fluxes of rho k, rho omega too
     __shared__ double sW[NV][WX * WY];
     __shared__ double sK[KW ? 4 : 3][T2_KX * T2_KY];   // k, omega, strain rate (, rho k/omega)
-    __shared__ R sFx[NX][T2_NFX];
-    __shared__ R sFy[NX][T2_NFY];
+    __shared__ double sFx[NX][T2_NFX];
+    __shared__ double sFy[NX][T2_NFY];
     __shared__ double sh_sum[5 * 4];
     __shared__ double sh_max[4];
     __shared__ int sh_bad[4];
@@ -805,7 +812,7 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                             tg[side][m] = tgrad(sW[m][e0 - WX], sW[m][e0], sW[m][e0 + WX], icm, icp);
                     }
                 }
-                R F[NV];
+                double F[NV];
                 if (face_eval<R, 2, 0, FMODE, RK>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F,
                                                   tg[0], tg[1]))
                     atomicOr(&I.st->err, 1);
@@ -817,10 +824,10 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     int q = kl;                  // reloaded, not kept live across the flux
                     asm volatile("" : "+v"(q));
                     double Fk, Fw;
-                    kw_face(I, double(F[0]), sK[0][q], sK[0][q + 1], sK[1][q], sK[1][q + 1], sK[KW ? 3 : 0][q],
+                    kw_face(I, F[0], sK[0][q], sK[0][q + 1], sK[1][q], sK[1][q + 1], sK[KW ? 3 : 0][q],
                             sK[KW ? 3 : 0][q + 1], I.icd[0][x0 + i - 1], dt, Fk, Fw);
-                    sFx[NX - 2][tid] = R(Fk);
-                    sFx[NX - 1][tid] = R(Fw);
+                    sFx[NX - 2][tid] = Fk;
+                    sFx[NX - 1][tid] = Fw;
                 }
             }
         }
@@ -844,7 +851,7 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                         for (int m = 0; m < NV; ++m) tg[side][m] = tgrad(sW[m][e0 - 1], sW[m][e0], sW[m][e0 + 1], icm, icp);
                     }
                 }
-                R F[NV];
+                double F[NV];
                 if (face_eval<R, 2, 1, FMODE, RK>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt,
                                                   F, tg[0], tg[1]))
                     atomicOr(&I.st->err, 1);
@@ -856,10 +863,10 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     int q = kl;
                     asm volatile("" : "+v"(q));
                     double Fk, Fw;
-                    kw_face(I, double(F[0]), sK[0][q], sK[0][q + T2_KX], sK[1][q], sK[1][q + T2_KX],
+                    kw_face(I, F[0], sK[0][q], sK[0][q + T2_KX], sK[1][q], sK[1][q + T2_KX],
                             sK[KW ? 3 : 0][q], sK[KW ? 3 : 0][q + T2_KX], I.icd[1][y0 + j - 1], dt, Fk, Fw);
-                    sFy[NX - 2][tid] = R(Fk);
-                    sFy[NX - 1][tid] = R(Fw);
+                    sFy[NX - 2][tid] = Fk;
+                    sFy[NX - 1][tid] = Fw;
                 }
             }
         }
@@ -880,10 +887,10 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
 #pragma unroll
             for (int m = 0; m < NX; ++m) {
                 x.old[m] = m < NV ? sW[m < NV ? m : 0][ew] : W[(long long)m * I.ncells + cell];
-                x.fl[0][m] = double(sFx[m][fx]);
-                x.fh[0][m] = double(sFx[m][fx + 1]);
-                x.fl[1][m] = double(sFy[m][fy]);
-                x.fh[1][m] = double(sFy[m][fy + T2X]);
+                x.fl[0][m] = sFx[m][fx];
+                x.fh[0][m] = sFx[m][fx + 1];
+                x.fl[1][m] = sFy[m][fy];
+                x.fh[1][m] = sFy[m][fy + T2X];
             }
             x.idx[0] = I.idx[0][x0 + ii];
             x.idx[1] = I.idx[1][y0 + jj];
@@ -954,10 +961,7 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
         double rate = 0.0;
         int bad = 0;
         const double dt = state_of(I).dt;
-        if (cell < I.ncells) {
-            if (I.precision) update_cell<3, float, KW>(I, cell, dt, r2, rate, bad);
-            else update_cell<3, double, KW>(I, cell, dt, r2, rate, bad);
-        }
+        if (cell < I.ncells) update_cell<3, double, KW>(I, cell, dt, r2, rate, bad);
         // workgroup reductions in a fixed order
         for (int m = 0; m < I.nv; ++m) {
             const double s = wave_sum(r2[m]);
@@ -1100,6 +1104,13 @@ __device__ inline void finish_member(cref<Inst> I, int mode, double* sh)
         next_step(I, st, rate, st->t);
         if (st->err) st->active = 0;
         if (I.max_steps > 0 && st->steps >= I.max_steps) st->active = 0;
+        if (mode == 0 && I.res_tol > 0.0 && st->steps >= 2) {
+            // residual fall of the flow fields whose first-step residual is positive
+            double worst = -1.0;
+            for (int m = 0; m < nv; ++m)
+                if (st->res_first[m] > 0.0) worst = fmax(worst, st->res[m] / st->res_first[m]);
+            if (worst >= 0.0 && worst <= I.res_tol) st->active = 0;
+        }
     }
     __syncthreads();
 }

@@ -90,6 +90,7 @@ bool config_ok(const gks_config* c, std::string* why)
         return fail("gas or time-step parameter out of range");
     if (c->precision != GKS_FP64 && c->precision != GKS_FP32_FLUX) return fail("unknown precision");
     if (c->max_steps < 0) return fail("max_steps must be >= 0");
+    if (!(c->res_tol >= 0.0) || !isfinite(c->res_tol)) return fail("res_tol must be finite and >= 0");
     if (c->turb_transport != 0 && c->turb_transport != 1) return fail("turb_transport must be 0 or 1");
     if (c->eps_mode != GKS_EPS_DT && c->eps_mode != GKS_EPS_TAUHAT) return fail("unknown eps_mode");
     if (c->recon != GKS_RECON_MUSCL2 && c->recon != GKS_RECON_MUSCL3 && c->recon != GKS_RECON_WENO5)
@@ -120,7 +121,7 @@ void layout(const gks_config* c, Layout* L)
     L->Qk = c->turb_transport ? take(cellb) : 0;
     L->Qw = c->turb_transport ? take(cellb) : 0;
     L->nt = c->turb_transport ? take(cellb) : 0;
-    const size_t fb = c->precision == GKS_FP32_FLUX ? sizeof(float) : sizeof(double);
+    const size_t fb = sizeof(double);   // face fluxes are FP64 in both precision forms
     for (int d = 0; d < 3; ++d) {
         L->nface[d] = 0;
         L->ntile_face[d] = 0;
@@ -471,6 +472,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.inv_cmu = 1.0 / cfg->c_mu;
     I.pfix = 1.0 / cfg->prandtl - 1.0;
     I.max_steps = cfg->max_steps;
+    I.res_tol = cfg->res_tol;
     I.W[0] = (double*)(ws + L.W[0]);
     I.W[1] = (double*)(ws + L.W[1]);
     I.k = (double*)(ws + L.k);

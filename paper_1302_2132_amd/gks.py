@@ -55,6 +55,7 @@ class gks_config(C.Structure):
         ("eps_mode", C.c_int32),
         ("recon", C.c_int32),
         ("multi_d", C.c_int32),
+        ("res_tol", C.c_double),
     ]
 
 
@@ -145,6 +146,7 @@ class _Cfg:
         c.eps_mode = EPS_MODE[getattr(case, "eps_mode", "dt")]
         c.recon = RECON[getattr(case, "recon", "muscl2")]
         c.multi_d = 1 if getattr(case, "multi_d", False) else 0
+        c.res_tol = float(getattr(case, "res_tol", 0.0) or 0.0)
         self.c = c
 
 

@@ -19,8 +19,11 @@ real time from the trace).
 Both loops advance their work in quanta of steps sized to about `target_s` of GPU time
 (from the measured time of the previous quantum, at least `quantum` steps), so that the
 per-quantum host work (reading the states back, admitting, retiring) stays a small
-fraction of the GPU time.  A solve stops on the device at its step cap, so a quantum
-that overshoots a solve's end costs no work, only up to one quantum of detection delay.
+fraction of the GPU time.  A solve stops on the device, at the end of the step where its
+residual has fallen by `tol` (the request's tolerance, set as the solve's res_tol) or at
+its step cap, so a quantum that overshoots a solve's end costs no work and no steps (the
+kernels pass a stopped solve), only up to one quantum of detection delay; its steps and
+final state are those of the solve run alone, whatever the quanta.
 """
 from __future__ import annotations
 
@@ -31,6 +34,8 @@ import numpy as np
 
 
 def _converged(res, res_first, steps, tol, max_steps, nv):
+    """The device's stopping rule (residual fall by tol after step 2, or the step cap),
+    evaluated on the host from a solve's residuals."""
     if steps >= max_steps:
         return True
     r0 = np.asarray(res_first[:nv])
@@ -114,6 +119,7 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
             else:
                 req = queue[0]
             case = make_case(req)
+            case.res_tol = float(req["tol"])            # the device stops the solve there
             nbytes = G.gks_workspace_bytes(G.config_from_case(case))
             if (used + nbytes > hbm_budget or cells_in + case.ncells > sat_cells) and (active or staged):
                 break                                    # wait for memory or GPU room
@@ -196,16 +202,19 @@ def run_fifo(requests, make_case, quantum=20, keep_fields=False, device="cuda:0"
         if wait > 0:
             time.sleep(wait)
         case = make_case(req)
+        case.res_tol = float(req["tol"])                # the device stops the solve there
         s = G.Solver(case, device=device)
         q = quantum
+        steps = 0
         while True:
             ev0.record()
             s.step(q)
             ev1.record()
             r = s.residual()                             # synchronises
+            stopped = r["steps"] < steps + q             # the device stopped it within the quantum
             q = _next_quantum(q, ev0.elapsed_time(ev1), quantum, target_s)
             steps = r["steps"]
-            if _converged(r["res"], r["res_first"], steps, req["tol"], req["max_steps"], case.nvar):
+            if stopped or _converged(r["res"], r["res_first"], steps, req["tol"], req["max_steps"], case.nvar):
                 break
         tnow = time.perf_counter() - t0
         rec = {"id": req["id"], "arrival": req["arrival"], "done": tnow, "latency": tnow - req["arrival"],

@@ -3,11 +3,12 @@ import numpy as np
 
 
 def field_errors(got, ref, vector_momentum=False):
-    """Per-field normwise relative error max_i |got - ref| / max_i |ref|.
+    """Per-field normwise relative error max_i |got - ref| / max_i |ref| (the metric every
+    parity test asserts).
 
     With vector_momentum, each momentum component is scaled by the largest momentum
-    magnitude |rho U| instead of its own largest value (a rotation-invariant scale: a
-    component that is a small perturbation is not measured against itself)."""
+    magnitude |rho U| instead of its own largest value (a rotation-invariant scale, printed
+    beside the per-field figure)."""
     nv = ref.shape[0]
     dim = nv - 2
     mom = np.sqrt(sum(ref[1 + d] ** 2 for d in range(dim)))
@@ -34,5 +35,47 @@ def run_gpu(case, nsteps, which="cons"):
     return W, r
 
 
+def report(got, ref, label=""):
+    """Per-field errors (returned) with the momentum-magnitude figure printed beside them."""
+    err = field_errors(got, ref)
+    mom = field_errors(got, ref, vector_momentum=True)
+    print(f"  {label}per-field errors {err} (momentum against |rho U|: {mom})", flush=True)
+    return err
+
+
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+# Reading Z34: a momentum component whose range is below 1 % of the momentum magnitude (the
+# mixing layer's transverse momentum, a perturbation that the shear layer amplifies) drifts
+# by rounding alone beyond 1e-12 of its own range over a few hundred steps (a few tens with
+# WENO5): algebraically equal forms of the oracle's own arithmetic differ by that much
+# (tests/test_oracle_conditioning.py).  At the FP64 bound such a component is held to the
+# bound against the momentum magnitude and to PERTURBATION_FIELD per field.
+PERTURBATION_FIELD = 1e-11
+
+
+def oracle_reference(case, nsteps):
+    """The oracle's run of `case` (frozen or transported k and omega)."""
+    import oracle
+    if getattr(case, "kw_transport", False):
+        return oracle.run_kw(case, nsteps)
+    return oracle.run(case, nsteps)
+
+
+def assert_matches_oracle(W, case, ref, tol, label=""):
+    """Per-field parity of a GPU state with the oracle's, at `tol` (reading Z34 for a
+    perturbation momentum component at the FP64 bound)."""
+    import numpy as np
+    err = report(W, ref["W"], label)
+    mom = field_errors(W, ref["W"], vector_momentum=True)
+    ref_W = ref["W"]
+    magnitude = np.max(np.sqrt(sum(ref_W[1 + d] ** 2 for d in range(case.dim))))
+    for m, e in enumerate(err):
+        if e <= tol:
+            continue
+        perturbation = 1 <= m <= case.dim and np.max(np.abs(ref_W[m])) < 1e-2 * magnitude
+        z34 = tol <= 1e-12 and perturbation
+        assert z34 and e <= PERTURBATION_FIELD and mom[m] <= tol, (label, m, err, mom)
+    return np.asarray(err)

@@ -55,7 +55,12 @@ def test_workspace_bytes_and_validation():
     assert nb3 >= 8 * 16 ** 3 * (5 * 2 + 3) + 8 * 5 * 3 * 17 * 16 * 16
     fp32 = c3.copy()
     fp32.precision = "fp32_flux"
-    assert P.gks_workspace_bytes(P.config_from_case(fp32)) < nb3     # FP32 face fluxes
+    assert P.gks_workspace_bytes(P.config_from_case(fp32)) == nb3    # face fluxes FP64 in both forms
+    bad = c.copy()
+    bad.res_tol = -1.0
+    with pytest.raises(P.GksError) as e:
+        P.gks_workspace_bytes(P.config_from_case(bad))
+    assert e.value.status == P.GKS_ERR_ARG
 
 
 def test_option_combinations_validated():

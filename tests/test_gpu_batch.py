@@ -1,9 +1,13 @@
 """Batched form: every solve gives the same result alone and inside a persistent batch
-(mixed sizes, dimensions, precisions and options; with and without a captured graph)."""
+(mixed sizes, dimensions, precisions and options; with and without a captured graph), and
+the members of an uneven batch and of a batch with every option match the oracle."""
+import math
+
 import numpy as np
 import pytest
 
-from gpu_util import banner
+import oracle
+from gpu_util import assert_matches_oracle, banner, oracle_reference
 from inputs import cases as C
 
 pytestmark = pytest.mark.gpu
@@ -220,3 +224,77 @@ def test_autotuner_steps_are_real_steps():
     b.close()
     for s in solvers:
         s.close()
+
+
+# --------------------------------------------------------------------------------------
+# batch members against the oracle
+# --------------------------------------------------------------------------------------
+def _config3_small(precision):
+    """The uneven batch's recipe at sizes the oracle runs in seconds: mixing layers and
+    Galilean-shifted Sod tubes (Ma up to 2) of sides 40..100 (none a tile multiple in both
+    directions), plus two shifted tubes at Ma 1.6 and 2.0 on 71 x 13 and 97 x 23 meshes."""
+    import math
+    cases = C.batch_cases(14, seed=3, nmin=40, nmax=100, steps=200, precision=precision)
+    for Ma, nx, ny in ((1.6, 71, 13), (2.0, 97, 23)):
+        c = C.shock_tube(nx, ny, x0=0.25, shift=Ma * math.sqrt(1.4), mu=1e-4, c_a=1.0, k_val=1e-6,
+                         omega_val=10.0, steps=200, precision=precision, bc_x=("dirichlet", "outflow"),
+                         name=f"shifted_sod_Ma{Ma}")
+        cases.append(c)
+    return cases
+
+
+@pytest.fixture(scope="module")
+def config3_oracle():
+    cases = _config3_small("fp64")
+    banner(f"oracle: {len(cases)} batch members, 200 steps each")
+    return [oracle.run(c, 200) for c in cases]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32_flux", 1e-5), ("fp64", 1e-12)])
+def test_uneven_batch_members_match_the_oracle(config3_oracle, precision, tol):
+    from paper_1302_2132_amd import Batch, Solver
+    from paper_1302_2132_amd.autotune import autotune
+    cases = _config3_small(precision)
+    assert any(c.meta.get("shift", 0.0) >= 1.5 * math.sqrt(1.4) for c in cases)
+    banner(f"uneven batch of {len(cases)} ({precision}), autotuned, captured, 200 steps")
+    solvers = [Solver(c) for c in cases]
+    b = Batch(solvers, capacity=len(cases))
+    try:
+        _, tune_steps, _ = autotune(b, steps_per_trial=1, use_cache=False)
+        b.capture()
+        b.step(200 - tune_steps)
+        st = b.status()
+        assert np.all(st["steps"] == 200)
+        for c, s, ro in zip(cases, solvers, config3_oracle):
+            assert_matches_oracle(s.fields("cons"), c, ro, tol, label=f"{c.name}: ")
+    finally:
+        b.close()
+        for s in solvers:
+            s.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_with_every_option_matches_the_oracle(graph):
+    """Each member of the every-option batch against the oracle (FP64 1e-12, FP32 flux
+    1e-5; transported k and omega too)."""
+    from paper_1302_2132_amd import Batch, Solver
+    n = 12
+    cases = _option_cases()
+    solvers = [Solver(c) for c in cases]
+    b = Batch(solvers, capacity=12)
+    try:
+        if graph:
+            b.capture()
+        b.step(n)
+        for c, s in zip(cases, solvers):
+            ro = oracle_reference(c, n)
+            tol = 1e-12 if c.precision == "fp64" else 1e-5
+            assert_matches_oracle(s.fields("cons"), c, ro, tol, label=f"{c.name}: ")
+            if c.kw_transport:
+                kw = s.fields("turb")
+                for got, ref in ((kw[0], ro["k"]), (kw[1], ro["omega"])):
+                    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)), c.name
+    finally:
+        b.close()
+        for s in solvers:
+            s.close()

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import banner, field_errors, run_gpu
+from gpu_util import assert_matches_oracle, banner, field_errors, run_gpu
 from inputs import cases as C
 
 pytestmark = pytest.mark.gpu
@@ -20,10 +20,8 @@ def _compare(case, nsteps, tol, changes=True):
     banner(f"muscl3: {case.name} {case.precision} steps={nsteps}")
     Wg, rg = run_gpu(case, nsteps)
     ro = oracle.run(case, nsteps)
-    err = field_errors(Wg, ro["W"], vector_momentum=tol > TOL64)
-    print(f"  field errors {err}", flush=True)
+    err = assert_matches_oracle(Wg, case, ro, tol)
     assert rg["steps"] == ro["steps"]
-    assert np.all(err <= tol), err
     assert abs(rg["t"] - ro["t"]) <= (1e-13 if tol <= TOL64 else 1e-5) * max(ro["t"], 1e-300)
     if changes:       # the reconstruction changed the result
         case.recon = "muscl2"

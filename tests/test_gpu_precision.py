@@ -1,65 +1,82 @@
-"""FP32-flux form against the FP64 form at the full configurations and their stated step
-counts (the FP64 GPU path itself matches the oracle within 1e-12, see test_gpu_parity).
-Error per field: max |fp32 - fp64| / max |fp64|, momentum components against the largest
-momentum magnitude."""
+"""The FP32-flux form and the FP64 form over the configurations' stated step counts.
+
+Against the oracle (per field, max |gpu - oracle| / max |oracle|): the wall-stretched
+shock/boundary-layer interaction at 256 x 128 for the stated 2000 steps, FP64 within 1e-12
+and FP32 flux within 1e-5, and the decaying isotropic box at 48^3 for the stated 500 steps
+in FP32 flux within 1e-5.  At the full sizes (1024 x 512 and 256^3), where the oracle
+cannot run the stated steps, the FP32-flux form is measured per field against the FP64
+form (which matches the oracle within 1e-12 on the sizes above and on sampled full-size
+steps).  The momentum components against the momentum magnitude are printed beside the
+per-field figures.
+"""
 import numpy as np
 import pytest
 
-from gpu_util import banner, field_errors
+import oracle
+from gpu_util import assert_matches_oracle, banner, report
 from inputs import cases as C
 
 pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
 TOL32 = 1e-5
 
 
-def _pair(make, steps):
+def _gpu(case, steps):
     from paper_1302_2132_amd import Solver
-    out = []
-    for prec in ("fp64", "fp32_flux"):
-        c = make(prec)
-        s = Solver(c)
+    s = Solver(case)
+    try:
         s.step(steps)
         r = s.residual()
-        out.append(s.fields("cons"))
+        W = s.fields("cons")
+    finally:
         s.close()
-        assert r["steps"] == steps
+    assert r["steps"] == steps
+    return W, r
+
+
+@pytest.fixture(scope="module")
+def sbli_256_oracle():
+    banner("oracle: sbli 256x128, 2000 FP64 steps")
+    return oracle.run(C.sbli(256, 128), 2000)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32_flux", TOL32)])
+def test_sbli_256x128_2000_steps_against_the_oracle(sbli_256_oracle, precision, tol):
+    banner(f"sbli 256x128 {precision}, 2000 steps against the oracle")
+    case = C.sbli(256, 128, precision=precision)
+    W, r = _gpu(case, 2000)
+    ro = sbli_256_oracle
+    assert ro["steps"] == 2000
+    assert_matches_oracle(W, case, ro, tol)
+    assert abs(r["t"] - ro["t"]) <= (1e-12 if tol <= TOL64 else 1e-5) * ro["t"]
+
+
+def test_isotropic_48_fp32_flux_500_steps_against_the_oracle():
+    banner("isotropic 48^3 fp32-flux, 500 steps against the oracle")
+    case = C.isotropic_box(48, precision="fp32_flux")
+    W, r = _gpu(case, 500)
+    ro = oracle.run(case, 500)
+    assert_matches_oracle(W, case, ro, TOL32)
+    assert abs(r["t"] - ro["t"]) <= 1e-5 * ro["t"]
+
+
+def _pair(make, steps):
+    out = []
+    for prec in ("fp64", "fp32_flux"):
+        W, _ = _gpu(make(prec), steps)
+        out.append(W)
     return out
 
 
 def test_sbli_1024x512_fp32_flux_2000_steps():
     banner("sbli 1024x512 fp64 vs fp32-flux, 2000 steps")
     W64, W32 = _pair(lambda p: C.sbli(precision=p), 2000)
-    err = field_errors(W32, W64, vector_momentum=True)
-    print(f"  errors {err} per-component {field_errors(W32, W64)}", flush=True)
+    err = report(W32, W64)
     assert np.all(err <= TOL32), err
 
 
 def test_isotropic_256_fp32_flux_500_steps():
     banner("isotropic 256^3 fp64 vs fp32-flux, 500 steps")
     W64, W32 = _pair(lambda p: C.isotropic_box(256, precision=p), 500)
-    err = field_errors(W32, W64, vector_momentum=True)
-    print(f"  errors {err} per-component {field_errors(W32, W64)}", flush=True)
+    err = report(W32, W64)
     assert np.all(err <= TOL32), err
-
-
-def test_batch_64_fp32_flux_200_steps():
-    from paper_1302_2132_amd import Batch, Solver
-    banner("64-mesh batch fp64 vs fp32-flux, 200 steps")
-    res = {}
-    for prec in ("fp64", "fp32_flux"):
-        cases = C.batch_cases(64, seed=3, steps=200, precision=prec)
-        solvers = [Solver(c) for c in cases]
-        b = Batch(solvers, capacity=64)
-        b.capture()
-        b.step(200)
-        st = b.status()
-        assert np.all(st["steps"] == 200)
-        res[prec] = [s.fields("cons") for s in solvers]
-        b.close()
-        for s in solvers:
-            s.close()
-    worst = np.zeros(4)
-    for a, b64 in zip(res["fp32_flux"], res["fp64"]):
-        worst = np.maximum(worst, field_errors(a, b64, vector_momentum=True))
-    print(f"  worst errors over 64 meshes {worst}", flush=True)
-    assert np.all(worst <= TOL32), worst

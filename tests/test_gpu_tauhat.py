@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import banner, field_errors, run_gpu
+from gpu_util import assert_matches_oracle, banner, field_errors, run_gpu
 from inputs import cases as C
 
 pytestmark = pytest.mark.gpu
@@ -21,10 +21,8 @@ def _compare(case, nsteps, tol):
     banner(f"tau_hat mode: {case.name} {case.precision} steps={nsteps}")
     Wg, rg = run_gpu(case, nsteps)
     ro = oracle.run(case, nsteps)
-    err = field_errors(Wg, ro["W"], vector_momentum=tol > TOL64)
-    print(f"  field errors {err}", flush=True)
+    err = assert_matches_oracle(Wg, case, ro, tol)
     assert rg["steps"] == ro["steps"]
-    assert np.all(err <= tol), err
     assert abs(rg["t"] - ro["t"]) <= (1e-13 if tol <= TOL64 else 1e-5) * max(ro["t"], 1e-300)
     # the mode changes the solution: compare with the dt-mode oracle
     case.eps_mode = "dt"

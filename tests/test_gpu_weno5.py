@@ -1,21 +1,20 @@
 """Fifth-order WENO face values (recon = GKS_RECON_WENO5) on the GPU against the oracle on
-the same seeded inputs: FP64 flux <= 1e-12 and FP32 flux <= 1e-5, normwise, the momentum
-components measured against the momentum magnitude (as in the FP32 parity tests) and the
-other fields each against its own.  The device forms the weighted mean over a common
-denominator (one reciprocal), the oracle with the weights themselves: equal up to rounding.
+the same seeded inputs: FP64 flux <= 1e-12 and FP32 flux <= 1e-5 per field, normwise.  The
+device forms the weighted mean over a common denominator (one reciprocal), the oracle with
+the weights themselves: equal up to rounding.
 
-Why the momentum magnitude: in the mixing layer the transverse momentum stays three orders
-below the streamwise one, and with WENO5 a one-ulp change of the face values anywhere
-grows to 1-2e-12 of max |rho V| within 20-60 steps.  Algebraically equal forms of the
-oracle's own WENO5 (its final division or its weights' divisions taken as reciprocals, or
-its 1/6 as a product) differ from it by 1.3e-12 (20 steps) to 2.1e-12 (60 steps) there,
-and by under 4e-15 against the momentum magnitude; second-order and third-order MUSCL
-face values, computed the same way on both sides, stay within the per-field bound."""
+Reading Z34: in the mixing layer the transverse momentum stays three orders below the
+streamwise one, and with WENO5 a one-ulp change of the face values anywhere grows to
+1-2e-12 of max |rho V| within 20-60 steps; algebraically equal forms of the oracle's own
+WENO5 differ from it by that much (measured in tests/test_oracle_weno5.py).  A momentum
+component at the FP64 bound is therefore held to 1e-12 against the momentum magnitude and
+to 1e-11 per field (gpu_util.assert_matches_oracle); every other field, and every FP32
+figure, per field."""
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import banner, field_errors, run_gpu
+from gpu_util import assert_matches_oracle, banner, field_errors, run_gpu
 from inputs import cases as C
 
 pytestmark = pytest.mark.gpu
@@ -30,10 +29,8 @@ def _compare(case, nsteps, tol, changes=True):
     banner(f"weno5: {case.name} {case.precision} n={case.n} steps={nsteps}")
     Wg, rg = run_gpu(case, nsteps)
     ro = oracle.run(case, nsteps)
-    err = field_errors(Wg, ro["W"], vector_momentum=True)
-    print(f"  field errors {err}", flush=True)
+    assert_matches_oracle(Wg, case, ro, tol)
     assert rg["steps"] == ro["steps"]
-    assert np.all(err <= tol), err
     assert abs(rg["t"] - ro["t"]) <= (1e-13 if tol <= TOL64 else 1e-5) * max(ro["t"], 1e-300)
     if changes:       # the reconstruction changed the result
         case.recon = "muscl2"
@@ -108,11 +105,11 @@ def test_weno5_with_transport(dim, mode):
     finally:
         s.close()
     ro = oracle.run_kw(c, n)
-    err = field_errors(W, ro["W"], vector_momentum=True)
+    assert_matches_oracle(W, c, ro, TOL64)
     ek = np.max(np.abs(kw[0] - ro["k"])) / np.max(np.abs(ro["k"]))
     ew = np.max(np.abs(kw[1] - ro["omega"])) / np.max(np.abs(ro["omega"]))
-    print(f"  flow errors {err}  k {ek:.3e}  omega {ew:.3e}", flush=True)
-    assert np.all(err <= TOL64) and ek <= TOL64 and ew <= TOL64
+    print(f"  k {ek:.3e}  omega {ew:.3e}", flush=True)
+    assert ek <= TOL64 and ew <= TOL64
     eo = oracle.eps_field(c, W, kw[0], kw[1])
     assert np.max(np.abs(e - eo)) <= 1e-12 * max(eo.max(), 1e-300)
 
@@ -154,6 +151,4 @@ def test_weno5_sbli_full_size_one_step():
         s.close()
     ro = oracle.run(c, 1, W=Wa, t0=ra["t"])
     assert abs(rb["dt"] - ro["dt"]) <= 1e-13 * ro["dt"]
-    err = field_errors(Wb, ro["W"], vector_momentum=True)
-    print(f"  field errors {err}", flush=True)
-    assert np.all(err <= TOL64)
+    assert_matches_oracle(Wb, c, ro, TOL64)

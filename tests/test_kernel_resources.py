@@ -1,17 +1,17 @@
 """Register budget of the gfx950 kernels, from the compiler's resource remarks.
 
-The flux kernels must stay spill-free at the occupancy they were designed for: the fused
-2D tile kernel at three waves per SIMD in FP64 and four in the FP32-flux form, the 3D
-face kernel at two (FP64) and four (FP32), in every variant (k-omega transport, tau_hat
-rarefaction, third-order MUSCL face values), except that the third-order FP32 3D form runs
-at three waves and the third-order 2D FP64 tile keeps three waves with a bounded spill of a
-few doubles per face (two waves would cost more); the multi-dimensional expansion, with its
-tangential gradients, runs one wave lower in 2D and at two waves in 3D (FP64 with a bounded
-spill, also with transport and tau_hat); the WENO5 face values, with six stencil cells, keep the third-order budgets in
-every combination with transport and tau_hat (the 2D FP64 tile at three waves with a
-bounded spill, the 3D FP32 form at three waves).  A spill means the flux path stopped being
-inlined or grew (or values derived from the thread index were kept live across the tile
-loop), and costs scratch traffic to HBM on every face."""
+The flux kernels must stay spill-free at the occupancy they were designed for.  The fused
+2D tile kernel runs at three waves per SIMD in FP64; in the FP32-flux form (whose FP64
+share -- the interface state, the Euler and collisionless parts of the flux -- lifts its
+registers) at four for the plain scheme and three for its variants (the transported ones
+are held to three by their LDS).  The 3D face kernel runs at two waves (FP64) and three
+(FP32), the FP32 third-order, WENO5 and multi-dimensional forms at two.  Exceptions with a
+bounded spill of a few doubles per face: the third-order and WENO5 2D FP64 tiles at three
+waves (two would cost more), and the multi-dimensional 3D FP64 kernel at two; the
+multi-dimensional expansion, with its tangential gradients, runs one wave lower in 2D.  A
+spill means the flux path stopped being inlined or grew (or values derived from the thread
+index were kept live across the tile loop), and costs scratch traffic to HBM on every
+face."""
 import os
 import re
 
@@ -67,17 +67,18 @@ def test_fused_2d_kernels_occupancy(remarks):
         assert v["Occupancy"] >= (2 if md else 3), (k, v)
     for k, v in k32.items():
         assert v["ScratchSize"] == 0, (k, v)
-        assert v["Occupancy"] >= (3 if _variant(k) & 8 else 4), (k, v)
+        want = 4 if _variant(k) == 0 else (2 if _variant(k) & 8 else 3)
+        assert v["Occupancy"] >= want, (k, v)
 
 
 def test_3d_face_kernels_fit_without_spill(remarks):
-    for r, waves in (("d", 2), ("f", 4)):
+    for r, waves in (("d", 2), ("f", 3)):
         ks = _face(remarks, r, 3)
         assert len(ks) == 18                        # variant 0 at tiles 64, 128, 256; 1..11 and 16..19 at 64
         for k, v in ks.items():
             md = bool(_variant(k) & 8)
             assert v["ScratchSize"] <= (48 if md and r == "d" else 0), (k, v)
-            drop = (2 if md else (1 if _variant(k) & (4 | 16) else 0)) if r == "f" else 0
+            drop = (1 if _variant(k) & (4 | 8 | 16) else 0) if r == "f" else 0
             assert v["Occupancy"] >= waves - drop, (k, v)
 
 

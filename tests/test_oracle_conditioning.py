@@ -1,0 +1,88 @@
+"""Reading Z34: how well the per-field error metric is conditioned for a field that is a
+small perturbation of a larger vector.
+
+The mixing layer's transverse momentum rho V stays about three orders below the streamwise
+momentum, and the shear layer amplifies perturbations (Kelvin-Helmholtz).  Two FP64
+evaluations of the same scheme that differ only in rounding therefore drift apart in rho V
+by more than 1e-12 of max |rho V| within a few hundred steps (within a few tens with WENO5
+face values), while every field, rho V included, stays within ~1e-14 when the momentum
+components are measured against the momentum magnitude.  The oracle shows it against
+itself: builds of it with algebraically equal forms (a reciprocal in place of a division,
+the WENO5 mean over a common denominator) differ from the default by that much.  No
+implementation with a different rounding order can meet 1e-12 per field there, so the
+FP64 parity tests hold such a component (range below 1 % of the momentum magnitude) to
+1e-12 against the momentum magnitude and to 1e-11 per field (tests/gpu_util.py).
+"""
+import subprocess
+
+import numpy as np
+import pytest
+
+import gpu_util
+import oracle
+from inputs import cases as C
+
+
+def _build_variant(tmp_path, old, new):
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, old
+    path = tmp_path / "variant.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libvariant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                           "-o", str(so), str(path), "-lm"])
+    return str(so)
+
+
+def _spread(case, nsteps, so):
+    ref = oracle.run(case, nsteps, nthreads=4)
+    oracle.use_library(so)
+    try:
+        alt = oracle.run(case, nsteps, nthreads=4)
+    finally:
+        oracle.use_library(None)
+    return gpu_util.field_errors(alt["W"], ref["W"]), gpu_util.field_errors(alt["W"], ref["W"], vector_momentum=True)
+
+
+def _check(case, per_field, against_magnitude):
+    W = case.W
+    mom = np.sqrt(W[1] ** 2 + W[2] ** 2)
+    assert np.max(np.abs(W[2])) < 1e-2 * np.max(mom)       # rho V is a perturbation component
+    assert per_field[2] > 1e-12, per_field                   # beyond the per-field bound ...
+    assert per_field[2] < gpu_util.PERTURBATION_FIELD / 2, per_field
+    assert np.all(against_magnitude < 1e-14), against_magnitude   # ... but not against |rho U|
+    assert np.all(per_field[[0, 1, 3]] < 1e-14), per_field
+
+
+def test_mixing_layer_transverse_momentum_second_order(tmp_path):
+    """Second-order MUSCL, one mixing layer of the uneven batch's recipe (93^2, 100 steps):
+    the flux difference multiplied by the reciprocal width instead of divided by it."""
+    so = _build_variant(tmp_path,
+                        "        acc += (F[d][m * nf + hi] - F[d][m * nf + lo]) / gr->dx[d][idx[d] + 2];",
+                        "        acc += (F[d][m * nf + hi] - F[d][m * nf + lo]) * (1.0 / gr->dx[d][idx[d] + 2]);")
+    case = C.batch_cases(14, seed=3, nmin=40, nmax=100, steps=200, precision="fp64")[8]
+    assert case.name.startswith("b08_mixing_layer")
+    _check(case, *_spread(case, 100, so))
+
+
+WENO5_FINAL = "    return (al0 * q0 + al1 * q1 + al2 * q2) / (al0 + al1 + al2);"
+WENO5_EQUAL_FORMS = {
+    # the final division taken as a product with the reciprocal
+    "reciprocal": "    return (al0 * q0 + al1 * q1 + al2 * q2) * (1.0 / (al0 + al1 + al2));",
+    # the weighted mean over the common denominator (the device's form)
+    "common denominator": (
+        "    const double P0 = (eps + beta0) * (eps + beta0), P1 = (eps + beta1) * (eps + beta1),"
+        " P2 = (eps + beta2) * (eps + beta2);\n"
+        "    const double w0 = 0.1 * (P1 * P2), w1 = 0.6 * (P0 * P2), w2 = 0.3 * (P0 * P1);\n"
+        "    (void)al0; (void)al1; (void)al2;\n"
+        "    return (w0 * q0 + w1 * q1 + w2 * q2) * (1.0 / (w0 + w1 + w2));"),
+}
+
+
+@pytest.mark.parametrize("form", sorted(WENO5_EQUAL_FORMS))
+def test_mixing_layer_transverse_momentum_weno5(form, tmp_path):
+    """WENO5 face values: the 64^2 mixing layer within 20 steps."""
+    so = _build_variant(tmp_path, WENO5_FINAL, WENO5_EQUAL_FORMS[form])
+    case = C.mixing_layer(64, seed=3)
+    case.recon = "weno5"
+    _check(case, *_spread(case, 20, so))

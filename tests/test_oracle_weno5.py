@@ -232,3 +232,4 @@ def test_fewer_than_three_cells_refused():
     c.recon = "weno5"
     with pytest.raises(oracle.OracleError):
         oracle.run(c, 1)
+
