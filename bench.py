@@ -84,8 +84,8 @@ def _profiled_traffic(kernel):
 
 def _roofline(case, leg, steps, flops_face, peak):
     """ALU roofline of the flux kernel: algorithmic flops of every face of the mesh, once
-    (the fused 2D kernel also recomputes its tile-edge faces and does the update, which
-    are not counted), over that kernel's average launch duration."""
+    (the fused 2D and 3D kernels also recompute their tiles' side faces and do the update,
+    which are not counted), over that kernel's average launch duration."""
     n = case.n
     faces = (n[0] + 1) * n[1] + n[0] * (n[1] + 1) if case.dim == 2 else \
         (n[0] + 1) * n[1] * n[2] + n[0] * (n[1] + 1) * n[2] + n[0] * n[1] * (n[2] + 1)
@@ -98,7 +98,12 @@ def _roofline(case, leg, steps, flops_face, peak):
     v = ((1 if getattr(case, "kw_transport", False) else 0) | (2 if getattr(case, "eps_mode", "dt") == "tauhat" else 0)
          | (4 if recon == "muscl3" else 0) | (8 if getattr(case, "multi_d", False) else 0)
          | (16 if recon == "weno5" else 0))
-    kernel = f"k_tile2<{r},{v}>" if case.dim == 2 else f"k_face<{r},3,64,{v}>"
+    # 2D: the fused tile kernel; 3D: the fused z-marching tile kernel, or the face kernel for
+    # transport, the multi-dimensional expansion and WENO5
+    if case.dim == 2:
+        kernel = f"k_tile2<{r},{v}>"
+    else:
+        kernel = f"k_tile3<{r},{v}>" if (v & (1 | 8 | 16)) == 0 else f"k_face<{r},3,64,{v}>"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": _profiled_traffic(kernel),
             "kernel": kernel, "flops_per_face": flops_face, "faces_per_launch": faces,

@@ -193,9 +193,10 @@ gks_status gks_destroy(gks_handle h);
 
 /* Per-kernel timing for benchmarks.  While enabled, gks_step launches each kernel with a
  * pair of HIP events on the handle's stream that the runtime stamps with that launch's
- * own start and end (no extra packets between launches).  A 3D step is three launches:
- * strain (which also ends the previous step), face and update; a 2D step two: strain and
- * the fused tile kernel, which computes the faces and updates (timed as face).  A call
+ * own start and end (no extra packets between launches).  A step is two launches: strain
+ * (which also ends the previous step) and the fused tile kernel, which computes the faces
+ * and updates (timed as face); a 3D step with transport, WENO5 or the multi-dimensional
+ * expansion is three: strain, face and update.  A call
  * adds one trailing end-of-step launch (finish).  gks_kernel_times synchronises and writes the summed
  * milliseconds of each launch kind since timing was enabled (ms[0..3] = strain, face,
  * update, finish) and the number of steps timed; enabling again resets. */
@@ -257,11 +258,13 @@ gks_status gks_batch_step(gks_batch b, int32_t nsteps);
 gks_status gks_batch_capture(gks_batch b);
 
 /* Launch shape of the batch kernels: kind 0 = strain, 1 = fused 2D tile kernel (FP64),
- * 2 = fused 2D tile kernel (FP32 flux), 3 = face (3D FP64), 4 = face (3D FP32), 5 = update
- * (3D).  grid = number of persistent workgroups walking the tile table (0 = one per
- * tile).  tile = faces per face-kernel tile and workgroup (64, 128 or 256) for kinds 3
- * and 4 (a class that holds a member with options keeps 64); 0 otherwise (the 2D tile is
- * fixed: 16 x 15 cells per 256-thread workgroup).
+ * 2 = fused 2D tile kernel (FP32 flux), 3 = 3D face-class kernels (FP64), 4 = the same in
+ * FP32 flux, 5 = update (3D solves outside the fused kernel).  grid = number of persistent
+ * workgroups walking the tile table (0 = one per tile).  The tiles are fixed: tile must
+ * be 0, or 256 for kinds 1-4 (the fused 2D tile of 16 x 15 cells and the fused 3D column
+ * of 16 x 15 cells marching along z, 256 threads each), or 64 for kinds 3-4 (faces per
+ * workgroup of the 3D face kernel of solves with transport, WENO5 or the
+ * multi-dimensional expansion); anything else is GKS_ERR_ARG.
  * Results do not depend on the launch shape (bitwise).  Invalidates a captured graph. */
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile);
 

@@ -4,9 +4,8 @@ The result of a step does not depend on the launch shape (every face flux and ev
 per-tile partial sum is computed the same way whatever workgroup handles it), so the
 tuner times candidate shapes on the live batch: the steps it spends measuring are real
 steps of the solves.  Searched: for each face-kernel class present, the persistent grid
-(one workgroup per tile, or 4/8/16 workgroups per CU) and, for the 3D classes, faces per
-tile (64 / 128 / 256; the fused 2D kernel has a fixed cell tile); then the grid of the
-strain kernel and, with 3D members, of the update kernel.  The winner is cached in a JSON
+(one workgroup per tile, or 4/8/16 workgroups per CU); then the grid of the strain kernel
+and, with 3D members, of the update kernel.  The winner is cached in a JSON
 file keyed by device, class mix and problem size, and reused without a search.
 """
 from __future__ import annotations
@@ -16,12 +15,10 @@ import os
 import time
 
 KIND_STRAIN, KIND_UPDATE = 0, 5
-TILES = (64, 128, 256)
-
-
 def tiles_of(c: int):
-    """Tile sizes of a face class: none to choose for the fused 2D kernel (classes 0, 1)."""
-    return (0,) if c < 2 else TILES
+    """Tile choices of a face class: none (the fused 2D and 3D tile kernels and the 3D face
+    kernel of the options outside the fused kernel have fixed tiles)."""
+    return (0,)
 
 
 def cls_of(case) -> int:
@@ -39,7 +36,7 @@ def _signature(batch) -> str:
     classes = sorted({cls_of(s.case) for s in batch.solvers})
     cells = sum(s.case.ncells for s in batch.solvers)
     bucket = 1 << max(int(cells).bit_length() - 1, 0)        # power-of-two size class
-    return f"{name}|classes={classes}|cells~{bucket}|members~{len(batch.solvers)}|fused2d"
+    return f"{name}|classes={classes}|cells~{bucket}|members~{len(batch.solvers)}|fused2d3d"
 
 
 def _time_steps(batch, n: int) -> float:

@@ -496,9 +496,14 @@ GKS_HD inline Kw<R> kw_narrow(const Kw<H>& k)
 template <typename R, typename H, int D>
 GKS_HD inline void mx_narrow(Mx<R, D>& g, const Mx<H, D>& w, R bt)
 {
-    R u[D];
-    for (int d = 0; d < D; ++d) u[d] = R(w.U[d]);
-    mx_set(g, R(w.rho), u, R(w.lam), R(w.h), bt);
+    if constexpr (std::is_same<R, H>::value) {
+        (void)bt;
+        g = w;
+    } else {
+        R u[D];
+        for (int d = 0; d < D; ++d) u[d] = R(w.U[d]);
+        mx_set(g, R(w.rho), u, R(w.lam), R(w.h), bt);
+    }
 }
 
 // The flux.  Returns 0, or 1 when a state met is non-physical (then Fout is meaningless).

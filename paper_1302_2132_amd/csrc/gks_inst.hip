@@ -3,7 +3,7 @@
 // The build compiles this unit once for each GKS_PART (0..7), so that the flux kernels,
 // which take most of the compile time, are compiled in parallel.  Every share defines
 // kernels that gks_kernels.hpp declares `extern template`; together the shares cover
-// GKS_TILE2_VARIANTS and GKS_FACE_VARIANTS exactly once.
+// GKS_TILE2_VARIANTS, GKS_TILE3_VARIANTS and GKS_FACE_VARIANTS exactly once.
 #include "gks_kernels.hpp"
 
 #ifndef GKS_PART
@@ -16,6 +16,8 @@ namespace gks {
 #define GKS_TILE2_F(V) template __global__ void k_tile2<float, V>(const void*, int, int);
 #define GKS_FACE_D(T, V) template __global__ void k_face<double, 3, T, V>(const void*, int, int);
 #define GKS_FACE_F(T, V) template __global__ void k_face<float, 3, T, V>(const void*, int, int);
+#define GKS_TILE3_D(V) template __global__ void k_tile3<double, V>(const void*, int, int);
+#define GKS_TILE3_F(V) template __global__ void k_tile3<float, V>(const void*, int, int);
 
 // 2D tiles: MUSCL reconstructions with transport and tau_hat (variants 0..7), then the
 // multi-dimensional expansion and WENO5 (8..11, 16..19)
@@ -29,18 +31,17 @@ GKS_TILE2_F(0) GKS_TILE2_F(1) GKS_TILE2_F(2) GKS_TILE2_F(3) GKS_TILE2_F(4) GKS_T
 #elif GKS_PART == 3
 GKS_TILE2_F(8) GKS_TILE2_F(9) GKS_TILE2_F(10) GKS_TILE2_F(11)
 GKS_TILE2_F(16) GKS_TILE2_F(17) GKS_TILE2_F(18) GKS_TILE2_F(19)
-// 3D face kernels: the plain scheme at three tile sizes and variants 1..7, then 8..11, 16..19
+// 3D: the fused tile kernel (the plain scheme, tau_hat, third-order MUSCL) and the face
+// kernel of the options with transport, the multi-dimensional expansion or WENO5
 #elif GKS_PART == 4
-GKS_FACE_D(64, 0) GKS_FACE_D(128, 0) GKS_FACE_D(256, 0)
-GKS_FACE_D(64, 1) GKS_FACE_D(64, 2) GKS_FACE_D(64, 3) GKS_FACE_D(64, 4) GKS_FACE_D(64, 5) GKS_FACE_D(64, 6)
-GKS_FACE_D(64, 7)
+GKS_TILE3_D(0) GKS_TILE3_D(2) GKS_TILE3_D(4) GKS_TILE3_D(6)
+GKS_FACE_D(64, 1) GKS_FACE_D(64, 3) GKS_FACE_D(64, 5) GKS_FACE_D(64, 7)
 #elif GKS_PART == 5
 GKS_FACE_D(64, 8) GKS_FACE_D(64, 9) GKS_FACE_D(64, 10) GKS_FACE_D(64, 11)
 GKS_FACE_D(64, 16) GKS_FACE_D(64, 17) GKS_FACE_D(64, 18) GKS_FACE_D(64, 19)
 #elif GKS_PART == 6
-GKS_FACE_F(64, 0) GKS_FACE_F(128, 0) GKS_FACE_F(256, 0)
-GKS_FACE_F(64, 1) GKS_FACE_F(64, 2) GKS_FACE_F(64, 3) GKS_FACE_F(64, 4) GKS_FACE_F(64, 5) GKS_FACE_F(64, 6)
-GKS_FACE_F(64, 7)
+GKS_TILE3_F(0) GKS_TILE3_F(2) GKS_TILE3_F(4) GKS_TILE3_F(6)
+GKS_FACE_F(64, 1) GKS_FACE_F(64, 3) GKS_FACE_F(64, 5) GKS_FACE_F(64, 7)
 #elif GKS_PART == 7
 GKS_FACE_F(64, 8) GKS_FACE_F(64, 9) GKS_FACE_F(64, 10) GKS_FACE_F(64, 11)
 GKS_FACE_F(64, 16) GKS_FACE_F(64, 17) GKS_FACE_F(64, 18) GKS_FACE_F(64, 19)

@@ -927,6 +927,344 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
     }
 }
 
+// --------------------------------------------------------------------------------------
+// fused 3D step: an x-y tile marching along z
+// --------------------------------------------------------------------------------------
+// A workgroup of T2_THREADS threads owns a column of T3X x T3Y cells over a run of
+// I.seg3 planes (fewer at the top; I.nseg3 runs per column).  For each plane k it holds in
+// LDS the tile's state on planes k-1 .. k+2 (a ring of four planes), the two-cell x- and
+// y-halos of plane k (arms, ghosts synthesised), and k, omega, strain rate of plane k on a
+// one-cell halo.  Each thread computes one x-face and one y-face of plane k (fluxes into
+// LDS) and the z-face above its own cell; the face below was computed on the previous
+// plane and kept in LDS.  Then every thread updates its own cell of plane k.  The z-faces
+// are computed once, the x- and y-faces on the tile's side edges twice (by both
+// neighbouring tiles); no flux goes to HBM and the update needs no launch of its own.
+// Residual sums and the CFL rate accumulate per thread over the run and are reduced once.
+// The arithmetic of every face and cell is that of k_face and k_update.  Variants: the
+// second- and third-order MUSCL face values with either eps mode (two-cell stencils);
+// transport, WENO5 and the multi-dimensional expansion use k_face and k_update.
+constexpr int T3X = 16, T3Y = 15;
+constexpr int T3_NC = T3X * T3Y;                        // cells per plane of a tile
+constexpr int T3_KX = T3X + 2, T3_KY = T3Y + 2;         // k, omega, strain window
+template <int V> constexpr bool fused3_variant() { return (V & (V_KW | V_MD | V_W5)) == 0; }
+static_assert(T3_NC <= T2_THREADS, "one z-face and one cell per thread");
+
+#ifndef GKS_TILE3_WAVES_FP64
+#define GKS_TILE3_WAVES_FP64 2
+#endif
+#ifndef GKS_TILE3_WAVES_FP32
+#define GKS_TILE3_WAVES_FP32 2
+#endif
+
+// LDS of a fused 3D tile.
+struct Tile3Lds {
+    double R[4][5][T3_NC];           // planes k-1 .. k+2 (slot z & 3)
+    double XA[5][T3Y * 4];           // x-halo of plane k: a = -2, -1, tx, tx+1 per row
+    double YA[5][T3X * 4];           // y-halo of plane k: b = -2, -1, ty, ty+1 per column
+    double K[3][T3_KX * T3_KY];      // k, omega, strain rate of plane k (one-cell halo)
+    double Fx[5][(T3X + 1) * T3Y];
+    double Fy[5][T3X * (T3Y + 1)];
+    double Fz[5][T3_NC];             // z-face below each cell of plane k
+};
+
+// Geometry of one fused 3D tile: origin, extent and z-run.
+struct Tile3 {
+    int x0, y0, tx, ty, z0, z1;
+    __device__ bool owns(int t) const { return t < T3_NC && t % T3X < tx && t / T3X < ty; }
+};
+
+// Stage the tile's state on plane z (possibly a ghost plane) into its ring slot.
+__device__ inline void t3_stage_plane(cref<Inst> I, const Tile3& g, Tile3Lds& L, int t, int z)
+{
+    if (!g.owns(t)) return;
+    const double* __restrict__ W = I.W[state_of(I).parity];
+    const int c[3] = {g.x0 + t % T3X, g.y0 + t / T3X, z};
+    double w[5];
+    load_state<3>(I, W, 2, c, w);
+    const int s = (z + 4) & 3;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) L.R[s][m][t] = w[m];
+}
+
+// Stage the x- and y-halo arms and k, omega, S of plane k.
+__device__ inline void t3_stage_halo(cref<Inst> I, const Tile3& g, Tile3Lds& L, int t, int k)
+{
+    const double* __restrict__ W = I.W[state_of(I).parity];
+    if (t < 4 * (T3Y + T3X)) {
+        const bool xarm = t < 4 * T3Y;
+        const int q = xarm ? t : t - 4 * T3Y;
+        const int line = q >> 2, s = q & 3;
+        const int off = s < 2 ? s - 2 : s - 2 + (xarm ? g.tx : g.ty);    // -2, -1, t_, t_+1
+        if (line < (xarm ? g.ty : g.tx)) {
+            const int c[3] = {xarm ? g.x0 + off : g.x0 + line, xarm ? g.y0 + line : g.y0 + off, k};
+            double w[5];
+            load_state<3>(I, W, xarm ? 0 : 1, c, w);
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                if (xarm) L.XA[m][q] = w[m];
+                else L.YA[m][q] = w[m];
+            }
+        }
+    }
+    for (int e = t; e < T3_KX * T3_KY; e += T2_THREADS) {
+        const int a = e % T3_KX, b = e / T3_KX;
+        const bool row = b >= 1 && b < g.ty + 1 && a < g.tx + 2;
+        const bool colm = a >= 1 && a < g.tx + 1 && b < g.ty + 2;
+        if (!(row || colm)) continue;
+        const int c[3] = {g.x0 - 1 + a, g.y0 - 1 + b, k};
+        const int d = (c[0] < 0 || c[0] >= I.n[0]) ? 0 : 1;
+        const int ic = image_cell<3>(I, d, c);
+        L.K[0][e] = I.k[ic];
+        L.K[1][e] = I.om[ic];
+        L.K[2][e] = I.S[ic];
+    }
+}
+
+// Flux through a face normal to axis `dir` at position `fpos` along it, from its four
+// stencil cells Wc already in the face-local component order (normal momentum first), the
+// face means of k, omega and strain rate, and the step; F in the face-local order.  The
+// axis is a runtime value here (one inlined flux serves the three axes of the fused 3D
+// kernel), so only the geometry arrays are selected by it.
+template <typename R, int MODE, int RK>
+__device__ __attribute__((always_inline)) inline int face_local3(cref<Inst> I, int dir, int fpos,
+                                                                 const double (*Wc)[5], double kf, double wf,
+                                                                 double Sf, double dt, double* F)
+{
+    FaceGeo<double> geo;
+    {
+        const double* __restrict__ icd = I.icd[dir];
+        geo.icd[0] = icd[fpos - 2];
+        geo.icd[1] = icd[fpos - 1];
+        geo.icd[2] = icd[fpos];
+        const double* __restrict__ fg = I.fgeo[dir] + 4 * fpos;
+        geo.dl = fg[0];
+        geo.dr = fg[1];
+        geo.idl = fg[2];
+        geo.idr = fg[3];
+    }
+    FaceIn<3, double> in;
+    reconstruct<3, double, RK>(Wc, geo, in);
+    in.kf = kf;
+    in.wf = wf;
+    in.Sf = Sf;
+    in.dt = dt;
+    GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
+    return face_flux<R, 3, double, MODE>(in, gas, F);
+}
+
+template <typename R, int V>
+__global__ __launch_bounds__(T2_THREADS)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GKS_TILE3_WAVES_FP32 : GKS_TILE3_WAVES_FP64)))
+void k_tile3(const void* __restrict__ table, int cap, int cls)
+{
+    static_assert(fused3_variant<V>(), "variant without a fused 3D step");
+    constexpr int FMODE = (V & V_TH) ? FLUX_TAUHAT : 0;
+    constexpr int RK = recon_of<V>();
+    constexpr int NV = 5;
+    __shared__ Tile3Lds L;
+    __shared__ double sh_sum[5 * 4];
+    __shared__ double sh_max[4];
+    __shared__ int sh_bad[4];
+    const TabC tv(table, cap);
+    const int count = tv.hdr->ncls[cls];
+    const int total = tv.hdr->total_face[cls];
+    cptr<int> prefix = tv.cls_prefix + cls * (cap + 1);
+    cptr<int> member = tv.cls_member + cls * cap;
+    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+        const int mj = find_member(prefix, count, tile);
+        const int mi = member[mj];
+        {
+            cref<Inst> I = tv.inst[mi];
+            if (I.variant != V || !state_of(I).active) continue;   // another variant's tile (batches)
+        }
+        const int lt = tile - prefix[mj];
+        Tile3 g;
+        int cur;
+        {
+            cref<Inst> I = tv.inst[mi];
+            const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+            const int ntx = (n0 + T3X - 1) / T3X, nty = (n1 + T3Y - 1) / T3Y;
+            const int col = lt % (ntx * nty), seg = lt / (ntx * nty);
+            g.x0 = (col % ntx) * T3X;
+            g.y0 = (col / ntx) * T3Y;
+            g.tx = min(T3X, n0 - g.x0);
+            g.ty = min(T3Y, n1 - g.y0);
+            g.z0 = seg * I.seg3;
+            g.z1 = min(n2, g.z0 + I.seg3);
+            cur = state_of(I).parity;
+            // planes z0-2 .. z0: the march below first stages z0+1 and makes the z-face under z0
+            for (int z = g.z0 - 2; z <= g.z0; ++z) t3_stage_plane(I, g, L, (int)threadIdx.x, z);
+        }
+
+        double r2[5] = {0, 0, 0, 0, 0};
+        double rate = 0.0;
+        int bad = 0;
+        // Plane k = z0-1 only makes the z-face under plane z0; every later plane also makes
+        // its x- and y-faces and updates its cells.
+        for (int k = g.z0 - 1; k < g.z1; ++k) {
+            // The member and the thread index are re-read opaquely on every plane, so that
+            // the loads of the descriptor and the values derived from the thread index are
+            // made again per plane instead of being kept live across the march, where they
+            // would take registers from the flux evaluation.
+            int mo = mi, t = (int)threadIdx.x;
+            asm volatile("" : "+s"(mo));
+            asm volatile("" : "+v"(t));
+            cref<Inst> I = tv.inst[mo];
+            const double dt = state_of(I).dt;
+            const bool full = k >= g.z0;
+
+            // plane k+2 into the slot of plane k-2; halo arms and k, omega, S of plane k
+            t3_stage_plane(I, g, L, t, k + 2);
+            if (full) t3_stage_halo(I, g, L, t, k);
+            __syncthreads();
+
+            const int sk = (k + 4) & 3;
+            double Fz[NV] = {0, 0, 0, 0, 0};       // z-face above this thread's cell, face-local order
+            // one flux evaluation for the three axes: pass 0 the x-face, pass 1 the y-face
+            // (both into LDS), pass 2 the z-face above the thread's cell
+#pragma unroll 1
+            for (int pass = full ? 0 : 2; pass < 3; ++pass) {
+                int u = (int)threadIdx.x;
+                asm volatile("" : "+v"(u));
+                // component order of the face-local frame: rho, normal momentum, the two
+                // tangential momenta in axis order, energy
+                const int c1 = 1 + pass, c2 = pass == 0 ? 2 : 1, c3 = pass == 2 ? 2 : 3;
+                const int comp[NV] = {0, c1, c2, c3, 4};
+                bool act;
+                int fpos;
+                double Wc[4][NV], kf, wf, Sf;
+                if (pass == 0) {          // x-face (i, j): between cells x0+i-1 and x0+i of row y0+j
+                    const int i = u % (T3X + 1), j = u / (T3X + 1);
+                    act = u < (T3X + 1) * T3Y && i <= g.tx && j < g.ty;
+                    fpos = g.x0 + i;
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        const int a = i - 2 + o;
+                        const bool in = a >= 0 && a < g.tx;
+                        const double* src = in ? &L.R[sk][0][j * T3X + (in ? a : 0)]
+                                               : &L.XA[0][j * 4 + (a < 0 ? a + 2 : a - g.tx + 2)];
+                        const int str = in ? T3_NC : T3Y * 4;
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) Wc[o][m] = act ? src[comp[m] * str] : 1.0;
+                    }
+                    const int kl = act ? (j + 1) * T3_KX + i : 0;
+                    kf = 0.5 * (L.K[0][kl] + L.K[0][kl + 1]);
+                    wf = 0.5 * (L.K[1][kl] + L.K[1][kl + 1]);
+                    Sf = 0.5 * (L.K[2][kl] + L.K[2][kl + 1]);
+                } else if (pass == 1) {   // y-face (i, j): between cells y0+j-1 and y0+j of column x0+i
+                    const int i = u % T3X, j = u / T3X;
+                    act = u < T3X * (T3Y + 1) && i < g.tx && j <= g.ty;
+                    fpos = g.y0 + j;
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        const int b = j - 2 + o;
+                        const bool in = b >= 0 && b < g.ty;
+                        const double* src = in ? &L.R[sk][0][(in ? b : 0) * T3X + i]
+                                               : &L.YA[0][i * 4 + (b < 0 ? b + 2 : b - g.ty + 2)];
+                        const int str = in ? T3_NC : T3X * 4;
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) Wc[o][m] = act ? src[comp[m] * str] : 1.0;
+                    }
+                    const int kl = act ? j * T3_KX + i + 1 : 0;
+                    kf = 0.5 * (L.K[0][kl] + L.K[0][kl + T3_KX]);
+                    wf = 0.5 * (L.K[1][kl] + L.K[1][kl + T3_KX]);
+                    Sf = 0.5 * (L.K[2][kl] + L.K[2][kl + T3_KX]);
+                } else {                  // z-face between planes k and k+1 of this thread's column
+                    act = g.owns(u);
+                    fpos = k + 1;
+                    const int uu = act ? u : 0;
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        const int s = (k - 1 + o + 4) & 3;
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) Wc[o][m] = act ? L.R[s][comp[m]][uu] : 1.0;
+                    }
+                    int cl[3] = {g.x0 + uu % T3X, g.y0 + uu / T3X, k}, cr[3] = {g.x0 + uu % T3X, g.y0 + uu / T3X, k + 1};
+                    const int il = image_cell<3>(I, 2, cl), ir = image_cell<3>(I, 2, cr);
+                    kf = 0.5 * (I.k[il] + I.k[ir]);
+                    wf = 0.5 * (I.om[il] + I.om[ir]);
+                    Sf = 0.5 * (I.S[il] + I.S[ir]);
+                }
+                if (act) {
+                    double F[NV];
+                    if (face_local3<R, FMODE, RK>(I, pass, fpos, Wc, kf, wf, Sf, dt, F)) atomicOr(&I.st->err, 1);
+                    if (pass == 2) {
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) Fz[m] = F[m];
+                    } else {
+                        double* out = pass == 0 ? &L.Fx[0][u] : &L.Fy[0][u];
+                        const int str = pass == 0 ? (T3X + 1) * T3Y : T3X * (T3Y + 1);
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) out[comp[m] * str] = F[m];
+                    }
+                }
+            }
+            __syncthreads();
+
+            {   // update of this thread's cell on plane k (plane z0-1: keep the z-face only)
+                int u = (int)threadIdx.x;
+                asm volatile("" : "+v"(u));
+                const bool own = g.owns(u);
+                // the z-face in global component order (face-local: rho, m_z, m_x, m_y, E)
+                const double Fzg[NV] = {Fz[0], Fz[2], Fz[3], Fz[1], Fz[4]};
+                if (full) {
+                    const int ii = own ? u % T3X : 0, jj = own ? u / T3X : 0;
+                    CellRead<3, false> x;
+                    const int fx = jj * (T3X + 1) + ii, fy = jj * T3X + ii, e = jj * T3X + ii;
+                    const int cell = (k * I.n[1] + g.y0 + jj) * I.n[0] + g.x0 + ii;
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) {
+                        x.old[m] = L.R[sk][m][e];
+                        x.fl[0][m] = L.Fx[m][fx];
+                        x.fh[0][m] = L.Fx[m][fx + 1];
+                        x.fl[1][m] = L.Fy[m][fy];
+                        x.fh[1][m] = L.Fy[m][fy + T3X];
+                        x.fl[2][m] = L.Fz[m][e];
+                        x.fh[2][m] = Fzg[m];
+                    }
+                    x.idx[0] = I.idx[0][g.x0 + ii];
+                    x.idx[1] = I.idx[1][g.y0 + jj];
+                    x.idx[2] = I.idx[2][k];
+                    const int ek = (jj + 1) * T3_KX + ii + 1;
+                    x.kc = L.K[0][ek];
+                    x.wc = L.K[1][ek];
+                    update_apply<3, false>(I, I.W[cur ^ 1], cell, own, x, dt, 1.0 / dt, r2, rate, bad);
+                }
+                if (own) {
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) L.Fz[m][u] = Fzg[m];   // the face below plane k+1
+                }
+            }
+            __syncthreads();
+        }
+
+        // tile partials in a fixed order
+        const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+        for (int m = 0; m < NV; ++m) {
+            const double s = wave_sum(r2[m]);
+            if (lane == 0) sh_sum[m * 4 + wv] = s;
+        }
+        {
+            const double mx = wave_max(rate);
+            const int any = __any(bad);
+            if (lane == 0) { sh_max[wv] = mx; sh_bad[wv] = any; }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            cref<Inst> I = tv.inst[mi];
+            State* st = I.st;                    // every workgroup of the solve writes the same values
+            st->fresh = cur ^ 1;
+            st->pending = 1;
+            double* part = I.part + (long long)lt * PSTRIDE;
+            for (int m = 0; m < NV; ++m)
+                part[m] = (sh_sum[m * 4 + 0] + sh_sum[m * 4 + 1]) + (sh_sum[m * 4 + 2] + sh_sum[m * 4 + 3]);
+            part[5] = fmax(fmax(sh_max[0], sh_max[1]), fmax(sh_max[2], sh_max[3]));
+            if (sh_bad[0] | sh_bad[1] | sh_bad[2] | sh_bad[3]) atomicOr(&I.st->err, 1);
+        }
+        __syncthreads();
+    }
+}
+
 // time step following a state whose max CFL rate is `rate`, and the time it ends at
 __device__ inline void next_step(cref<Inst> I, State* st, double rate, double t)
 {
@@ -953,8 +1291,9 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
     for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int mi = find_member(tv.cell_prefix, count, tile);
         cref<Inst> I = tv.inst[mi];
-        // 2D solves update in k_tile2; a batch launches the transported form separately
-        if (I.dim == 2 || I.kw != (KW ? 1 : 0) || !state_of(I).active) continue;
+        // 2D solves update in k_tile2 and fused 3D solves in k_tile3; a batch launches the
+        // transported form separately
+        if (I.dim == 2 || I.fused3 || I.kw != (KW ? 1 : 0) || !state_of(I).active) continue;
         const int lt = tile - tv.cell_prefix[mi];
         const int cell = lt * CELL_TILE + (int)threadIdx.x;
         double r2[5] = {0, 0, 0, 0, 0};
@@ -1234,18 +1573,23 @@ extern __global__ void k_states(const void* __restrict__ table, int cap, State* 
 // compiles in parallel; every other unit sees these declarations only.  GKS_TILE2_VARIANTS
 // and GKS_FACE_VARIANTS list every (tile, variant) pair the library launches.
 #define GKS_TILE2_VARIANTS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(16) X(17) X(18) X(19)
-#define GKS_FACE_VARIANTS(X)                                                                         \
-    X(64, 0) X(128, 0) X(256, 0) X(64, 1) X(64, 2) X(64, 3) X(64, 4) X(64, 5) X(64, 6) X(64, 7) X(64, 8) \
-        X(64, 9) X(64, 10) X(64, 11) X(64, 16) X(64, 17) X(64, 18) X(64, 19)
+#define GKS_FACE_VARIANTS(X) \
+    X(64, 1) X(64, 3) X(64, 5) X(64, 7) X(64, 8) X(64, 9) X(64, 10) X(64, 11) X(64, 16) X(64, 17) X(64, 18) X(64, 19)
 #define GKS_TILE2_DECL(V)                                                      \
     extern template __global__ void k_tile2<double, V>(const void*, int, int); \
     extern template __global__ void k_tile2<float, V>(const void*, int, int);
 #define GKS_FACE_DECL(T, V)                                                           \
     extern template __global__ void k_face<double, 3, T, V>(const void*, int, int); \
     extern template __global__ void k_face<float, 3, T, V>(const void*, int, int);
+#define GKS_TILE3_VARIANTS(X) X(0) X(2) X(4) X(6)
+#define GKS_TILE3_DECL(V)                                                      \
+    extern template __global__ void k_tile3<double, V>(const void*, int, int); \
+    extern template __global__ void k_tile3<float, V>(const void*, int, int);
 GKS_TILE2_VARIANTS(GKS_TILE2_DECL)
 GKS_FACE_VARIANTS(GKS_FACE_DECL)
+GKS_TILE3_VARIANTS(GKS_TILE3_DECL)
 #undef GKS_TILE2_DECL
 #undef GKS_FACE_DECL
+#undef GKS_TILE3_DECL
 
 }  // namespace gks

@@ -48,11 +48,29 @@ struct Layout {
     int ntan[3];
     int ntile_cell, ntile_face[3];
     int ntile2;        // fused 2D tiles (2D only)
+    int fused3, seg3, nseg3, ntile3;   // fused 3D step: planes per z-run, runs per column, tiles
     int nstep_part;    // partial slots of a step
 };
 
 // fused 2D tiles of an n0 x n1 mesh
 static int tiles2(long long n0, long long n1) { return (int)(((n0 + T2X - 1) / T2X) * ((n1 + T2Y - 1) / T2Y)); }
+
+// Options whose 3D step runs in the fused tile kernel (two-cell stencils, no transport).
+static bool fused3_config(const gks_config* c)
+{
+    return c->dim == 3 && !c->turb_transport && !c->multi_d && c->recon != GKS_RECON_WENO5;
+}
+
+// z-runs of a fused 3D mesh: about 4608 tiles in all (enough rounds of workgroups to keep
+// every CU busy to the end), runs of at least four planes.
+static void runs3(long long n0, long long n1, long long n2, int* seg, int* nseg)
+{
+    const long long cols = ((n0 + T3X - 1) / T3X) * ((n1 + T3Y - 1) / T3Y);
+    long long ns = std::max<long long>(1, std::min<long long>(n2 / 4, (4608 + cols - 1) / cols));
+    const long long s = (n2 + ns - 1) / ns;
+    *seg = (int)s;
+    *nseg = (int)((n2 + s - 1) / s);
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -132,7 +150,7 @@ void layout(const gks_config* c, Layout* L)
         L->nface[d] = L->ncells / n[d] * (n[d] + 1);
         L->ntan[d] = (int)(L->ncells / n[d]);
         L->ntile_face[d] = (int)((L->nface[d] + FACE_TILE - 1) / FACE_TILE);
-        if (D == 3) L->F[d] = take(fb * nx * (size_t)L->nface[d]);   // 2D fluxes stay in LDS
+        if (D == 3 && !fused3_config(c)) L->F[d] = take(fb * nx * (size_t)L->nface[d]);   // else in LDS
         L->xf[d] = take(sizeof(double) * (n[d] + 5));
         L->xc[d] = take(sizeof(double) * (n[d] + 4));
         L->dx[d] = take(sizeof(double) * (n[d] + 4));
@@ -147,7 +165,13 @@ void layout(const gks_config* c, Layout* L)
     }
     L->ntile_cell = (int)((L->ncells + CELL_TILE - 1) / CELL_TILE);
     L->ntile2 = D == 2 ? tiles2(n[0], n[1]) : 0;
-    L->nstep_part = D == 2 ? L->ntile2 : L->ntile_cell;
+    L->fused3 = fused3_config(c) ? 1 : 0;
+    L->seg3 = L->nseg3 = L->ntile3 = 0;
+    if (L->fused3) {
+        runs3(n[0], n[1], n[2], &L->seg3, &L->nseg3);
+        L->ntile3 = (int)(((n[0] + T3X - 1) / T3X) * ((n[1] + T3Y - 1) / T3Y)) * L->nseg3;
+    }
+    L->nstep_part = D == 2 ? L->ntile2 : (L->fused3 ? L->ntile3 : L->ntile_cell);
     L->part = take(sizeof(double) * PSTRIDE * (size_t)std::max(L->ntile_cell, L->nstep_part));
     L->st = take(sizeof(State));
     L->tab = take(TabView::bytes(1));
@@ -227,12 +251,9 @@ struct gks_ctx {
 struct Present {
     std::bitset<NCLS * 32> face;      // bit cls * 32 + variant
     bool strain[2] = {false, false};  // frozen, transported
-    bool update[2] = {false, false};  // 3D frozen, 3D transported
-    int tile[NCLS] = {0, 0, 0, 0};    // faces per tile of each class in the table
+    bool update[2] = {false, false};  // 3D frozen, 3D transported (members outside k_tile3)
     bool covers(const Present& o) const
     {
-        for (int c = 0; c < NCLS; ++c)
-            if (tile[c] != o.tile[c]) return false;
         return (o.face & ~face).none() && (strain[0] || !o.strain[0]) && (strain[1] || !o.strain[1]) &&
                (update[0] || !o.update[0]) && (update[1] || !o.update[1]);
     }
@@ -244,7 +265,6 @@ struct gks_batch_ctx {
     hipStream_t stream;
     void* tab;
     int grid[6];
-    int face_tile[NCLS];
     bool captured;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -286,10 +306,10 @@ static int device_cus()
     return cus;
 }
 
-// Fill a host image of a tile table for `members` (capacity cap), with face tiles of
-// face_tile[cls] faces for each face-kernel class.
-static void build_table(std::vector<char>& img, int cap, const std::vector<const Inst*>& members,
-                        const int* face_tile)
+// Fill a host image of a tile table for `members` (capacity cap): cell tiles of every
+// member, and the face-kernel tiles of each class (fused 2D and 3D tiles, or FACE_TILE faces
+// for the 3D face kernel of the options outside k_tile3).
+static void build_table(std::vector<char>& img, int cap, const std::vector<const Inst*>& members)
 {
     img.assign(TabView::bytes(cap), 0);
     TabView tv(img.data(), cap);
@@ -303,8 +323,11 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
         if (I.dim == 2) {                        // fused 2D kernel: fixed cell tiles
             I.face_tile = T2_THREADS;
             I.ntile_face_all = tiles2(I.n[0], I.n[1]);
+        } else if (I.fused3) {                   // fused 3D kernel: column tiles times z-runs
+            I.face_tile = T2_THREADS;
+            I.ntile_face_all = ((I.n[0] + T3X - 1) / T3X) * ((I.n[1] + T3Y - 1) / T3Y) * I.nseg3;
         } else {
-            const int ft = face_tile[I.cls];
+            const int ft = FACE_TILE;
             I.face_tile = ft;
             I.ntile_face_all = 0;
             for (int d = 0; d < 3; ++d) {
@@ -324,44 +347,71 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
     for (int c = 0; c < NCLS; ++c) tv.hdr->total_face[c] = faces[c];
 }
 
-// Kernel of a face class: the fused 2D tile kernel (fixed workgroup of T2_THREADS) for the
-// 2D classes, the 3D face kernel with `tile` faces per workgroup otherwise.
 typedef void (*face_kernel_t)(const void*, int, int);
-template <int T, int V>
-static face_kernel_t face_kernel_t_(int cls)
+template <int V>
+static face_kernel_t tile2_kernel(int cls)
 {
-    switch (cls) {
-    case 0: return k_tile2<double, V>;
-    case 1: return k_tile2<float, V>;
-    case 2: return k_face<double, 3, T, V>;
-    default: return k_face<float, 3, T, V>;
+    return cls == 1 ? k_tile2<float, V> : k_tile2<double, V>;
+}
+template <int V>
+static face_kernel_t face3_kernel(int cls)
+{
+    return cls == 3 ? k_face<float, 3, FACE_TILE, V> : k_face<double, 3, FACE_TILE, V>;
+}
+// Fused 3D kernel of a precision and variant (the variants fused3_config admits).
+static face_kernel_t tile3_kernel(int cls, int variant)
+{
+    const bool f = cls == 3;
+    switch (variant) {
+    case V_TH: return f ? k_tile3<float, V_TH> : k_tile3<double, V_TH>;
+    case V_R3: return f ? k_tile3<float, V_R3> : k_tile3<double, V_R3>;
+    case V_TH | V_R3: return f ? k_tile3<float, V_TH | V_R3> : k_tile3<double, V_TH | V_R3>;
+    default: return f ? k_tile3<float, 0> : k_tile3<double, 0>;
     }
 }
-// Face kernel of a class and variant (V_KW and V_TH with one of V_R3, V_W5, V_MD).  Variants
-// other than 0 use the default tile, alone and in batches.
-static face_kernel_t face_kernel(int cls, int tile, int variant = 0)
+static bool fused3_variant_rt(int variant) { return (variant & (V_KW | V_MD | V_W5)) == 0; }
+
+// Face kernel of a class and variant (V_KW and V_TH with one of V_R3, V_W5, V_MD): the
+// fused 2D tile kernel for the 2D classes; for 3D the fused tile kernel, or the face kernel
+// (FACE_TILE faces per workgroup, then k_update) for transport, WENO5 and the
+// multi-dimensional expansion.
+static face_kernel_t face_kernel(int cls, int variant)
 {
-    switch (variant) {
-    case 1: return face_kernel_t_<FACE_TILE, 1>(cls);
-    case 2: return face_kernel_t_<FACE_TILE, 2>(cls);
-    case 3: return face_kernel_t_<FACE_TILE, 3>(cls);
-    case 4: return face_kernel_t_<FACE_TILE, 4>(cls);
-    case 5: return face_kernel_t_<FACE_TILE, 5>(cls);
-    case 6: return face_kernel_t_<FACE_TILE, 6>(cls);
-    case 7: return face_kernel_t_<FACE_TILE, 7>(cls);
-    case V_MD: return face_kernel_t_<FACE_TILE, V_MD>(cls);
-    case V_MD | V_KW: return face_kernel_t_<FACE_TILE, V_MD | V_KW>(cls);
-    case V_MD | V_TH: return face_kernel_t_<FACE_TILE, V_MD | V_TH>(cls);
-    case V_MD | V_KW | V_TH: return face_kernel_t_<FACE_TILE, V_MD | V_KW | V_TH>(cls);
-    case V_W5: return face_kernel_t_<FACE_TILE, V_W5>(cls);
-    case V_W5 | V_KW: return face_kernel_t_<FACE_TILE, V_W5 | V_KW>(cls);
-    case V_W5 | V_TH: return face_kernel_t_<FACE_TILE, V_W5 | V_TH>(cls);
-    case V_W5 | V_KW | V_TH: return face_kernel_t_<FACE_TILE, V_W5 | V_KW | V_TH>(cls);
-    default: break;
+    if (cls >= 2 && fused3_variant_rt(variant)) return tile3_kernel(cls, variant);
+    if (cls < 2) {
+        switch (variant) {
+        case 1: return tile2_kernel<1>(cls);
+        case 2: return tile2_kernel<2>(cls);
+        case 3: return tile2_kernel<3>(cls);
+        case 4: return tile2_kernel<4>(cls);
+        case 5: return tile2_kernel<5>(cls);
+        case 6: return tile2_kernel<6>(cls);
+        case 7: return tile2_kernel<7>(cls);
+        case V_MD: return tile2_kernel<V_MD>(cls);
+        case V_MD | V_KW: return tile2_kernel<V_MD | V_KW>(cls);
+        case V_MD | V_TH: return tile2_kernel<V_MD | V_TH>(cls);
+        case V_MD | V_KW | V_TH: return tile2_kernel<V_MD | V_KW | V_TH>(cls);
+        case V_W5: return tile2_kernel<V_W5>(cls);
+        case V_W5 | V_KW: return tile2_kernel<V_W5 | V_KW>(cls);
+        case V_W5 | V_TH: return tile2_kernel<V_W5 | V_TH>(cls);
+        case V_W5 | V_KW | V_TH: return tile2_kernel<V_W5 | V_KW | V_TH>(cls);
+        default: return tile2_kernel<0>(cls);
+        }
     }
-    if (tile == 128) return face_kernel_t_<128, 0>(cls);
-    if (tile == 256) return face_kernel_t_<256, 0>(cls);
-    return face_kernel_t_<64, 0>(cls);
+    switch (variant) {
+    case 1: return face3_kernel<1>(cls);
+    case 3: return face3_kernel<3>(cls);
+    case 5: return face3_kernel<5>(cls);
+    case 7: return face3_kernel<7>(cls);
+    case V_MD: return face3_kernel<V_MD>(cls);
+    case V_MD | V_KW: return face3_kernel<V_MD | V_KW>(cls);
+    case V_MD | V_TH: return face3_kernel<V_MD | V_TH>(cls);
+    case V_MD | V_KW | V_TH: return face3_kernel<V_MD | V_KW | V_TH>(cls);
+    case V_W5: return face3_kernel<V_W5>(cls);
+    case V_W5 | V_KW: return face3_kernel<V_W5 | V_KW>(cls);
+    case V_W5 | V_TH: return face3_kernel<V_W5 | V_TH>(cls);
+    default: return face3_kernel<V_W5 | V_KW | V_TH>(cls);
+    }
 }
 static int variant_of(const gks_config* c)
 {
@@ -369,8 +419,10 @@ static int variant_of(const gks_config* c)
            (c->recon == GKS_RECON_MUSCL3 ? V_R3 : 0) | (c->multi_d ? V_MD : 0) |
            (c->recon == GKS_RECON_WENO5 ? V_W5 : 0);
 }
-static int face_block(int cls, int tile) { return cls < 2 ? T2_THREADS : tile; }
-static const int kDefaultFaceTiles[NCLS] = {FACE_TILE, FACE_TILE, FACE_TILE, FACE_TILE};
+static int face_block(int cls, int variant)
+{
+    return (cls < 2 || fused3_variant_rt(variant)) ? T2_THREADS : FACE_TILE;
+}
 
 extern "C" {
 
@@ -472,6 +524,9 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.inv_cmu = 1.0 / cfg->c_mu;
     I.pfix = 1.0 / cfg->prandtl - 1.0;
     I.max_steps = cfg->max_steps;
+    I.fused3 = L.fused3;
+    I.seg3 = L.seg3;
+    I.nseg3 = L.nseg3;
     I.res_tol = cfg->res_tol;
     I.W[0] = (double*)(ws + L.W[0]);
     I.W[1] = (double*)(ws + L.W[1]);
@@ -485,8 +540,8 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     I.st = (State*)(ws + L.st);
     I.ntile_cell = L.ntile_cell;
     I.nstep_part = L.nstep_part;
-    I.face_tile = D == 2 ? T2_THREADS : FACE_TILE;
-    I.ntile_face_all = D == 2 ? L.ntile2 : L.ntile_face[0] + L.ntile_face[1] + L.ntile_face[2];
+    I.face_tile = (D == 2 || L.fused3) ? T2_THREADS : FACE_TILE;
+    I.ntile_face_all = D == 2 ? L.ntile2 : (L.fused3 ? L.ntile3 : L.ntile_face[0] + L.ntile_face[1] + L.ntile_face[2]);
 
     HIP_TRY(h, hipMemcpyAsync(I.W[0], W, cellb * nv, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipMemcpyAsync((void*)I.k, k, cellb, hipMemcpyHostToDevice, s));
@@ -536,7 +591,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     h->tab = ws + L.tab;
     std::vector<char> img;
     std::vector<const Inst*> mem{&I};
-    build_table(img, 1, mem, kDefaultFaceTiles);
+    build_table(img, 1, mem);
     HIP_TRY(h, hipMemcpyAsync(h->tab, img.data(), img.size(), hipMemcpyHostToDevice, s));
     h->grid_cell = L.ntile_cell;
     h->grid_face = I.ntile_face_all;
@@ -570,9 +625,9 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
     hipStream_t s = h->stream;
     const void* tab = h->tab;
     const bool kw = h->cfg.turb_transport != 0;
-    face_kernel_t fk = face_kernel(h->cls, FACE_TILE, variant_of(&h->cfg));
-    const dim3 fblock(face_block(h->cls, FACE_TILE));
-    const bool upd = h->cfg.dim == 3;
+    face_kernel_t fk = face_kernel(h->cls, variant_of(&h->cfg));
+    const dim3 fblock(face_block(h->cls, variant_of(&h->cfg)));
+    const bool upd = h->cfg.dim == 3 && !h->inst.fused3;
     void (*ks)(const void*, int, int, int) = kw ? k_strain<true> : k_strain<false>;
     void (*ku)(const void*, int) = kw ? k_update<true> : k_update<false>;
     const int grid_head = h->grid_cell + 1;
@@ -855,16 +910,9 @@ static gks_status batch_upload(gks_batch b)
         const int kw = h->cfg.turb_transport ? 1 : 0;
         present.face.set(h->cls * 32 + variant_of(&h->cfg));
         present.strain[kw] = true;
-        if (h->cfg.dim == 3) present.update[kw] = true;
+        if (h->cfg.dim == 3 && !h->inst.fused3) present.update[kw] = true;
     }
-    // The 3D face kernels with options exist at the default tile only, and a class's table
-    // has one tile size: a 3D class with such a member keeps the default.
-    for (int c = 0; c < NCLS; ++c) {
-        present.tile[c] = b->face_tile[c];
-        for (int v = 1; v < 32; ++v)
-            if (c >= 2 && present.face.test(c * 32 + v)) present.tile[c] = FACE_TILE;
-    }
-    build_table(b->host_tab, b->cap, mem, present.tile);
+    build_table(b->host_tab, b->cap, mem);
     if (hipMemcpyAsync(b->tab, b->host_tab.data(), b->host_tab.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
         b->err = "table upload failed";
@@ -897,7 +945,6 @@ static gks_status batch_make(const gks_handle* hs, int32_t count, int32_t capaci
     b->grid[5] = cus * 8;        // update
     b->grid[1] = b->grid[2] = 0;                       // fused 2D kernel: one workgroup per tile
     b->grid[3] = b->grid[4] = cus * 16;                // 3D face: one-wave workgroups
-    for (int c = 0; c < NCLS; ++c) b->face_tile[c] = FACE_TILE;
     // the whole table image (zeros included) is written before any kernel reads it, so a
     // reused scratch needs no clearing; the read-back array is written by k_states first
     gks_status r = batch_upload(b);
@@ -979,8 +1026,7 @@ static void batch_launch(gks_batch b, const Present& present)
     for (int c = 0; c < NCLS; ++c)
         for (int v = 0; v < 32; ++v)
             if (present.face.test(c * 32 + v)) {
-                const int tile = present.tile[c];
-                hipLaunchKernelGGL(face_kernel(c, tile, v), dim3(batch_grid(b, 1 + c)), dim3(face_block(c, tile)), 0,
+                hipLaunchKernelGGL(face_kernel(c, v), dim3(batch_grid(b, 1 + c)), dim3(face_block(c, v)), 0,
                                    b->stream, tab, b->cap, c);
             }
     if (present.update[0])   // 3D members update in their own launch
@@ -1030,18 +1076,16 @@ gks_status gks_batch_capture(gks_batch b)
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile)
 {
     if (!b || kind < 0 || kind > 5 || grid < 0) return fail_h(nullptr, GKS_ERR_ARG, "bad launch shape");
-    const bool face = kind >= 3 && kind <= 4;        // 3D face kinds; the 2D tile is fixed
-    if (face ? (tile != 64 && tile != 128 && tile != 256) : (tile != 0 && !(kind >= 1 && kind <= 2 && tile == T2_THREADS)))
-        return fail_h(nullptr, GKS_ERR_ARG, "unsupported tile size");
+    // the tiles are fixed: 256 threads for the fused 2D and 3D kernels, FACE_TILE faces for
+    // the 3D face kernel of the options outside k_tile3
+    const bool ok_tile = tile == 0 || (kind >= 1 && kind <= 4 && tile == T2_THREADS) ||
+                         (kind >= 3 && kind <= 4 && tile == FACE_TILE);
+    if (!ok_tile) return fail_h(nullptr, GKS_ERR_ARG, "unsupported tile size");
     b->grid[kind] = grid;
     if (b->captured) {
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);
         b->captured = false;
-    }
-    if (face && b->face_tile[kind - 1] != tile) {
-        b->face_tile[kind - 1] = tile;
-        return batch_upload(b);   // tile counts of that class change
     }
     return GKS_OK;
 }

@@ -51,8 +51,12 @@ def test_workspace_bytes_and_validation():
         P.gks_workspace_bytes(P.config_from_case(bad))
     c3 = C.isotropic_box(16, precision="fp64")
     nb3 = P.gks_workspace_bytes(P.config_from_case(c3))
-    # 3D: two state buffers + k, omega, strain + x/y/z face fluxes (FP64) at least
-    assert nb3 >= 8 * 16 ** 3 * (5 * 2 + 3) + 8 * 5 * 3 * 17 * 16 * 16
+    # 3D, fused step: two state buffers + k, omega, strain; no face fluxes in HBM
+    assert 8 * 16 ** 3 * (5 * 2 + 3) <= nb3 < 8 * 16 ** 3 * (5 * 2 + 3) + 8 * 5 * 3 * 17 * 16 * 16
+    # a transported 3D solve keeps the face-kernel path: x/y/z face fluxes (FP64) in HBM
+    kw3 = c3.copy()
+    kw3.kw_transport = True
+    assert P.gks_workspace_bytes(P.config_from_case(kw3)) >= 8 * 16 ** 3 * (7 * 2 + 6) + 8 * 7 * 3 * 17 * 16 * 16
     fp32 = c3.copy()
     fp32.precision = "fp32_flux"
     assert P.gks_workspace_bytes(P.config_from_case(fp32)) == nb3    # face fluxes FP64 in both forms

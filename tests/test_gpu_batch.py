@@ -183,14 +183,19 @@ def test_batch_admitting_a_new_variant_drops_the_graph():
 
 
 def test_launch_shapes_do_not_change_results():
-    """Every tile size (3D face kernels) and persistent grid gives the same fields, bitwise,
-    also for members with options (their kernels walk the same persistent grids)."""
+    """Every persistent grid gives the same fields, bitwise, also for members with options
+    (their kernels walk the same persistent grids); the tiles are fixed, and a face-kernel
+    tile the library does not have is refused."""
     from paper_1302_2132_amd import Batch, Solver
     cases = _cases()[:4] + [_option_cases()[i] for i in (1, 4, 8)]
     ref = [_alone(c, 12) for c in cases]
     solvers = [Solver(c) for c in cases]
     b = Batch(solvers, capacity=8)
-    shapes = [(64, 0), (128, 512), (256, 0), (64, 4096)]
+    from paper_1302_2132_amd import GKS_ERR_ARG, GksError
+    with pytest.raises(GksError) as e:
+        b.set_launch(3, 0, 128)
+    assert e.value.status == GKS_ERR_ARG
+    shapes = [(64, 0), (0, 512), (256, 0), (64, 4096)]
     for i, (tile, grid) in enumerate(shapes):
         for kind in (1, 2):                  # fused 2D kernel: fixed tile
             b.set_launch(kind, grid, 0)

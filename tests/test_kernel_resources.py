@@ -71,10 +71,27 @@ def test_fused_2d_kernels_occupancy(remarks):
         assert v["Occupancy"] >= want, (k, v)
 
 
+def _tile3(res, r):
+    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks7k_tile3I{r}Li\d+EEEvPKvii", k)}
+
+
+def test_fused_3d_kernels_fit_without_spill(remarks):
+    """The fused 3D step (one flux evaluation serving its three axes) at two waves per SIMD
+    with no spill, and its LDS (a four-plane ring, halo arms, k/omega/S and the fluxes of a
+    plane) within half a CU's 160 KiB, so two workgroups share a CU."""
+    for r in ("d", "f"):
+        ks = _tile3(remarks, r)
+        assert sorted(_variant(k) for k in ks) == [0, 2, 4, 6]   # plain, tau_hat, MUSCL3, both
+        for k, v in ks.items():
+            assert v["ScratchSize"] == 0, (k, v)
+            assert v["Occupancy"] >= 2, (k, v)
+            assert v["LDS Size"] <= 80 * 1024, (k, v)
+
+
 def test_3d_face_kernels_fit_without_spill(remarks):
     for r, waves in (("d", 2), ("f", 3)):
         ks = _face(remarks, r, 3)
-        assert len(ks) == 18                        # variant 0 at tiles 64, 128, 256; 1..11 and 16..19 at 64
+        assert len(ks) == 12                        # transport, multi-d, WENO5 and their combinations
         for k, v in ks.items():
             md = bool(_variant(k) & 8)
             assert v["ScratchSize"] <= (48 if md and r == "d" else 0), (k, v)
