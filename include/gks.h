@@ -257,6 +257,14 @@ gks_status gks_batch_step(gks_batch b, int32_t nsteps);
 /* Capture one step of the batch as a HIP graph; later gks_batch_step calls replay it. */
 gks_status gks_batch_capture(gks_batch b);
 
+/* Capture `steps` (1..1024) consecutive steps as one HIP graph: gks_batch_step(n) then
+ * replays it n / steps times and launches the remaining n % steps steps directly.  Every
+ * step reads its parity, time step and activity from the device, so the replays are
+ * identical launches and each member's result is the same as with one-step graphs or none
+ * (bitwise).  Invalidated like a one-step graph by set_launch and by membership changes
+ * that need kernels the graph lacks. */
+gks_status gks_batch_capture_steps(gks_batch b, int32_t steps);
+
 /* Launch shape of the batch kernels: kind 0 = strain, 1 = fused 2D tile kernel (FP64),
  * 2 = fused 2D tile kernel (FP32 flux), 3 = 3D face-class kernels (FP64), 4 = the same in
  * FP32 flux, 5 = update (3D solves outside the fused kernel).  grid = number of persistent

@@ -14,6 +14,6 @@ from .gks import (  # noqa: F401
     gks_set_timing, gks_kernel_times,
     gks_batch_workspace_bytes, gks_batch_create, gks_batch_set_members, gks_batch_step,
     gks_batch_capture, gks_batch_set_launch, gks_batch_status, gks_batch_destroy,
-    gks_batch_create_static, GKS_BATCH_STATIC_CAPACITY,
+    gks_batch_create_static, GKS_BATCH_STATIC_CAPACITY, gks_batch_capture_steps,
     Solver, Batch, EXPORTED,
 )

@@ -72,13 +72,22 @@ __device__ inline cref<State> state_of(cref<Inst> I) { return *(cptr<State>)I.st
 // --------------------------------------------------------------------------------------
 // helpers
 // --------------------------------------------------------------------------------------
-__device__ inline int xcd_block()
+// Tiles of a grid-stride walk, XCD-aware.  Workgroups are dispatched round-robin over the
+// 8 XCDs (block b runs on XCD b % 8), and each XCD has its own L2: the tile range is split
+// into 8 contiguous parts, part x walked by the blocks of XCD x, so that neighbouring
+// tiles, which share halo cells, stay in one L2, and every XCD gets an equal share however
+// the grid compares with the tile count.  Grids that are not a multiple of 8 walk the
+// plain grid stride.
+struct TileWalk {
+    int first, end, stride;
+};
+__device__ inline TileWalk xcd_walk(int total)
 {
-    // Workgroups are dispatched round-robin over the 8 XCDs; renumber so that XCD x owns
-    // a contiguous run of virtual ids.
     const int g = gridDim.x, b = blockIdx.x;
-    if (g % 8) return b;
-    return (b % 8) * (g / 8) + b / 8;
+    if (g % 8) return {b, total, g};
+    const int per = (total + 7) / 8;
+    const int x = b % 8, lo = x * per;
+    return {lo + b / 8, min(total, lo + per), g / 8};
 }
 
 // index of the member owning `tile` (prefix has count+1 entries, prefix[0] = 0)
@@ -534,7 +543,8 @@ void k_face(const void* __restrict__ table, int cap, int cls)
     const int total = tv.hdr->total_face[cls];
     cptr<int> prefix = tv.cls_prefix + cls * (cap + 1);
     cptr<int> member = tv.cls_member + cls * cap;
-    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+    for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
+        const int tile = tw.first;
         const int mj = find_member(prefix, count, tile);
         cref<Inst> I = tv.inst[member[mj]];
         // a batch launches each variant present over its class; other variants' tiles pass
@@ -737,7 +747,8 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
     const int total = tv.hdr->total_face[cls];
     cptr<int> prefix = tv.cls_prefix + cls * (cap + 1);
     cptr<int> member = tv.cls_member + cls * cap;
-    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+    for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
+        const int tile = tw.first;
         // The thread index is made opaque per tile so that the LDS offsets derived from it
         // are recomputed (a few integer operations) rather than kept live across the tile
         // loop, where they would take registers from the flux evaluation.
@@ -1070,7 +1081,8 @@ void k_tile3(const void* __restrict__ table, int cap, int cls)
     const int total = tv.hdr->total_face[cls];
     cptr<int> prefix = tv.cls_prefix + cls * (cap + 1);
     cptr<int> member = tv.cls_member + cls * cap;
-    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+    for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
+        const int tile = tw.first;
         const int mj = find_member(prefix, count, tile);
         const int mi = member[mj];
         {
@@ -1288,7 +1300,8 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
     __shared__ double sh_max[4];
     __shared__ int sh_bad[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+    for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
+        const int tile = tw.first;
         const int mi = find_member(tv.cell_prefix, count, tile);
         cref<Inst> I = tv.inst[mi];
         // 2D solves update in k_tile2 and fused 3D solves in k_tile3; a batch launches the
@@ -1336,7 +1349,8 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
     __shared__ double sh_max[4];
     __shared__ int sh_bad[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
+    for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
+        const int tile = tw.first;
         const int mi = find_member(tv.cell_prefix, count, tile);
         cref<Inst> I = tv.inst[mi];
         const int lt = tile - tv.cell_prefix[mi];
@@ -1477,7 +1491,8 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
     const int head = finish ? count : 0;
     const int total = head + tv.hdr->total_cell;
     __shared__ double sh[6 * 4];
-    for (int item = xcd_block(); item < total; item += gridDim.x) {
+    for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
+        const int item = tw.first;
         if (item < head) {
             finish_member(tv.inst[item], 0, sh);
             continue;

@@ -266,6 +266,7 @@ struct gks_batch_ctx {
     void* tab;
     int grid[6];
     bool captured;
+    int graph_steps;                  // steps one replay of the captured graph advances
     hipGraph_t graph;
     hipGraphExec_t exec;
     Present present;                  // launches the current (or captured) step makes
@@ -297,6 +298,7 @@ static gks_status sync_batch(gks_ctx* h)
 }
 
 static int cls_of(int dim, int precision) { return (dim == 3 ? 2 : 0) + (precision ? 1 : 0); }
+static int round8(int n) { return (n + 7) & ~7; }
 
 static int device_cus()
 {
@@ -593,8 +595,10 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     std::vector<const Inst*> mem{&I};
     build_table(img, 1, mem);
     HIP_TRY(h, hipMemcpyAsync(h->tab, img.data(), img.size(), hipMemcpyHostToDevice, s));
-    h->grid_cell = L.ntile_cell;
-    h->grid_face = I.ntile_face_all;
+    // one workgroup per tile, rounded up to a multiple of the 8 XCDs so that the kernels'
+    // walk gives each XCD a contiguous eighth of the tiles (the extra groups find none)
+    h->grid_cell = round8(L.ntile_cell);
+    h->grid_face = round8(I.ntile_face_all);
     hipLaunchKernelGGL(k_rate, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, (const void*)h->tab, 1);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, (const void*)h->tab, 1, 1);
     HIP_TRY(h, hipGetLastError());
@@ -630,7 +634,7 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
     const bool upd = h->cfg.dim == 3 && !h->inst.fused3;
     void (*ks)(const void*, int, int, int) = kw ? k_strain<true> : k_strain<false>;
     void (*ku)(const void*, int) = kw ? k_update<true> : k_update<false>;
-    const int grid_head = h->grid_cell + 1;
+    const int grid_head = round8(h->inst.ntile_cell + 1);
     if (nsteps == 0) return GKS_OK;
     if (!h->timing) {
         for (int i = 0; i < nsteps; ++i) {
@@ -939,6 +943,7 @@ static gks_status batch_make(const gks_handle* hs, int32_t count, int32_t capaci
     b->stream = (hipStream_t)hip_stream;
     b->tab = tab;
     b->captured = false;
+    b->graph_steps = 1;
     b->static_dev = static_dev;
     const int cus = device_cus();
     b->grid[0] = cus * 8;        // strain: 256-thread workgroups
@@ -1000,7 +1005,7 @@ gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t coun
 }
 
 // Grid of a launch kind: the persistent size set by gks_batch_set_launch, or (0) one
-// workgroup per tile of the current table.  The kernels walk the table with a grid-stride
+// workgroup per tile of the current table (rounded up to a multiple of the 8 XCDs).  The kernels walk the table with a grid-stride
 // loop, so any grid covers any membership (a captured graph keeps its grid).
 static int batch_grid(gks_batch b, int kind)
 {
@@ -1009,7 +1014,7 @@ static int batch_grid(gks_batch b, int kind)
     // the strain launch also carries one end-of-step work item per member
     const int tiles = kind == 0 ? tv.hdr->total_cell + tv.hdr->count
                                 : (kind == 5 ? tv.hdr->total_cell : tv.hdr->total_face[kind - 1]);
-    return tiles > 0 ? tiles : 1;
+    return round8(tiles > 0 ? tiles : 1);
 }
 
 // One batch step: the frozen-form strain pass, which also ends every member's previous
@@ -1038,13 +1043,11 @@ static void batch_launch(gks_batch b, const Present& present)
 gks_status gks_batch_step(gks_batch b, int32_t nsteps)
 {
     if (!b || nsteps < 0) return fail_h(nullptr, GKS_ERR_ARG, "bad batch step");
-    for (int i = 0; i < nsteps; ++i) {
-        if (b->captured) {
-            if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "graph launch failed");
-        } else {
-            batch_launch(b, b->present);
-        }
-    }
+    // whole replays of the captured graph, then the remaining steps launched directly
+    const int replays = b->captured ? nsteps / b->graph_steps : 0;
+    for (int i = 0; i < replays; ++i)
+        if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return fail_h(nullptr, GKS_ERR_DEVICE, "graph launch failed");
+    for (int i = replays * (b->captured ? b->graph_steps : 0); i < nsteps; ++i) batch_launch(b, b->present);
     // end of the last step (outside the captured step graph)
     if (nsteps > 0)
         hipLaunchKernelGGL(k_finish, dim3(b->cap), dim3(CELL_TILE), 0, b->stream, (const void*)b->tab, b->cap, 0);
@@ -1052,9 +1055,11 @@ gks_status gks_batch_step(gks_batch b, int32_t nsteps)
     return GKS_OK;
 }
 
-gks_status gks_batch_capture(gks_batch b)
+gks_status gks_batch_capture(gks_batch b) { return gks_batch_capture_steps(b, 1); }
+
+gks_status gks_batch_capture_steps(gks_batch b, int32_t steps)
 {
-    if (!b) return fail_h(nullptr, GKS_ERR_ARG, "NULL batch");
+    if (!b || steps < 1 || steps > 1024) return fail_h(nullptr, GKS_ERR_ARG, "NULL batch or steps outside 1..1024");
     if (b->captured) {
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);
@@ -1062,7 +1067,7 @@ gks_status gks_batch_capture(gks_batch b)
     }
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail_h(nullptr, GKS_ERR_DEVICE, "begin capture failed");
-    batch_launch(b, b->present);
+    for (int i = 0; i < steps; ++i) batch_launch(b, b->present);
     if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess)
         return fail_h(nullptr, GKS_ERR_DEVICE, "end capture failed");
     if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -1070,6 +1075,7 @@ gks_status gks_batch_capture(gks_batch b)
         return fail_h(nullptr, GKS_ERR_DEVICE, "graph instantiate failed");
     }
     b->captured = true;
+    b->graph_steps = steps;
     return GKS_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTED = (
     "gks_set_timing", "gks_kernel_times",
     "gks_batch_workspace_bytes", "gks_batch_create", "gks_batch_set_members", "gks_batch_step",
     "gks_batch_capture", "gks_batch_set_launch", "gks_batch_status", "gks_batch_destroy",
-    "gks_batch_create_static",
+    "gks_batch_create_static", "gks_batch_capture_steps",
 )
 GKS_BATCH_STATIC_CAPACITY = 256
 
@@ -101,6 +101,7 @@ def lib():
         L.gks_batch_status.argtypes = [vp, C.POINTER(i64), dp, dp, dp, C.POINTER(i32)]
         L.gks_batch_destroy.argtypes = [vp]
         L.gks_batch_create_static.argtypes = [C.POINTER(vp), i32, i32, vp, C.POINTER(vp)]
+        L.gks_batch_capture_steps.argtypes = [vp, i32]
         for nm in EXPORTED:
             if nm != "gks_last_error":
                 getattr(L, nm).restype = C.c_int
@@ -280,6 +281,10 @@ def gks_batch_capture(b):
     _check(lib().gks_batch_capture(b))
 
 
+def gks_batch_capture_steps(b, steps):
+    _check(lib().gks_batch_capture_steps(b, int(steps)))
+
+
 def gks_batch_set_launch(b, kind, grid, tile=0):
     _check(lib().gks_batch_set_launch(b, int(kind), int(grid), int(tile)))
 
@@ -379,8 +384,12 @@ class Batch:
         self.solvers = list(solvers)
         gks_batch_set_members(self.b, [s.h for s in self.solvers])
 
-    def capture(self):
-        gks_batch_capture(self.b)
+    def capture(self, steps=1):
+        """Capture `steps` consecutive steps as one graph (replayed by step())."""
+        if steps == 1:
+            gks_batch_capture(self.b)
+        else:
+            gks_batch_capture_steps(self.b, steps)
 
     def set_launch(self, kind, grid, tile=0):
         gks_batch_set_launch(self.b, kind, grid, tile)

@@ -3,8 +3,8 @@
 Each request is a solve (a Case) that runs until its residual has fallen by `tol`
 relative to its first step (max over fields of res_m / res_first_m) or until
 `max_steps`.  The server keeps every admitted solve's state on the device and advances
-all of them together with the persistent batch kernels (one captured graph per step;
-admissions and retirements rewrite the batch table in place).  Requests are admitted in
+all of them together with the persistent batch kernels (a captured graph of several
+steps; admissions and retirements rewrite the batch table in place).  Requests are admitted in
 arrival order (or, with order="shortest", smallest expected work first: cells x step
 cap) whenever a batch slot and enough HBM (the solve's workspace footprint) are free and
 the cells already in the batch do not saturate the GPU (`sat_cells`: past that point a
@@ -68,7 +68,7 @@ def _summary(lat, cell_updates, makespan, n):
 
 
 def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=20, keep_fields=False,
-                device="cuda:0", target_s=0.004, log=None, sat_cells=None, order="arrival"):
+                device="cuda:0", target_s=0.004, log=None, sat_cells=None, order="arrival", graph_steps=16):
     """Serve `requests` (dicts with id, arrival [s], max_steps, tol) with continuous
     batching.  Returns (summary, per-request records).  `log(msg)`, if given, is called
     every 16 completions.
@@ -76,7 +76,8 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
     Each iteration enqueues the next `quantum` steps of the running batch first, then does
     the host work (building and initialising newly arrived solves on their own stream)
     while those steps run, then synchronises, retires finished solves and admits the new
-    ones by rewriting the batch table in place."""
+    ones by rewriting the batch table in place.  The steps replay a graph of `graph_steps`
+    captured steps (quanta are rounded up to whole replays)."""
     import torch
 
     from . import gks as G
@@ -109,6 +110,7 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
         while pending and pending[0]["arrival"] <= t:
             queue.append(pending.popleft())
         if active:
+            q = -(-q // graph_steps) * graph_steps       # whole replays of the captured steps
             ev0.record(run_stream)
             batch.step(q)                                # GPU works while the host admits
             ev1.record(run_stream)
@@ -169,13 +171,13 @@ def run_batched(requests, make_case, hbm_budget=64 << 30, capacity=64, quantum=2
                     batch.set_launch(kind, 16 * cus, 64)
                 batch.set_launch(0, 8 * cus, 0)
                 batch.set_launch(5, 8 * cus, 0)
-                batch.capture()
+                batch.capture(steps=graph_steps)
                 classes = new_classes
             else:
                 batch.set_members(members)
                 if not new_classes <= classes:           # a new kernel class joins: recapture
                     classes = classes | new_classes
-                    batch.capture()
+                    batch.capture(steps=graph_steps)
         if not active and pending and not queue:
             time.sleep(max(0.0, min(0.05, pending[0]["arrival"] - now())))
     makespan = now()

@@ -303,3 +303,29 @@ def test_batch_with_every_option_matches_the_oracle(graph):
         b.close()
         for s in solvers:
             s.close()
+
+
+def test_multi_step_graph_replays_equal_alone():
+    """A graph of 8 captured steps, replayed twice with status reads (synchronising eager
+    work) between the replays, then 5 more steps launched directly: every member equals its
+    solve alone after each stage, bitwise."""
+    from paper_1302_2132_amd import Batch, Solver
+    cases = _cases()[:4] + [_option_cases()[1]]
+    refs = {n: [_alone(c, n) for c in cases] for n in (8, 16, 21)}
+    solvers = [Solver(c) for c in cases]
+    b = Batch(solvers, capacity=8)
+    try:
+        b.capture(steps=8)
+        done = 0
+        for n in (8, 8, 5):
+            b.step(n)
+            done += n
+            st = b.status()
+            for i, (c, s) in enumerate(zip(cases, solvers)):
+                W, r = refs[done][i]
+                assert st["steps"][i] == r["steps"], (done, c.name)
+                assert np.array_equal(s.fields("cons"), W), (done, c.name)
+    finally:
+        b.close()
+        for s in solvers:
+            s.close()
