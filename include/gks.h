@@ -268,12 +268,15 @@ gks_status gks_batch_capture_steps(gks_batch b, int32_t steps);
 /* Launch shape of the batch kernels: kind 0 = strain, 1 = fused 2D tile kernel (FP64),
  * 2 = fused 2D tile kernel (FP32 flux), 3 = 3D face-class kernels (FP64), 4 = the same in
  * FP32 flux, 5 = update (3D solves outside the fused kernel).  grid = number of persistent
- * workgroups walking the tile table (0 = one per tile).  The tiles are fixed: tile must
- * be 0, or 256 for kinds 1-4 (the fused 2D tile of 16 x 15 cells and the fused 3D column
- * of 16 x 15 cells marching along z, 256 threads each), or 64 for kinds 3-4 (faces per
+ * workgroups walking the tile table (0 = one per tile).  tile: for kinds 1 and 2 the cell
+ * tile of the plain scheme's fused 2D kernel, GKS_TILE2_16X15 (0, also 256),
+ * GKS_TILE2_32X7 or GKS_TILE2_8X28 (solves with options keep 16 x 15); for kinds 3 and 4
+ * 0, 256 (the fused 3D column of 16 x 15 cells marching along z) or 64 (faces per
  * workgroup of the 3D face kernel of solves with transport, WENO5 or the
- * multi-dimensional expansion); anything else is GKS_ERR_ARG.
- * Results do not depend on the launch shape (bitwise).  Invalidates a captured graph. */
+ * multi-dimensional expansion); 0 for the other kinds.  Anything else is GKS_ERR_ARG.
+ * Results do not depend on the launch shape: the state bitwise, the residual up to the
+ * rounding of its per-tile partial sums.  Invalidates a captured graph. */
+enum { GKS_TILE2_16X15 = 0, GKS_TILE2_32X7 = 1, GKS_TILE2_8X28 = 2 };
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile);
 
 /* Synchronise; copy per-member steps done, residual of the last step and of the first

@@ -4,7 +4,8 @@ The result of a step does not depend on the launch shape (every face flux and ev
 per-tile partial sum is computed the same way whatever workgroup handles it), so the
 tuner times candidate shapes on the live batch: the steps it spends measuring are real
 steps of the solves.  Searched: for each face-kernel class present, the persistent grid
-(one workgroup per tile, or 4/8/16 workgroups per CU); then the grid of the strain kernel
+(one workgroup per tile, or 4/8/16 workgroups per CU) and, for the 2D classes, the cell-tile
+shape of the fused kernel (16 x 15, 32 x 7 or 8 x 28); then the grid of the strain kernel
 and, with 3D members, of the update kernel.  The winner is cached in a JSON
 file keyed by device, class mix and problem size, and reused without a search.
 """
@@ -15,10 +16,14 @@ import os
 import time
 
 KIND_STRAIN, KIND_UPDATE = 0, 5
+TILE2_SHAPES = (0, 1, 2)     # GKS_TILE2_16X15, GKS_TILE2_32X7, GKS_TILE2_8X28
+
+
 def tiles_of(c: int):
-    """Tile choices of a face class: none (the fused 2D and 3D tile kernels and the 3D face
-    kernel of the options outside the fused kernel have fixed tiles)."""
-    return (0,)
+    """Tile choices of a face class: the fused 2D kernel's cell-tile shape for the 2D
+    classes (0, 1); none for 3D (the fused 3D column and the 3D face kernel of the options
+    outside it have fixed tiles)."""
+    return TILE2_SHAPES if c < 2 else (0,)
 
 
 def cls_of(case) -> int:

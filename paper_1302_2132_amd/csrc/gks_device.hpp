@@ -73,6 +73,7 @@ struct Inst {
     int ntile_face[3];
     int ntile_face_all;
     int face_tile;             // faces per face-kernel tile in the table holding this copy
+    int shape2;                // 2D: tile shape code of the fused kernel in the table holding this copy
     int fused3;                // 3D step in one fused tile kernel (k_tile3): no face fluxes in HBM
     int seg3, nseg3;           // planes per z-run of a fused 3D tile, runs per tile column
     long long max_steps;       // > 0: deactivate after this many steps

@@ -12,8 +12,8 @@
 
 namespace gks {
 
-#define GKS_TILE2_D(V) template __global__ void k_tile2<double, V>(const void*, int, int);
-#define GKS_TILE2_F(V) template __global__ void k_tile2<float, V>(const void*, int, int);
+#define GKS_TILE2_D(V) template __global__ void k_tile2<double, V, 0>(const void*, int, int);
+#define GKS_TILE2_F(V) template __global__ void k_tile2<float, V, 0>(const void*, int, int);
 #define GKS_FACE_D(T, V) template __global__ void k_face<double, 3, T, V>(const void*, int, int);
 #define GKS_FACE_F(T, V) template __global__ void k_face<float, 3, T, V>(const void*, int, int);
 #define GKS_TILE3_D(V) template __global__ void k_tile3<double, V>(const void*, int, int);
@@ -36,13 +36,17 @@ GKS_TILE2_F(16) GKS_TILE2_F(17) GKS_TILE2_F(18) GKS_TILE2_F(19)
 #elif GKS_PART == 4
 GKS_TILE3_D(0) GKS_TILE3_D(2) GKS_TILE3_D(4) GKS_TILE3_D(6)
 GKS_FACE_D(64, 1) GKS_FACE_D(64, 3) GKS_FACE_D(64, 5) GKS_FACE_D(64, 7)
+template __global__ void k_tile2<double, 0, 1>(const void*, int, int);
 #elif GKS_PART == 5
+template __global__ void k_tile2<double, 0, 2>(const void*, int, int);
 GKS_FACE_D(64, 8) GKS_FACE_D(64, 9) GKS_FACE_D(64, 10) GKS_FACE_D(64, 11)
 GKS_FACE_D(64, 16) GKS_FACE_D(64, 17) GKS_FACE_D(64, 18) GKS_FACE_D(64, 19)
 #elif GKS_PART == 6
 GKS_TILE3_F(0) GKS_TILE3_F(2) GKS_TILE3_F(4) GKS_TILE3_F(6)
 GKS_FACE_F(64, 1) GKS_FACE_F(64, 3) GKS_FACE_F(64, 5) GKS_FACE_F(64, 7)
+template __global__ void k_tile2<float, 0, 1>(const void*, int, int);
 #elif GKS_PART == 7
+template __global__ void k_tile2<float, 0, 2>(const void*, int, int);
 GKS_FACE_F(64, 8) GKS_FACE_F(64, 9) GKS_FACE_F(64, 10) GKS_FACE_F(64, 11)
 GKS_FACE_F(64, 16) GKS_FACE_F(64, 17) GKS_FACE_F(64, 18) GKS_FACE_F(64, 19)
 #else

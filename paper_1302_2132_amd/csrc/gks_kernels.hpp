@@ -705,10 +705,20 @@ __device__ inline void update_cell(cref<Inst> I, int cell, double dt, double* r2
 // updates its cells from LDS.  Fluxes never go to HBM, and the update needs no launch of
 // its own.  The arithmetic of every face and cell is that of k_face and k_update.
 constexpr int T2X = 16, T2Y = 15, T2_THREADS = 256;
-constexpr int T2_KX = T2X + 2, T2_KY = T2Y + 2;     // k, omega, strain window (one-cell halo)
-constexpr int T2_NFX = (T2X + 1) * T2Y, T2_NFY = T2X * (T2Y + 1);
-static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_THREADS,
-              "one x-face, one y-face and one cell per thread");
+// Tile shapes of the fused 2D kernel (shape code S): 16 x 15 (the default), 32 x 7 and
+// 8 x 28 cells, each with at most one x-face, one y-face and one cell per thread.  A batch's
+// autotuner picks one per class for the plain scheme; the options keep 16 x 15.
+constexpr int NSHAPE2 = 3;
+__host__ __device__ constexpr int tile2_x(int S) { return S == 1 ? 32 : (S == 2 ? 8 : T2X); }
+__host__ __device__ constexpr int tile2_y(int S) { return S == 1 ? 7 : (S == 2 ? 28 : T2Y); }
+template <int S>
+struct Shape2 {
+    static constexpr int X = tile2_x(S), Y = tile2_y(S);
+    static constexpr int KX = X + 2, KY = Y + 2;                  // k, omega, strain window
+    static constexpr int NFX = (X + 1) * Y, NFY = X * (Y + 1);
+    static_assert(NFX <= T2_THREADS && NFY <= T2_THREADS && X * Y <= T2_THREADS,
+                  "one x-face, one y-face and one cell per thread");
+};
 
 // Register budget: 3 waves per SIMD leave 168 VGPRs per lane, enough for the 2D FP64 flux;
 // the plain FP32-flux form gets 4 (128 VGPRs), its variants 3 (the transported ones are
@@ -721,12 +731,15 @@ static_assert(T2_NFX <= T2_THREADS && T2_NFY <= T2_THREADS && T2X * T2Y <= T2_TH
 #define GKS_TILE2_WAVES_FP32 4
 #endif
 
-template <typename R, int V>
+template <typename R, int V, int S = 0>
 __global__ __launch_bounds__(T2_THREADS)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (V == 0 ? GKS_TILE2_WAVES_FP32 : 3) - ((V & V_MD) ? 1 : 0)
                                                    : GKS_TILE2_WAVES_FP64 - ((V & V_MD) ? 1 : 0))))
 void k_tile2(const void* __restrict__ table, int cap, int cls)
 {
+    constexpr int T2X = Shape2<S>::X, T2Y = Shape2<S>::Y;
+    constexpr int T2_KX = Shape2<S>::KX, T2_KY = Shape2<S>::KY;
+    constexpr int T2_NFX = Shape2<S>::NFX, T2_NFY = Shape2<S>::NFY;
     constexpr bool KW = V & V_KW;
     constexpr bool MD = V & V_MD;
     constexpr int FMODE = ((V & V_TH) ? FLUX_TAUHAT : 0) | (MD ? FLUX_MULTID : 0);
@@ -1590,9 +1603,14 @@ extern __global__ void k_states(const void* __restrict__ table, int cap, State* 
 #define GKS_TILE2_VARIANTS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(16) X(17) X(18) X(19)
 #define GKS_FACE_VARIANTS(X) \
     X(64, 1) X(64, 3) X(64, 5) X(64, 7) X(64, 8) X(64, 9) X(64, 10) X(64, 11) X(64, 16) X(64, 17) X(64, 18) X(64, 19)
-#define GKS_TILE2_DECL(V)                                                      \
-    extern template __global__ void k_tile2<double, V>(const void*, int, int); \
-    extern template __global__ void k_tile2<float, V>(const void*, int, int);
+#define GKS_TILE2_DECL(V)                                                         \
+    extern template __global__ void k_tile2<double, V, 0>(const void*, int, int); \
+    extern template __global__ void k_tile2<float, V, 0>(const void*, int, int);
+// the plain scheme's other tile shapes
+extern template __global__ void k_tile2<double, 0, 1>(const void*, int, int);
+extern template __global__ void k_tile2<float, 0, 1>(const void*, int, int);
+extern template __global__ void k_tile2<double, 0, 2>(const void*, int, int);
+extern template __global__ void k_tile2<float, 0, 2>(const void*, int, int);
 #define GKS_FACE_DECL(T, V)                                                           \
     extern template __global__ void k_face<double, 3, T, V>(const void*, int, int); \
     extern template __global__ void k_face<float, 3, T, V>(const void*, int, int);

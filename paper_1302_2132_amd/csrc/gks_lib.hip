@@ -52,8 +52,12 @@ struct Layout {
     int nstep_part;    // partial slots of a step
 };
 
-// fused 2D tiles of an n0 x n1 mesh
-static int tiles2(long long n0, long long n1) { return (int)(((n0 + T2X - 1) / T2X) * ((n1 + T2Y - 1) / T2Y)); }
+// fused 2D tiles of an n0 x n1 mesh in tile shape `shape`
+static int tiles2(long long n0, long long n1, int shape = 0)
+{
+    const long long tx = tile2_x(shape), ty = tile2_y(shape);
+    return (int)(((n0 + tx - 1) / tx) * ((n1 + ty - 1) / ty));
+}
 
 // Options whose 3D step runs in the fused tile kernel (two-cell stencils, no transport).
 static bool fused3_config(const gks_config* c)
@@ -172,7 +176,11 @@ void layout(const gks_config* c, Layout* L)
         L->ntile3 = (int)(((n[0] + T3X - 1) / T3X) * ((n[1] + T3Y - 1) / T3Y)) * L->nseg3;
     }
     L->nstep_part = D == 2 ? L->ntile2 : (L->fused3 ? L->ntile3 : L->ntile_cell);
-    L->part = take(sizeof(double) * PSTRIDE * (size_t)std::max(L->ntile_cell, L->nstep_part));
+    // partial slots for the largest tile count a step can make (any 2D tile shape)
+    int slots = std::max(L->ntile_cell, L->nstep_part);
+    if (D == 2)
+        for (int s = 0; s < NSHAPE2; ++s) slots = std::max(slots, tiles2(n[0], n[1], s));
+    L->part = take(sizeof(double) * PSTRIDE * (size_t)slots);
     L->st = take(sizeof(State));
     L->tab = take(TabView::bytes(1));
     L->total = off;
@@ -267,6 +275,7 @@ struct gks_batch_ctx {
     int grid[6];
     bool captured;
     int graph_steps;                  // steps one replay of the captured graph advances
+    int shape2[2] = {0, 0};           // fused 2D tile shape of the plain scheme, per 2D class
     hipGraph_t graph;
     hipGraphExec_t exec;
     Present present;                  // launches the current (or captured) step makes
@@ -309,9 +318,11 @@ static int device_cus()
 }
 
 // Fill a host image of a tile table for `members` (capacity cap): cell tiles of every
-// member, and the face-kernel tiles of each class (fused 2D and 3D tiles, or FACE_TILE faces
-// for the 3D face kernel of the options outside k_tile3).
-static void build_table(std::vector<char>& img, int cap, const std::vector<const Inst*>& members)
+// member, and the face-kernel tiles of each class (fused 2D tiles in the class's shape
+// shape2[cls] for the plain scheme and 16 x 15 for the options, fused 3D tiles, or
+// FACE_TILE faces for the 3D face kernel of the options outside k_tile3).
+static void build_table(std::vector<char>& img, int cap, const std::vector<const Inst*>& members,
+                        const int* shape2 = nullptr)
 {
     img.assign(TabView::bytes(cap), 0);
     TabView tv(img.data(), cap);
@@ -322,9 +333,11 @@ static void build_table(std::vector<char>& img, int cap, const std::vector<const
     for (size_t i = 0; i < members.size(); ++i) {
         tv.inst[i] = *members[i];
         Inst& I = tv.inst[i];
-        if (I.dim == 2) {                        // fused 2D kernel: fixed cell tiles
+        if (I.dim == 2) {                        // fused 2D kernel: cell tiles of the class's shape
             I.face_tile = T2_THREADS;
-            I.ntile_face_all = tiles2(I.n[0], I.n[1]);
+            I.shape2 = (shape2 && I.variant == 0) ? shape2[I.cls] : 0;
+            I.ntile_face_all = tiles2(I.n[0], I.n[1], I.shape2);
+            I.nstep_part = I.ntile_face_all;
         } else if (I.fused3) {                   // fused 3D kernel: column tiles times z-runs
             I.face_tile = T2_THREADS;
             I.ntile_face_all = ((I.n[0] + T3X - 1) / T3X) * ((I.n[1] + T3Y - 1) / T3Y) * I.nseg3;
@@ -353,7 +366,15 @@ typedef void (*face_kernel_t)(const void*, int, int);
 template <int V>
 static face_kernel_t tile2_kernel(int cls)
 {
-    return cls == 1 ? k_tile2<float, V> : k_tile2<double, V>;
+    return cls == 1 ? k_tile2<float, V, 0> : k_tile2<double, V, 0>;
+}
+// the plain scheme's fused 2D kernel in tile shape `shape`
+static face_kernel_t tile2_plain(int cls, int shape)
+{
+    const bool f = cls == 1;
+    if (shape == 1) return f ? k_tile2<float, 0, 1> : k_tile2<double, 0, 1>;
+    if (shape == 2) return f ? k_tile2<float, 0, 2> : k_tile2<double, 0, 2>;
+    return f ? k_tile2<float, 0, 0> : k_tile2<double, 0, 0>;
 }
 template <int V>
 static face_kernel_t face3_kernel(int cls)
@@ -377,11 +398,12 @@ static bool fused3_variant_rt(int variant) { return (variant & (V_KW | V_MD | V_
 // fused 2D tile kernel for the 2D classes; for 3D the fused tile kernel, or the face kernel
 // (FACE_TILE faces per workgroup, then k_update) for transport, WENO5 and the
 // multi-dimensional expansion.
-static face_kernel_t face_kernel(int cls, int variant)
+static face_kernel_t face_kernel(int cls, int variant, int shape2 = 0)
 {
     if (cls >= 2 && fused3_variant_rt(variant)) return tile3_kernel(cls, variant);
     if (cls < 2) {
         switch (variant) {
+        case 0: return tile2_plain(cls, shape2);
         case 1: return tile2_kernel<1>(cls);
         case 2: return tile2_kernel<2>(cls);
         case 3: return tile2_kernel<3>(cls);
@@ -397,7 +419,7 @@ static face_kernel_t face_kernel(int cls, int variant)
         case V_W5 | V_KW: return tile2_kernel<V_W5 | V_KW>(cls);
         case V_W5 | V_TH: return tile2_kernel<V_W5 | V_TH>(cls);
         case V_W5 | V_KW | V_TH: return tile2_kernel<V_W5 | V_KW | V_TH>(cls);
-        default: return tile2_kernel<0>(cls);
+        default: return tile2_plain(cls, 0);
         }
     }
     switch (variant) {
@@ -916,7 +938,7 @@ static gks_status batch_upload(gks_batch b)
         present.strain[kw] = true;
         if (h->cfg.dim == 3 && !h->inst.fused3) present.update[kw] = true;
     }
-    build_table(b->host_tab, b->cap, mem);
+    build_table(b->host_tab, b->cap, mem, b->shape2);
     if (hipMemcpyAsync(b->tab, b->host_tab.data(), b->host_tab.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
         b->err = "table upload failed";
@@ -1031,8 +1053,8 @@ static void batch_launch(gks_batch b, const Present& present)
     for (int c = 0; c < NCLS; ++c)
         for (int v = 0; v < 32; ++v)
             if (present.face.test(c * 32 + v)) {
-                hipLaunchKernelGGL(face_kernel(c, v), dim3(batch_grid(b, 1 + c)), dim3(face_block(c, v)), 0,
-                                   b->stream, tab, b->cap, c);
+                hipLaunchKernelGGL(face_kernel(c, v, c < 2 ? b->shape2[c] : 0), dim3(batch_grid(b, 1 + c)),
+                                   dim3(face_block(c, v)), 0, b->stream, tab, b->cap, c);
             }
     if (present.update[0])   // 3D members update in their own launch
         hipLaunchKernelGGL(k_update<false>, dim3(batch_grid(b, 5)), dim3(CELL_TILE), 0, b->stream, tab, b->cap);
@@ -1082,16 +1104,25 @@ gks_status gks_batch_capture_steps(gks_batch b, int32_t steps)
 gks_status gks_batch_set_launch(gks_batch b, int32_t kind, int32_t grid, int32_t tile)
 {
     if (!b || kind < 0 || kind > 5 || grid < 0) return fail_h(nullptr, GKS_ERR_ARG, "bad launch shape");
-    // the tiles are fixed: 256 threads for the fused 2D and 3D kernels, FACE_TILE faces for
-    // the 3D face kernel of the options outside k_tile3
-    const bool ok_tile = tile == 0 || (kind >= 1 && kind <= 4 && tile == T2_THREADS) ||
-                         (kind >= 3 && kind <= 4 && tile == FACE_TILE);
+    // kinds 1, 2: the fused 2D kernel's tile shape (GKS_TILE2_*, 256 meaning the default
+    // 16 x 15); kinds 3, 4: 0, 256 (the fused 3D kernel's fixed tile) or FACE_TILE (the 3D face
+    // kernel of the options outside k_tile3); other kinds: 0
+    const bool two = kind == 1 || kind == 2;
+    const bool ok_tile = tile == 0 || (two && (tile == GKS_TILE2_32X7 || tile == GKS_TILE2_8X28 || tile == T2_THREADS)) ||
+                         (kind >= 3 && kind <= 4 && (tile == T2_THREADS || tile == FACE_TILE));
     if (!ok_tile) return fail_h(nullptr, GKS_ERR_ARG, "unsupported tile size");
     b->grid[kind] = grid;
     if (b->captured) {
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);
         b->captured = false;
+    }
+    if (two) {
+        const int shape = tile == T2_THREADS ? 0 : tile;
+        if (b->shape2[kind - 1] != shape) {
+            b->shape2[kind - 1] = shape;
+            return batch_upload(b);     // the class's tile counts change
+        }
     }
     return GKS_OK;
 }

@@ -188,17 +188,18 @@ def test_launch_shapes_do_not_change_results():
     tile the library does not have is refused."""
     from paper_1302_2132_amd import Batch, Solver
     cases = _cases()[:4] + [_option_cases()[i] for i in (1, 4, 8)]
-    ref = [_alone(c, 12) for c in cases]
+    ref = [_alone(c, 15) for c in cases]
     solvers = [Solver(c) for c in cases]
     b = Batch(solvers, capacity=8)
     from paper_1302_2132_amd import GKS_ERR_ARG, GksError
     with pytest.raises(GksError) as e:
         b.set_launch(3, 0, 128)
     assert e.value.status == GKS_ERR_ARG
-    shapes = [(64, 0), (0, 512), (256, 0), (64, 4096)]
-    for i, (tile, grid) in enumerate(shapes):
-        for kind in (1, 2):                  # fused 2D kernel: fixed tile
-            b.set_launch(kind, grid, 0)
+    # (3D tile, 2D tile shape, grid): 2D shapes 16 x 15, 32 x 7, 8 x 28
+    shapes = [(64, 0, 0), (0, 1, 512), (256, 2, 0), (64, 1, 4096), (0, 0, 0)]
+    for i, (tile, shape2, grid) in enumerate(shapes):
+        for kind in (1, 2):
+            b.set_launch(kind, grid, shape2)
         for kind in (3, 4):
             b.set_launch(kind, grid, tile)
         b.set_launch(0, grid, 0)

@@ -50,17 +50,20 @@ def _face(res, r, d):
 
 
 def _tile2(res, r):
-    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks7k_tile2I{r}Li\d+EEEvPKvii", k)}
+    return {k: v for k, v in res.items() if re.match(rf"_ZN3gks7k_tile2I{r}Li\d+ELi\d+EEEvPKvii", k)}
 
 
 def _variant(name):
     """Variant bits: 1 transport, 2 tau_hat, 4 third-order MUSCL, 8 multi-dimensional, 16 WENO5."""
-    return int(re.search(r"Li(\d+)EEEvPKvii$", name).group(1))
+    m = re.search(r"k_tile2I[df]Li(\d+)ELi\d+E", name)
+    return int(m.group(1) if m else re.search(r"Li(\d+)EEEvPKvii$", name).group(1))
 
 
 def test_fused_2d_kernels_occupancy(remarks):
     k64, k32 = _tile2(remarks, "d"), _tile2(remarks, "f")
-    assert len(k64) == 16 and len(k32) == 16       # transport x tau_hat x (MUSCL2, MUSCL3, WENO5, multi-d)
+    # transport x tau_hat x (MUSCL2, MUSCL3, WENO5, multi-d), plus the plain scheme in the
+    # 32 x 7 and 8 x 28 tile shapes
+    assert len(k64) == 18 and len(k32) == 18
     for k, v in k64.items():
         md = bool(_variant(k) & 8)
         assert v["ScratchSize"] <= (40 if _variant(k) & 4 else (96 if _variant(k) & 16 else 0)), (k, v)
