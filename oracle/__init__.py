@@ -96,6 +96,8 @@ def _bind(L):
     if hasattr(_lib, "og_kogan_e"):
         _lib.og_kogan_e.argtypes = [C.c_double, C.c_double, C.c_double, dp]
         _lib.og_eps_field.argtypes = [C.c_void_p, dp, dp, dp, dp]
+    if hasattr(_lib, "og_tau_field"):
+        _lib.og_tau_field.argtypes = [C.c_void_p, dp, dp, dp, dp]
     if hasattr(_lib, "og_run_kw"):
         _lib.og_run_kw.argtypes = [C.c_void_p, dp, dp, dp, C.c_int, C.c_int, dp, dp, dp, C.POINTER(C.c_long)]
         _lib.og_kw_sources.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
@@ -321,6 +323,17 @@ def eps_field(case, W=None, k=None, omega=None):
     b = _Bound(case)
     out = np.zeros(case.ncells)
     st = lib().og_eps_field(b.ptr, _dp(_flat(case.W if W is None else W)), _dp(_flat(case.k if k is None else k)),
+                            _dp(_flat(case.omega if omega is None else omega)), _dp(out))
+    if st:
+        raise OracleError(st)
+    return out.reshape(case.k.shape)
+
+
+def tau_field(case, W=None, k=None, omega=None):
+    """The relaxation time tau of every face at the state's CFL step, largest per cell."""
+    b = _Bound(case)
+    out = np.zeros(case.ncells)
+    st = lib().og_tau_field(b.ptr, _dp(_flat(case.W if W is None else W)), _dp(_flat(case.k if k is None else k)),
                             _dp(_flat(case.omega if omega is None else omega)), _dp(out))
     if st:
         raise OracleError(st)

@@ -947,10 +947,11 @@ static int og_max_rate(const og_grid* gr, const double* W, const double* kk, con
 }
 
 /* Flux through one face.  axis d; (fi, fj, fk) are face coordinates (the face lies on the low
- * side of cell (fi, fj, fk) along d).  Fout in global component order. */
+ * side of cell (fi, fj, fk) along d).  Fout in global component order.  diag_out (or NULL):
+ * the face's eps_hat = tau/tau_hat and its relaxation time tau. */
 static int og_face_at(const og_grid* gr, const double* We, const double* kk, const double* om,
                       const double* S, int d, long fi, long fj, long fk, double dt, double* Fout,
-                      double* eps_out)
+                      double* diag_out)
 {
     const int dim = gr->c->dim, nv = gr->nv;
     long base[3] = {fi, fj, fk};
@@ -1021,9 +1022,12 @@ static int og_face_at(const og_grid* gr, const double* We, const double* kk, con
     double Sf = 0.5 * (S[il] + S[ir]);
     double F[5], info[OG_INFO_LEN];
     int st = og_face(&gr->gas, lWL, lWR, lsL, lsR, tsl, tsr, lWi, lWi1, xface - xcs[1], xcs[2] - xface,
-                     kf, wf, Sf, dt, F, NULL, NULL, eps_out ? info : NULL);
+                     kf, wf, Sf, dt, F, NULL, NULL, diag_out ? info : NULL);
     if (st) return st;
-    if (eps_out) *eps_out = info[50];
+    if (diag_out) {
+        diag_out[0] = info[50];
+        diag_out[1] = info[40];
+    }
     for (int m = 0; m < nv; ++m) {
         int dst = (m >= 1 && m <= dim) ? 1 + perm[m - 1] : m;
         Fout[dst] = F[m];
@@ -1485,7 +1489,12 @@ int og_kogan_e(double tau, double tau_e, double dt, double* out)
 
 /* Degree of rarefaction eps_hat = tau/tau_hat of every face at state W, with the CFL step
  * of W, reduced to each cell as the largest over its 2 dim faces. */
-int og_eps_field(const og_case* c, const double* W, const double* kk, const double* om, double* out)
+/* A per-cell diagnostic of the face fluxes at the state's CFL step (which = 0: eps_hat =
+ * tau/tau_hat, the rarefaction measure of Eqs. tautautilde and epsilonkomega; which = 1: the
+ * relaxation time tau of Eqs. relaxation time, taua and tautchenadjusted): the largest over
+ * the cell's faces. */
+static int og_face_diag_field(const og_case* c, const double* W, const double* kk, const double* om, int which,
+                              double* out)
 {
     og_grid gr;
     int st = og_grid_init(&gr, c);
@@ -1508,15 +1517,27 @@ int og_eps_field(const og_case* c, const double* W, const double* kk, const doub
             for (int side = 0; side < 2; ++side) {
                 long f[3] = {idx[0], idx[1], idx[2]};
                 f[d] += side;
-                double e;
-                if (og_face_at(&gr, We, kk, om, S, d, f[0], f[1], f[2], dt, F, &e)) { bad = 1; continue; }
-                if (e > mx) mx = e;
+                double diag[2];
+                if (og_face_at(&gr, We, kk, om, S, d, f[0], f[1], f[2], dt, F, diag)) { bad = 1; continue; }
+                if (diag[which] > mx) mx = diag[which];
             }
         out[s] = mx;
     }
     free(We); free(S);
     og_grid_free(&gr);
     return bad ? OG_ERR_NONPHYSICAL : OG_OK;
+}
+
+/* eps_hat = tau/tau_hat of every face at the state's CFL step, the largest per cell. */
+int og_eps_field(const og_case* c, const double* W, const double* kk, const double* om, double* out)
+{
+    return og_face_diag_field(c, W, kk, om, 0, out);
+}
+
+/* The relaxation time tau of every face at the state's CFL step, the largest per cell. */
+int og_tau_field(const og_case* c, const double* W, const double* kk, const double* om, double* out)
+{
+    return og_face_diag_field(c, W, kk, om, 1, out);
 }
 
 /* Solve <psi_m psi_n>_g x = r for a Maxwellian given by (rho, U[3], lam); face-local frame. */

@@ -16,6 +16,7 @@ import test_oracle_multid as MD
 import test_oracle_muscl3 as M3
 import test_oracle_pins as P
 import test_oracle_step_cells as SC
+import test_oracle_tau_field as TF
 import test_oracle_tauhat as TH
 import test_oracle_weno5 as W5
 
@@ -102,6 +103,7 @@ MUTANTS = {
                                       "*wr = og_weno5(w[-1], w[0], w[1], w[2], w[3]);"),
     "sampled-cell flux difference sign": ("acc[m] -= (Fhi[m] - Flo[m]) / gr.dx[d][idx[d] + 2];",
                                           "acc[m] -= (Flo[m] - Fhi[m]) / gr.dx[d][idx[d] + 2];"),
+    "tau field reports the rarefaction": ("        diag_out[1] = info[40];", "        diag_out[1] = info[50];"),
     "sampled-cell width of the wrong cell": ("acc[m] -= (Fhi[m] - Flo[m]) / gr.dx[d][idx[d] + 2];",
                                              "acc[m] -= (Fhi[m] - Flo[m]) / gr.dx[d][idx[d] + 3];"),
 }
@@ -166,6 +168,7 @@ PINS = [
     lambda: W5.test_mirror_and_minmod_gradients(),
     lambda: SC.step_cells_matches_run("2d_mixed_bc"),
     lambda: SC.step_cells_matches_run("3d_mixed_bc"),
+    lambda: TF.test_tau_field_of_a_uniform_flow(2),
 ]
 
 
