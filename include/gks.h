@@ -122,8 +122,11 @@ enum { GKS_RECON_MUSCL2 = 0, GKS_RECON_MUSCL3 = 1, GKS_RECON_WENO5 = 2 };
  * then omega (2 x ncells): those of the current state when transported (computed on the
  * device from rho k, rho omega), the frozen inputs otherwise. EPS: eps_hat = tau/tau_hat of
  * each face at the current state and step, the largest over the cell's faces (ncells; in
- * either eps_mode, as the "turbulent Knudsen number" diagnostic). */
-enum { GKS_FIELD_CONS = 0, GKS_FIELD_PRIM = 1, GKS_FIELD_STRAIN = 2, GKS_FIELD_TURB = 3, GKS_FIELD_EPS = 4 };
+ * either eps_mode, as the "turbulent Knudsen number" diagnostic). TAU: the relaxation time
+ * tau = mu/p0 + tau_a + the k-omega part (Eqs. relaxation time, taua, tautchenadjusted) of
+ * each face at the current state and step, the largest over the cell's faces (ncells). */
+enum { GKS_FIELD_CONS = 0, GKS_FIELD_PRIM = 1, GKS_FIELD_STRAIN = 2, GKS_FIELD_TURB = 3, GKS_FIELD_EPS = 4,
+       GKS_FIELD_TAU = 5 };
 
 typedef struct {
     int32_t dim;                  /* 2 or 3 */

@@ -346,7 +346,8 @@ GKS_HD inline Kw<R> kogan_e(R tau, R tau_e, R dt)
 }
 
 // Flux modes (bits): FLUX_TAUHAT evaluates the time weights with eps = tau/tau_hat;
-// FLUX_EPS_OUT also stores eps_hat = tau/tau_hat in F[D + 2] (the caller provides room);
+// FLUX_EPS_OUT also stores eps_hat = tau/tau_hat in F[D + 2] and the relaxation time tau in
+// F[D + 3] (the caller provides room);
 // FLUX_MULTID expands the distributions along the tangential axes too (FaceIn::tl, tr).
 enum { FLUX_TAUHAT = 1, FLUX_EPS_OUT = 2, FLUX_MULTID = 4 };
 
@@ -602,6 +603,7 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         tau = ip0 * (H(gas.mu) + in.kf * r0 * g_rsqrt(in.wf * in.wf + sc * sc));
         if (gas.c_a > 0.0) tau = tau + H(gas.c_a) * g_abs(pr - pl) * g_rcp(pr + pl) * in.dt;
     }
+    if (MODE & FLUX_EPS_OUT) Fout[D + 3] = tau;
     Kw<H> kwh;
     if (MODE & (FLUX_TAUHAT | FLUX_EPS_OUT)) kwh = mode_weights<D, H, MODE>(in, tau, W0, U0d, ir0, Fout);
     else kwh = kogan(tau, in.dt);

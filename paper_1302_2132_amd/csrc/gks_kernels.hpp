@@ -408,14 +408,17 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
     in.Sf = 0.5 * (ss[il] + ss[ir]);
     in.dt = dt;
     GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
-    double F[NV + ((MODE & FLUX_EPS_OUT) ? 1 : 0)];
+    double F[NV + ((MODE & FLUX_EPS_OUT) ? 2 : 0)];
     const int bad = face_flux<R, D, double, MODE>(in, gas, F);
     Fg[0] = F[0];
     Fg[1 + DIR] = F[1];
     Fg[1 + P1] = F[2];
     if (D == 3) Fg[1 + P2] = F[3];
     Fg[D + 1] = F[D + 1];
-    if (MODE & FLUX_EPS_OUT) Fg[D + 2] = F[(MODE & FLUX_EPS_OUT) ? D + 2 : 0];
+    if (MODE & FLUX_EPS_OUT) {
+        Fg[D + 2] = F[(MODE & FLUX_EPS_OUT) ? D + 2 : 0];
+        Fg[D + 3] = F[(MODE & FLUX_EPS_OUT) ? D + 3 : 0];
+    }
     return bad;
 }
 
@@ -1528,11 +1531,11 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
 
 // Degree of rarefaction eps_hat = tau/tau_hat of the faces of each cell at the current
 // state and step (the strain rate, k and omega of that state already in place), largest
-// over the cell's 2 D faces, into out[cell].  V selects the solve's time weights and
-// reconstruction, so that the evaluation is that of the step.  A diagnostic: each face is
-// evaluated by both of its cells.
+// over the cell's 2 D faces, into out[cell] (which = 0), or the faces' relaxation time tau
+// (which = 1).  V selects the solve's time weights and reconstruction, so that the
+// evaluation is that of the step.  A diagnostic: each face is evaluated by both of its cells.
 template <int D, int V>
-__device__ inline double cell_eps(cref<Inst> I, int cell)
+__device__ inline double cell_eps(cref<Inst> I, int cell, int which)
 {
     constexpr int NV = D + 2;
     const double* __restrict__ W = I.W[state_of(I).parity];
@@ -1557,11 +1560,11 @@ __device__ inline double cell_eps(cref<Inst> I, int cell)
         int cl[3] = {fc[0], fc[1], fc[2]};
         cl[DIR] -= 1;
         const int il = image_cell<D>(I, DIR, cl), ir = image_cell<D>(I, DIR, fc);
-        double F[NV + 1];
+        double F[NV + 2];
         if (face_eval<double, D, DIR, FLUX_EPS_OUT | ((V & V_TH) ? FLUX_TAUHAT : 0), recon_of<V>()>(
                 I, fc[DIR], Wc, I.k, I.om, I.S, il, ir, dt, F))
             atomicOr(&I.st->err, 1);
-        mx = fmax(mx, F[NV]);
+        mx = fmax(mx, which ? F[NV + 1] : F[NV]);
     };
     using D0 = std::integral_constant<int, 0>;
     using D1 = std::integral_constant<int, 1>;
@@ -1573,12 +1576,13 @@ __device__ inline double cell_eps(cref<Inst> I, int cell)
 }
 
 template <int V>
-__global__ __launch_bounds__(64) void k_eps(const void* __restrict__ table, int cap, double* __restrict__ out)
+__global__ __launch_bounds__(64) void k_eps(const void* __restrict__ table, int cap, double* __restrict__ out,
+                                            int which)
 {
     const TabC tv(table, cap);
     cref<Inst> I = tv.inst[0];
     for (int cell = blockIdx.x * blockDim.x + (int)threadIdx.x; cell < I.ncells; cell += gridDim.x * blockDim.x)
-        out[cell] = I.dim == 2 ? cell_eps<2, V>(I, cell) : cell_eps<3, V>(I, cell);
+        out[cell] = I.dim == 2 ? cell_eps<2, V>(I, cell, which) : cell_eps<3, V>(I, cell, which);
 }
 
 // Copy of every member's step state into one array, so that a batch's states come back

@@ -26,12 +26,12 @@
 using namespace gks;
 
 namespace gks {
-template __global__ void k_eps<0>(const void*, int, double*);
-template __global__ void k_eps<V_TH>(const void*, int, double*);
-template __global__ void k_eps<V_R3>(const void*, int, double*);
-template __global__ void k_eps<V_W5>(const void*, int, double*);
-template __global__ void k_eps<V_TH | V_W5>(const void*, int, double*);
-template __global__ void k_eps<V_TH | V_R3>(const void*, int, double*);
+template __global__ void k_eps<0>(const void*, int, double*, int);
+template __global__ void k_eps<V_TH>(const void*, int, double*, int);
+template __global__ void k_eps<V_R3>(const void*, int, double*, int);
+template __global__ void k_eps<V_W5>(const void*, int, double*, int);
+template __global__ void k_eps<V_TH | V_W5>(const void*, int, double*, int);
+template __global__ void k_eps<V_TH | V_R3>(const void*, int, double*, int);
 template __global__ void k_update<false>(const void*, int);
 template __global__ void k_update<true>(const void*, int);
 template __global__ void k_strain<false>(const void*, int, int, int);
@@ -733,7 +733,7 @@ gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt
 gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
 {
     if (!h || !host_out) return fail_h(h, GKS_ERR_ARG, "NULL argument");
-    if (which < GKS_FIELD_CONS || which > GKS_FIELD_EPS) return fail_h(h, GKS_ERR_ARG, "unknown field");
+    if (which < GKS_FIELD_CONS || which > GKS_FIELD_TAU) return fail_h(h, GKS_ERR_ARG, "unknown field");
     gks_status rs = sync_batch(h);
     if (rs != GKS_OK) return rs;
     State st;
@@ -741,7 +741,8 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const long long N = h->L.ncells;
     const int nv = h->nv, D = h->cfg.dim;
-    if (which == GKS_FIELD_STRAIN || which == GKS_FIELD_EPS || (which == GKS_FIELD_TURB && h->cfg.turb_transport)) {
+    const bool diag = which == GKS_FIELD_EPS || which == GKS_FIELD_TAU;
+    if (which == GKS_FIELD_STRAIN || diag || (which == GKS_FIELD_TURB && h->cfg.turb_transport)) {
         // a strain pass over the current state (with transport it also writes k and omega)
         hipLaunchKernelGGL(h->cfg.turb_transport ? k_strain<true> : k_strain<false>, dim3(h->grid_cell),
                            dim3(CELL_TILE), 0, h->stream, (const void*)h->tab, 1, 1, 0);
@@ -752,12 +753,12 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         return GKS_OK;
     }
-    if (which == GKS_FIELD_EPS) {
+    if (diag) {
         // into the older state buffer, which no step reads again before writing it
         double* out = h->inst.W[st.parity ^ 1];
         const int grid = (int)std::min<long long>((N + 63) / 64, 1 << 20);
         const int v = variant_of(&h->cfg) & (V_TH | V_R3 | V_W5);
-        void (*ke)(const void*, int, double*) = k_eps<0>;
+        void (*ke)(const void*, int, double*, int) = k_eps<0>;
         switch (v) {
         case V_TH: ke = k_eps<V_TH>; break;
         case V_R3: ke = k_eps<V_R3>; break;
@@ -766,7 +767,8 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
         case V_TH | V_W5: ke = k_eps<V_TH | V_W5>; break;
         default: break;
         }
-        hipLaunchKernelGGL(ke, dim3(grid), dim3(64), 0, h->stream, (const void*)h->tab, 1, out);
+        hipLaunchKernelGGL(ke, dim3(grid), dim3(64), 0, h->stream, (const void*)h->tab, 1, out,
+                           which == GKS_FIELD_TAU ? 1 : 0);
         HIP_TRY(h, hipGetLastError());
         HIP_TRY(h, hipMemcpyAsync(host_out, out, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));

@@ -17,7 +17,7 @@ GKS_OK, GKS_ERR_ARG, GKS_ERR_NONPHYSICAL, GKS_ERR_NOMEM, GKS_ERR_DEVICE, GKS_ERR
 _NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NONPHYSICAL", 3: "ERR_NOMEM", 4: "ERR_DEVICE", 5: "ERR_STATE"}
 BC = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
-FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3, "eps": 4}
+FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3, "eps": 4, "tau": 5}
 EPS_MODE = {"dt": 0, "tauhat": 1}
 RECON = {"muscl2": 0, "muscl3": 1, "weno5": 2}
 
@@ -339,8 +339,8 @@ class Solver:
         return gks_residual(self.h, self.nv)
 
     def fields(self, which="cons"):
-        """cons / prim: (nvar, nz, ny, nx); strain, eps: (nz, ny, nx); turb: (2, nz, ny, nx), k and omega."""
-        shape = {"strain": self.case.k.shape, "eps": self.case.k.shape,
+        """cons / prim: (nvar, nz, ny, nx); strain, eps, tau: (nz, ny, nx); turb: (2, nz, ny, nx), k and omega."""
+        shape = {"strain": self.case.k.shape, "eps": self.case.k.shape, "tau": self.case.k.shape,
                  "turb": (2,) + self.case.k.shape}.get(which, self.case.W.shape)
         return gks_fields(self.h, which, shape)
 
