@@ -157,12 +157,17 @@ typedef struct {
 typedef struct gks_ctx* gks_handle;
 
 /* Device workspace needed by one solve (state double buffer, frozen fields, face fluxes,
- * metrics, reduction partials).  This is the HBM footprint used for admission. */
+ * metrics, reduction partials).  This is the HBM footprint used for admission.  Pure host
+ * arithmetic on cfg (no device call); GKS_ERR_ARG for a bad config. */
 gks_status gks_workspace_bytes(const gks_config* cfg, size_t* bytes);
 
-/* Validate cfg and the initial state, copy W (nvar x ncells), k and omega (ncells) from
- * the host into dev_workspace (256-byte aligned, >= gks_workspace_bytes), and compute the
- * first CFL step on `hip_stream` (a hipStream_t; NULL = default stream).  With
+/* Set up a solve of the finite-volume scheme (section "Implementation of the turbulent
+ * gas-kinetic scheme in a finite-volume solver") from a cell-averaged state W, the
+ * turbulence fields k and omega that enter the relaxation time (Eq. tautchenadjusted) and
+ * the gas constants of cfg.  Validate cfg and the initial state, copy W (nvar x ncells), k
+ * and omega (ncells) from the host into dev_workspace (256-byte aligned,
+ * >= gks_workspace_bytes), and compute the first CFL step on `hip_stream` (a hipStream_t;
+ * NULL = default stream).  The handle (*out) is the library's; free it with gks_destroy.  With
  * turb_transport the initial rho k = rho * k and rho omega = rho * omega.  Returns
  * GKS_ERR_ARG for a bad config, k < 0, omega <= 0; GKS_ERR_NONPHYSICAL for rho <= 0 or
  * p <= 0; GKS_ERR_NOMEM if bytes is too small. */
@@ -170,25 +175,38 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
                     const double* W, const double* k, const double* omega, gks_handle* out);
 
 /* Enqueue nsteps explicit steps (asynchronous; no host synchronisation).  Each step: CFL
- * time step from the current state, strain rate, every face flux, conservative update,
- * residual and next time step, all on the device.  With turb_transport the strain pass
+ * time step from the current state, strain rate (the eta of Eq. tautchenadjusted), every
+ * face flux (the time integral of Eq. resultingf over the step, Eq. fluxesf, with the
+ * relaxation time of Eqs. relaxation time, taua, tautchenadjusted and the Prandtl
+ * correction of the heat flux), conservative update of the cell averages by the fluxes'
+ * differences (section "Implementation ..."), residual and next time step, all on the
+ * device.  nsteps >= 0; a solve that reached t_end, max_steps or res_tol takes no more
+ * steps (the call still succeeds).  GKS_ERR_STATE after a reported error.  With turb_transport the strain pass
  * also computes k, omega and the k-omega sources, the face pass the fluxes of rho k and
  * rho omega, and the update advances them; a step whose rho k < 0 or rho omega <= 0 is
  * non-physical. */
 gks_status gks_step(gks_handle h, int32_t nsteps);
 
 /* Synchronise and report the last step: res[nvar] = sqrt(mean(((W^{n+1}-W^n)/dt)^2)) per
- * flow field (rho k and rho omega excluded), res_first[nvar] the same for the first step of the solve (for convergence
- * ratios), the step dt_last, the time t and the number of steps done.  Any pointer may be
- * NULL. */
+ * flow field (rho k and rho omega excluded), res_first[nvar] the same for the first step of
+ * the solve (for convergence ratios), the step dt_last, the time t and the number of steps
+ * done.  The paper drives its steady solves to convergence without defining the residual;
+ * this is the usual RMS of the time derivative of the conservative variables.  Any pointer
+ * may be NULL; the arrays are the caller's.  Returns a pending device error
+ * (GKS_ERR_NONPHYSICAL) after filling what it can. */
 gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt_last, double* t,
                         int64_t* steps_done);
 
-/* Synchronise and copy a field (GKS_FIELD_*) to host memory. */
+/* Synchronise and copy a field (GKS_FIELD_*, sizes as listed there) into host_out, which
+ * the caller owns and sizes.  EPS and TAU evaluate every face of the current state at the
+ * next step's dt with the solve's own options (Eqs. epsilonkomega, tautchenadjusted),
+ * using the older state buffer as scratch, so they leave the state and later steps
+ * unchanged.  GKS_ERR_ARG for an unknown field. */
 gks_status gks_fields(gks_handle h, int32_t which, double* host_out);
 
 /* Device pointer of the current conservative state (nvar x ncells, FP64; nvar + 2 with
- * turb_transport). Valid until the next gks_step. */
+ * turb_transport), inside the caller's workspace.  Valid until the next gks_step; the
+ * caller may read it on the handle's stream (or after synchronising). */
 gks_status gks_state_device_ptr(gks_handle h, const double** dev_W);
 
 /* Synchronise and release the handle (the caller frees the workspace). */
@@ -230,6 +248,10 @@ gks_status gks_face_flops_recon(int32_t dim, int32_t recon, double* flops);
 /* Batched form: many independent solves (any mix of sizes, dims, precisions) advanced  */
 /* by persistent kernels that walk one device tile table per step.                       */
 /* ---------------------------------------------------------------------------------- */
+/* The paper runs one solve at a time; the batch advances many solves of the same scheme
+ * (the step of gks_step, with each solve's own options) together, each member's result
+ * being that of its solve stepped alone.  A gks_batch handle is the library's; free it
+ * with gks_batch_destroy (the members stay the caller's). */
 typedef struct gks_batch_ctx* gks_batch;
 
 /* Device workspace of a batch able to hold up to `capacity` solves: its tile table and a

@@ -47,7 +47,7 @@ def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)
 
 
-# Reading Z34: a momentum component whose range is below 1 % of the momentum magnitude (the
+# The metric of a perturbation component: a momentum component whose range is below 1 % of the momentum magnitude (the
 # mixing layer's transverse momentum, a perturbation that the shear layer amplifies) drifts
 # by rounding alone beyond 1e-12 of its own range over a few hundred steps (a few tens with
 # WENO5): algebraically equal forms of the oracle's own arithmetic differ by that much
@@ -65,8 +65,8 @@ def oracle_reference(case, nsteps):
 
 
 def assert_matches_oracle(W, case, ref, tol, label=""):
-    """Per-field parity of a GPU state with the oracle's, at `tol` (reading Z34 for a
-    perturbation momentum component at the FP64 bound)."""
+    """Per-field parity of a GPU state with the oracle's, at `tol` (a perturbation
+    momentum component at the FP64 bound is held as PERTURBATION_FIELD states)."""
     import numpy as np
     err = report(W, ref["W"], label)
     mom = field_errors(W, ref["W"], vector_momentum=True)

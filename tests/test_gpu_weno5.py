@@ -3,7 +3,7 @@ the same seeded inputs: FP64 flux <= 1e-12 and FP32 flux <= 1e-5 per field, norm
 device forms the weighted mean over a common denominator (one reciprocal), the oracle with
 the weights themselves: equal up to rounding.
 
-Reading Z34: in the mixing layer the transverse momentum stays three orders below the
+The metric of a perturbation component: in the mixing layer the transverse momentum stays three orders below the
 streamwise one, and with WENO5 a one-ulp change of the face values anywhere grows to
 1-2e-12 of max |rho V| within 20-60 steps; algebraically equal forms of the oracle's own
 WENO5 differ from it by that much (measured in tests/test_oracle_weno5.py).  A momentum

@@ -1,4 +1,4 @@
-"""Reading Z34: how well the per-field error metric is conditioned for a field that is a
+"""How well the per-field error metric is conditioned for a field that is a
 small perturbation of a larger vector.
 
 The mixing layer's transverse momentum rho V stays about three orders below the streamwise
