@@ -124,9 +124,11 @@ enum { GKS_RECON_MUSCL2 = 0, GKS_RECON_MUSCL3 = 1, GKS_RECON_WENO5 = 2 };
  * each face at the current state and step, the largest over the cell's faces (ncells; in
  * either eps_mode, as the "turbulent Knudsen number" diagnostic). TAU: the relaxation time
  * tau = mu/p0 + tau_a + the k-omega part (Eqs. relaxation time, taua, tautchenadjusted) of
- * each face at the current state and step, the largest over the cell's faces (ncells). */
+ * each face at the current state and step, the largest over the cell's faces (ncells).
+ * TURB_CONS: rho k then rho omega of the current state (2 x ncells; turb_transport only,
+ * else GKS_ERR_ARG), the transported variables as stored, for a checkpoint. */
 enum { GKS_FIELD_CONS = 0, GKS_FIELD_PRIM = 1, GKS_FIELD_STRAIN = 2, GKS_FIELD_TURB = 3, GKS_FIELD_EPS = 4,
-       GKS_FIELD_TAU = 5 };
+       GKS_FIELD_TAU = 5, GKS_FIELD_TURB_CONS = 6 };
 
 typedef struct {
     int32_t dim;                  /* 2 or 3 */
@@ -203,6 +205,23 @@ gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt
  * using the older state buffer as scratch, so they leave the state and later steps
  * unchanged.  GKS_ERR_ARG for an unknown field. */
 gks_status gks_fields(gks_handle h, int32_t which, double* host_out);
+
+/* Checkpoint/resume.  A solve is saved by gks_fields(CONS) (and TURB_CONS with
+ * turb_transport) plus what gks_residual reports; it is restored by gks_init from the
+ * saved CONS state (with the solve's k and omega, or any valid pair with transport)
+ * followed by gks_resume with the saved values.  gks_resume sets the time, the step count
+ * (counted towards max_steps), the last and first-step residuals (res_first drives
+ * res_tol) and, with turb_transport, overwrites rho k and rho omega with turb_cons
+ * (2 x ncells, host; NULL keeps rho k = rho * k of gks_init); then it recomputes the next
+ * CFL step, clipped to t_end, by the arithmetic that ends every step.  The resumed solve
+ * continues exactly as the saved one would have: stepping n, saving, resuming and stepping
+ * m gives the state, residuals, time and step count of n + m steps, bitwise.  Only on a
+ * handle that has taken no step and joined no batch (else GKS_ERR_STATE); res/res_first
+ * (nvar each) may be NULL (zeros).  GKS_ERR_ARG for negative or non-finite values or
+ * turb_cons without turb_transport; GKS_ERR_NONPHYSICAL (handle then in the error state)
+ * when the restored state is not physical. */
+gks_status gks_resume(gks_handle h, const double* res, const double* res_first, double dt_last, double t,
+                      int64_t steps_done, const double* turb_cons);
 
 /* Device pointer of the current conservative state (nvar x ncells, FP64; nvar + 2 with
  * turb_transport), inside the caller's workspace.  Valid until the next gks_step; the

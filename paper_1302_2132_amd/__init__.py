@@ -10,7 +10,7 @@ from .gks import (  # noqa: F401
     GksError, lib, lib_path, config_from_case, gks_workspace_bytes, gks_init, gks_step,
     gks_residual, gks_fields, gks_destroy, gks_last_error, gks_face_flops, gks_kw_face_flops, gks_face_flops_multid,
     gks_face_flops_recon,
-    gks_state_device_ptr,
+    gks_state_device_ptr, gks_resume,
     gks_set_timing, gks_kernel_times,
     gks_batch_workspace_bytes, gks_batch_create, gks_batch_set_members, gks_batch_step,
     gks_batch_capture, gks_batch_set_launch, gks_batch_status, gks_batch_destroy,

@@ -627,6 +627,32 @@ __device__ inline void update_read(cref<Inst> I, const double* __restrict__ Wo, 
     }
 }
 
+// CFL rate of a cell of conservative state w (flow variables), k/omega `kow` and inverse
+// widths idx:  sum_d (|U_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2 with
+// nu_eff = (mu/rho + k/omega) max(4/3, gamma/Pr).  False when rho or p is not positive and
+// finite, or the rate is not finite (a non-finite k or omega, which the relaxation time
+// would otherwise pass on unnoticed).  The end of every step and the initial rate pass both
+// use it, so a solve re-initialised from a saved state takes the same time steps, bitwise.
+template <int D>
+__device__ inline bool cell_rate(cref<Inst> I, const double* w, double kow, const double* idx, double& rate)
+{
+    double ke = 0.0, U[3];
+    const double rho = w[0], irho = 1.0 / rho;
+    for (int d = 0; d < D; ++d) { U[d] = w[1 + d] * irho; ke += U[d] * w[1 + d]; }
+    const double p = I.two_over_b * (w[D + 1] - 0.5 * ke);
+    if (!(rho > 0.0) || !(p > 0.0) || !(rho < 1e300) || !(p < 1e300)) return false;
+    const double cs = sqrt(I.gamma * p * irho);
+    const double fac = fmax(4.0 / 3.0, I.gamma / I.prandtl);
+    const double nu = (I.mu * irho + kow) * fac;
+    double r = 0.0, r2s = 0.0;
+    for (int d = 0; d < D; ++d) {
+        r += (fabs(U[d]) + cs) * idx[d];
+        r2s += idx[d] * idx[d];
+    }
+    rate = r + 2.0 * nu * r2s;
+    return rate < 1e300;
+}
+
 // New state of one cell (stored when `store`), its squared residual components added to
 // r2 (flow variables only), its CFL rate folded into `rate` (max), a non-physical state
 // flagged in `bad`.  With transport, rho k and rho omega take their flux differences and
@@ -668,21 +694,9 @@ __device__ inline void update_apply(cref<Inst> I, double* __restrict__ Wn, int c
     }
     if (!store) return;
     // positivity and the CFL rate of the new state
-    double ke = 0.0, U[3];
-    const double rho = w[0], irho = 1.0 / rho;
-    for (int d = 0; d < D; ++d) { U[d] = w[1 + d] * irho; ke += U[d] * w[1 + d]; }
-    const double p = I.two_over_b * (w[D + 1] - 0.5 * ke);
-    if (!(rho > 0.0) || !(p > 0.0) || !(rho < 1e300) || !(p < 1e300)) { bad = 1; return; }
-    // CFL rate  sum_d (|U_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2
-    const double cs = sqrt(I.gamma * p * irho);
-    const double fac = fmax(4.0 / 3.0, I.gamma / I.prandtl);
-    const double nu = (I.mu * irho + kow) * fac;
-    double r = 0.0, r2s = 0.0;
-    for (int d = 0; d < D; ++d) {
-        r += (fabs(U[d]) + cs) * x.idx[d];
-        r2s += x.idx[d] * x.idx[d];
-    }
-    rate = fmax(rate, r + 2.0 * nu * r2s);
+    double cr;
+    if (!cell_rate<D>(I, w, kow, x.idx, cr)) { bad = 1; return; }
+    rate = fmax(rate, cr);
 }
 
 // Update of one cell from the face fluxes in HBM: every read first (the compiler cannot
@@ -1355,7 +1369,30 @@ __global__ __launch_bounds__(CELL_TILE) void k_update(const void* __restrict__ t
     }
 }
 
-// Max CFL rate of the current state of each member (first step at init).
+// Max CFL rate of the current state of each member (first step at init), by the same
+// arithmetic as the end of a step: k/omega from the frozen fields, or with transport from
+// the state's rho k / rho omega.
+template <int D>
+__device__ inline bool init_rate(cref<Inst> I, const double* __restrict__ W, int cell, double& rate)
+{
+    double w[D + 2], idx[D];
+    for (int m = 0; m < D + 2; ++m) w[m] = W[(long long)m * I.ncells + cell];
+    int c[3];
+    c[0] = cell % I.n[0];
+    c[1] = (cell / I.n[0]) % I.n[1];
+    c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
+    for (int d = 0; d < D; ++d) idx[d] = I.idx[d][c[d]];
+    double kow;
+    if (I.kw) {
+        const double rk = W[(long long)(D + 2) * I.ncells + cell], rw = W[(long long)(D + 3) * I.ncells + cell];
+        if (!(rk >= 0.0) || !(rw > 0.0) || !(rk < 1e300) || !(rw < 1e300)) return false;
+        kow = rk / rw;
+    } else {
+        kow = I.k[cell] / I.om[cell];
+    }
+    return cell_rate<D>(I, w, kow, idx, rate);
+}
+
 #ifdef GKS_LIB_UNIT   // defined in the library unit only
 __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ table, int cap)
 {
@@ -1375,28 +1412,8 @@ __global__ __launch_bounds__(CELL_TILE) void k_rate(const void* __restrict__ tab
         int bad = 0;
         if (cell < I.ncells) {
             const double* W = I.W[state_of(I).parity];
-            const int D = I.dim;
-            double w[5];
-            for (int m = 0; m < I.nv; ++m) w[m] = W[(long long)m * I.ncells + cell];
-            int c[3];
-            c[0] = cell % I.n[0];
-            c[1] = (cell / I.n[0]) % I.n[1];
-            c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
-            double ke = 0.0, U[3];
-            for (int d = 0; d < D; ++d) { U[d] = w[1 + d] / w[0]; ke += U[d] * w[1 + d]; }
-            const double rho = w[0], p = (2.0 / I.b) * (w[D + 1] - 0.5 * ke);
-            if (!(rho > 0.0) || !(p > 0.0)) bad = 1;
-            else {
-                const double cs = sqrt(I.gamma * p / rho);
-                const double nu = (I.mu + rho * I.k[cell] / I.om[cell]) / rho * fmax(4.0 / 3.0, I.gamma / I.prandtl);
-                double r = 0.0, r2s = 0.0;
-                for (int d = 0; d < D; ++d) {
-                    const double h = I.dx[d][c[d]];
-                    r += (fabs(U[d]) + cs) / h;
-                    r2s += 1.0 / (h * h);
-                }
-                rate = r + 2.0 * nu * r2s;
-            }
+            const bool ok = I.dim == 2 ? init_rate<2>(I, W, cell, rate) : init_rate<3>(I, W, cell, rate);
+            if (!ok) { bad = 1; rate = 0.0; }
         }
         const double mx = wave_max(rate);
         const int any = __any(bad);
@@ -1473,7 +1490,7 @@ __device__ inline void finish_member(cref<Inst> I, int mode, double* sh)
         next_step(I, st, rate, st->t);
         if (st->err) st->active = 0;
         if (I.max_steps > 0 && st->steps >= I.max_steps) st->active = 0;
-        if (mode == 0 && I.res_tol > 0.0 && st->steps >= 2) {
+        if (I.res_tol > 0.0 && st->steps >= 2) {      // (mode 1: a resumed solve)
             // residual fall of the flow fields whose first-step residual is positive
             double worst = -1.0;
             for (int m = 0; m < nv; ++m)

@@ -245,6 +245,7 @@ struct gks_ctx {
     State* st;      // device step state
     std::string err;
     bool broken;
+    bool pristine;  // no step taken and in no batch yet: gks_resume is allowed
     int grid_cell, grid_face;
     bool timing;
     hipStream_t batch_stream;         // stream of the batch that last advanced this solve
@@ -511,6 +512,7 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
     h->ws_bytes = bytes;
     h->L = L;
     h->broken = false;
+    h->pristine = true;
     h->timing = false;
     h->batch_stream = nullptr;
     h->events_used = 0;
@@ -700,6 +702,7 @@ gks_status gks_step(gks_handle h, int32_t nsteps)
     if (h->broken) return fail_h(h, GKS_ERR_STATE, "handle is in the error state");
     gks_status r = sync_batch(h);
     if (r != GKS_OK) return r;
+    if (nsteps > 0) h->pristine = false;
     return enqueue_steps(h, nsteps);
 }
 
@@ -733,7 +736,9 @@ gks_status gks_residual(gks_handle h, double* res, double* res_first, double* dt
 gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
 {
     if (!h || !host_out) return fail_h(h, GKS_ERR_ARG, "NULL argument");
-    if (which < GKS_FIELD_CONS || which > GKS_FIELD_TAU) return fail_h(h, GKS_ERR_ARG, "unknown field");
+    if (which < GKS_FIELD_CONS || which > GKS_FIELD_TURB_CONS) return fail_h(h, GKS_ERR_ARG, "unknown field");
+    if (which == GKS_FIELD_TURB_CONS && !h->cfg.turb_transport)
+        return fail_h(h, GKS_ERR_ARG, "TURB_CONS needs turb_transport");
     gks_status rs = sync_batch(h);
     if (rs != GKS_OK) return rs;
     State st;
@@ -774,6 +779,12 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         return GKS_OK;
     }
+    if (which == GKS_FIELD_TURB_CONS) {
+        HIP_TRY(h, hipMemcpyAsync(host_out, h->inst.W[st.parity] + (size_t)nv * N, sizeof(double) * 2 * N,
+                                  hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        return GKS_OK;
+    }
     if (which == GKS_FIELD_TURB) {
         HIP_TRY(h, hipMemcpyAsync(host_out, h->inst.k, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipMemcpyAsync(host_out + N, h->inst.om, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
@@ -793,6 +804,53 @@ gks_status gks_fields(gks_handle h, int32_t which, double* host_out)
             }
             host_out[(D + 1) * N + i] = (h->cfg.gamma - 1.0) * (host_out[(D + 1) * N + i] - 0.5 * ke);
         }
+    }
+    return GKS_OK;
+}
+
+gks_status gks_resume(gks_handle h, const double* res, const double* res_first, double dt_last, double t,
+                      int64_t steps_done, const double* turb_cons)
+{
+    if (!h) return fail_h(nullptr, GKS_ERR_ARG, "NULL handle");
+    if (h->broken || !h->pristine) return fail_h(h, GKS_ERR_STATE, "resume needs a handle that has taken no step");
+    if (!(t >= 0.0) || !isfinite(t) || !(dt_last >= 0.0) || !isfinite(dt_last) || steps_done < 0)
+        return fail_h(h, GKS_ERR_ARG, "bad progress values");
+    const int nv = h->nv;
+    for (int m = 0; m < nv; ++m)
+        if ((res && (!(res[m] >= 0.0) || !isfinite(res[m]))) ||
+            (res_first && (!(res_first[m] >= 0.0) || !isfinite(res_first[m]))))
+            return fail_h(h, GKS_ERR_ARG, "residuals must be finite and >= 0");
+    if (turb_cons && !h->cfg.turb_transport) return fail_h(h, GKS_ERR_ARG, "turb_cons needs turb_transport");
+    const long long N = h->L.ncells;
+    if (turb_cons)
+        for (long long i = 0; i < N; ++i)
+            if (!(turb_cons[i] >= 0.0) || !isfinite(turb_cons[i]) || !(turb_cons[N + i] > 0.0) ||
+                !isfinite(turb_cons[N + i]))
+                return fail_h(h, GKS_ERR_ARG, "rho k must be finite and >= 0, rho omega finite and > 0");
+    hipStream_t s = h->stream;
+    State st;
+    HIP_TRY(h, hipMemcpyAsync(&st, h->st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    if (turb_cons)
+        HIP_TRY(h, hipMemcpyAsync(h->inst.W[st.parity] + (size_t)nv * N, turb_cons, sizeof(double) * 2 * N,
+                                  hipMemcpyHostToDevice, s));
+    st.t = t;
+    st.steps = steps_done;
+    st.dt_last = dt_last;
+    for (int m = 0; m < 5; ++m) {
+        st.res[m] = res && m < nv ? res[m] : 0.0;
+        st.res_first[m] = res_first && m < nv ? res_first[m] : 0.0;
+    }
+    HIP_TRY(h, hipMemcpyAsync(h->st, &st, sizeof(State), hipMemcpyHostToDevice, s));
+    // the first step again, from the restored time, step count and (with transport) rho k
+    hipLaunchKernelGGL(k_rate, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, (const void*)h->tab, 1);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(CELL_TILE), 0, s, (const void*)h->tab, 1, 1);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipMemcpyAsync(&st, h->st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    if (st.err) {
+        h->broken = true;
+        return fail_h(h, GKS_ERR_NONPHYSICAL, "resumed state is not physical");
     }
     return GKS_OK;
 }
@@ -963,6 +1021,7 @@ static gks_status batch_make(const gks_handle* hs, int32_t count, int32_t capaci
 {
     gks_batch b = new gks_batch_ctx();
     b->members.assign(hs, hs + count);
+    for (int i = 0; i < count; ++i) hs[i]->pristine = false;
     b->cap = capacity;
     b->stream = (hipStream_t)hip_stream;
     b->tab = tab;
@@ -1025,6 +1084,7 @@ gks_status gks_batch_set_members(gks_batch b, const gks_handle* hs, int32_t coun
     for (int i = 0; i < count; ++i)
         if (!hs[i] || hs[i]->broken) return fail_h(nullptr, GKS_ERR_ARG, "member handle is NULL or broken");
     b->members.assign(hs, hs + count);
+    for (int i = 0; i < count; ++i) hs[i]->pristine = false;
     return batch_upload(b);
 }
 

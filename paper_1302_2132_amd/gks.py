@@ -17,7 +17,7 @@ GKS_OK, GKS_ERR_ARG, GKS_ERR_NONPHYSICAL, GKS_ERR_NOMEM, GKS_ERR_DEVICE, GKS_ERR
 _NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_NONPHYSICAL", 3: "ERR_NOMEM", 4: "ERR_DEVICE", 5: "ERR_STATE"}
 BC = {"periodic": 0, "wall": 1, "dirichlet": 2, "profile": 3, "outflow": 4}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
-FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3, "eps": 4, "tau": 5}
+FIELD = {"cons": 0, "prim": 1, "strain": 2, "turb": 3, "eps": 4, "tau": 5, "turb_cons": 6}
 EPS_MODE = {"dt": 0, "tauhat": 1}
 RECON = {"muscl2": 0, "muscl3": 1, "weno5": 2}
 
@@ -29,7 +29,7 @@ EXPORTED = (
     "gks_set_timing", "gks_kernel_times",
     "gks_batch_workspace_bytes", "gks_batch_create", "gks_batch_set_members", "gks_batch_step",
     "gks_batch_capture", "gks_batch_set_launch", "gks_batch_status", "gks_batch_destroy",
-    "gks_batch_create_static", "gks_batch_capture_steps",
+    "gks_batch_create_static", "gks_batch_capture_steps", "gks_resume",
 )
 GKS_BATCH_STATIC_CAPACITY = 256
 
@@ -83,6 +83,7 @@ def lib():
         L.gks_residual.argtypes = [vp, dp, dp, dp, dp, C.POINTER(i64)]
         L.gks_fields.argtypes = [vp, i32, dp]
         L.gks_state_device_ptr.argtypes = [vp, C.POINTER(vp)]
+        L.gks_resume.argtypes = [vp, dp, dp, C.c_double, C.c_double, i64, dp]
         L.gks_destroy.argtypes = [vp]
         L.gks_last_error.argtypes = [vp]
         L.gks_last_error.restype = C.c_char_p
@@ -191,6 +192,14 @@ def gks_fields(h, which, shape):
     out = np.zeros(shape, dtype=np.float64)
     _check(lib().gks_fields(h, FIELD[which], _dp(out)), h)
     return out
+
+
+def gks_resume(h, res, res_first, dt_last, t, steps_done, turb_cons=None):
+    res = None if res is None else np.ascontiguousarray(res, dtype=np.float64)
+    res_first = None if res_first is None else np.ascontiguousarray(res_first, dtype=np.float64)
+    tc = None if turb_cons is None else np.ascontiguousarray(turb_cons, dtype=np.float64)
+    _check(lib().gks_resume(h, None if res is None else _dp(res), None if res_first is None else _dp(res_first),
+                            float(dt_last), float(t), int(steps_done), None if tc is None else _dp(tc)), h)
 
 
 def gks_state_device_ptr(h):
@@ -318,7 +327,9 @@ def _torch_stream(stream):
 class Solver:
     """One solve: workspace tensor + handle.  `case` is an inputs.cases.Case."""
 
-    def __init__(self, case, device="cuda:0", stream=None):
+    def __init__(self, case, device="cuda:0", stream=None, resume=None):
+        """`resume`: a dict from checkpoint() of a solve of the same case; the new solve
+        continues it exactly."""
         import torch
         lib()
         if not torch.cuda.is_available():
@@ -326,11 +337,25 @@ class Solver:
         self.case = case
         self.cfg = config_from_case(case)
         self.nbytes = gks_workspace_bytes(self.cfg)
+        self.h = None
+        W = case.W if resume is None else resume["W"]
         with torch.cuda.device(device):
             self.stream, sp = _torch_stream(stream)
             self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
-            self.h = gks_init(self.cfg, self.ws.data_ptr(), self.nbytes, sp, case.W, case.k, case.omega)
+            self.h = gks_init(self.cfg, self.ws.data_ptr(), self.nbytes, sp, W, case.k, case.omega)
+            if resume is not None:
+                gks_resume(self.h, resume["res"], resume["res_first"], resume["dt"], resume["t"], resume["steps"],
+                           resume.get("turb_cons"))
         self.nv = case.nvar
+
+    def checkpoint(self):
+        """What a resumed solve needs: the conservative state, with transport rho k and rho
+        omega, and the time, step count and residuals."""
+        ck = dict(self.residual())
+        ck["W"] = self.fields("cons")
+        if getattr(self.case, "kw_transport", False):
+            ck["turb_cons"] = self.fields("turb_cons")
+        return ck
 
     def step(self, n=1):
         gks_step(self.h, n)
@@ -341,7 +366,7 @@ class Solver:
     def fields(self, which="cons"):
         """cons / prim: (nvar, nz, ny, nx); strain, eps, tau: (nz, ny, nx); turb: (2, nz, ny, nx), k and omega."""
         shape = {"strain": self.case.k.shape, "eps": self.case.k.shape, "tau": self.case.k.shape,
-                 "turb": (2,) + self.case.k.shape}.get(which, self.case.W.shape)
+                 "turb": (2,) + self.case.k.shape, "turb_cons": (2,) + self.case.k.shape}.get(which, self.case.W.shape)
         return gks_fields(self.h, which, shape)
 
     def close(self):

@@ -114,6 +114,22 @@ def test_init_validation_before_any_device_call():
     with pytest.raises(P.GksError) as e:     # misaligned workspace
         P.gks_init(cfg, 257, 1 << 30, 0, c.W, c.k, c.omega)
     assert e.value.status == P.GKS_ERR_ARG
+    # non-finite or out-of-range fields are refused on the host, before the workspace (a
+    # bogus pointer here) is touched: NaN in k or omega is an argument error, NaN in the
+    # flow state a non-physical one
+    for field, idx, val, want in [("k", (0, 3, 5), np.nan, P.GKS_ERR_ARG), ("k", (0, 0, 0), -1e-9, P.GKS_ERR_ARG),
+                                  ("k", (0, 7, 1), np.inf, P.GKS_ERR_ARG),
+                                  ("omega", (0, 2, 2), np.nan, P.GKS_ERR_ARG), ("omega", (0, 1, 9), 0.0, P.GKS_ERR_ARG),
+                                  ("W", (0, 0, 4, 4), np.nan, P.GKS_ERR_NONPHYSICAL),
+                                  ("W", (3, 0, 1, 1), np.nan, P.GKS_ERR_NONPHYSICAL)]:
+        arrs = {"W": c.W.copy(), "k": c.k.copy(), "omega": c.omega.copy()}
+        arrs[field][idx] = val
+        with pytest.raises(P.GksError) as e:
+            P.gks_init(cfg, 256, 1 << 30, 0, arrs["W"], arrs["k"], arrs["omega"])
+        assert e.value.status == want, (field, idx, val)
+    with pytest.raises(P.GksError) as e:     # resume without a handle
+        P.gks_resume(None, None, None, 0.0, 0.0, 0)
+    assert e.value.status == P.GKS_ERR_ARG
 
 
 def test_face_flop_count():
