@@ -31,14 +31,41 @@ FP32_PEAK_TFLOPS = 78.6    # scalar FP32 VALU at the same rate (packed FP32 is n
 HBM_PEAK_GBS = 8000.0
 
 
+# The GPU's clocks rise from their idle state over the first ~25 ms of sustained load
+# (measured on the SBLI step: 115 us for the first step, 77 us/step after 5 ms, a steady
+# 70 us/step from ~25 ms on), and fall back while the host prepares the next leg.  Each
+# timed section is therefore preceded by _spin(): 40 ms of steps of a separate SBLI solve
+# (kept for the run), which leaves the measured solves' own step counts untouched.
+SPIN_MS = 40.0
+_SPINNER = []
+
+
+def _spin(ms=SPIN_MS):
+    import torch
+
+    from inputs import cases as C
+    from paper_1302_2132_amd import Solver
+    if not _SPINNER or _SPINNER[1] > 1500:       # a fresh solve within the stated 2000 steps
+        if _SPINNER:
+            _SPINNER[0].close()
+        _SPINNER[:] = [Solver(C.sbli(1024, 512)), 0]
+    s = _SPINNER[0]
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        s.step(40)
+        _SPINNER[1] += 40
+        torch.cuda.synchronize()
+
+
 def _leg(case, steps, warmup, eps_field=False):
-    """Warm-up, then `steps` plain steps on the clock (the throughput), then the same
-    number again with every launch carrying its own start/stop event pair (the per-kernel
-    durations).  The state read back has advanced warmup + 2 * steps steps."""
+    """Clock spin-up and warm-up, then `steps` plain steps on the clock (the throughput),
+    then the same number again with every launch carrying its own start/stop event pair
+    (the per-kernel durations).  The state read back has advanced warmup + 2 * steps steps."""
     import torch
 
     from paper_1302_2132_amd import Solver, gks_kernel_times, gks_set_timing
     s = Solver(case)
+    _spin()
     s.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -152,7 +179,7 @@ def _batch_leg(steps=200, count=64, check=8):
     cases = C.batch_cases(count, seed=3, steps=steps, precision="fp32_flux")
     cell_updates = sum(c.ncells for c in cases) * steps
     solvers = [Solver(c) for c in cases]
-    torch.cuda.synchronize()
+    _spin()
     t0 = time.perf_counter()
     for s in solvers:
         s.step(steps)
@@ -166,7 +193,7 @@ def _batch_leg(steps=200, count=64, check=8):
 
     solvers = [Solver(c) for c in cases]
     b = Batch(solvers, capacity=count)
-    torch.cuda.synchronize()
+    _spin()
     t0 = time.perf_counter()
     shape, tune_steps, tune_s = autotune(b, use_cache=False)
     b.capture()
@@ -293,7 +320,7 @@ def main():
         "metric": "cell-updates/s FP64 vs FP32-flux at stated err; p50/p99 served solve latency",
         "value": value,
         "unit": "cell-updates/s",
-        "n_gpus": 1, "steps": K, "warmup": Wm,
+        "n_gpus": 1, "steps": K, "warmup": Wm, "clock_spinup_ms_before_warmup": SPIN_MS,
         "ms_per_step": leg64["seconds"] * 1e3 / K,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
