@@ -420,36 +420,51 @@ GKS_HD inline H weno5(H a, H b, H c, H d, H e)
     return (w0 * q0 + w1 * q1 + w2 * q2) * g_rcp(w0 + w1 + w2);
 }
 
-// Reconstruction along the face normal from the cell averages Wc[0..3] (cells i-1, i,
-// i+1, i+2 around face i+1/2; with RK = 2 also Wc[-1] and Wc[4], cells i-2 and i+3),
+// Reconstruction along the face normal from the cell averages w(0..3, m) (cells i-1, i,
+// i+1, i+2 around face i+1/2; with RK = 2 also w(-1, m) and w(4, m), cells i-2 and i+3),
 // conservative variables, one-sided differences on centre-to-centre distances.  The
 // gradients are their minmod; the face values come from those gradients (RK = 0, second
 // order), from the third-order slopes above (RK = 1) or are the WENO5 values (RK = 2).
-template <int D, typename H, int RK = 0>
-GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const FaceGeo<H>& geo, FaceIn<D, H>& in)
+// `w(o, m)` reads component m of stencil cell o (a private array or the tile's LDS); the
+// components are reconstructed one at a time, and with the wider stencils the device code
+// keeps them apart, so that only one component's stencil is held at once.
+template <int D, typename H, int RK = 0, typename SW>
+GKS_HD inline void reconstruct_s(const SW& w, const FaceGeo<H>& geo, FaceIn<D, H>& in)
 {
+#pragma unroll
     for (int m = 0; m < D + 2; ++m) {
-        const H d0 = (Wc[1][m] - Wc[0][m]) * geo.icd[0];
-        const H d1 = (Wc[2][m] - Wc[1][m]) * geo.icd[1];
-        const H d2 = (Wc[3][m] - Wc[2][m]) * geo.icd[2];
+        const H c0 = w(0, m), c1 = w(1, m), c2 = w(2, m), c3 = w(3, m);
+        const H d0 = (c1 - c0) * geo.icd[0];
+        const H d1 = (c2 - c1) * geo.icd[1];
+        const H d2 = (c3 - c2) * geo.icd[2];
         const H sl = minmod(d0, d1), sr = minmod(d1, d2);
         in.sl[m] = sl;
         in.sr[m] = sr;
         if constexpr (RK == 2) {
-            in.Wl[m] = weno5(Wc[-1][m], Wc[0][m], Wc[1][m], Wc[2][m], Wc[3][m]);
-            in.Wr[m] = weno5(Wc[4][m], Wc[3][m], Wc[2][m], Wc[1][m], Wc[0][m]);
+            const H cm = w(-1, m), c4 = w(4, m);
+            in.Wl[m] = weno5(cm, c0, c1, c2, c3);
+            in.Wr[m] = weno5(c4, c3, c2, c1, c0);
         } else if constexpr (RK == 1) {
-            in.Wl[m] = Wc[1][m] + muscl3(d0, d1) * geo.dl;
-            in.Wr[m] = Wc[2][m] - muscl3(d2, d1) * geo.dr;
+            in.Wl[m] = c1 + muscl3(d0, d1) * geo.dl;
+            in.Wr[m] = c2 - muscl3(d2, d1) * geo.dr;
         } else {
-            in.Wl[m] = Wc[1][m] + sl * geo.dl;
-            in.Wr[m] = Wc[2][m] - sr * geo.dr;
+            in.Wl[m] = c1 + sl * geo.dl;
+            in.Wr[m] = c2 - sr * geo.dr;
         }
-        in.Wi[m] = Wc[1][m];
-        in.Wi1[m] = Wc[2][m];
+        in.Wi[m] = c1;
+        in.Wi1[m] = c2;
+#ifdef __HIP_DEVICE_COMPILE__
+        if constexpr (RK != 0) __builtin_amdgcn_sched_barrier(0);
+#endif
     }
     in.idl = geo.idl;
     in.idr = geo.idr;
+}
+
+template <int D, typename H, int RK = 0>
+GKS_HD inline void reconstruct(const H (*Wc)[D + 2], const FaceGeo<H>& geo, FaceIn<D, H>& in)
+{
+    reconstruct_s<D, H, RK>([Wc](int o, int m) { return Wc[o][m]; }, geo, in);
 }
 
 // Primitive recovery in the wide type: rho, 1/rho, U, p.  Returns false for rho <= 0 or

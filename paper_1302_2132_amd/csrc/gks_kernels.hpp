@@ -122,12 +122,13 @@ __device__ inline int cell_index(cref<Inst> I, int i, int j, int k)
 // coordinates are interior).  Ghosts take the boundary condition of axis d: an interior
 // image (periodic, wall with the momentum negated, outflow), the fixed state, or the
 // fixed profile at the cell's position in the boundary plane.  Source, stride and element
-// are selected per lane, then every component is loaded unconditionally.
-template <int D>
+// are selected per lane, then every component is loaded unconditionally (the first NL
+// components: all of them, or density and momenta where only velocities are needed).
+template <int D, int NL = D + 2>
 __device__ inline __attribute__((always_inline)) void load_state(cref<Inst> I, const double* __restrict__ W, int d,
                                                                  const int* c, double* w)
 {
-    constexpr int NV = D + 2;
+    constexpr int NV = NL;
     const int n = I.n[d];
     const int id = c[d];
     const bool hi = id >= n;
@@ -229,8 +230,8 @@ __device__ inline void strain_cell(cref<Inst> I, int cell)
         int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
         cp[b] += 1;
         cm[b] -= 1;
-        load_state<D>(I, W, b, cp, wp);
-        load_state<D>(I, W, b, cm, wm);
+        load_state<D, D + 1>(I, W, b, cp, wp);      // density and momenta
+        load_state<D, D + 1>(I, W, b, cm, wm);
         const double ip = 1.0 / wp[0], im = 1.0 / wm[0], ih = I.ic2[b][c[b]];
         for (int a = 0; a < D; ++a) g[a][b] = (wp[1 + a] * ip - wm[1 + a] * im) * ih;
     }
@@ -358,11 +359,11 @@ template <int V> constexpr int halo_of() { return (V & V_W5) ? 3 : 2; }
 
 // tg_l, tg_r: with FLUX_MULTID, the tangential gradients of the two cells, [(D-1) x (D+2)]
 // in the global component order, tangential axes in increasing order.
-template <typename R, int D, int DIR, int MODE, int RK, typename P>
-__device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int i, const double (*Wc)[D + 2],
-                                                               P kk, P ww, P ss, int il, int ir, double dt, double* Fg,
-                                                               const double* tg_l = nullptr,
-                                                               const double* tg_r = nullptr)
+template <typename R, int D, int DIR, int MODE, int RK, typename P, typename SW>
+__device__ __attribute__((always_inline)) inline int face_eval_s(cref<Inst> I, int i, const SW& Wc, P kk, P ww, P ss,
+                                                                 int il, int ir, double dt, double* Fg,
+                                                                 const double* tg_l = nullptr,
+                                                                 const double* tg_r = nullptr)
 {
     constexpr int NV = D + 2;
     FaceGeo<double> geo;
@@ -378,7 +379,7 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
         geo.idr = fg[3];
     }
     FaceIn<D, double> in;
-    reconstruct<D, double, RK>(Wc, geo, in);
+    reconstruct_s<D, double, RK>(Wc, geo, in);
 
     // face-local frame: normal momentum first, then the remaining axes in order
     constexpr int P1 = DIR == 0 ? 1 : 0;             // first tangential axis
@@ -420,6 +421,17 @@ __device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int
         Fg[D + 3] = F[(MODE & FLUX_EPS_OUT) ? D + 3 : 0];
     }
     return bad;
+}
+
+// The same with the stencil in a private array: Wc[o][m], o from -1 (WENO5) to 4.
+template <typename R, int D, int DIR, int MODE, int RK, typename P>
+__device__ __attribute__((always_inline)) inline int face_eval(cref<Inst> I, int i, const double (*Wc)[D + 2],
+                                                               P kk, P ww, P ss, int il, int ir, double dt, double* Fg,
+                                                               const double* tg_l = nullptr,
+                                                               const double* tg_r = nullptr)
+{
+    return face_eval_s<R, D, DIR, MODE, RK>(I, i, [Wc](int o, int m) { return Wc[o][m]; }, kk, ww, ss, il, ir, dt,
+                                            Fg, tg_l, tg_r);
 }
 
 // One face normal to axis DIR, stencil read from the state in HBM, flux written to the
@@ -854,9 +866,19 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     }
                 }
                 double F[NV];
-                if (face_eval<R, 2, 0, FMODE, RK>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F,
-                                                  tg[0], tg[1]))
-                    atomicOr(&I.st->err, 1);
+                int bad;
+                if constexpr (RK == 0) {
+                    bad = face_eval<R, 2, 0, FMODE, RK>(I, x0 + i, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1,
+                                                        dt, F, tg[0], tg[1]);
+                } else {
+                    // the wider stencils are read from LDS one component at a time
+                    (void)Wc;
+                    const int e0 = (j + HW) * WX + i + HW - 2;
+                    bad = face_eval_s<R, 2, 0, FMODE, RK>(I, x0 + i, [&](int o, int m) { return sW[m][e0 + o]; },
+                                                          &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F, tg[0],
+                                                          tg[1]);
+                }
+                if (bad) atomicOr(&I.st->err, 1);
                 sFx[0][tid] = F[0];
                 sFx[1][tid] = F[1];
                 sFx[2][tid] = F[2];
@@ -893,9 +915,18 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     }
                 }
                 double F[NV];
-                if (face_eval<R, 2, 1, FMODE, RK>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt,
-                                                  F, tg[0], tg[1]))
-                    atomicOr(&I.st->err, 1);
+                int bad;
+                if constexpr (RK == 0) {
+                    bad = face_eval<R, 2, 1, FMODE, RK>(I, y0 + j, Wc, &sK[0][0], &sK[1][0], &sK[2][0], kl,
+                                                        kl + T2_KX, dt, F, tg[0], tg[1]);
+                } else {
+                    (void)Wc;
+                    const int e0 = (j + HW - 2) * WX + i + HW;
+                    bad = face_eval_s<R, 2, 1, FMODE, RK>(I, y0 + j, [&](int o, int m) { return sW[m][e0 + o * WX]; },
+                                                          &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt, F,
+                                                          tg[0], tg[1]);
+                }
+                if (bad) atomicOr(&I.st->err, 1);
                 sFy[0][tid] = F[0];
                 sFy[1][tid] = F[1];
                 sFy[2][tid] = F[2];
