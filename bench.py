@@ -85,7 +85,7 @@ def _leg(case, steps, warmup, eps_field=False):
 
 KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_lib.hip", "gks_inst.hip", "erfc_poly.hpp")
 TRAFFIC_SUMMARIES = (os.path.join(ROOT, "profiles", "k_tile2_sbli_1024x512_hbm_traffic.md"),
-                     os.path.join(ROOT, "profiles", "k_face_isotropic_256_trace_and_traffic.md"))
+                     os.path.join(ROOT, "profiles", "k_tile3_isotropic_256_trace_and_traffic.md"))
 
 
 def _profiled_traffic(kernel):
