@@ -191,3 +191,13 @@ def test_failed_init_frees_its_context():
     assert r.returncode == 0, r.stderr[-2000:]
     growth = float(r.stdout.split()[-1])
     assert growth < 5.0, growth          # 20000 leaked contexts would be ~30 MB
+
+
+def test_entry_points_carry_marker_ranges():
+    """The stepping, set-up and read-back entry points push named roctx ranges (shown by a
+    profiler's marker trace, profiles/gks_step_marker_trace_sbli_1024x512.md): the library
+    imports the range calls."""
+    import subprocess
+    from paper_1302_2132_amd.gks import lib_path
+    syms = subprocess.run(["nm", "-D", lib_path], capture_output=True, text=True, check=True).stdout
+    assert "roctxRangePushA" in syms and "roctxRangePop" in syms
