@@ -216,6 +216,37 @@ __device__ inline double tgrad(double wm, double w0, double wp, double icm, doub
 // --------------------------------------------------------------------------------------
 // strain rate
 // --------------------------------------------------------------------------------------
+// Velocity of a conservative state: u_a = (rho u_a) * (1/rho), the reciprocal rounded once.
+// Every strain evaluation forms its neighbours' velocities this way, so that the per-cell
+// pass and the z-marching 3D pass give the same strain rate bitwise.
+template <int D>
+__device__ inline void velocity_of(const double* w, double* u)
+{
+    const double ir = 1.0 / w[0];
+    for (int a = 0; a < D; ++a) u[a] = w[1 + a] * ir;
+}
+
+// Strain-rate magnitude sqrt(2 S_ab S_ab) from the velocities of a cell's lower and upper
+// neighbours along each axis b (um[b], up[b]) and ih[b] = 1/(xc[i+1] - xc[i-1]): central
+// differences du_a/dx_b = (up[b][a] - um[b][a]) ih[b].
+// Contraction into multiply-adds is off here, so that the two passes, compiled in
+// different contexts, round every operation alike.
+template <int D>
+__device__ inline double strain_of(const double (*um)[D], const double (*up)[D], const double* ih)
+{
+#pragma clang fp contract(off)
+    double g[3][3];
+    for (int b = 0; b < D; ++b)
+        for (int a = 0; a < D; ++a) g[a][b] = (up[b][a] - um[b][a]) * ih[b];
+    double ss = 0.0;
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+            const double s = 0.5 * (g[a][b] + g[b][a]);
+            ss += s * s;
+        }
+    return sqrt(2.0 * ss);
+}
+
 template <int D>
 __device__ inline void strain_cell(cref<Inst> I, int cell)
 {
@@ -224,7 +255,7 @@ __device__ inline void strain_cell(cref<Inst> I, int cell)
     c[0] = cell % I.n[0];
     c[1] = (cell / I.n[0]) % I.n[1];
     c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
-    double g[3][3];
+    double um[D][D], up[D][D], ih[D];
     for (int b = 0; b < D; ++b) {
         double wp[D + 2], wm[D + 2];
         int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
@@ -232,16 +263,11 @@ __device__ inline void strain_cell(cref<Inst> I, int cell)
         cm[b] -= 1;
         load_state<D, D + 1>(I, W, b, cp, wp);      // density and momenta
         load_state<D, D + 1>(I, W, b, cm, wm);
-        const double ip = 1.0 / wp[0], im = 1.0 / wm[0], ih = I.ic2[b][c[b]];
-        for (int a = 0; a < D; ++a) g[a][b] = (wp[1 + a] * ip - wm[1 + a] * im) * ih;
+        velocity_of<D>(wp, up[b]);
+        velocity_of<D>(wm, um[b]);
+        ih[b] = I.ic2[b][c[b]];
     }
-    double ss = 0.0;
-    for (int a = 0; a < D; ++a)
-        for (int b = 0; b < D; ++b) {
-            const double s = 0.5 * (g[a][b] + g[b][a]);
-            ss += s * s;
-        }
-    I.S[cell] = sqrt(2.0 * ss);
+    I.S[cell] = strain_of<D>(um, up, ih);
 }
 
 // --------------------------------------------------------------------------------------
@@ -1576,6 +1602,111 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
         }
     }
 }
+
+// Strain pass of a single 3D solve with frozen k and omega, marching along z: a workgroup
+// owns a 64 x 4 column of cells (a wave per row, so that every load is a contiguous row
+// segment) over a run of `seg` planes (`nseg` runs per column).  Each
+// thread keeps the velocities of its own column on planes k-1, k, k+1 in registers; the
+// velocities of plane k on the column and its one-cell x/y ring (ghost-filled along the
+// ring's axis) go through LDS for the x and y differences.  Every cell's state is read
+// about 1.3 times (the ring, and two extra planes per run) instead of once per neighbour,
+// and the arithmetic is strain_cell's (velocity_of, strain_of): the same strain rate,
+// bitwise.  With `finish` set, work item 0 ends the pending step first, as in k_strain.
+constexpr int S3X = 64, S3Y = 4;
+#ifdef GKS_LIB_UNIT   // defined in the library unit only
+__global__ __launch_bounds__(CELL_TILE) void k_strain3(const void* __restrict__ table, int finish, int seg, int nseg)
+{
+    static_assert(S3X * S3Y == CELL_TILE, "one column per thread");
+    constexpr int RX = S3X + 2, RY = S3Y + 2;
+    const TabC tv(table, 1);
+    cref<Inst> I = tv.inst[0];
+    __shared__ double sh[6 * 4];
+    __shared__ double sV[3][RX * RY];      // velocities of plane k: column and one-cell ring
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    const int ntx = (n0 + S3X - 1) / S3X, nty = (n1 + S3Y - 1) / S3Y;
+    const int head = finish ? 1 : 0;
+    const int total = head + ntx * nty * nseg;
+    for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
+        const int item = tw.first;
+        if (item < head) {
+            finish_member(I, 0, sh);
+            continue;
+        }
+        if (!state_of(I).active) continue;
+        const double* __restrict__ W = I.W[state_of(I).fresh];
+        const int lt = item - head, col = lt % (ntx * nty), run = lt / (ntx * nty);
+        const int x0 = (col % ntx) * S3X, y0 = (col / ntx) * S3Y;
+        const int tx = min(S3X, n0 - x0), ty = min(S3Y, n1 - y0);
+        const int z0 = run * seg, z1 = min(n2, z0 + seg);
+        const int t = (int)threadIdx.x, i = t % S3X, j = t / S3X;
+        const bool own = i < tx && j < ty;
+        const int ci = own ? i : 0, cj = own ? j : 0;
+        // the ring cell this thread stages (threads 0 .. 2 (tx + ty) - 1): left, right, bottom, top
+        const int nr = 2 * (tx + ty);
+        int ra = -1, rb = -1, rd = 0;
+        if (t < nr) {
+            if (t < ty) { ra = -1; rb = t; rd = 0; }
+            else if (t < 2 * ty) { ra = tx; rb = t - ty; rd = 0; }
+            else if (t < 2 * ty + tx) { ra = t - 2 * ty; rb = -1; rd = 1; }
+            else { ra = t - 2 * ty - tx; rb = ty; rd = 1; }
+        }
+        auto column = [&](int z, double* u) {      // velocity of this thread's column at plane z
+            const int c[3] = {x0 + ci, y0 + cj, z};
+            double w[4];
+            load_state<3, 4>(I, W, 2, c, w);
+            velocity_of<3>(w, u);
+        };
+        double um[3], uc[3], up[3];
+        column(z0 - 1, um);
+        column(z0, uc);
+        for (int k = z0; k < z1; ++k) {
+            column(k + 1, up);
+            if (t < nr) {
+                const int c[3] = {x0 + ra, y0 + rb, k};
+                double w[4], u[3];
+                load_state<3, 4>(I, W, rd, c, w);
+                velocity_of<3>(w, u);
+                const int e = (rb + 1) * RX + ra + 1;
+                sV[0][e] = u[0];
+                sV[1][e] = u[1];
+                sV[2][e] = u[2];
+            }
+            {
+                const int e = (cj + 1) * RX + ci + 1;
+                if (own) {
+                    sV[0][e] = uc[0];
+                    sV[1][e] = uc[1];
+                    sV[2][e] = uc[2];
+                }
+            }
+            __syncthreads();
+            if (own) {
+                const int e = (cj + 1) * RX + ci + 1;
+                double vm[3][3], vp[3][3], ih[3];
+                for (int a = 0; a < 3; ++a) {
+                    vm[0][a] = sV[a][e - 1];
+                    vp[0][a] = sV[a][e + 1];
+                    vm[1][a] = sV[a][e - RX];
+                    vp[1][a] = sV[a][e + RX];
+                    vm[2][a] = um[a];
+                    vp[2][a] = up[a];
+                }
+                ih[0] = I.ic2[0][x0 + ci];
+                ih[1] = I.ic2[1][y0 + cj];
+                ih[2] = I.ic2[2][k];
+                I.S[(long long)(k * n1 + y0 + cj) * n0 + x0 + ci] = strain_of<3>(vm, vp, ih);
+            }
+            __syncthreads();
+            for (int a = 0; a < 3; ++a) {
+                um[a] = uc[a];
+                uc[a] = up[a];
+            }
+        }
+    }
+}
+#else
+extern __global__ void k_strain3(const void* __restrict__ table, int finish, int seg, int nseg);
+#endif
 
 // Degree of rarefaction eps_hat = tau/tau_hat of the faces of each cell at the current
 // state and step (the strain rate, k and omega of that state already in place), largest

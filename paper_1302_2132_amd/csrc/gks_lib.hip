@@ -658,6 +658,9 @@ static gks_status next_event(gks_ctx* h, hipEvent_t* ev)
 // A 3D step is three launches (strain with the previous step's end folded in, face,
 // update); a 2D step two (strain, fused tile kernel).  One trailing k_finish ends the last
 // step so the state is complete when the call's work has run.
+#ifndef GKS_STRAIN3_ITEMS
+#define GKS_STRAIN3_ITEMS 8192     // work items of the z-marching strain pass (columns x runs)
+#endif
 static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
 {
     hipStream_t s = h->stream;
@@ -669,10 +672,23 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
     void (*ks)(const void*, int, int, int) = kw ? k_strain<true> : k_strain<false>;
     void (*ku)(const void*, int) = kw ? k_update<true> : k_update<false>;
     const int grid_head = round8(h->inst.ntile_cell + 1);
+    // a 3D solve with frozen k and omega takes the z-marching strain pass (runs of planes
+    // over 64 x 4 columns, about 8192 work items), the others the per-cell one
+    const bool strain3 = h->cfg.dim == 3 && !kw;
+    int seg3s = 1, nseg3s = 1, grid3s = 8;
+    if (strain3) {
+        const int n0 = h->inst.n[0], n1 = h->inst.n[1], n2 = h->inst.n[2];
+        const int cols = ((n0 + S3X - 1) / S3X) * ((n1 + S3Y - 1) / S3Y);
+        nseg3s = std::max(1, std::min(std::max(1, n2 / 4), (GKS_STRAIN3_ITEMS + cols - 1) / cols));
+        seg3s = (n2 + nseg3s - 1) / nseg3s;
+        nseg3s = (n2 + seg3s - 1) / seg3s;
+        grid3s = round8(1 + cols * nseg3s);
+    }
     if (nsteps == 0) return GKS_OK;
     if (!h->timing) {
         for (int i = 0; i < nsteps; ++i) {
-            hipLaunchKernelGGL(ks, dim3(grid_head), dim3(CELL_TILE), 0, s, tab, 1, 0, 1);
+            if (strain3) hipLaunchKernelGGL(k_strain3, dim3(grid3s), dim3(CELL_TILE), 0, s, tab, 1, seg3s, nseg3s);
+            else hipLaunchKernelGGL(ks, dim3(grid_head), dim3(CELL_TILE), 0, s, tab, 1, 0, 1);
             hipLaunchKernelGGL(fk, dim3(h->grid_face), fblock, 0, s, tab, 1, h->cls);
             if (upd) hipLaunchKernelGGL(ku, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
         }
@@ -685,7 +701,11 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
                 gks_status r = next_event(h, &ev[q]);
                 if (r != GKS_OK) return r;
             }
-            hipExtLaunchKernelGGL(ks, dim3(grid_head), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, 0, 1);
+            if (strain3)
+                hipExtLaunchKernelGGL(k_strain3, dim3(grid3s), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, seg3s,
+                                      nseg3s);
+            else
+                hipExtLaunchKernelGGL(ks, dim3(grid_head), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, 0, 1);
             hipExtLaunchKernelGGL(fk, dim3(h->grid_face), fblock, 0, s, ev[2], ev[3], 0, tab, 1, h->cls);
             h->timed_kind.insert(h->timed_kind.end(), {0, 1});
             if (upd) {
