@@ -289,11 +289,23 @@ def _cpu_baseline(case, target_s=15.0):
         s.close()
         check[f"{prec}_max_rel_err_vs_oracle_per_field"] = [
             float(np.max(np.abs(W[m] - r["W"][m])) / np.max(np.abs(r["W"][m]))) for m in range(case.nvar)]
+    # the oracle's own operation count of one face flux (its counting build), beside the
+    # kernel's count of its closed form that the rooflines use
+    from paper_1302_2132_amd import gks_face_flops
+    ops = {}
+    for dim in (2, 3):
+        nv = dim + 2
+        st = np.array([1.0, 0.3, -0.1, 0.05, 2.3][:nv - 1] + [2.3])
+        sl = np.linspace(0.5, -0.5, nv)
+        cnt, _ = oracle.face_op_counts(dim, st, st * 1.01, sl, -sl, st, st * 1.02, 0.005, 0.005, 1e-3, 10.0, 5.0,
+                                       3e-3, mu=1e-3, c_a=0.1)
+        ops[f"{dim}d"] = {"oracle_ops_per_face": cnt, "oracle_total": sum(cnt.values()),
+                          "kernel_flops_per_face": gks_face_flops(dim)}
     return {"value": case.ncells * steps / total, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} FP64 steps of the full {case.n[0]}x{case.n[1]} workload "
                       f"({total:.1f} s, OpenMP over faces/cells)",
-            "gpu_vs_oracle": check}
+            "gpu_vs_oracle": check, "face_operation_counts": ops}
 
 
 def main():

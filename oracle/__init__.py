@@ -277,6 +277,62 @@ def face_flux(dim, Wl, Wr, sl, sr, Wi, Wi1, dxl, dxr, kf, wf, Sf, dt,
     return {"F": F, "G": G, "q": float(q[0]), "info": d}
 
 
+OPCOUNT_SRC = os.path.join(HERE, "opcount.cpp")
+OPCOUNT_LIB = os.path.join(HERE, "libgks_oracle_opcount.so")
+OP_KINDS = ("add", "mul", "div", "sqrt", "exp", "erfc")
+_oplib = None
+
+
+def build_opcount(force: bool = True) -> str:
+    """Compile the operation-counting build of the oracle (opcount.cpp: the oracle's source
+    with its scalar type replaced by a counting one)."""
+    if force or not os.path.exists(OPCOUNT_LIB):
+        cmd = ["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+               "-I", HERE, "-o", OPCOUNT_LIB + ".tmp", OPCOUNT_SRC]
+        subprocess.check_call(cmd)
+        os.replace(OPCOUNT_LIB + ".tmp", OPCOUNT_LIB)
+    return OPCOUNT_LIB
+
+
+def _opcount_lib():
+    global _oplib
+    if _oplib is None:
+        stale = (not os.path.exists(OPCOUNT_LIB) or os.path.getmtime(OPCOUNT_LIB) < os.path.getmtime(SRC)
+                 or os.path.getmtime(OPCOUNT_LIB) < os.path.getmtime(OPCOUNT_SRC))
+        if stale:
+            build_opcount()
+        L = C.CDLL(OPCOUNT_LIB)
+        dp = C.POINTER(C.c_double)
+        L.og_face_flux.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_double,
+                                   C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.og_face_flux.restype = C.c_int
+        L.og_ops_reset.argtypes = []
+        L.og_ops_get.argtypes = [C.POINTER(C.c_ulonglong)]
+        _oplib = L
+    return _oplib
+
+
+def face_op_counts(dim, Wl, Wr, sl, sr, Wi, Wi1, dxl, dxr, kf, wf, Sf, dt, gamma=1.4, prandtl=0.72, mu=1e-3,
+                   c_a=0.0, c_mu=0.09, eps_mode="dt"):
+    """The oracle's operations for one face flux (the arguments of face_flux), by kind
+    (OP_KINDS), from the counting build; also returns that build's flux."""
+    L = _opcount_lib()
+    nv = dim + 2
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (Wl, Wr, sl, sr)]
+    wis = [np.ascontiguousarray(x, dtype=np.float64) for x in (Wi, Wi1)]
+    params = np.array([gamma, prandtl, mu, c_a, c_mu, EPS_MODE[eps_mode]], dtype=np.float64)
+    F, G, q, info = np.zeros(nv), np.zeros(nv), np.zeros(1), np.zeros(INFO_LEN)
+    L.og_ops_reset()
+    st = L.og_face_flux(dim, _dp(params), *[_dp(a) for a in arrs], None, None, *[_dp(a) for a in wis],
+                        float(dxl), float(dxr), float(kf), float(wf), float(Sf), float(dt),
+                        _dp(F), _dp(G), _dp(q), _dp(info))
+    if st:
+        raise OracleError(st)
+    out = (C.c_ulonglong * len(OP_KINDS))()
+    L.og_ops_get(out)
+    return dict(zip(OP_KINDS, [int(v) for v in out])), F
+
+
 def moments_u(U, lam):
     out = np.zeros(3 * NU)
     lib().og_moments_u(float(U), float(lam), _dp(out))
