@@ -835,40 +835,63 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
         const double* __restrict__ W = I.W[cur];
         const double dt = state_of(I).dt;
 
-        // stage the state window: tile rows with the x halo, tile columns with the y halo
-        // (with the multi-dimensional expansion also the four diagonal neighbours of the
-        // tile's corner cells, for the tangential gradients of the edge faces' cells)
-        for (int e = tid; e < WX * WY; e += T2_THREADS) {
+        // Stage the state window (tile rows with the x halo, tile columns with the y halo;
+        // with the multi-dimensional expansion also the four diagonal neighbours of the
+        // tile's corner cells, for the tangential gradients of the edge faces' cells) and
+        // k, omega and strain rate on the one-cell halo.  Every load of the tile is issued
+        // before the first LDS store, so that the tile waits on one round trip to memory
+        // rather than one per pass of each loop; a thread with no cell in a pass loads the
+        // tile's first cell and stores nothing.
+        constexpr int NWI = (WX * WY + T2_THREADS - 1) / T2_THREADS;
+        constexpr int NKI = (T2_KX * T2_KY + T2_THREADS - 1) / T2_THREADS;
+        constexpr int NKC = KW ? 4 : 3;
+        double ws[NWI][NV], ks[NKI][NKC];
+        bool wu[NWI], ku[NKI];
+#pragma unroll
+        for (int it = 0; it < NWI; ++it) {
+            const int e = tid + it * T2_THREADS;
             const int a = e % WX, b = e / WX;
             const bool row = b >= HW && b < ty + HW && a < tx + 2 * HW;
             const bool col = a >= HW && a < tx + HW && b < ty + 2 * HW;
             const bool corner = MD && (a == HW - 1 || a == tx + HW) && (b == HW - 1 || b == ty + HW);
-            if (!(row || col || corner)) continue;
-            const int c[3] = {x0 - HW + a, y0 - HW + b, 0};
-            double w[NV];
-            if (corner) {
-                load_state_c<2>(I, W, c, w);
+            wu[it] = e < WX * WY && (row || col || corner);
+            const int c[3] = {wu[it] ? x0 - HW + a : x0, wu[it] ? y0 - HW + b : y0, 0};
+            if (MD && wu[it] && corner) {
+                load_state_c<2>(I, W, c, ws[it]);
             } else {
                 const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;     // the ghost axis, if any
-                load_state<2>(I, W, d, c, w);
+                load_state<2>(I, W, d, c, ws[it]);
             }
-#pragma unroll
-            for (int m = 0; m < NV; ++m) sW[m][e] = w[m];
         }
-        // stage k, omega and strain rate on the one-cell halo
-        for (int e = tid; e < T2_KX * T2_KY; e += T2_THREADS) {
+#pragma unroll
+        for (int it = 0; it < NKI; ++it) {
+            const int e = tid + it * T2_THREADS;
             const int a = e % T2_KX, b = e / T2_KX;
             const bool row = b >= 1 && b < ty + 1 && a < tx + 2;
             const bool col = a >= 1 && a < tx + 1 && b < ty + 2;
-            if (!(row || col)) continue;
-            const int c[3] = {x0 - 1 + a, y0 - 1 + b, 0};
+            ku[it] = e < T2_KX * T2_KY && (row || col);
+            const int c[3] = {ku[it] ? x0 - 1 + a : x0, ku[it] ? y0 - 1 + b : y0, 0};
             const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;
             const int ic = image_cell<2>(I, d, c);
-            sK[0][e] = I.k[ic];
-            sK[1][e] = I.om[ic];
-            sK[2][e] = I.S[ic];
-            if (KW) sK[KW ? 3 : 0][e] = I.nt[ic];
+            ks[it][0] = I.k[ic];
+            ks[it][1] = I.om[ic];
+            ks[it][2] = I.S[ic];
+            if (KW) ks[it][NKC - 1] = I.nt[ic];
         }
+#pragma unroll
+        for (int it = 0; it < NWI; ++it)
+            if (wu[it]) {
+                const int e = tid + it * T2_THREADS;
+#pragma unroll
+                for (int m = 0; m < NV; ++m) sW[m][e] = ws[it][m];
+            }
+#pragma unroll
+        for (int it = 0; it < NKI; ++it)
+            if (ku[it]) {
+                const int e = tid + it * T2_THREADS;
+#pragma unroll
+                for (int q = 0; q < NKC; ++q) sK[q][e] = ks[it][q];
+            }
         __syncthreads();
 
         {   // x-face (i, j): between cells x0+i-1 and x0+i of row y0+j
@@ -1084,37 +1107,69 @@ __device__ inline void t3_stage_plane(cref<Inst> I, const Tile3& g, Tile3Lds& L,
     for (int m = 0; m < 5; ++m) L.R[s][m][t] = w[m];
 }
 
-// Stage the x- and y-halo arms and k, omega, S of plane k.
-__device__ inline void t3_stage_halo(cref<Inst> I, const Tile3& g, Tile3Lds& L, int t, int k)
+// Stage plane k+2 into the slot of plane k-2 and, on a full plane, the x- and y-halo arms
+// and k, omega, S of plane k (one-cell halo).  Every load is issued before the first LDS
+// store, so that a plane waits on one round trip to memory rather than one per array; a
+// thread with nothing to stage in a part loads an interior cell of the tile and stores
+// nothing.
+__device__ inline void t3_stage(cref<Inst> I, const Tile3& g, Tile3Lds& L, int t, int k, bool full)
 {
     const double* __restrict__ W = I.W[state_of(I).parity];
-    if (t < 4 * (T3Y + T3X)) {
+    constexpr int NKI = (T3_KX * T3_KY + T2_THREADS - 1) / T2_THREADS;
+    const bool po = g.owns(t);
+    double wp[5];
+    {
+        const int tt = po ? t : 0;
+        const int c[3] = {g.x0 + tt % T3X, g.y0 + tt / T3X, k + 2};
+        load_state<3>(I, W, 2, c, wp);
+    }
+    if (full) {                 // uniform over the workgroup
         const bool xarm = t < 4 * T3Y;
         const int q = xarm ? t : t - 4 * T3Y;
         const int line = q >> 2, s = q & 3;
-        const int off = s < 2 ? s - 2 : s - 2 + (xarm ? g.tx : g.ty);    // -2, -1, t_, t_+1
-        if (line < (xarm ? g.ty : g.tx)) {
-            const int c[3] = {xarm ? g.x0 + off : g.x0 + line, xarm ? g.y0 + line : g.y0 + off, k};
-            double w[5];
-            load_state<3>(I, W, xarm ? 0 : 1, c, w);
+        const bool au = t < 4 * (T3Y + T3X) && line < (xarm ? g.ty : g.tx);
+        double wa[5], ks[NKI][3];
+        bool ku[NKI];
+        {
+            const int off = s < 2 ? s - 2 : s - 2 + (xarm ? g.tx : g.ty);     // -2, -1, t_, t_+1
+            const int c[3] = {au ? (xarm ? g.x0 + off : g.x0 + line) : g.x0,
+                              au ? (xarm ? g.y0 + line : g.y0 + off) : g.y0, k};
+            load_state<3>(I, W, xarm ? 0 : 1, c, wa);
+        }
+#pragma unroll
+        for (int it = 0; it < NKI; ++it) {
+            const int e = t + it * T2_THREADS;
+            const int a = e % T3_KX, b = e / T3_KX;
+            const bool row = b >= 1 && b < g.ty + 1 && a < g.tx + 2;
+            const bool colm = a >= 1 && a < g.tx + 1 && b < g.ty + 2;
+            ku[it] = e < T3_KX * T3_KY && (row || colm);
+            const int c[3] = {ku[it] ? g.x0 - 1 + a : g.x0, ku[it] ? g.y0 - 1 + b : g.y0, k};
+            const int d = (c[0] < 0 || c[0] >= I.n[0]) ? 0 : 1;
+            const int ic = image_cell<3>(I, d, c);
+            ks[it][0] = I.k[ic];
+            ks[it][1] = I.om[ic];
+            ks[it][2] = I.S[ic];
+        }
+        if (au) {
 #pragma unroll
             for (int m = 0; m < 5; ++m) {
-                if (xarm) L.XA[m][q] = w[m];
-                else L.YA[m][q] = w[m];
+                if (xarm) L.XA[m][q] = wa[m];
+                else L.YA[m][q] = wa[m];
             }
         }
+#pragma unroll
+        for (int it = 0; it < NKI; ++it)
+            if (ku[it]) {
+                const int e = t + it * T2_THREADS;
+                L.K[0][e] = ks[it][0];
+                L.K[1][e] = ks[it][1];
+                L.K[2][e] = ks[it][2];
+            }
     }
-    for (int e = t; e < T3_KX * T3_KY; e += T2_THREADS) {
-        const int a = e % T3_KX, b = e / T3_KX;
-        const bool row = b >= 1 && b < g.ty + 1 && a < g.tx + 2;
-        const bool colm = a >= 1 && a < g.tx + 1 && b < g.ty + 2;
-        if (!(row || colm)) continue;
-        const int c[3] = {g.x0 - 1 + a, g.y0 - 1 + b, k};
-        const int d = (c[0] < 0 || c[0] >= I.n[0]) ? 0 : 1;
-        const int ic = image_cell<3>(I, d, c);
-        L.K[0][e] = I.k[ic];
-        L.K[1][e] = I.om[ic];
-        L.K[2][e] = I.S[ic];
+    if (po) {
+        const int s = (k + 2 + 4) & 3;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) L.R[s][m][t] = wp[m];
     }
 }
 
@@ -1213,8 +1268,7 @@ void k_tile3(const void* __restrict__ table, int cap, int cls)
             const bool full = k >= g.z0;
 
             // plane k+2 into the slot of plane k-2; halo arms and k, omega, S of plane k
-            t3_stage_plane(I, g, L, t, k + 2);
-            if (full) t3_stage_halo(I, g, L, t, k);
+            t3_stage(I, g, L, t, k, full);
             __syncthreads();
 
             const int sk = (k + 4) & 3;

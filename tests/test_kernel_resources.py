@@ -7,7 +7,10 @@ registers) at four for the plain scheme and three for its variants (the transpor
 are held to three by their LDS).  The 3D face kernel runs at two waves (FP64) and three
 (FP32), the FP32 third-order, WENO5 and multi-dimensional forms at two.  Exceptions with a
 bounded spill of a few doubles per face: the third-order and WENO5 2D FP64 tiles at three
-waves (two would cost more), and the multi-dimensional 3D FP64 kernel at two; the
+waves (two would cost more), the multi-dimensional 3D FP64 kernel at two, and the plain
+FP32-flux 2D tile at four, which holds the tile's staging loads in registers (all issued
+before the first LDS store) and reloads one dword per face pass (measured faster than the
+spill-free form, whose staging waited on memory once per loop pass); the
 multi-dimensional expansion, with its tangential gradients, runs one wave lower in 2D.  A
 spill means the flux path stopped being inlined or grew (or values derived from the thread
 index were kept live across the tile loop), and costs scratch traffic to HBM on every
@@ -69,7 +72,7 @@ def test_fused_2d_kernels_occupancy(remarks):
         assert v["ScratchSize"] <= (40 if _variant(k) & 4 else (96 if _variant(k) & 16 else 0)), (k, v)
         assert v["Occupancy"] >= (2 if md else 3), (k, v)
     for k, v in k32.items():
-        assert v["ScratchSize"] == 0, (k, v)
+        assert v["ScratchSize"] <= (8 if _variant(k) == 0 else 0), (k, v)
         want = 4 if _variant(k) == 0 else (2 if _variant(k) & 8 else 3)
         assert v["Occupancy"] >= want, (k, v)
 
