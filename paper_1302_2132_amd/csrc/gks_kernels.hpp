@@ -817,6 +817,10 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
     cptr<int> member = tv.cls_member + cls * cap;
     for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
         const int tile = tw.first;
+        // A tile's prologue and staging run at a raised wave priority, so that a workgroup
+        // that has just started issues its loads ahead of the flux arithmetic of the other
+        // workgroups on its compute unit; the flux passes run at the normal priority.
+        __builtin_amdgcn_s_setprio(2);
         // The thread index is made opaque per tile so that the LDS offsets derived from it
         // are recomputed (a few integer operations) rather than kept live across the tile
         // loop, where they would take registers from the flux evaluation.
@@ -893,6 +897,7 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                 for (int q = 0; q < NKC; ++q) sK[q][e] = ks[it][q];
             }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
 
         {   // x-face (i, j): between cells x0+i-1 and x0+i of row y0+j
             const int i = tid % (T2X + 1), j = tid / (T2X + 1);
@@ -1268,8 +1273,10 @@ void k_tile3(const void* __restrict__ table, int cap, int cls)
             const bool full = k >= g.z0;
 
             // plane k+2 into the slot of plane k-2; halo arms and k, omega, S of plane k
+            __builtin_amdgcn_s_setprio(2);         // staging ahead of the other workgroup's flux
             t3_stage(I, g, L, t, k, full);
             __syncthreads();
+            __builtin_amdgcn_s_setprio(0);
 
             const int sk = (k + 4) & 3;
             double Fz[NV] = {0, 0, 0, 0, 0};       // z-face above this thread's cell, face-local order
