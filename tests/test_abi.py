@@ -201,3 +201,40 @@ def test_entry_points_carry_marker_ranges():
     from paper_1302_2132_amd.gks import lib_path
     syms = subprocess.run(["nm", "-D", lib_path], capture_output=True, text=True, check=True).stdout
     assert "roctxRangePushA" in syms and "roctxRangePop" in syms
+
+
+def test_mesh_size_limits():
+    """The kernels index cells and faces with 32-bit integers, so the host refuses meshes
+    they cannot address before any device call: more than 2^29 cells, or an axis longer
+    than 2^24 cells; it also refuses an axis of fewer than two cells, and WENO5 on an axis
+    of fewer than three (its three ghost layers).  The largest accepted mesh gets a
+    workspace size (two state buffers, k, omega, strain: 13 doubles a cell in 3D)."""
+    import numpy as np
+
+    import paper_1302_2132_amd as P
+    base = C.isotropic_box(4, precision="fp64")          # periodic on every axis: no boundary data
+
+    def cfg_with(n, recon="muscl2"):
+        b = base.copy()
+        b.recon = recon
+        cfg = P.config_from_case(b)
+        for d in range(3):
+            xf = np.linspace(0.0, 1.0, n[d] + 1)
+            cfg.keep.append(xf)
+            cfg.c.n[d] = n[d]
+            cfg.c.xf[d] = xf.ctypes.data
+        return cfg
+
+    def refused(cfg, why):
+        with pytest.raises(P.GksError) as e:
+            P.gks_workspace_bytes(cfg)
+        assert e.value.status == P.GKS_ERR_ARG and why in str(e.value), str(e.value)
+
+    nb = P.gks_workspace_bytes(cfg_with((1024, 1024, 512)))             # 2^29 cells
+    assert nb >= 8 * 2 ** 29 * 13
+    refused(cfg_with((1024, 1024, 513)), "too many cells")
+    refused(cfg_with(((1 << 24) + 1, 2, 2)), "axis too long")
+    assert P.gks_workspace_bytes(cfg_with((1 << 24, 2, 2))) > 0          # the longest axis
+    refused(cfg_with((8, 1, 8)), "at least 2 cells")
+    refused(cfg_with((8, 2, 8), recon="weno5"), "WENO5 needs at least 3 cells")
+    assert P.gks_workspace_bytes(cfg_with((8, 3, 8), recon="weno5")) > 0
