@@ -87,7 +87,8 @@ def _leg(case, steps, warmup, eps_field=False):
 # the files that define the kernels' code (the host unit gks_lib.hip only instantiates them)
 KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_inst.hip", "erfc_poly.hpp")
 TRAFFIC_SUMMARIES = (os.path.join(ROOT, "profiles", "k_tile2_sbli_1024x512_hbm_traffic.md"),
-                     os.path.join(ROOT, "profiles", "k_tile3_isotropic_256_trace_and_traffic.md"))
+                     os.path.join(ROOT, "profiles", "k_tile3_isotropic_256_trace_and_traffic.md"),
+                     os.path.join(ROOT, "profiles", "k_tile2_mixing_layer_1024_tauhat_trace_and_traffic.md"))
 
 
 def _profiled_traffic(kernel):
