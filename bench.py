@@ -88,7 +88,8 @@ def _leg(case, steps, warmup, eps_field=False):
 KERNEL_SOURCES = ("gks_flux.hpp", "gks_kernels.hpp", "gks_device.hpp", "gks_inst.hip", "erfc_poly.hpp")
 TRAFFIC_SUMMARIES = (os.path.join(ROOT, "profiles", "k_tile2_sbli_1024x512_hbm_traffic.md"),
                      os.path.join(ROOT, "profiles", "k_tile3_isotropic_256_trace_and_traffic.md"),
-                     os.path.join(ROOT, "profiles", "k_tile2_mixing_layer_1024_tauhat_trace_and_traffic.md"))
+                     os.path.join(ROOT, "profiles", "k_tile2_mixing_layer_1024_tauhat_trace_and_traffic.md"),
+                     os.path.join(ROOT, "profiles", "k_face_isotropic_256_options_trace_and_traffic.md"))
 
 
 def _profiled_traffic(kernel):
@@ -147,9 +148,11 @@ def _roofline(case, leg, steps, flops_face, peak):
     return out
 
 
-def _iso_leg(steps=20, warmup=3):
+def _iso_leg(steps=20, warmup=3, options=True):
     """3D periodic isotropic box 256^3 (Ma_t 0.5), FP32-flux (the configuration's form) and
-    FP64, with the FP32-flux error against FP64 after the same steps."""
+    FP64, with the FP32-flux error against FP64 after the same steps; with `options`, also
+    the box with k-omega transport and with WENO5 face values (FP32 flux), which take the
+    face-kernel path."""
     import numpy as np
 
     from inputs import cases as C
@@ -170,6 +173,23 @@ def _iso_leg(steps=20, warmup=3):
     err = [float(np.max(np.abs(W32[m] - W64[m])) / np.max(np.abs(W64[m]))) for m in range(5)]
     out["fp32_flux"]["max_rel_err_vs_fp64_gpu_per_field"] = err
     out["fp32_flux"]["after_steps"] = leg["steps_done"]
+    if options:
+        # the 3D options that take the face-kernel path (fluxes through HBM, a separate
+        # update): k-omega transport and WENO5 face values, FP32 flux as the box's form
+        from paper_1302_2132_amd import gks_face_flops_recon, gks_kw_face_flops
+        for name, opt, flops in (("kw_transport_fp32_flux", {"kw_transport": True},
+                                  gks_face_flops(3, "fp32_flux") + gks_kw_face_flops()),
+                                 ("weno5_fp32_flux", {"recon": "weno5"}, gks_face_flops_recon(3, "weno5"))):
+            c = C.isotropic_box(256, precision="fp32_flux")
+            for k, v in opt.items():
+                setattr(c, k, v)
+            leg = _leg(c, steps, warmup)
+            out[name] = {"value": c.ncells * steps / leg["seconds"], "unit": "cell-updates/s",
+                         "ms_per_step": leg["seconds"] * 1e3 / steps,
+                         "vs_fused_step": (c.ncells * steps / leg["seconds"]) / out["fp32_flux"]["value"],
+                         "roofline": _roofline(c, leg, steps, flops, FP64_PEAK_TFLOPS),
+                         "kernel_ms_per_step": {k: round(v / steps, 4) for k, v in leg["kernels"].items()
+                                                if k != "steps"}}
     return out
 
 
