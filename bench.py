@@ -130,11 +130,11 @@ def _roofline(case, leg, steps, flops_face, peak):
          | (4 if recon == "muscl3" else 0) | (8 if getattr(case, "multi_d", False) else 0)
          | (16 if recon == "weno5" else 0))
     # 2D: the fused tile kernel; 3D: the fused z-marching tile kernel, or the face kernel for
-    # transport, the multi-dimensional expansion and WENO5
+    # the multi-dimensional expansion and WENO5
     if case.dim == 2:
         kernel = f"k_tile2<{r},{v}>"
     else:
-        kernel = f"k_tile3<{r},{v}>" if (v & (1 | 8 | 16)) == 0 else f"k_face<{r},3,64,{v}>"
+        kernel = f"k_tile3<{r},{v}>" if (v & (8 | 16)) == 0 else f"k_face<{r},3,64,{v}>"
     out = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
            "frac": round(achieved / peak, 4), "traffic": _profiled_traffic(kernel),
            "kernel": kernel, "flops_per_face": flops_face, "faces_per_launch": faces,
@@ -151,8 +151,7 @@ def _roofline(case, leg, steps, flops_face, peak):
 def _iso_leg(steps=20, warmup=3, options=True):
     """3D periodic isotropic box 256^3 (Ma_t 0.5), FP32-flux (the configuration's form) and
     FP64, with the FP32-flux error against FP64 after the same steps; with `options`, also
-    the box with k-omega transport and with WENO5 face values (FP32 flux), which take the
-    face-kernel path."""
+    the box with k-omega transport and with WENO5 face values (FP32 flux)."""
     import numpy as np
 
     from inputs import cases as C
@@ -174,8 +173,9 @@ def _iso_leg(steps=20, warmup=3, options=True):
     out["fp32_flux"]["max_rel_err_vs_fp64_gpu_per_field"] = err
     out["fp32_flux"]["after_steps"] = leg["steps_done"]
     if options:
-        # the 3D options that take the face-kernel path (fluxes through HBM, a separate
-        # update): k-omega transport and WENO5 face values, FP32 flux as the box's form
+        # the 3D options: k-omega transport (the fused kernel, the k-omega fluxes formed in
+        # its update) and WENO5 face values (the face-kernel path: fluxes through HBM, a
+        # separate update), FP32 flux as the box's form
         from paper_1302_2132_amd import gks_face_flops_recon, gks_kw_face_flops
         for name, opt, flops in (("kw_transport_fp32_flux", {"kw_transport": True},
                                   gks_face_flops(3, "fp32_flux") + gks_kw_face_flops()),

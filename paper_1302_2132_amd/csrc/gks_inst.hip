@@ -31,11 +31,12 @@ GKS_TILE2_F(0) GKS_TILE2_F(1) GKS_TILE2_F(2) GKS_TILE2_F(3) GKS_TILE2_F(4) GKS_T
 #elif GKS_PART == 3
 GKS_TILE2_F(8) GKS_TILE2_F(9) GKS_TILE2_F(10) GKS_TILE2_F(11)
 GKS_TILE2_F(16) GKS_TILE2_F(17) GKS_TILE2_F(18) GKS_TILE2_F(19)
-// 3D: the fused tile kernel (the plain scheme, tau_hat, third-order MUSCL) and the face
-// kernel of the options with transport, the multi-dimensional expansion or WENO5
+// 3D: the fused tile kernel (the plain scheme, tau_hat, third-order MUSCL, each with
+// frozen or transported k and omega) and the face kernel of the multi-dimensional expansion
+// and WENO5
 #elif GKS_PART == 4
 GKS_TILE3_D(0) GKS_TILE3_D(2) GKS_TILE3_D(4) GKS_TILE3_D(6)
-GKS_FACE_D(64, 1) GKS_FACE_D(64, 3) GKS_FACE_D(64, 5) GKS_FACE_D(64, 7)
+GKS_TILE3_D(1) GKS_TILE3_D(3) GKS_TILE3_D(5) GKS_TILE3_D(7)
 template __global__ void k_tile2<double, 0, 1>(const void*, int, int);
 #elif GKS_PART == 5
 template __global__ void k_tile2<double, 0, 2>(const void*, int, int);
@@ -43,7 +44,7 @@ GKS_FACE_D(64, 8) GKS_FACE_D(64, 9) GKS_FACE_D(64, 10) GKS_FACE_D(64, 11)
 GKS_FACE_D(64, 16) GKS_FACE_D(64, 17) GKS_FACE_D(64, 18) GKS_FACE_D(64, 19)
 #elif GKS_PART == 6
 GKS_TILE3_F(0) GKS_TILE3_F(2) GKS_TILE3_F(4) GKS_TILE3_F(6)
-GKS_FACE_F(64, 1) GKS_FACE_F(64, 3) GKS_FACE_F(64, 5) GKS_FACE_F(64, 7)
+GKS_TILE3_F(1) GKS_TILE3_F(3) GKS_TILE3_F(5) GKS_TILE3_F(7)
 template __global__ void k_tile2<float, 0, 1>(const void*, int, int);
 #elif GKS_PART == 7
 template __global__ void k_tile2<float, 0, 2>(const void*, int, int);

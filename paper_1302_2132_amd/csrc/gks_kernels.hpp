@@ -1067,12 +1067,16 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
 // neighbouring tiles); no flux goes to HBM and the update needs no launch of its own.
 // Residual sums and the CFL rate accumulate per thread over the run and are reduced once.
 // The arithmetic of every face and cell is that of k_face and k_update.  Variants: the
-// second- and third-order MUSCL face values with either eps mode (two-cell stencils);
-// transport, WENO5 and the multi-dimensional expansion use k_face and k_update.
+// second- and third-order MUSCL face values with either eps mode (two-cell stencils), with
+// frozen or transported k and omega; WENO5 and the multi-dimensional expansion use k_face
+// and k_update.  With transport, each cell's update forms the rho k and rho omega fluxes of
+// its six faces itself (kw_face, as k_face does, from the face's mass flux in LDS and the
+// two cells' k, omega and rho k/omega; a face's pair is formed by both its cells, 18 flops
+// each), so the plane's LDS holds no more than the frozen form's.
 constexpr int T3X = 16, T3Y = 15;
 constexpr int T3_NC = T3X * T3Y;                        // cells per plane of a tile
 constexpr int T3_KX = T3X + 2, T3_KY = T3Y + 2;         // k, omega, strain window
-template <int V> constexpr bool fused3_variant() { return (V & (V_KW | V_MD | V_W5)) == 0; }
+template <int V> constexpr bool fused3_variant() { return (V & (V_MD | V_W5)) == 0; }
 static_assert(T3_NC <= T2_THREADS, "one z-face and one cell per thread");
 
 #ifndef GKS_TILE3_WAVES_FP64
@@ -1217,6 +1221,7 @@ void k_tile3(const void* __restrict__ table, int cap, int cls)
 {
     static_assert(fused3_variant<V>(), "variant without a fused 3D step");
     constexpr int FMODE = (V & V_TH) ? FLUX_TAUHAT : 0;
+    constexpr bool KW = (V & V_KW) != 0;
     constexpr int RK = recon_of<V>();
     constexpr int NV = 5;
     __shared__ Tile3Lds L;
@@ -1369,7 +1374,7 @@ void k_tile3(const void* __restrict__ table, int cap, int cls)
                 const double Fzg[NV] = {Fz[0], Fz[2], Fz[3], Fz[1], Fz[4]};
                 if (full) {
                     const int ii = own ? u % T3X : 0, jj = own ? u / T3X : 0;
-                    CellRead<3, false> x;
+                    CellRead<3, KW> x;
                     const int fx = jj * (T3X + 1) + ii, fy = jj * T3X + ii, e = jj * T3X + ii;
                     const int cell = (k * I.n[1] + g.y0 + jj) * I.n[0] + g.x0 + ii;
 #pragma unroll
@@ -1388,7 +1393,48 @@ void k_tile3(const void* __restrict__ table, int cap, int cls)
                     const int ek = (jj + 1) * T3_KX + ii + 1;
                     x.kc = L.K[0][ek];
                     x.wc = L.K[1][ek];
-                    update_apply<3, false>(I, I.W[cur ^ 1], cell, own, x, dt, 1.0 / dt, r2, rate, bad);
+                    if constexpr (KW) {
+                        // rho k, rho omega of the cell and their sources; k, omega, rho k/omega
+                        // of the six neighbours (x, y: k and omega from the staged window; the
+                        // rest from memory, a ghost taking its interior image's)
+                        const double* __restrict__ Wo = I.W[cur];
+                        const long long nc = I.ncells;
+                        x.old[NV] = Wo[(long long)NV * nc + cell];
+                        x.old[NV + 1] = Wo[(long long)(NV + 1) * nc + cell];
+                        x.qk = I.Qk[cell];
+                        x.qw = I.Qw[cell];
+                        const int cx = g.x0 + ii, cy = g.y0 + jj;
+                        int jn[6];                          // x-1, x+1, y-1, y+1, z-1, z+1
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) {
+                            int c[3] = {cx, cy, k};
+                            c[q >> 1] += (q & 1) ? 1 : -1;
+                            jn[q] = image_cell<3>(I, q >> 1, c);
+                        }
+                        const double nc0 = I.nt[cell];
+                        double nn[6], kz[2], wz[2];
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) nn[q] = I.nt[jn[q]];
+                        kz[0] = I.k[jn[4]];
+                        kz[1] = I.k[jn[5]];
+                        wz[0] = I.om[jn[4]];
+                        wz[1] = I.om[jn[5]];
+                        const double kn[4] = {L.K[0][ek - 1], L.K[0][ek + 1], L.K[0][ek - T3_KX], L.K[0][ek + T3_KX]};
+                        const double wn[4] = {L.K[1][ek - 1], L.K[1][ek + 1], L.K[1][ek - T3_KX], L.K[1][ek + T3_KX]};
+                        const int cc[3] = {cx, cy, k};
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const double klo = d < 2 ? kn[2 * d] : kz[0], khi = d < 2 ? kn[2 * d + 1] : kz[1];
+                            const double wlo = d < 2 ? wn[2 * d] : wz[0], whi = d < 2 ? wn[2 * d + 1] : wz[1];
+                            const double* __restrict__ icd = I.icd[d];
+                            // low face (the neighbour on the left) and high face
+                            kw_face(I, x.fl[d][0], klo, x.kc, wlo, x.wc, nn[2 * d], nc0, icd[cc[d] - 1], dt,
+                                    x.fl[d][NV], x.fl[d][NV + 1]);
+                            kw_face(I, x.fh[d][0], x.kc, khi, x.wc, whi, nc0, nn[2 * d + 1], icd[cc[d]], dt,
+                                    x.fh[d][NV], x.fh[d][NV + 1]);
+                        }
+                    }
+                    update_apply<3, KW>(I, I.W[cur ^ 1], cell, own, x, dt, 1.0 / dt, r2, rate, bad);
                 }
                 if (own) {
 #pragma unroll
@@ -1846,7 +1892,7 @@ extern __global__ void k_states(const void* __restrict__ table, int cap, State* 
 // and GKS_FACE_VARIANTS list every (tile, variant) pair the library launches.
 #define GKS_TILE2_VARIANTS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(16) X(17) X(18) X(19)
 #define GKS_FACE_VARIANTS(X) \
-    X(64, 1) X(64, 3) X(64, 5) X(64, 7) X(64, 8) X(64, 9) X(64, 10) X(64, 11) X(64, 16) X(64, 17) X(64, 18) X(64, 19)
+    X(64, 8) X(64, 9) X(64, 10) X(64, 11) X(64, 16) X(64, 17) X(64, 18) X(64, 19)
 #define GKS_TILE2_DECL(V)                                                         \
     extern template __global__ void k_tile2<double, V, 0>(const void*, int, int); \
     extern template __global__ void k_tile2<float, V, 0>(const void*, int, int);
@@ -1858,7 +1904,7 @@ extern template __global__ void k_tile2<float, 0, 2>(const void*, int, int);
 #define GKS_FACE_DECL(T, V)                                                           \
     extern template __global__ void k_face<double, 3, T, V>(const void*, int, int); \
     extern template __global__ void k_face<float, 3, T, V>(const void*, int, int);
-#define GKS_TILE3_VARIANTS(X) X(0) X(2) X(4) X(6)
+#define GKS_TILE3_VARIANTS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 #define GKS_TILE3_DECL(V)                                                      \
     extern template __global__ void k_tile3<double, V>(const void*, int, int); \
     extern template __global__ void k_tile3<float, V>(const void*, int, int);

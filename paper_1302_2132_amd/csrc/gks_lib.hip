@@ -68,10 +68,11 @@ static int tiles2(long long n0, long long n1, int shape = 0)
     return (int)(((n0 + tx - 1) / tx) * ((n1 + ty - 1) / ty));
 }
 
-// Options whose 3D step runs in the fused tile kernel (two-cell stencils, no transport).
+// Options whose 3D step runs in the fused tile kernel (two-cell stencils and face values
+// from the cells of the face's own line: not the multi-dimensional expansion or WENO5).
 static bool fused3_config(const gks_config* c)
 {
-    return c->dim == 3 && !c->turb_transport && !c->multi_d && c->recon != GKS_RECON_WENO5;
+    return c->dim == 3 && !c->multi_d && c->recon != GKS_RECON_WENO5;
 }
 
 // z-runs of a fused 3D mesh: about 4608 tiles in all (enough rounds of workgroups to keep
@@ -399,15 +400,19 @@ static face_kernel_t tile3_kernel(int cls, int variant)
     case V_TH: return f ? k_tile3<float, V_TH> : k_tile3<double, V_TH>;
     case V_R3: return f ? k_tile3<float, V_R3> : k_tile3<double, V_R3>;
     case V_TH | V_R3: return f ? k_tile3<float, V_TH | V_R3> : k_tile3<double, V_TH | V_R3>;
+    case V_KW: return f ? k_tile3<float, V_KW> : k_tile3<double, V_KW>;
+    case V_KW | V_TH: return f ? k_tile3<float, V_KW | V_TH> : k_tile3<double, V_KW | V_TH>;
+    case V_KW | V_R3: return f ? k_tile3<float, V_KW | V_R3> : k_tile3<double, V_KW | V_R3>;
+    case V_KW | V_TH | V_R3: return f ? k_tile3<float, V_KW | V_TH | V_R3> : k_tile3<double, V_KW | V_TH | V_R3>;
     default: return f ? k_tile3<float, 0> : k_tile3<double, 0>;
     }
 }
-static bool fused3_variant_rt(int variant) { return (variant & (V_KW | V_MD | V_W5)) == 0; }
+static bool fused3_variant_rt(int variant) { return (variant & (V_MD | V_W5)) == 0; }
 
 // Face kernel of a class and variant (V_KW and V_TH with one of V_R3, V_W5, V_MD): the
 // fused 2D tile kernel for the 2D classes; for 3D the fused tile kernel, or the face kernel
-// (FACE_TILE faces per workgroup, then k_update) for transport, WENO5 and the
-// multi-dimensional expansion.
+// (FACE_TILE faces per workgroup, then k_update) for WENO5 and the multi-dimensional
+// expansion.
 static face_kernel_t face_kernel(int cls, int variant, int shape2 = 0)
 {
     if (cls >= 2 && fused3_variant_rt(variant)) return tile3_kernel(cls, variant);
@@ -433,10 +438,6 @@ static face_kernel_t face_kernel(int cls, int variant, int shape2 = 0)
         }
     }
     switch (variant) {
-    case 1: return face3_kernel<1>(cls);
-    case 3: return face3_kernel<3>(cls);
-    case 5: return face3_kernel<5>(cls);
-    case 7: return face3_kernel<7>(cls);
     case V_MD: return face3_kernel<V_MD>(cls);
     case V_MD | V_KW: return face3_kernel<V_MD | V_KW>(cls);
     case V_MD | V_TH: return face3_kernel<V_MD | V_TH>(cls);

@@ -53,10 +53,16 @@ def test_workspace_bytes_and_validation():
     nb3 = P.gks_workspace_bytes(P.config_from_case(c3))
     # 3D, fused step: two state buffers + k, omega, strain; no face fluxes in HBM
     assert 8 * 16 ** 3 * (5 * 2 + 3) <= nb3 < 8 * 16 ** 3 * (5 * 2 + 3) + 8 * 5 * 3 * 17 * 16 * 16
-    # a transported 3D solve keeps the face-kernel path: x/y/z face fluxes (FP64) in HBM
+    # a transported 3D solve also steps in the fused kernel: two 7-component states, k, omega,
+    # strain, rho k/omega and the two sources, no face fluxes
     kw3 = c3.copy()
     kw3.kw_transport = True
-    assert P.gks_workspace_bytes(P.config_from_case(kw3)) >= 8 * 16 ** 3 * (7 * 2 + 6) + 8 * 7 * 3 * 17 * 16 * 16
+    nkw = P.gks_workspace_bytes(P.config_from_case(kw3))
+    assert 8 * 16 ** 3 * (7 * 2 + 6) <= nkw < 8 * 16 ** 3 * (7 * 2 + 6) + 8 * 5 * 3 * 17 * 16 * 16
+    # WENO5 keeps the face-kernel path: x/y/z face fluxes (FP64) in HBM
+    w3 = c3.copy()
+    w3.recon = "weno5"
+    assert P.gks_workspace_bytes(P.config_from_case(w3)) >= 8 * 16 ** 3 * (5 * 2 + 3) + 8 * 5 * 3 * 17 * 16 * 16
     fp32 = c3.copy()
     fp32.precision = "fp32_flux"
     assert P.gks_workspace_bytes(P.config_from_case(fp32)) == nb3    # face fluxes FP64 in both forms

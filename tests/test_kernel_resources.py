@@ -82,14 +82,18 @@ def _tile3(res, r):
 
 
 def test_fused_3d_kernels_fit_without_spill(remarks):
-    """The fused 3D step (one flux evaluation serving its three axes) at two waves per SIMD
-    with no spill, and its LDS (a four-plane ring, halo arms, k/omega/S and the fluxes of a
-    plane) within half a CU's 160 KiB, so two workgroups share a CU."""
+    """The fused 3D step (one flux evaluation serving its three axes) at two waves per SIMD,
+    and its LDS (a four-plane ring, halo arms, k/omega/S and the fluxes of a plane) within
+    half a CU's 160 KiB, so two workgroups share a CU.  No spill, except a few doubles in the
+    FP64 transported forms, whose update also forms the k-omega fluxes of the cell's six
+    faces (the update phase, once per cell and plane, not the flux)."""
     for r in ("d", "f"):
         ks = _tile3(remarks, r)
-        assert sorted(_variant(k) for k in ks) == [0, 2, 4, 6]   # plain, tau_hat, MUSCL3, both
+        # plain, tau_hat, MUSCL3, both; each frozen and transported
+        assert sorted(_variant(k) for k in ks) == [0, 1, 2, 3, 4, 5, 6, 7]
         for k, v in ks.items():
-            assert v["ScratchSize"] == 0, (k, v)
+            kw = bool(_variant(k) & 1)
+            assert v["ScratchSize"] <= (24 if kw and r == "d" else 0), (k, v)
             assert v["Occupancy"] >= 2, (k, v)
             assert v["LDS Size"] <= 80 * 1024, (k, v)
 
@@ -97,7 +101,7 @@ def test_fused_3d_kernels_fit_without_spill(remarks):
 def test_3d_face_kernels_fit_without_spill(remarks):
     for r, waves in (("d", 2), ("f", 3)):
         ks = _face(remarks, r, 3)
-        assert len(ks) == 12                        # transport, multi-d, WENO5 and their combinations
+        assert len(ks) == 8                         # multi-d, WENO5, each alone, with transport, tau_hat
         for k, v in ks.items():
             md = bool(_variant(k) & 8)
             assert v["ScratchSize"] <= (48 if md and r == "d" else 0), (k, v)
