@@ -291,32 +291,26 @@ constexpr double KW_SIGMA_DO = 0.125;
 // eta = S/(C_mu omega): alpha (omega/k) times the production of k, written without the
 // division by k.  Gradients are central differences over the neighbouring centres; a
 // ghost neighbour's k and omega are those of its interior image.
+// Gradients along axis b of a cell from its two neighbours there: velocities (up, um),
+// k and omega (kp, km, qp, qm), inverse centre distance ih.  Contraction off, so that every
+// pass that forms them (per cell or marching) gets the same values, bitwise.
 template <int D>
-__device__ inline void strain_cell_kw(cref<Inst> I, int cell)
+__device__ inline void kw_grad_axis(const double* up, const double* um, double kp, double km, double qp, double qm,
+                                    double ih, int b, double (*g)[3], double* gk, double* gw)
 {
-    const double* __restrict__ W = I.W[state_of(I).fresh];
-    const long long nc = I.ncells;
-    int c[3];
-    c[0] = cell % I.n[0];
-    c[1] = (cell / I.n[0]) % I.n[1];
-    c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
-    double g[3][3], gk[3], gw[3];
-    for (int b = 0; b < D; ++b) {
-        double wp[D + 2], wm[D + 2];
-        int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
-        cp[b] += 1;
-        cm[b] -= 1;
-        load_state<D>(I, W, b, cp, wp);
-        load_state<D>(I, W, b, cm, wm);
-        const int jp = image_cell<D>(I, b, cp), jm = image_cell<D>(I, b, cm);
-        const double rp = W[jp], rm = W[jm];
-        const double kp = W[(D + 2) * nc + jp] / rp, km = W[(D + 2) * nc + jm] / rm;
-        const double qp = W[(D + 3) * nc + jp] / rp, qm = W[(D + 3) * nc + jm] / rm;
-        const double ip = 1.0 / wp[0], im = 1.0 / wm[0], ih = I.ic2[b][c[b]];
-        for (int a = 0; a < D; ++a) g[a][b] = (wp[1 + a] * ip - wm[1 + a] * im) * ih;
-        gk[b] = (kp - km) * ih;
-        gw[b] = (qp - qm) * ih;
-    }
+#pragma clang fp contract(off)
+    for (int a = 0; a < D; ++a) g[a][b] = (up[a] - um[a]) * ih;
+    gk[b] = (kp - km) * ih;
+    gw[b] = (qp - qm) * ih;
+}
+
+// The cell's outputs of the transport strain pass from its gradients and its rho, rho k,
+// rho omega (contraction off, as kw_grad_axis).
+template <int D>
+__device__ inline void kw_cell_out(cref<Inst> I, const double (*g)[3], const double* gk, const double* gw, double rho,
+                                   double rk, double rw, long long cell)
+{
+#pragma clang fp contract(off)
     double ss = 0.0, div = 0.0, cross = 0.0;
     for (int a = 0; a < D; ++a) {
         div += g[a][a];
@@ -327,8 +321,7 @@ __device__ inline void strain_cell_kw(cref<Inst> I, int cell)
         }
     }
     const double s2 = 2.0 * ss, S = sqrt(s2);
-    const double rho = W[cell];
-    const double kc = W[(D + 2) * nc + cell] / rho, wc = W[(D + 3) * nc + cell] / rho;
+    const double kc = rk / rho, wc = rw / rho;
     const double eta = S / (I.c_mu * wc);
     const double root = sqrt(1.0 + eta * eta);
     const double shear = s2 - (2.0 / 3.0) * div * div;
@@ -341,6 +334,42 @@ __device__ inline void strain_cell_kw(cref<Inst> I, int cell)
     I.nt[cell] = rho * kc / wc;
     I.Qk[cell] = mut * shear - (2.0 / 3.0) * rho * kc * div;
     I.Qw[cell] = qw;
+}
+
+// k and omega of the interior image j of a (possibly ghost) cell: rho k / rho, rho omega / rho
+// (a ghost's k and omega are those of its image).
+__device__ inline void kw_of_image(const double* __restrict__ W, long long nc, int nv, int j, double& kq, double& wq)
+{
+    const double r = W[j];
+    kq = W[(long long)nv * nc + j] / r;
+    wq = W[(long long)(nv + 1) * nc + j] / r;
+}
+
+template <int D>
+__device__ inline void strain_cell_kw(cref<Inst> I, int cell)
+{
+    const double* __restrict__ W = I.W[state_of(I).fresh];
+    const long long nc = I.ncells;
+    int c[3];
+    c[0] = cell % I.n[0];
+    c[1] = (cell / I.n[0]) % I.n[1];
+    c[2] = (D == 3) ? cell / (I.n[0] * I.n[1]) : 0;
+    double g[3][3], gk[3], gw[3];
+    for (int b = 0; b < D; ++b) {
+        double wp[D + 1], wm[D + 1], up[D], um[D];
+        int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+        cp[b] += 1;
+        cm[b] -= 1;
+        load_state<D, D + 1>(I, W, b, cp, wp);      // density and momenta
+        load_state<D, D + 1>(I, W, b, cm, wm);
+        velocity_of<D>(wp, up);
+        velocity_of<D>(wm, um);
+        double kp, km, qp, qm;
+        kw_of_image(W, nc, D + 2, image_cell<D>(I, b, cp), kp, qp);
+        kw_of_image(W, nc, D + 2, image_cell<D>(I, b, cm), km, qm);
+        kw_grad_axis<D>(up, um, kp, km, qp, qm, I.ic2[b][c[b]], b, g, gk, gw);
+    }
+    kw_cell_out<D>(I, g, gk, gw, W[cell], W[(D + 2) * nc + cell], W[(D + 3) * nc + cell], cell);
 }
 
 // Time-integrated fluxes of rho k and rho omega through a face: convection by the face's
@@ -1811,8 +1840,121 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain3(const void* __restrict__ 
         }
     }
 }
+
+// The transport strain pass of a single 3D solve, marching along z like k_strain3: besides
+// the velocities, each column carries k and omega of planes k-1, k, k+1 (those of a ghost
+// plane from its interior image) and rho, rho k, rho omega of plane k, and the one-cell ring
+// of plane k goes through LDS with its velocities, k and omega.  The arithmetic is
+// strain_cell_kw's (velocity_of, kw_grad_axis per axis in order, kw_cell_out): the same
+// outputs, bitwise.  With `finish` set, work item 0 ends the pending step first.
+__global__ __launch_bounds__(CELL_TILE) void k_strain3kw(const void* __restrict__ table, int finish, int seg, int nseg)
+{
+    static_assert(S3X * S3Y == CELL_TILE, "one column per thread");
+    constexpr int RX = S3X + 2, RY = S3Y + 2;
+    const TabC tv(table, 1);
+    cref<Inst> I = tv.inst[0];
+    __shared__ double sh[6 * 4];
+    __shared__ double sV[5][RX * RY];      // velocities, k, omega of plane k: column and ring
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    const long long nc = I.ncells;
+    const int ntx = (n0 + S3X - 1) / S3X, nty = (n1 + S3Y - 1) / S3Y;
+    const int head = finish ? 1 : 0;
+    const int total = head + ntx * nty * nseg;
+    for (TileWalk tw = xcd_walk(total); tw.first < tw.end; tw.first += tw.stride) {
+        const int item = tw.first;
+        if (item < head) {
+            finish_member(I, 0, sh);
+            continue;
+        }
+        if (!state_of(I).active) continue;
+        const double* __restrict__ W = I.W[state_of(I).fresh];
+        const int lt = item - head, col = lt % (ntx * nty), run = lt / (ntx * nty);
+        const int x0 = (col % ntx) * S3X, y0 = (col / ntx) * S3Y;
+        const int tx = min(S3X, n0 - x0), ty = min(S3Y, n1 - y0);
+        const int z0 = run * seg, z1 = min(n2, z0 + seg);
+        const int t = (int)threadIdx.x, i = t % S3X, j = t / S3X;
+        const bool own = i < tx && j < ty;
+        const int ci = own ? i : 0, cj = own ? j : 0;
+        const int nr = 2 * (tx + ty);
+        int ra = -1, rb = -1, rd = 0;
+        if (t < nr) {
+            if (t < ty) { ra = -1; rb = t; rd = 0; }
+            else if (t < 2 * ty) { ra = tx; rb = t - ty; rd = 0; }
+            else if (t < 2 * ty + tx) { ra = t - 2 * ty; rb = -1; rd = 1; }
+            else { ra = t - 2 * ty - tx; rb = ty; rd = 1; }
+        }
+        // velocity, k and omega of this thread's column at plane z (ghost planes: velocity
+        // from the ghost state, k and omega from the image), and rho, rho k, rho omega there
+        auto column = [&](int z, double* u, double& kq, double& wq, double* raw) {
+            const int c[3] = {x0 + ci, y0 + cj, z};
+            double w[4];
+            load_state<3, 4>(I, W, 2, c, w);
+            velocity_of<3>(w, u);
+            const int jz = image_cell<3>(I, 2, c);
+            raw[0] = W[jz];
+            raw[1] = W[5 * nc + jz];
+            raw[2] = W[6 * nc + jz];
+            kw_of_image(W, nc, 5, jz, kq, wq);
+        };
+        double um[3], uc[3], up[3], km, kc, kp, wm, wc, wp, rm[3], rc[3], rp[3];
+        column(z0 - 1, um, km, wm, rm);
+        column(z0, uc, kc, wc, rc);
+        for (int k = z0; k < z1; ++k) {
+            column(k + 1, up, kp, wp, rp);
+            if (t < nr) {
+                const int c[3] = {x0 + ra, y0 + rb, k};
+                double w[4], u[3], kq, wq;
+                load_state<3, 4>(I, W, rd, c, w);
+                velocity_of<3>(w, u);
+                kw_of_image(W, nc, 5, image_cell<3>(I, rd, c), kq, wq);
+                const int e = (rb + 1) * RX + ra + 1;
+                sV[0][e] = u[0];
+                sV[1][e] = u[1];
+                sV[2][e] = u[2];
+                sV[3][e] = kq;
+                sV[4][e] = wq;
+            }
+            {
+                const int e = (cj + 1) * RX + ci + 1;
+                if (own) {
+                    sV[0][e] = uc[0];
+                    sV[1][e] = uc[1];
+                    sV[2][e] = uc[2];
+                    sV[3][e] = kc;
+                    sV[4][e] = wc;
+                }
+            }
+            __syncthreads();
+            if (own) {
+                const int e = (cj + 1) * RX + ci + 1;
+                double g[3][3], gk[3], gw[3];
+                const int off[2] = {1, RX};
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double vp[3] = {sV[0][e + off[b]], sV[1][e + off[b]], sV[2][e + off[b]]};
+                    const double vm[3] = {sV[0][e - off[b]], sV[1][e - off[b]], sV[2][e - off[b]]};
+                    const double ih = I.ic2[b][b == 0 ? x0 + ci : y0 + cj];
+                    kw_grad_axis<3>(vp, vm, sV[3][e + off[b]], sV[3][e - off[b]], sV[4][e + off[b]], sV[4][e - off[b]],
+                                    ih, b, g, gk, gw);
+                }
+                kw_grad_axis<3>(up, um, kp, km, wp, wm, I.ic2[2][k], 2, g, gk, gw);
+                kw_cell_out<3>(I, g, gk, gw, rc[0], rc[1], rc[2], (long long)(k * n1 + y0 + cj) * n0 + x0 + ci);
+            }
+            __syncthreads();
+            for (int a = 0; a < 3; ++a) {
+                um[a] = uc[a];
+                uc[a] = up[a];
+                rm[a] = rc[a];
+                rc[a] = rp[a];
+            }
+            km = kc; kc = kp;
+            wm = wc; wc = wp;
+        }
+    }
+}
 #else
 extern __global__ void k_strain3(const void* __restrict__ table, int finish, int seg, int nseg);
+extern __global__ void k_strain3kw(const void* __restrict__ table, int finish, int seg, int nseg);
 #endif
 
 // Degree of rarefaction eps_hat = tau/tau_hat of the faces of each cell at the current

@@ -673,9 +673,10 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
     void (*ks)(const void*, int, int, int) = kw ? k_strain<true> : k_strain<false>;
     void (*ku)(const void*, int) = kw ? k_update<true> : k_update<false>;
     const int grid_head = round8(h->inst.ntile_cell + 1);
-    // a 3D solve with frozen k and omega takes the z-marching strain pass (runs of planes
-    // over 64 x 4 columns, about 8192 work items), the others the per-cell one
-    const bool strain3 = h->cfg.dim == 3 && !kw;
+    // a 3D solve takes the z-marching strain pass (runs of planes over 64 x 4 columns, about
+    // 8192 work items; with transport the pass that also forms k, omega and the sources), a
+    // 2D one the per-cell pass
+    const bool strain3 = h->cfg.dim == 3;
     int seg3s = 1, nseg3s = 1, grid3s = 8;
     if (strain3) {
         const int n0 = h->inst.n[0], n1 = h->inst.n[1], n2 = h->inst.n[2];
@@ -688,7 +689,8 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
     if (nsteps == 0) return GKS_OK;
     if (!h->timing) {
         for (int i = 0; i < nsteps; ++i) {
-            if (strain3) hipLaunchKernelGGL(k_strain3, dim3(grid3s), dim3(CELL_TILE), 0, s, tab, 1, seg3s, nseg3s);
+            if (strain3) hipLaunchKernelGGL(kw ? k_strain3kw : k_strain3, dim3(grid3s), dim3(CELL_TILE), 0, s, tab, 1,
+                                            seg3s, nseg3s);
             else hipLaunchKernelGGL(ks, dim3(grid_head), dim3(CELL_TILE), 0, s, tab, 1, 0, 1);
             hipLaunchKernelGGL(fk, dim3(h->grid_face), fblock, 0, s, tab, 1, h->cls);
             if (upd) hipLaunchKernelGGL(ku, dim3(h->grid_cell), dim3(CELL_TILE), 0, s, tab, 1);
@@ -703,8 +705,8 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
                 if (r != GKS_OK) return r;
             }
             if (strain3)
-                hipExtLaunchKernelGGL(k_strain3, dim3(grid3s), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, seg3s,
-                                      nseg3s);
+                hipExtLaunchKernelGGL(kw ? k_strain3kw : k_strain3, dim3(grid3s), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0,
+                                      tab, 1, seg3s, nseg3s);
             else
                 hipExtLaunchKernelGGL(ks, dim3(grid_head), dim3(CELL_TILE), 0, s, ev[0], ev[1], 0, tab, 1, 0, 1);
             hipExtLaunchKernelGGL(fk, dim3(h->grid_face), fblock, 0, s, ev[2], ev[3], 0, tab, 1, h->cls);
