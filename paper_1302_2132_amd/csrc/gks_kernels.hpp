@@ -290,7 +290,10 @@ constexpr double KW_SIGMA_DO = 0.125;
 //        + sigma_do (rho/omega) grad k . grad omega   (the last term only where positive),
 // eta = S/(C_mu omega): alpha (omega/k) times the production of k, written without the
 // division by k.  Gradients are central differences over the neighbouring centres; a
-// ghost neighbour's k and omega are those of its interior image.
+// ghost neighbour's k and omega are those of its interior image.  The pass is split into
+// kw_grad_axis (the gradients along one axis) and kw_cell_out (the outputs), which the
+// per-cell pass (strain_cell_kw) and the z-marching one (k_strain3kw) share.
+//
 // Gradients along axis b of a cell from its two neighbours there: velocities (up, um),
 // k and omega (kp, km, qp, qm), inverse centre distance ih.  Contraction off, so that every
 // pass that forms them (per cell or marching) gets the same values, bitwise.
