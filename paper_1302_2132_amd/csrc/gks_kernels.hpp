@@ -1711,8 +1711,10 @@ extern __global__ void k_finish(const void* __restrict__ table, int cap, int mod
 
 // Strain pass over every cell tile of the table (of active members unless `force`).
 // With `finish` set, the first `count` work items instead end the pending step of each
-// member (the strain items read W[fresh], which ending a step leaves alone).
-template <bool KW>
+// member (the strain items read W[fresh], which ending a step leaves alone).  DIM = 2
+// builds the pass for tables of 2D solves only (a single 2D solve's steps): without the
+// 3D path's registers it holds more workgroups per compute unit; DIM = 0 serves any table.
+template <bool KW, int DIM = 0>
 __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ table, int cap, int force, int finish)
 {
     const TabC tv(table, cap);
@@ -1732,7 +1734,10 @@ __global__ __launch_bounds__(CELL_TILE) void k_strain(const void* __restrict__ t
         if (I.kw != (KW ? 1 : 0) || (!force && !state_of(I).active)) continue;   // the other form's solves
         const int cell = (tile - tv.cell_prefix[mi]) * CELL_TILE + (int)threadIdx.x;
         if (cell >= I.ncells) continue;
-        if (KW) {
+        if constexpr (DIM == 2) {
+            if (KW) strain_cell_kw<2>(I, cell);
+            else strain_cell<2>(I, cell);
+        } else if (KW) {
             if (I.dim == 2) strain_cell_kw<2>(I, cell);
             else strain_cell_kw<3>(I, cell);
         } else {

@@ -37,6 +37,8 @@ template __global__ void k_update<false>(const void*, int);
 template __global__ void k_update<true>(const void*, int);
 template __global__ void k_strain<false>(const void*, int, int, int);
 template __global__ void k_strain<true>(const void*, int, int, int);
+template __global__ void k_strain<false, 2>(const void*, int, int, int);
+template __global__ void k_strain<true, 2>(const void*, int, int, int);
 }  // namespace gks
 
 // A named range around an entry point, for the marker traces of profilers (rocprofv3
@@ -670,7 +672,10 @@ static gks_status enqueue_steps(gks_ctx* h, int32_t nsteps)
     face_kernel_t fk = face_kernel(h->cls, variant_of(&h->cfg));
     const dim3 fblock(face_block(h->cls, variant_of(&h->cfg)));
     const bool upd = h->cfg.dim == 3 && !h->inst.fused3;
-    void (*ks)(const void*, int, int, int) = kw ? k_strain<true> : k_strain<false>;
+    // a single 2D solve's strain pass is built for 2D tables only (fewer registers)
+    const bool d2 = h->cfg.dim == 2;
+    void (*ks)(const void*, int, int, int) =
+        kw ? (d2 ? k_strain<true, 2> : k_strain<true>) : (d2 ? k_strain<false, 2> : k_strain<false>);
     void (*ku)(const void*, int) = kw ? k_update<true> : k_update<false>;
     const int grid_head = round8(h->inst.ntile_cell + 1);
     // a 3D solve takes the z-marching strain pass (runs of planes over 64 x 4 columns, about
