@@ -158,8 +158,8 @@ typedef struct {
 
 typedef struct gks_ctx* gks_handle;
 
-/* Device workspace needed by one solve (state double buffer, frozen fields, face fluxes,
- * metrics, reduction partials).  This is the HBM footprint used for admission.  Pure host
+/* Device workspace needed by one solve (state double buffer, frozen fields, face fluxes
+ * of 3D solves with WENO5 or the multi-dimensional expansion, metrics, reduction partials).  This is the HBM footprint used for admission.  Pure host
  * arithmetic on cfg (no device call); GKS_ERR_ARG for a bad config. */
 gks_status gks_workspace_bytes(const gks_config* cfg, size_t* bytes);
 
@@ -184,8 +184,8 @@ gks_status gks_init(const gks_config* cfg, void* dev_workspace, size_t bytes, vo
  * differences (section "Implementation ..."), residual and next time step, all on the
  * device.  nsteps >= 0; a solve that reached t_end, max_steps or res_tol takes no more
  * steps (the call still succeeds).  GKS_ERR_STATE after a reported error.  With turb_transport the strain pass
- * also computes k, omega and the k-omega sources, the face pass the fluxes of rho k and
- * rho omega, and the update advances them; a step whose rho k < 0 or rho omega <= 0 is
+ * also computes k, omega and the k-omega sources, the flux pass the fluxes of rho k and
+ * rho omega through every face, and the update advances them; a step whose rho k < 0 or rho omega <= 0 is
  * non-physical. */
 gks_status gks_step(gks_handle h, int32_t nsteps);
 
