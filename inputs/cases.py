@@ -73,6 +73,44 @@ class Case:
         c.meta = dict(self.meta)
         return c
 
+    # scalar fields written to the case file (the arrays go to the .npz beside it)
+    _SCALARS = ("name", "dim", "gamma", "prandtl", "mu", "c_a", "c_mu", "cfl", "t_end", "steps", "precision",
+                "max_steps", "res_tol", "kw_transport", "eps_mode", "recon", "multi_d")
+
+    def save(self, path: str) -> None:
+        """Write the case as `path` (JSON: sizes, boundary names, gas and run parameters,
+        options, meta) and `path` + ".npz" (the arrays: W, k, omega, face coordinates,
+        boundary data); `Case.load(path)` reads it back bitwise."""
+        import json
+        doc = {f: getattr(self, f) for f in self._SCALARS}
+        doc["n"] = [int(v) for v in self.n]
+        doc["bc"] = [list(p) for p in self.bc]
+        doc["bc_data"] = [[a is not None for a in p] for p in self.bc_data]
+        doc["meta"] = {k: v for k, v in self.meta.items() if isinstance(v, (bool, int, float, str))}
+        arrays = {"W": self.W, "k": self.k, "omega": self.omega}
+        for d in range(self.dim):
+            arrays[f"xf{d}"] = self.xf[d]
+            for s in range(2):
+                if self.bc_data[d][s] is not None:
+                    arrays[f"bc{d}{s}"] = np.asarray(self.bc_data[d][s])
+        with open(path, "w") as f:
+            json.dump(doc, f, indent=1, sort_keys=True)
+        np.savez(path + ".npz", **arrays)
+
+    @classmethod
+    def load(cls, path: str) -> "Case":
+        """Read a case written by `save` (JSON and arrays only: nothing in the files is run)."""
+        import json
+        with open(path) as f:
+            doc = json.load(f)
+        with np.load(path + ".npz", allow_pickle=False) as z:
+            a = {k: z[k] for k in z.files}
+        dim = int(doc["dim"])
+        bcd = [[a[f"bc{d}{s}"] if doc["bc_data"][d][s] else None for s in range(2)] for d in range(dim)]
+        kw = {f: doc[f] for f in cls._SCALARS}
+        return cls(n=tuple(doc["n"]), xf=[a[f"xf{d}"] for d in range(dim)], bc=doc["bc"], bc_data=bcd,
+                   W=a["W"], k=a["k"], omega=a["omega"], meta=doc["meta"], **kw)
+
 
 def cons_from_prim(rho, vel, p, gamma):
     """(rho, [U, V, (W)], p) -> conservative stack (nvar, ...)."""
