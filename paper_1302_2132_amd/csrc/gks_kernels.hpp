@@ -883,36 +883,69 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
         constexpr int NKC = KW ? 4 : 3;
         double ws[NWI][NV], ks[NKI][NKC];
         bool wu[NWI], ku[NKI];
+        // A tile whose window lies inside the mesh (most tiles) addresses its cells directly;
+        // the others take the ghost rules of load_state and image_cell, which give the same
+        // values for interior cells.
+        const bool inner = x0 >= HW && y0 >= HW && x0 + tx + HW <= n0 && y0 + ty + HW <= n1;
+        if (inner) {
+            const long long nc = I.ncells;
 #pragma unroll
-        for (int it = 0; it < NWI; ++it) {
-            const int e = tid + it * T2_THREADS;
-            const int a = e % WX, b = e / WX;
-            const bool row = b >= HW && b < ty + HW && a < tx + 2 * HW;
-            const bool col = a >= HW && a < tx + HW && b < ty + 2 * HW;
-            const bool corner = MD && (a == HW - 1 || a == tx + HW) && (b == HW - 1 || b == ty + HW);
-            wu[it] = e < WX * WY && (row || col || corner);
-            const int c[3] = {wu[it] ? x0 - HW + a : x0, wu[it] ? y0 - HW + b : y0, 0};
-            if (MD && wu[it] && corner) {
-                load_state_c<2>(I, W, c, ws[it]);
-            } else {
-                const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;     // the ghost axis, if any
-                load_state<2>(I, W, d, c, ws[it]);
+            for (int it = 0; it < NWI; ++it) {
+                const int e = tid + it * T2_THREADS;
+                const int a = e % WX, b = e / WX;
+                const bool row = b >= HW && b < ty + HW && a < tx + 2 * HW;
+                const bool col = a >= HW && a < tx + HW && b < ty + 2 * HW;
+                const bool corner = MD && (a == HW - 1 || a == tx + HW) && (b == HW - 1 || b == ty + HW);
+                wu[it] = e < WX * WY && (row || col || corner);
+                const int cell = wu[it] ? (y0 - HW + b) * n0 + x0 - HW + a : y0 * n0 + x0;
+#pragma unroll
+                for (int m = 0; m < NV; ++m) ws[it][m] = W[(long long)m * nc + cell];
             }
-        }
 #pragma unroll
-        for (int it = 0; it < NKI; ++it) {
-            const int e = tid + it * T2_THREADS;
-            const int a = e % T2_KX, b = e / T2_KX;
-            const bool row = b >= 1 && b < ty + 1 && a < tx + 2;
-            const bool col = a >= 1 && a < tx + 1 && b < ty + 2;
-            ku[it] = e < T2_KX * T2_KY && (row || col);
-            const int c[3] = {ku[it] ? x0 - 1 + a : x0, ku[it] ? y0 - 1 + b : y0, 0};
-            const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;
-            const int ic = image_cell<2>(I, d, c);
-            ks[it][0] = I.k[ic];
-            ks[it][1] = I.om[ic];
-            ks[it][2] = I.S[ic];
-            if (KW) ks[it][NKC - 1] = I.nt[ic];
+            for (int it = 0; it < NKI; ++it) {
+                const int e = tid + it * T2_THREADS;
+                const int a = e % T2_KX, b = e / T2_KX;
+                const bool row = b >= 1 && b < ty + 1 && a < tx + 2;
+                const bool col = a >= 1 && a < tx + 1 && b < ty + 2;
+                ku[it] = e < T2_KX * T2_KY && (row || col);
+                const int ic = ku[it] ? (y0 - 1 + b) * n0 + x0 - 1 + a : y0 * n0 + x0;
+                ks[it][0] = I.k[ic];
+                ks[it][1] = I.om[ic];
+                ks[it][2] = I.S[ic];
+                if (KW) ks[it][NKC - 1] = I.nt[ic];
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < NWI; ++it) {
+                const int e = tid + it * T2_THREADS;
+                const int a = e % WX, b = e / WX;
+                const bool row = b >= HW && b < ty + HW && a < tx + 2 * HW;
+                const bool col = a >= HW && a < tx + HW && b < ty + 2 * HW;
+                const bool corner = MD && (a == HW - 1 || a == tx + HW) && (b == HW - 1 || b == ty + HW);
+                wu[it] = e < WX * WY && (row || col || corner);
+                const int c[3] = {wu[it] ? x0 - HW + a : x0, wu[it] ? y0 - HW + b : y0, 0};
+                if (MD && wu[it] && corner) {
+                    load_state_c<2>(I, W, c, ws[it]);
+                } else {
+                    const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;     // the ghost axis, if any
+                    load_state<2>(I, W, d, c, ws[it]);
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < NKI; ++it) {
+                const int e = tid + it * T2_THREADS;
+                const int a = e % T2_KX, b = e / T2_KX;
+                const bool row = b >= 1 && b < ty + 1 && a < tx + 2;
+                const bool col = a >= 1 && a < tx + 1 && b < ty + 2;
+                ku[it] = e < T2_KX * T2_KY && (row || col);
+                const int c[3] = {ku[it] ? x0 - 1 + a : x0, ku[it] ? y0 - 1 + b : y0, 0};
+                const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;
+                const int ic = image_cell<2>(I, d, c);
+                ks[it][0] = I.k[ic];
+                ks[it][1] = I.om[ic];
+                ks[it][2] = I.S[ic];
+                if (KW) ks[it][NKC - 1] = I.nt[ic];
+            }
         }
 #pragma unroll
         for (int it = 0; it < NWI; ++it)
@@ -1157,12 +1190,24 @@ __device__ inline void t3_stage(cref<Inst> I, const Tile3& g, Tile3Lds& L, int t
 {
     const double* __restrict__ W = I.W[state_of(I).parity];
     constexpr int NKI = (T3_KX * T3_KY + T2_THREADS - 1) / T2_THREADS;
+    const int n0 = I.n[0], n1 = I.n[1];
+    const long long nc = I.ncells;
+    // Planes inside the mesh and tiles whose x-y window lies inside it (most of them)
+    // address their cells directly; the others take the ghost rules of load_state and
+    // image_cell, which give the same values for interior cells.
+    const bool inner = g.x0 >= 2 && g.y0 >= 2 && g.x0 + g.tx + 2 <= n0 && g.y0 + g.ty + 2 <= n1;
     const bool po = g.owns(t);
     double wp[5];
     {
         const int tt = po ? t : 0;
         const int c[3] = {g.x0 + tt % T3X, g.y0 + tt / T3X, k + 2};
-        load_state<3>(I, W, 2, c, wp);
+        if (k + 2 < I.n[2]) {
+            const int cell = (c[2] * n1 + c[1]) * n0 + c[0];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) wp[m] = W[m * nc + cell];
+        } else {
+            load_state<3>(I, W, 2, c, wp);
+        }
     }
     if (full) {                 // uniform over the workgroup
         const bool xarm = t < 4 * T3Y;
@@ -1175,7 +1220,13 @@ __device__ inline void t3_stage(cref<Inst> I, const Tile3& g, Tile3Lds& L, int t
             const int off = s < 2 ? s - 2 : s - 2 + (xarm ? g.tx : g.ty);     // -2, -1, t_, t_+1
             const int c[3] = {au ? (xarm ? g.x0 + off : g.x0 + line) : g.x0,
                               au ? (xarm ? g.y0 + line : g.y0 + off) : g.y0, k};
-            load_state<3>(I, W, xarm ? 0 : 1, c, wa);
+            if (inner) {
+                const int cell = (k * n1 + c[1]) * n0 + c[0];
+#pragma unroll
+                for (int m = 0; m < 5; ++m) wa[m] = W[m * nc + cell];
+            } else {
+                load_state<3>(I, W, xarm ? 0 : 1, c, wa);
+            }
         }
 #pragma unroll
         for (int it = 0; it < NKI; ++it) {
@@ -1185,8 +1236,13 @@ __device__ inline void t3_stage(cref<Inst> I, const Tile3& g, Tile3Lds& L, int t
             const bool colm = a >= 1 && a < g.tx + 1 && b < g.ty + 2;
             ku[it] = e < T3_KX * T3_KY && (row || colm);
             const int c[3] = {ku[it] ? g.x0 - 1 + a : g.x0, ku[it] ? g.y0 - 1 + b : g.y0, k};
-            const int d = (c[0] < 0 || c[0] >= I.n[0]) ? 0 : 1;
-            const int ic = image_cell<3>(I, d, c);
+            int ic;
+            if (inner) {
+                ic = (k * n1 + c[1]) * n0 + c[0];
+            } else {
+                const int d = (c[0] < 0 || c[0] >= n0) ? 0 : 1;
+                ic = image_cell<3>(I, d, c);
+            }
             ks[it][0] = I.k[ic];
             ks[it][1] = I.om[ic];
             ks[it][2] = I.S[ic];
