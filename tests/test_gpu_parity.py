@@ -203,3 +203,7 @@ def test_sbli_full_size_fp32_flux_sampled():
 
 def test_isotropic_full_size_fp32_flux_sampled():
     _sampled_step(C.isotropic_box(256), 2, 2000, TOL32)
+
+
+def test_isotropic_full_size_fp64_sampled():
+    _sampled_step(C.isotropic_box(256, precision="fp64"), 2, 2000, TOL64)
