@@ -361,6 +361,17 @@ struct FaceIn {
     H tl[D - 1][D + 2], tr[D - 1][D + 2];   // tangential gradients of the two cells (FLUX_MULTID)
 };
 
+// Where the flux reads the two cells' states (the equilibrium slopes through the interface
+// state): by default the copies in FaceIn; a caller whose stencil sits in LDS may pass a
+// functor cs(side, m) that reads them again there at the point of use.
+struct InCells {};
+template <int D, typename H, typename CS>
+GKS_HD __attribute__((always_inline)) inline H cell_of(const FaceIn<D, H>& in, const CS& cs, int side, int m)
+{
+    if constexpr (std::is_same<CS, InCells>::value) return side ? in.Wi1[m] : in.Wi[m];
+    else return cs(side, m);
+}
+
 // Per-solve constants; the reciprocals are formed once on the host.
 struct GasC {
     double mu, c_a, b;
@@ -485,13 +496,13 @@ GKS_HD inline bool prim_wide(const H* W, H two_over_b, H& rho, H& irho, H* U, H&
 // gives d_t rho = -d_x (rho U)) from the mean of the one-sided gradients through the
 // interface state W0 (rho w00, normal momentum w01); eps_hat = tau/tau_hat, stored in
 // Fout[D + 2] with FLUX_EPS_OUT.
-template <int D, typename H, int MODE>
+template <int D, typename H, int MODE, typename CS = InCells>
 GKS_HD __attribute__((always_inline)) inline Kw<H> mode_weights(const FaceIn<D, H>& in, H tau, const H* W0,
-                                                               const H* U0d, H ir0, H* Fout)
+                                                               const H* U0d, H ir0, H* Fout, const CS& cs = CS())
 {
     const H w00 = W0[0], w01 = W0[1];
-    const H grho = H(0.5) * ((w00 - in.Wi[0]) * in.idl + (in.Wi1[0] - w00) * in.idr);
-    const H gmom = H(0.5) * ((w01 - in.Wi[1]) * in.idl + (in.Wi1[1] - w01) * in.idr);
+    const H grho = H(0.5) * ((w00 - cell_of(in, cs, 0, 0)) * in.idl + (cell_of(in, cs, 1, 0) - w00) * in.idr);
+    const H gmom = H(0.5) * ((w01 - cell_of(in, cs, 0, 1)) * in.idl + (cell_of(in, cs, 1, 1) - w01) * in.idr);
     const H eps = tau * g_abs(U0d[0] * grho - gmom) * ir0;
     if (MODE & FLUX_EPS_OUT) Fout[D + 2] = eps;
     return (MODE & FLUX_TAUHAT) ? kogan_e(tau, in.dt * eps, in.dt) : kogan(tau, in.dt);
@@ -542,8 +553,9 @@ GKS_HD inline void mx_narrow(Mx<R, D>& g, const Mx<H, D>& w, R bt)
 // the equilibrium-slope terms, then the left side, then the right side are each folded
 // into F and into the right-hand side Rv of the Abar system as soon as their
 // coefficients exist; Abar and the remaining equilibrium terms come last.
-template <typename R, int D, typename H = double, int MODE = 0>
-GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, H* Fout)
+template <typename R, int D, typename H = double, int MODE = 0, typename CS = InCells>
+GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& in, const GasC& gas, H* Fout,
+                                                           const CS& cs = CS())
 {
     constexpr int NV = D + 2;
     constexpr bool SPLIT = !std::is_same<R, H>::value;
@@ -620,7 +632,7 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
     }
     if (MODE & FLUX_EPS_OUT) Fout[D + 3] = tau;
     Kw<H> kwh;
-    if (MODE & (FLUX_TAUHAT | FLUX_EPS_OUT)) kwh = mode_weights<D, H, MODE>(in, tau, W0, U0d, ir0, Fout);
+    if (MODE & (FLUX_TAUHAT | FLUX_EPS_OUT)) kwh = mode_weights<D, H, MODE>(in, tau, W0, U0d, ir0, Fout, cs);
     else kwh = kogan(tau, in.dt);
     const Kw<R> kw = kw_narrow<R>(kwh);
 
@@ -681,11 +693,11 @@ GKS_HD __attribute__((always_inline)) inline int face_flux(const FaceIn<D, H>& i
         urec(m0n, U, g0.h, 6);
         R r[NV], ab[NV], T1[NV], T2[NV];
         const H il = ir0 * in.idl, ir = ir0 * in.idr;
-        for (int m = 0; m < NV; ++m) r[m] = R((W0[m] - in.Wi[m]) * il);
+        for (int m = 0; m < NV; ++m) r[m] = R((W0[m] - cell_of(in, cs, 0, m)) * il);
         solve(g0, r, b, inv_b, ab);
         tmom(g0, m0p + 1, ab, bt, T1);                 // <u psi abar_l.psi>_{g0,>0}
         tmom(g0, m0p + 2, ab, bt, T2);                 // <u^2 psi abar_l.psi>_{g0,>0}
-        for (int m = 0; m < NV; ++m) r[m] = R((in.Wi1[m] - W0[m]) * ir);
+        for (int m = 0; m < NV; ++m) r[m] = R((cell_of(in, cs, 1, m) - W0[m]) * ir);
         solve(g0, r, b, inv_b, ab);
         R T3[NV];
         tmom(g0, m0n + 1, ab, bt, T3);

@@ -417,11 +417,11 @@ template <int V> constexpr int halo_of() { return (V & V_W5) ? 3 : 2; }
 
 // tg_l, tg_r: with FLUX_MULTID, the tangential gradients of the two cells, [(D-1) x (D+2)]
 // in the global component order, tangential axes in increasing order.
-template <typename R, int D, int DIR, int MODE, int RK, typename P, typename SW>
+template <typename R, int D, int DIR, int MODE, int RK, typename P, typename SW, typename CS = InCells>
 __device__ __attribute__((always_inline)) inline int face_eval_s(cref<Inst> I, int i, const SW& Wc, P kk, P ww, P ss,
                                                                  int il, int ir, double dt, double* Fg,
                                                                  const double* tg_l = nullptr,
-                                                                 const double* tg_r = nullptr)
+                                                                 const double* tg_r = nullptr, const CS& cs = CS())
 {
     constexpr int NV = D + 2;
     FaceGeo<double> geo;
@@ -468,7 +468,16 @@ __device__ __attribute__((always_inline)) inline int face_eval_s(cref<Inst> I, i
     in.dt = dt;
     GasC gas{I.mu, I.c_a, I.b, I.two_over_b, I.inv_b, I.inv_cmu, I.pfix};
     double F[NV + ((MODE & FLUX_EPS_OUT) ? 2 : 0)];
-    const int bad = face_flux<R, D, double, MODE>(in, gas, F);
+    int bad;
+    if constexpr (std::is_same<CS, InCells>::value) {
+        bad = face_flux<R, D, double, MODE>(in, gas, F);
+    } else {
+        // cs reads global components; the flux asks for face-local ones
+        auto local = [&](int side, int m) {
+            return cs(side, m == 1 ? 1 + DIR : (m == 2 ? 1 + P1 : ((m == 3 && D == 3) ? 1 + P2 : m)));
+        };
+        bad = face_flux<R, D, double, MODE>(in, gas, F, local);
+    }
     Fg[0] = F[0];
     Fg[1 + DIR] = F[1];
     Fg[1 + P1] = F[2];
@@ -993,9 +1002,18 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                     // the wider stencils are read from LDS one component at a time
                     (void)Wc;
                     const int e0 = (j + HW) * WX + i + HW - 2;
+                    // The two cells' states are read again from LDS where the flux uses them
+                    // (the equilibrium slopes), through an opaque index so that the earlier
+                    // reads are not reused: eight values fewer stay live through the flux,
+                    // which the wider reconstructions' face values would otherwise spill.
+                    auto cells = [&](int side, int m) {
+                        int e = e0;
+                        asm volatile("" : "+v"(e));
+                        return sW[m][e + 1 + side];
+                    };
                     bad = face_eval_s<R, 2, 0, FMODE, RK>(I, x0 + i, [&](int o, int m) { return sW[m][e0 + o]; },
                                                           &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + 1, dt, F, tg[0],
-                                                          tg[1]);
+                                                          tg[1], cells);
                 }
                 if (bad) atomicOr(&I.st->err, 1);
                 sFx[0][tid] = F[0];
@@ -1041,9 +1059,14 @@ void k_tile2(const void* __restrict__ table, int cap, int cls)
                 } else {
                     (void)Wc;
                     const int e0 = (j + HW - 2) * WX + i + HW;
+                    auto cells = [&](int side, int m) {
+                        int e = e0;
+                        asm volatile("" : "+v"(e));
+                        return sW[m][e + (1 + side) * WX];
+                    };
                     bad = face_eval_s<R, 2, 1, FMODE, RK>(I, y0 + j, [&](int o, int m) { return sW[m][e0 + o * WX]; },
                                                           &sK[0][0], &sK[1][0], &sK[2][0], kl, kl + T2_KX, dt, F,
-                                                          tg[0], tg[1]);
+                                                          tg[0], tg[1], cells);
                 }
                 if (bad) atomicOr(&I.st->err, 1);
                 sFy[0][tid] = F[0];

@@ -69,7 +69,9 @@ def test_fused_2d_kernels_occupancy(remarks):
     assert len(k64) == 18 and len(k32) == 18
     for k, v in k64.items():
         md = bool(_variant(k) & 8)
-        assert v["ScratchSize"] <= (40 if _variant(k) & 4 else (96 if _variant(k) & 16 else 0)), (k, v)
+        # the cells' states are reread from LDS late in the flux: at most 20 bytes remain
+        # (third-order without tau_hat, and the transported WENO5 forms)
+        assert v["ScratchSize"] <= (24 if _variant(k) & (4 | 16) else 0), (k, v)
         assert v["Occupancy"] >= (2 if md else 3), (k, v)
     for k, v in k32.items():
         assert v["ScratchSize"] <= (8 if _variant(k) == 0 else 0), (k, v)
