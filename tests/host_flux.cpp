@@ -13,7 +13,7 @@ using std::sqrt;
 
 namespace {
 template <typename R, int D, int MODE>
-int run(const double* gp, const double* const* a, const double* sc, double* F)
+int run(const double* gp, const double* const* a, const double* sc, double* F, bool source = false)
 {
     constexpr int NV = D + 2;
     gks::FaceIn<D, double> in;
@@ -38,18 +38,31 @@ int run(const double* gp, const double* const* a, const double* sc, double* F)
     in.dt = sc[5];
     const double gamma = gp[0], prandtl = gp[1], b = 2.0 / (gamma - 1.0);
     gks::GasC gas{gp[2], gp[3], b, 2.0 / b, 1.0 / b, 1.0 / gp[4], 1.0 / prandtl - 1.0};
-    return gks::face_flux<R, D, double, MODE>(in, gas, F);
+    if (!source) return gks::face_flux<R, D, double, MODE>(in, gas, F);
+    // the two cells' states through the optional source, with the FaceIn copies spoiled, so
+    // that any read of the copies shows in the flux
+    for (int m = 0; m < NV; ++m) in.Wi[m] = in.Wi1[m] = std::nan("");
+    auto cells = [a](int side, int m) { return a[4 + side][m]; };
+    return gks::face_flux<R, D, double, MODE>(in, gas, F, cells);
 }
 
 template <typename R, int D>
-int by_mode(int mode, const double* gp, const double* const* a, const double* sc, double* F)
+int by_mode(int mode, const double* gp, const double* const* a, const double* sc, double* F, bool source)
 {
     switch (mode) {
-    case 0: return run<R, D, 0>(gp, a, sc, F);
-    case gks::FLUX_TAUHAT: return run<R, D, gks::FLUX_TAUHAT>(gp, a, sc, F);
-    case gks::FLUX_MULTID: return run<R, D, gks::FLUX_MULTID>(gp, a, sc, F);
-    default: return run<R, D, gks::FLUX_TAUHAT | gks::FLUX_MULTID>(gp, a, sc, F);
+    case 0: return run<R, D, 0>(gp, a, sc, F, source);
+    case gks::FLUX_TAUHAT: return run<R, D, gks::FLUX_TAUHAT>(gp, a, sc, F, source);
+    case gks::FLUX_MULTID: return run<R, D, gks::FLUX_MULTID>(gp, a, sc, F, source);
+    default: return run<R, D, gks::FLUX_TAUHAT | gks::FLUX_MULTID>(gp, a, sc, F, source);
     }
+}
+
+int any(int dim, int fp32, int mode, const double* gp, const double* const* a, const double* sc, double* F,
+        bool source)
+{
+    if (dim == 2)
+        return fp32 ? by_mode<float, 2>(mode, gp, a, sc, F, source) : by_mode<double, 2>(mode, gp, a, sc, F, source);
+    return fp32 ? by_mode<float, 3>(mode, gp, a, sc, F, source) : by_mode<double, 3>(mode, gp, a, sc, F, source);
 }
 }  // namespace
 
@@ -64,6 +77,16 @@ extern "C" int hf_face_flux(int dim, int fp32, int mode, const double* gp, const
                             const double* tl, const double* tr, const double* sc, double* F)
 {
     const double* a[8] = {Wl, Wr, sl, sr, Wi, Wi1, tl, tr};
-    if (dim == 2) return fp32 ? by_mode<float, 2>(mode, gp, a, sc, F) : by_mode<double, 2>(mode, gp, a, sc, F);
-    return fp32 ? by_mode<float, 3>(mode, gp, a, sc, F) : by_mode<double, 3>(mode, gp, a, sc, F);
+    return any(dim, fp32, mode, gp, a, sc, F, false);
+}
+
+// The same face with the two cells' states Wi, Wi1 handed to the flux through its optional
+// source (as the 2D tile kernel does for the wider reconstructions) instead of FaceIn.
+extern "C" int hf_face_flux_source(int dim, int fp32, int mode, const double* gp, const double* Wl,
+                                   const double* Wr, const double* sl, const double* sr, const double* Wi,
+                                   const double* Wi1, const double* tl, const double* tr, const double* sc,
+                                   double* F)
+{
+    const double* a[8] = {Wl, Wr, sl, sr, Wi, Wi1, tl, tr};
+    return any(dim, fp32, mode, gp, a, sc, F, true);
 }

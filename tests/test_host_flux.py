@@ -32,8 +32,9 @@ def hf(tmp_path_factory):
                            "-I", os.path.join(ROOT, "paper_1302_2132_amd", "csrc"), "-o", lib,
                            os.path.join(ROOT, "tests", "host_flux.cpp")])
     L = C.CDLL(lib)
-    L.hf_face_flux.argtypes = [C.c_int, C.c_int, C.c_int] + [DP] * 11
-    L.hf_face_flux.restype = C.c_int
+    for f in (L.hf_face_flux, L.hf_face_flux_source):
+        f.argtypes = [C.c_int, C.c_int, C.c_int] + [DP] * 11
+        f.restype = C.c_int
     return L
 
 
@@ -105,3 +106,26 @@ def test_non_physical_state_is_reported_by_both(hf):
                            F.ctypes.data_as(DP)) == 1
     with pytest.raises(oracle.OracleError):
         oracle.face_flux(2, bad, w, z, z, w, w, 0.01, 0.01, 1e-3, 10.0, 1.0, 1e-4)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 4, 5], ids=["dt", "tauhat", "multid", "multid-tauhat"])
+@pytest.mark.parametrize("fp32", [0, 1], ids=["fp64", "fp32_flux"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cell_states_through_the_optional_source(hf, dim, fp32, mode):
+    """The 2D tile kernel hands the flux the two cells' states through an optional source
+    (read again from LDS where they are used) rather than the FaceIn copies.  With the
+    copies spoiled (NaN), the flux through the source must equal the default one bitwise:
+    every use of the cells' states goes through the source, and nothing else changes."""
+    rng = np.random.default_rng(700 + 100 * dim + 10 * fp32 + mode)
+    nv = dim + 2
+    for _ in range(100):
+        f = _face(dim, rng, mode & 4)
+        gp = np.array([1.4, 0.72, f["mu"], f["c_a"], 0.09])
+        sc = np.array([f["dx"], f["dx"], f["kf"], f["wf"], f["Sf"], f["dt"]])
+        args = [_p(gp)] + [_p(f[k]) for k in ("Wl", "Wr", "sl", "sr", "Wi", "Wi1")] + [_p(f["tl"]), _p(f["tr"]),
+                                                                                      _p(sc)]
+        Fa, Fb = np.zeros(nv), np.zeros(nv)
+        sa = hf.hf_face_flux(dim, fp32, mode, *args, Fa.ctypes.data_as(DP))
+        sb = hf.hf_face_flux_source(dim, fp32, mode, *args, Fb.ctypes.data_as(DP))
+        assert sa == sb == 0
+        assert np.array_equal(Fa, Fb), (Fa, Fb)
